@@ -1,0 +1,563 @@
+"""FP64 CPU oracle for one step of the regularised lattice Boltzmann method of
+Brownlee, Levesley, Packwood and Gorban, "Add-ons for Lattice Boltzmann
+Methods: Regularization, Filtering and Limiters" (arXiv:1110.0270).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+benchmark's CPU-baseline leg, never by the HIP library or its binding.
+
+Plain PyTorch CPU operations in float64, written for readability, not speed.
+Populations are tensors of shape (Q, ny, nx); D1Q3 uses ny = 1.  One time
+step, all sites at once (a Jacobi update from the state at time t), in the
+order:
+
+  stream (pull, boundaries)            -- section 2, eq. of free flight
+  moments, equilibrium                 -- section 2; section 6 (1D equilibria);
+                                          section 8 (2D product equilibrium)
+  nonequilibrium entropy Delta S       -- section 4, Kullback entropy (eq. Kul, DelS)
+  median entropy filter (optional)     -- section 4, "Median entropy filter"
+  Ehrenfest selection (optional)       -- section 4, Ehrenfests' regularisation
+  collision: LBGK | MRT | ELBM         -- eq. CollisionIntegral; section 5; section 3
+  positivity rule (optional)           -- section 4, eq. LimGenF and StrLine
+
+Readings of passages that the paper leaves open are marked "Reading:" where
+they are used.  Autograd through `step` gives the exact (sub)gradient of the
+step; the ELBM root carries its implicit-function derivative.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, replace
+from typing import Optional
+
+import torch
+
+DT = torch.float64
+
+__all__ = [
+    "Lattice", "Config", "relaxation_rate", "phi_poly", "phi_entropic",
+    "equilibrium", "moments", "velocity", "stream", "entropy", "h_fn",
+    "kullback_dS", "lbgk", "mrt_basis", "mrt_rates", "mrt", "elbm_alpha",
+    "elbm", "positivity", "median_filter", "ehrenfest_select", "step", "run",
+    "stats", "init_equilibrium", "ELBM_ROOT", "ELBM_CUTOFF", "ELBM_NOROOT",
+    "ELBM_NONPOS",
+]
+
+
+# ---------------------------------------------------------------------------
+# Lattices.  Section 6 gives the D1Q3 velocities (-1, 0, 1); its polynomial
+# equilibria at u = 0 fix the weights (1/6, 2/3, 1/6).  D2Q9 (section 5) has
+# the nine velocities (a, b) in {-1,0,1}^2; the product equilibrium of
+# section 8 fixes w_(a,b) = w_a w_b.  Index order ("tensor order"):
+# i = 3 (b + 1) + (a + 1), so the opposite of i is Q - 1 - i.
+# ---------------------------------------------------------------------------
+class Lattice:
+    def __init__(self, name: str):
+        w1 = (1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0)
+        if name == "D1Q3":
+            vel = [(-1, 0), (0, 0), (1, 0)]
+            w = list(w1)
+        elif name == "D2Q9":
+            vel = [(a, b) for b in (-1, 0, 1) for a in (-1, 0, 1)]
+            w = [w1[a + 1] * w1[b + 1] for (a, b) in vel]
+        else:
+            raise ValueError(f"unknown lattice {name}")
+        self.name = name
+        self.Q = len(vel)
+        self.vel = vel
+        self.opp = [vel.index((-a, -b)) for (a, b) in vel]
+        self.vx = torch.tensor([a for a, _ in vel], dtype=DT)
+        self.vy = torch.tensor([b for _, b in vel], dtype=DT)
+        self.w = torch.tensor(w, dtype=DT)
+
+    def col(self, t: torch.Tensor) -> torch.Tensor:
+        """Reshape a (Q,) tensor to broadcast against (Q, ...) populations."""
+        return t.view(self.Q, *([1] * 2))
+
+
+@dataclass
+class Config:
+    lattice: str = "D2Q9"
+    nx: int = 16
+    ny: int = 16
+    bc: str = "periodic"          # periodic | bounceback | cavity | couette
+    u_lid: float = 0.0
+    rho_wall: float = 1.0
+    collision: str = "lbgk"       # lbgk | mrt | elbm
+    equilibrium: str = "poly"     # poly | entropic (ELBM always uses entropic)
+    nu: Optional[float] = None
+    omega: Optional[float] = None
+    mrt_basis: str = "M1"         # M1 (section 5, C1 rates) | M2 (C2 rates)
+    s_e: float = 1.64
+    s_eps: float = 1.54
+    s_q: float = 1.9
+    ehrenfest: bool = False
+    ehr_k: int = 0
+    ehr_delta: float = 0.0
+    median: bool = False
+    med_delta: float = 1e-3
+    positivity: bool = False
+    elbm_norm: str = "entropic"   # entropic | l1
+    elbm_fallback: str = "positivity"  # positivity | ehrenfest
+    elbm_eps: float = 1e-14
+    elbm_max_iter: int = 32
+    elbm_dS_cut: float = 1e-15
+
+    def with_(self, **kw) -> "Config":
+        return replace(self, **kw)
+
+
+def relaxation_rate(cfg: Config) -> float:
+    """omega from nu = c_s^2 (1/omega - 1/2), c_s^2 = 1/3.
+
+    Reading: the paper's beta = eps/(2 nu + eps) (section 2) uses a different
+    viscosity scale; the rate is bound here to the lattice viscosity
+    nu = c_s^2 (1/omega - 1/2) whose decay the shear-wave test measures."""
+    if cfg.omega is not None:
+        return float(cfg.omega)
+    return 1.0 / (3.0 * cfg.nu + 0.5)
+
+
+# ---------------------------------------------------------------------------
+# Equilibria (section 6: 1D polynomial and entropic equilibria; section 8:
+# the 2D quasi-equilibrium is the product of the 1D ones).  phi(u) returns
+# the three factors for a = -1, 0, +1 stacked on dim 0.
+# ---------------------------------------------------------------------------
+def phi_poly(u: torch.Tensor) -> torch.Tensor:
+    return torch.stack([(1.0 - 3.0 * u + 3.0 * u * u) / 6.0,
+                        (2.0 / 3.0) * (1.0 - 1.5 * u * u),
+                        (1.0 + 3.0 * u + 3.0 * u * u) / 6.0])
+
+
+def phi_entropic(u: torch.Tensor) -> torch.Tensor:
+    s = torch.sqrt(1.0 + 3.0 * u * u)
+    return torch.stack([(-3.0 * u - 1.0 + 2.0 * s) / 6.0,
+                        (2.0 / 3.0) * (2.0 - s),
+                        (3.0 * u - 1.0 + 2.0 * s) / 6.0])
+
+
+def equilibrium(lat: Lattice, rho, ux, uy, kind: str = "poly") -> torch.Tensor:
+    phi = phi_poly if kind == "poly" else phi_entropic
+    px = phi(ux)
+    if lat.name == "D1Q3":
+        return rho.unsqueeze(0) * px
+    py = phi(uy)
+    return torch.stack([rho * px[a + 1] * py[b + 1] for (a, b) in lat.vel])
+
+
+def moments(lat: Lattice, f: torch.Tensor):
+    """rho = sum_i f_i and rho u = sum_i v_i f_i (section 2)."""
+    rho = f.sum(0)
+    jx = (lat.col(lat.vx) * f).sum(0)
+    jy = (lat.col(lat.vy) * f).sum(0)
+    return rho, jx, jy
+
+
+def velocity(lat: Lattice, f: torch.Tensor):
+    rho, jx, jy = moments(lat, f)
+    return rho, jx / rho, jy / rho
+
+
+def init_equilibrium(lat: Lattice, rho, ux, uy, kind="poly") -> torch.Tensor:
+    """Populations at equilibrium for given macroscopic fields (ny, nx)."""
+    t = lambda a: torch.as_tensor(a, dtype=DT)  # noqa: E731
+    return equilibrium(lat, t(rho), t(ux), t(uy), kind)
+
+
+# ---------------------------------------------------------------------------
+# Free flight (section 2): f_i(x, t+1) = f_i(x - v_i, t), as a pull.
+# Reading of "bounce back" (section 8): halfway bounce-back with every node a
+# fluid node.  A population whose source x - v_i lies outside the domain is
+# the opposite population of the same node; when the source lies above the
+# top row of a cavity (the lid takes precedence at the two top corners), the
+# moving wall adds 6 w_i rho_wall (v_i . u_wall), u_wall = (u_lid, 0).
+# "couette" is the same lid over a bounce-back floor with periodic sides.
+# ---------------------------------------------------------------------------
+def stream(lat: Lattice, g: torch.Tensor, bc: str, u_lid: float = 0.0,
+           rho_wall: float = 1.0) -> torch.Tensor:
+    Q, ny, nx = g.shape
+    ys = torch.arange(ny).view(ny, 1)
+    xs = torch.arange(nx).view(1, nx)
+    out = []
+    for i, (a, b) in enumerate(lat.vel):
+        shifted = torch.roll(g[i], shifts=(b, a), dims=(0, 1))
+        if bc == "periodic":
+            out.append(shifted)
+            continue
+        sx, sy = xs - a, ys - b
+        outside = (sy < 0) | (sy >= ny)
+        if bc != "couette":                 # couette: periodic in x
+            outside = outside | (sx < 0) | (sx >= nx)
+        outside = outside.expand(ny, nx)
+        refl = g[lat.opp[i]]
+        if bc in ("cavity", "couette"):
+            from_lid = (sy >= ny).expand(ny, nx)
+            lid = 6.0 * float(lat.w[i]) * rho_wall * a * u_lid
+            refl = refl + torch.where(from_lid, lid, 0.0).to(DT)
+        elif bc != "bounceback":
+            raise ValueError(bc)
+        out.append(torch.where(outside, refl, shifted))
+    return torch.stack(out)
+
+
+# ---------------------------------------------------------------------------
+# Entropy and nonequilibrium entropy (section 3, eq. ELBMEntropy; section 4,
+# eqs. Kul, KulSq, DelS).  Perfect entropy S(f) = -sum f_i ln(f_i / W_i) with
+# W_i = w_i (the D1Q3 form with W = (1, 4, 1) differs by a multiple of rho).
+# ---------------------------------------------------------------------------
+def entropy(lat: Lattice, f: torch.Tensor) -> torch.Tensor:
+    return -torch.xlogy(f, f / lat.col(lat.w)).sum(0)
+
+
+_H_SERIES = [((-1.0) ** n) / (n * (n - 1)) for n in range(2, 17)]
+
+
+def h_fn(x: torch.Tensor) -> torch.Tensor:
+    """h(x) = (1 + x) ln(1 + x) - x for x >= -1, with h(-1) = 1 (0 ln 0 = 0).
+
+    For |x| < 0.1 the Taylor series sum_{n>=2} (-1)^n x^n / (n (n-1)) is
+    summed to n = 16 (truncation below 1e-16 relative), avoiding the
+    cancellation of the direct form."""
+    small = x.abs() < 0.1
+    xs = torch.where(small, x, torch.zeros_like(x))
+    acc = torch.zeros_like(x)
+    for c in reversed(_H_SERIES[1:]):
+        acc = (acc + c) * xs
+    series = (acc + _H_SERIES[0]) * xs * xs
+    edge = x <= -1.0
+    xd = torch.where(small | edge, torch.full_like(x, 0.5), x)
+    direct = (1.0 + xd) * torch.log1p(xd) - xd
+    return torch.where(small, series, torch.where(edge, torch.ones_like(x), direct))
+
+
+def kullback_dS(f: torch.Tensor, feq: torch.Tensor) -> torch.Tensor:
+    """Delta S = sum_i f_i ln(f_i / f*_i) (eq. DelS), evaluated as
+    sum_i f*_i h((f_i - f*_i) / f*_i), which is the same sum because f and f*
+    share their density.  This form keeps full relative accuracy when Delta S
+    is far below rounding of rho.  Reading: Delta S = +inf at a site with a
+    negative population (the Kullback sum is undefined there)."""
+    x = (f - feq) / feq
+    terms = feq * h_fn(x)
+    bad = ((f < 0) | (feq <= 0)).any(0)
+    return torch.where(bad, torch.full_like(terms[0], math.inf), terms.sum(0))
+
+
+# ---------------------------------------------------------------------------
+# Collisions.
+# ---------------------------------------------------------------------------
+def lbgk(f, feq, omega):
+    """F(f) = f + alpha beta (f* - f) with alpha beta = omega
+    (eq. CollisionIntegral)."""
+    return f + omega * (feq - f)
+
+
+def mrt_basis(kind: str) -> torch.Tensor:
+    """Change-of-basis matrix rebuilt from its defining velocity polynomials
+    (section 5), columns in tensor order.
+
+    M1 rows: rho, e, epsilon, j_x, q_x, j_y, q_y, p_xx, p_xy, i.e. 1,
+    -4 + 3 v^2, 4 - 21/2 v^2 + 9/2 v^4, v_x, (-5 + 3 v^2) v_x, v_y,
+    (-5 + 3 v^2) v_y, v_x^2 - v_y^2, v_x v_y.
+    M2 rows: 1, v_x, v_y, v_x^2 + v_y^2, v_x^2 - v_y^2, v_x v_y, v_x^2 v_y,
+    v_x v_y^2, v_x^2 v_y^2 (the listed basis; the printed M2 has its last two
+    cubic rows interchanged, which the C2 rates make immaterial)."""
+    lat = Lattice("D2Q9")
+    vx, vy = lat.vx, lat.vy
+    v2 = vx * vx + vy * vy
+    one = torch.ones_like(vx)
+    if kind == "M1":
+        rows = [one, -4 + 3 * v2, 4 - 10.5 * v2 + 4.5 * v2 * v2, vx,
+                (-5 + 3 * v2) * vx, vy, (-5 + 3 * v2) * vy, vx * vx - vy * vy,
+                vx * vy]
+    elif kind == "M2":
+        rows = [one, vx, vy, v2, vx * vx - vy * vy, vx * vy, vx * vx * vy,
+                vx * vy * vy, vx * vx * vy * vy]
+    else:
+        raise ValueError(kind)
+    return torch.stack(rows)
+
+
+def mrt_rates(kind: str, s_e: float, s_eps: float, s_q: float, s_nu):
+    """Diagonal of C1 = diag(1, s_e, s_eps, 1, s_q, 1, s_q, s_nu, s_nu) or
+    C2 = diag(1, 1, 1, 1, s_nu, s_nu, 1, 1, 1) (section 5).  s_nu may be a
+    tensor (per-site shear rate); the result then has shape (9, *s_nu.shape).
+    Reading: s_nu is the shear rate (the text names the second-order rates
+    both ways; the TRT paragraph ties s_nu to shear viscosity)."""
+    s_nu = torch.as_tensor(s_nu, dtype=DT)
+    one = torch.ones_like(s_nu)
+    if kind == "M1":
+        c = [one, s_e * one, s_eps * one, one, s_q * one, one, s_q * one, s_nu, s_nu]
+    else:
+        c = [one, one, one, one, s_nu, s_nu, one, one, one]
+    return torch.stack(c)
+
+
+def mrt(f, feq, M, rates):
+    """F(f) = f + M^{-1} C M (f* - f) (section 5), applied in moment space.
+    `rates` has shape (9,) or (9, ny, nx)."""
+    Minv = torch.linalg.inv(M)
+    Q = f.shape[0]
+    d = (feq - f).reshape(Q, -1)
+    m = M @ d
+    r = rates.reshape(Q, -1) if rates.dim() > 1 else rates.view(Q, 1)
+    return f + (Minv @ (r * m)).reshape(f.shape)
+
+
+# ---------------------------------------------------------------------------
+# ELBM (section 3): alpha is the nontrivial root of S(f + alpha (f* - f)) =
+# S(f), found by successive parabolas from the LBGK estimate alpha = 2.
+# With Delta = f* - f and entropic f*, S_f(alpha) = S(f + alpha Delta) - S(f)
+# and its derivatives are evaluated in a cancellation-free form that uses
+# the exact identities sum_i Delta_i = 0 and sum_i Delta_i ln(f*_i/W_i) = 0:
+#   S_f   = -sum f_i h(alpha Delta_i / f_i) - alpha sum Delta_i ln(f_i / f*_i)
+#   S_f'  = -sum Delta_i ln((f_i + alpha Delta_i) / f*_i)
+#   S_f'' = -sum Delta_i^2 / (f_i + alpha Delta_i)
+# ---------------------------------------------------------------------------
+def _sf_parts(f, D, feq, alpha):
+    x = alpha * D / f
+    lnr = torch.log1p(-D / feq)                       # ln(f_i / f*_i)
+    sf = -(f * h_fn(x)).sum(0) - alpha * (D * lnr).sum(0)
+    d1 = -(D * (torch.log1p(x.clamp(min=-1.0)) + lnr)).sum(0)
+    d2 = -(D * D / (f + alpha * D)).sum(0)
+    return sf, d1, d2
+
+
+# branch codes shared by elbm_alpha's outputs
+ELBM_ROOT, ELBM_CUTOFF, ELBM_NOROOT, ELBM_NONPOS = 0, 1, 2, 3
+
+
+def elbm_alpha(f, feq, *, eps=1e-14, max_iter=32, dS_cut=1e-15,
+               norm="entropic", fallback="positivity"):
+    """Per-site alpha for ELBM.  f, feq: (Q, n).  Returns (alpha, branch).
+
+    Steps (section 3, "ELBM algorithm" and "Numerical method"):
+      * Delta S < dS_cut (1e-15 in the paper): plain LBGK, alpha = 2.
+      * alpha_max = min over Delta_i < 0 of f_i / (-Delta_i), the largest
+        alpha keeping f + alpha Delta >= 0.  If S_f(alpha_max) >= 0 there is
+        no nontrivial root: the positivity rule takes alpha = alpha_max, the
+        Ehrenfest rule alpha = 1.
+      * Otherwise iterate from alpha_0 = 2 (Reading: (1 + alpha_max)/2 when 2
+        is not below alpha_max): stop when |S_f / S_f'| * ||Delta|| < eps
+        (eq. ConvergenceTwo with the Newton estimate eq. Stopping), else move
+        to the greater root of the second-order Taylor parabola, written as
+        2 S_f / (-S_f' + sqrt(S_f'^2 - 2 S_f S_f'')).  Reading: a negative
+        discriminant takes a Newton step; a step leaving (1, alpha_max) is
+        replaced by bisection towards the violated bound.
+      * After convergence, if S_f(alpha) < 0 take one double-length Newton
+        step alpha - 2 S_f / S_f' to land below the root.
+    Reading: ||Delta|| is the entropic norm sqrt(sum Delta_i^2 / f*_i) (the
+    square root of the quadratic form of the second differential), or L1;
+    eps = 1e-14 (no value is printed).  Reading: a site with a non-positive
+    population has no entropy; it takes alpha = 1."""
+    with torch.no_grad():
+        fd, qd = f.detach(), feq.detach()
+        D = qd - fd
+        n = fd.shape[1]
+        dS = kullback_dS(fd, qd)
+        nonpos = (fd <= 0).any(0)
+        cut = (dS < dS_cut) & ~nonpos
+        ratio = torch.where(D < 0, fd / (-D).clamp(min=1e-300), torch.full_like(fd, math.inf))
+        amax = ratio.min(0).values
+        finite = torch.isfinite(amax)
+        a_probe = torch.where(finite, amax, torch.full_like(amax, 2.0))
+        sf_max, _, _ = _sf_parts(fd, D, qd, a_probe)
+        noroot = ~cut & ~nonpos & finite & (sf_max >= 0)
+        active = ~cut & ~nonpos & ~noroot
+        nrm = torch.sqrt((D * D / qd).sum(0)) if norm == "entropic" else D.abs().sum(0)
+        alpha = torch.where(amax > 2.0, torch.full_like(amax, 2.0), 0.5 * (1.0 + amax))
+        todo = active.clone()
+        for _ in range(max_iter):
+            if not bool(todo.any()):
+                break
+            sf, d1, d2 = _sf_parts(fd, D, qd, alpha)
+            stop = (sf / d1).abs() * nrm < eps
+            todo = todo & ~stop
+            disc = d1 * d1 - 2.0 * sf * d2
+            par = 2.0 * sf / (-d1 + torch.sqrt(disc.clamp(min=0.0)))
+            newton = -sf / d1
+            delta = torch.where(disc >= 0, par, newton)
+            anew = alpha + delta
+            anew = torch.where(anew >= amax, 0.5 * (alpha + amax), anew)
+            anew = torch.where(anew <= 1.0, 0.5 * (alpha + 1.0), anew)
+            alpha = torch.where(todo, anew, alpha)
+        sf, d1, _ = _sf_parts(fd, D, qd, alpha)
+        alpha = torch.where(active & (sf < 0), alpha - 2.0 * sf / d1, alpha)
+        fb = amax if fallback == "positivity" else torch.ones_like(amax)
+        alpha = torch.where(noroot, fb, alpha)
+        alpha = torch.where(cut, torch.full_like(alpha, 2.0), alpha)
+        alpha = torch.where(nonpos, torch.ones_like(alpha), alpha)
+        branch = torch.full((n,), ELBM_ROOT, dtype=torch.int64)
+        branch[cut] = ELBM_CUTOFF
+        branch[noroot] = ELBM_NOROOT
+        branch[nonpos] = ELBM_NONPOS
+
+    if not (torch.is_grad_enabled() and (f.requires_grad or feq.requires_grad)):
+        return alpha, branch
+    out = alpha.clone()
+    # Implicit derivative at the root: d alpha = -(d_f S_f) / (d_alpha S_f).
+    ridx = torch.nonzero(branch == ELBM_ROOT).flatten()
+    if ridx.numel() > 0:
+        fr, qr, ar = f[:, ridx], feq[:, ridx], alpha[ridx]
+        sf, _, _ = _sf_parts(fr, qr - fr, qr, ar)
+        _, d1, _ = _sf_parts(fr.detach(), (qr - fr).detach(), qr.detach(), ar)
+        corr = -sf / d1
+        out = out.index_put((ridx,), ar + (corr - corr.detach()))
+    # Positivity fallback: alpha = alpha_max depends on f through the argmin.
+    if fallback == "positivity":
+        pidx = torch.nonzero(branch == ELBM_NOROOT).flatten()
+        if pidx.numel() > 0:
+            fp, qp = f[:, pidx], feq[:, pidx]
+            Dp = qp - fp
+            ratio = torch.where(Dp < 0, fp / (-Dp).clamp(min=1e-300),
+                                torch.full_like(fp, math.inf))
+            out = out.index_put((pidx,), ratio.min(0).values)
+    return out, branch
+
+
+def elbm(f, feq, omega, **kw):
+    """ELBGK collision f + alpha beta (f* - f) with beta = omega / 2 and
+    alpha from `elbm_alpha` (section 3).  f, feq: (Q, ny, nx)."""
+    Q = f.shape[0]
+    fl, ql = f.reshape(Q, -1), feq.reshape(Q, -1)
+    alpha, branch = elbm_alpha(fl, ql, **kw)
+    om = torch.as_tensor(omega, dtype=DT)
+    beta = (om.reshape(-1) if om.dim() > 0 else om) / 2.0
+    post = fl + alpha * beta * (ql - fl)
+    return post.reshape(f.shape), alpha, branch
+
+
+# ---------------------------------------------------------------------------
+# Limiters (section 4).
+# ---------------------------------------------------------------------------
+def positivity(post, feq):
+    """Positivity rule: a state with a negative component is replaced by the
+    closest non-negative state on the line through it and f*, i.e.
+    f* + phi (F - f*) with phi = min over F_i < 0 of f*_i / (f*_i - F_i).
+    Reading: the component that attains the minimum is set to exactly 0;
+    components with f*_i <= 0 are not eligible.  Returns (out, mask)."""
+    neg = (post < 0) & (feq > 0)
+    ratio = torch.where(neg, feq / (feq - post).clamp(min=1e-300), torch.full_like(post, math.inf))
+    phi, arg = ratio.min(0)
+    act = neg.any(0)
+    phi_s = torch.where(act, phi, torch.ones_like(phi))
+    out = feq + phi_s.unsqueeze(0) * (post - feq)
+    onehot = torch.zeros_like(post, dtype=torch.bool).scatter_(0, arg.unsqueeze(0), True)
+    out = torch.where(onehot & act.unsqueeze(0), torch.zeros_like(out), out)
+    return torch.where(act.unsqueeze(0), out, post), act
+
+
+def median_filter(lat: Lattice, cfg: Config, f, feq, dS):
+    """Median entropy filter (section 4): dS_med is the middle value of the
+    neighbourhood of each site (itself included; 3 sites in 1D, 3x3 in 2D);
+    where dS_med < dS the homothety f* + sqrt(dS_med / dS) (f - f*) is
+    applied (eq. entrHom with the median as threshold).
+    Reading: only neighbours inside the domain count (periodic domains wrap);
+    with n of them the median is the ceil(n/2)-th smallest (2nd of 3, 5th of
+    9 as printed; 3rd of 6 and 2nd of 4 at walls).  Reading: the paper's
+    delta (1e-3 in the Hopf study) is an acceptance threshold: only sites
+    with dS > delta are filtered.  Returns (f_new, mask)."""
+    ny, nx = dS.shape
+    offs = [(0, -1), (0, 0), (0, 1)] if lat.name == "D1Q3" else \
+        [(dy, dx) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+    ys = torch.arange(ny).view(ny, 1)
+    xs = torch.arange(nx).view(1, nx)
+    vals, valid = [], []
+    for dy, dx in offs:
+        v = torch.roll(dS, shifts=(-dy, -dx), dims=(0, 1))   # v[y,x] = dS[y+dy, x+dx]
+        if cfg.bc == "periodic":
+            ok = torch.ones((ny, nx), dtype=torch.bool)
+        else:
+            sy, sx = ys + dy, xs + dx
+            ok = (sy >= 0) & (sy < ny) & (sx >= 0) & (sx < nx)
+        vals.append(torch.where(ok, v, torch.full_like(v, math.inf)))
+        valid.append(ok)
+    stack = torch.stack(vals)
+    n = torch.stack(valid).sum(0)
+    srt = stack.sort(0).values
+    rank = (n + 1) // 2 - 1                                   # ceil(n/2) - 1
+    med = srt.gather(0, rank.unsqueeze(0)).squeeze(0)
+    accept = (dS > cfg.med_delta) & (med < dS) & torch.isfinite(dS)
+    ratio = torch.where(accept, med / torch.where(accept, dS, torch.ones_like(dS)),
+                        torch.ones_like(dS))
+    coef = torch.where(accept, torch.sqrt(ratio.clamp(min=0.0)), torch.ones_like(dS))
+    return feq + coef.unsqueeze(0) * (f - feq), accept
+
+
+def ehrenfest_select(dS_flat: torch.Tensor, k: int, delta: float) -> torch.Tensor:
+    """Ehrenfests' regularisation with a budget (section 4): the k sites with
+    the highest Delta S > delta, ties broken by the lower linear index
+    y * nx + x.  Returns the selected linear indices, sorted ascending."""
+    idx = torch.nonzero(dS_flat > delta).flatten()
+    if k <= 0 or idx.numel() == 0:
+        return torch.zeros(0, dtype=torch.int64)
+    order = torch.sort(-dS_flat[idx], stable=True).indices
+    return torch.sort(idx[order[:k]]).values
+
+
+# ---------------------------------------------------------------------------
+# One step.
+# ---------------------------------------------------------------------------
+def step(lat: Lattice, cfg: Config, g: torch.Tensor,
+         omega_field: Optional[torch.Tensor] = None):
+    """One time step from the stored post-collision lattice g (Q, ny, nx).
+    Returns (g_next, info).  Reading: the Ehrenfest step replaces the
+    collision at the selected sites (f' = f*), and selection ranks the
+    unfiltered Delta S; the median filter acts on the pre-collision state."""
+    pre = stream(lat, g, cfg.bc, cfg.u_lid, cfg.rho_wall)
+    rho, jx, jy = moments(lat, pre)
+    kind = "entropic" if cfg.collision == "elbm" else cfg.equilibrium
+    feq = equilibrium(lat, rho, jx / rho, jy / rho, kind)
+    omega = omega_field if omega_field is not None else relaxation_rate(cfg)
+    info = {}
+    dS = None
+    if cfg.ehrenfest or cfg.median:
+        dS = kullback_dS(pre, feq)
+        info["dS"] = dS.detach()
+    if cfg.median:
+        pre, acc = median_filter(lat, cfg, pre, feq, dS)
+        info["median_mask"] = acc
+    sel = None
+    if cfg.ehrenfest:
+        sel = ehrenfest_select(dS.detach().flatten(), cfg.ehr_k, cfg.ehr_delta)
+        info["selected"] = sel
+    if cfg.collision == "lbgk":
+        post = lbgk(pre, feq, omega)
+    elif cfg.collision == "mrt":
+        M = mrt_basis(cfg.mrt_basis)
+        post = mrt(pre, feq, M, mrt_rates(cfg.mrt_basis, cfg.s_e, cfg.s_eps, cfg.s_q, omega))
+    elif cfg.collision == "elbm":
+        post, alpha, branch = elbm(pre, feq, omega, eps=cfg.elbm_eps,
+                                   max_iter=cfg.elbm_max_iter, dS_cut=cfg.elbm_dS_cut,
+                                   norm=cfg.elbm_norm, fallback=cfg.elbm_fallback)
+        info["alpha"] = alpha.detach().reshape(rho.shape)
+        info["branch"] = branch.reshape(rho.shape)
+    else:
+        raise ValueError(cfg.collision)
+    selmask = torch.zeros(rho.numel(), dtype=torch.bool)
+    if sel is not None and sel.numel() > 0:
+        selmask[sel] = True
+        selmask_q = selmask.view(1, *rho.shape)
+        post = torch.where(selmask_q, feq, post)
+    if cfg.positivity:
+        lim, act = positivity(post, feq)
+        act = act & ~selmask.view(rho.shape)
+        post = torch.where(act.unsqueeze(0), lim, post)
+        info["positivity_mask"] = act
+    return post, info
+
+
+def run(lat: Lattice, cfg: Config, g: torch.Tensor, n: int,
+        omega_field: Optional[torch.Tensor] = None, keep_info: bool = False):
+    infos = []
+    for _ in range(n):
+        g, info = step(lat, cfg, g, omega_field)
+        if keep_info:
+            infos.append(info)
+    return (g, infos) if keep_info else g
+
+
+def stats(lat: Lattice, g: torch.Tensor) -> dict:
+    """Whole-lattice mass, momentum and entropy (sum over sites of
+    -sum_i f_i ln(f_i / w_i)) in float64."""
+    rho, jx, jy = moments(lat, g)
+    return {"mass": float(rho.sum()), "mom_x": float(jx.sum()),
+            "mom_y": float(jy.sum()), "entropy": float(entropy(lat, g).sum())}
