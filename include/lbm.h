@@ -1,0 +1,208 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) library for the regularised lattice
+ * Boltzmann step of Brownlee, Levesley, Packwood and Gorban, "Add-ons for
+ * Lattice Boltzmann Methods: Regularization, Filtering and Limiters"
+ * (arXiv:1110.0270).
+ *
+ * One call of lbm_step advances the lattice by n time steps.  Each step is
+ * the fused per-site pull-stream + collide of section 2 with
+ *   - the LBGK collision (section 2, eq. CollisionIntegral),
+ *   - MRT relaxation in the M1/C1 or M2/C2 basis (section 5),
+ *   - ELBM with the per-site entropic root alpha (section 3),
+ * and the add-on limiters of section 4: the median entropy filter, the
+ * Ehrenfest step on the k sites of largest nonequilibrium entropy, and the
+ * positivity rule.  lbm_backward runs the adjoint of a recorded forward
+ * rollout.
+ *
+ * Memory layout of populations (device and caller buffers alike):
+ *   structure of arrays f[i][y][x], i = 0..Q-1, y = 0..ny-1, x = 0..nx-1,
+ *   x fastest, caller buffers densely packed (row pitch nx).  Velocity
+ *   order ("tensor order"): D2Q9 i = 3 (b + 1) + (a + 1) for velocity
+ *   (a, b) in {-1,0,1}^2, so the opposite of i is 8 - i and i = 4 is rest;
+ *   D1Q3 i = a + 1 for a in {-1, 0, 1}, with ny = 1.
+ *   The site index used for ties is y * nx + x.
+ *   Caller populations are always unshifted f_i; the library may store them
+ *   internally as shifted deviations f_i - w_i rho0 (LBM_F16S, LBM_BF16S).
+ *
+ * Ownership: the caller allocates every device buffer, including the
+ * workspace (lbm_workspace_bytes); the library never allocates device
+ * memory and never frees caller memory.  Buffers passed by pointer must stay
+ * valid while work that uses them can still run on the stream.  The context
+ * object itself is host memory owned by the library (lbm_destroy frees it).
+ *
+ * Streams: every call except lbm_stats, lbm_selected_count and lbm_destroy
+ * only enqueues work on the stream given to lbm_init and returns.  Calls on
+ * one context must not be made from two threads at once.
+ *
+ * Errors: every function returns an lbm_status; nothing aborts or throws
+ * across the ABI.  On failure lbm_last_error() returns a message for the
+ * failing call of this thread.  Invalid arguments leave the context as it
+ * was.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,        /* bad configuration or argument                  */
+  LBM_EWORKSPACE = -2,    /* workspace smaller than lbm_workspace_bytes     */
+  LBM_EHIP = -3,          /* a HIP runtime call failed; message has details */
+  LBM_EDIVERGED = -4,     /* a check found a non-finite value or rho <= 0   */
+  LBM_ESTATE = -5,        /* call out of order (e.g. backward w/o forward)  */
+  LBM_EUNSUPPORTED = -6,  /* valid but not implemented combination          */
+  LBM_ESELECT = -7        /* Ehrenfest candidate buffer overflowed          */
+} lbm_status;
+
+enum { LBM_D1Q3 = 1, LBM_D2Q9 = 2 };
+/* Boundaries: periodic in x and y; bounce-back walls on all sides; cavity =
+ * bounce-back walls with the top wall moving at (u_lid, 0); couette =
+ * periodic in x, resting bottom wall, moving top wall. */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_BOUNCEBACK = 1, LBM_BC_CAVITY = 2, LBM_BC_COUETTE = 3 };
+enum { LBM_LBGK = 0, LBM_MRT = 1, LBM_ELBM = 2 };
+enum { LBM_EQ_POLY = 0, LBM_EQ_ENTROPIC = 1 };
+enum { LBM_MRT_M1 = 0, LBM_MRT_M2 = 1 };
+enum { LBM_LIM_EHRENFEST = 1, LBM_LIM_POSITIVITY = 2, LBM_LIM_MEDIAN = 4 };
+enum { LBM_NORM_ENTROPIC = 0, LBM_NORM_L1 = 1 };
+enum { LBM_FB_POSITIVITY = 0, LBM_FB_EHRENFEST = 1 };
+/* Storage forms of the lattice, and dtype codes of caller buffers
+ * (caller buffers accept LBM_F64 and LBM_F32 only). */
+enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3 };
+
+typedef struct lbm_config {
+  int lattice;            /* LBM_D1Q3 | LBM_D2Q9                                */
+  int nx, ny;             /* grid; ny = 1 for D1Q3                              */
+  int bc;                 /* LBM_BC_*                                           */
+  double u_lid;           /* moving-wall speed (cavity, couette)                */
+  double rho_wall;        /* wall density in the moving-wall term (1.0)         */
+  int collision;          /* LBM_LBGK | LBM_MRT | LBM_ELBM                       */
+  int equilibrium;        /* LBM_EQ_POLY | LBM_EQ_ENTROPIC (ELBM: entropic)      */
+  double nu;              /* viscosity; omega = 1/(3 nu + 1/2).  nu < 0: use omega */
+  double omega;           /* relaxation rate when nu < 0                        */
+  int mrt_basis;          /* LBM_MRT_M1 (C1 rates) | LBM_MRT_M2 (C2 rates)       */
+  double s_e, s_eps, s_q; /* MRT rates of e, epsilon, q (M1 only)               */
+  unsigned limiters;      /* bit set of LBM_LIM_*                               */
+  long long ehr_k;        /* Ehrenfest budget: k sites per step                 */
+  double ehr_delta;       /* Ehrenfest threshold: only Delta S > delta          */
+  double med_delta;       /* median filter acts only where Delta S > med_delta  */
+  int elbm_norm;          /* LBM_NORM_*                                         */
+  int elbm_fallback;      /* no-root rule: LBM_FB_POSITIVITY | LBM_FB_EHRENFEST  */
+  double elbm_eps;        /* stop when |S_f/S_f'| * ||Delta|| < eps (1e-14)     */
+  int elbm_max_iter;      /* parabola iterations (32)                           */
+  double elbm_dS_cut;     /* Delta S below this: plain LBGK (1e-15)             */
+  double elbm_f64_below;  /* FP32 modes: sites with alpha_max below this bound
+                             solve the root in FP64 (3.0)                      */
+  int storage;            /* LBM_F64 | LBM_F32 | LBM_F16S | LBM_BF16S            */
+  double rho0;            /* reference density of the shifted storage (1.0)     */
+  int omega_field;        /* 1: a per-site relaxation field is used (lbm_set_omega) */
+  int checkpoint_every;   /* K > 0: record a rollout for lbm_backward           */
+  long long max_steps;    /* longest rollout lbm_backward must cover            */
+  int check_interval;     /* steps between divergence checks (0: only on lbm_stats) */
+  long long select_capacity; /* Ehrenfest candidate buffer entries (0: automatic) */
+} lbm_config;
+
+typedef struct lbm_stats {
+  double mass;            /* sum over sites of rho                              */
+  double mom_x, mom_y;    /* sum over sites of rho u                            */
+  double entropy;         /* sum over sites of -sum_i f_i ln(f_i / w_i)         */
+  double min_rho;         /* smallest density                                   */
+  long long steps;        /* steps taken since the last lbm_set_*               */
+  long long diverged_step;/* first step at which a check failed, or -1          */
+  long long n_selected;   /* Ehrenfest sites chosen in the last step            */
+  long long select_fallbacks; /* steps whose selection needed a full rescan     */
+  long long select_overflow;  /* steps whose candidate buffer overflowed        */
+  int nonfinite;          /* 1 if the last check found NaN or Inf               */
+} lbm_stats;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Fill *cfg with defaults (D2Q9 64x64 periodic LBGK, omega = 1, FP32). */
+void lbm_config_default(lbm_config* cfg);
+
+/* Bytes of device workspace lbm_init needs for cfg (0 if cfg is invalid;
+ * lbm_last_error then says why).  Includes the checkpoint store when
+ * cfg->checkpoint_every > 0. */
+size_t lbm_workspace_bytes(const lbm_config* cfg);
+
+/* Create a context on the current HIP device.  dev_workspace: device
+ * buffer of at least lbm_workspace_bytes(cfg) bytes, 256-byte aligned,
+ * owned by the caller.  stream: a hipStream_t (NULL = default stream).
+ * The lattice is undefined until lbm_set_equilibrium or
+ * lbm_set_populations.  Errors: LBM_EINVAL, LBM_EWORKSPACE, LBM_EHIP. */
+lbm_status lbm_init(const lbm_config* cfg, void* dev_workspace, size_t ws_bytes,
+                    void* stream, lbm_ctx** out);
+
+/* Set the lattice to the equilibrium f*(rho, u) of the configured kind
+ * (sections 6 and 8: 1D polynomial or entropic equilibria, and their
+ * product in 2D).  rho, ux, uy: device arrays of ny*nx values of the given
+ * dtype (LBM_F64 or LBM_F32); uy is ignored for D1Q3 and may be NULL.
+ * Resets the step counter and the recorded rollout. */
+lbm_status lbm_set_equilibrium(lbm_ctx* ctx, const void* rho, const void* ux,
+                               const void* uy, int dtype);
+
+/* Set the lattice to caller populations f[Q][ny][nx] (device, dtype
+ * LBM_F64 or LBM_F32, unshifted).  Resets the step counter and rollout. */
+lbm_status lbm_set_populations(lbm_ctx* ctx, const void* f, int dtype);
+
+/* Copy the lattice out as unshifted populations f[Q][ny][nx]. */
+lbm_status lbm_get_populations(lbm_ctx* ctx, void* f, int dtype);
+
+/* Per-site relaxation rate omega(x) (device, ny*nx values, dtype LBM_F64 or
+ * LBM_F32); requires cfg.omega_field = 1.  It replaces omega in LBGK and
+ * ELBM (beta = omega/2) and is the shear rate s_nu of MRT (section 5). */
+lbm_status lbm_set_omega(lbm_ctx* ctx, const void* omega, int dtype);
+
+/* Advance n >= 0 time steps (section 2: free flight, then collision, with
+ * the configured limiters of section 4).  Asynchronous. */
+lbm_status lbm_step(lbm_ctx* ctx, long long n);
+
+/* Density and velocity of every site, rho = sum f_i, u = sum v_i f_i / rho
+ * (section 2), into device arrays of ny*nx values (uy may be NULL for
+ * D1Q3). */
+lbm_status lbm_moments(lbm_ctx* ctx, void* rho, void* ux, void* uy, int dtype);
+
+/* Adjoint of the rollout recorded since the last lbm_set_* (requires
+ * cfg.checkpoint_every > 0 and at most cfg.max_steps steps).  dL_dfT: the
+ * gradient of a loss with respect to the final populations f[Q][ny][nx]
+ * (device, dtype).  Writes dL/df0 into dL_df0 and, when dL_domega is not
+ * NULL, dL/d omega(x) into dL_domega (ny*nx).  Gradients pass through the
+ * limiters as subgradients along the branch the forward pass took, and
+ * through the ELBM root by implicit differentiation.  The lattice is left
+ * in its final state.  Errors: LBM_ESTATE without a recorded rollout;
+ * LBM_EUNSUPPORTED for the median filter. */
+lbm_status lbm_backward(lbm_ctx* ctx, const void* dL_dfT, void* dL_df0,
+                        void* dL_domega, int dtype);
+
+/* Synchronise the stream, run a whole-lattice FP64 reduction and fill *out.
+ * Returns LBM_EDIVERGED if this or an earlier check found a non-finite
+ * value or rho <= 0, LBM_ESELECT if a selection overflowed. */
+lbm_status lbm_stats_get(lbm_ctx* ctx, lbm_stats* out);
+
+/* Synchronise and copy the site indices chosen by the Ehrenfest limiter in
+ * the last step into the host array idx (capacity cap, ascending order).
+ * *count receives the number chosen. */
+lbm_status lbm_selected(lbm_ctx* ctx, long long* idx, long long cap, long long* count);
+
+/* Synchronise and copy the cumulative limiter counters into out[0..n-1]:
+ * positivity-rule activations, median-filter corrections, ELBM sites with no
+ * nontrivial root, ELBM sites solved in FP64, ELBM sites with a
+ * non-positive population. */
+lbm_status lbm_counters(lbm_ctx* ctx, unsigned long long* out, int n);
+
+/* Free the context (not the caller's buffers). NULL is allowed. */
+void lbm_destroy(lbm_ctx* ctx);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

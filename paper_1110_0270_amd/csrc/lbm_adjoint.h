@@ -1,0 +1,47 @@
+// Recording of a forward rollout for the adjoint (checkpoints every K steps
+// and the per-step Ehrenfest selections) and the backward pass.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/lbm.h"
+
+namespace lbm {
+
+struct AdjointLayout {
+  bool on = false;
+  int K = 0;                 // checkpoint interval
+  long long max_steps = 0;
+  long long n_ckpt = 0;      // slots: state after 0, K, 2K, ... steps
+  long long k = 0;           // selection budget per step (tape width)
+  size_t lat_bytes = 0;
+  size_t lam_bytes = 0;      // one adjoint lattice (compute precision)
+  size_t off_ckpt = 0;       // n_ckpt lattices
+  size_t off_seg = 0;        // K lattices: states of the segment being reversed
+  size_t off_lam[2] = {0, 0};
+  size_t off_gom = 0;        // per-site omega gradient accumulator
+  size_t off_tape_sel = 0;   // max_steps * k site indices
+  size_t off_tape_cnt = 0;   // max_steps counts
+  size_t end = 0;
+};
+
+AdjointLayout adjoint_layout(const lbm_config* c, size_t lat_bytes, long long qs, long long k,
+                             size_t offset);
+hipError_t adjoint_begin_record(const AdjointLayout& L, char* ws, const void* lat,
+                                size_t lat_bytes, hipStream_t s);
+hipError_t adjoint_after_step(const AdjointLayout& L, char* ws, long long steps_done,
+                              const void* lat, size_t lat_bytes, hipStream_t s);
+// Where step t writes its selected site indices (the tape when recording).
+int32_t* adjoint_selected_slot(const AdjointLayout& L, char* ws, long long t, int32_t* dflt);
+long long* adjoint_count_slot(const AdjointLayout& L, char* ws, long long t);
+
+hipError_t launch_convert_field(const void* src, int src_f64, void* dst, int dst_f64, int nx,
+                                int ny, int pitch, hipStream_t s);
+
+}  // namespace lbm
+
+struct lbm_ctx;
+// Backward pass over the recorded rollout; implemented in lbm_api.hip.

@@ -1,0 +1,485 @@
+// Host implementation of the C ABI declared in include/lbm.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_adjoint.h"
+#include "lbm_internal.h"
+#include "lbm_site.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+lbm_status fail(lbm_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+lbm_status hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return LBM_EHIP;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int elem_bytes(int storage) { return storage == LBM_F64 ? 8 : storage == LBM_F32 ? 4 : 2; }
+bool is_f64(int storage) { return storage == LBM_F64; }
+
+struct Layout {
+  int Q = 0, pitch = 0;
+  long long qs = 0, n_sites = 0, cap = 0, k = 0;
+  size_t lat_bytes = 0;
+  size_t off_lat[2] = {0, 0}, off_omega = 0, off_sel = 0, off_cnt = 0, off_partial = 0,
+         off_stats = 0, off_div = 0, off_ckey = 0, off_cidx = 0, off_cmom = 0, off_hist = 0,
+         off_coarse = 0, off_blist = 0, off_selected = 0;
+  AdjointLayout adj;
+  size_t total = 0;
+};
+
+bool validate(const lbm_config* c, std::string& why) {
+  if (!c) { why = "config is NULL"; return false; }
+  if (c->lattice != LBM_D1Q3 && c->lattice != LBM_D2Q9) { why = "lattice must be LBM_D1Q3 or LBM_D2Q9"; return false; }
+  if (c->nx < 1 || c->ny < 1) { why = "nx and ny must be positive"; return false; }
+  if ((long long)c->nx * c->ny >= (1ll << 31)) { why = "nx*ny must be below 2^31"; return false; }
+  if (c->lattice == LBM_D1Q3 && c->ny != 1) { why = "D1Q3 needs ny = 1"; return false; }
+  if (c->lattice == LBM_D1Q3 && c->bc != LBM_BC_PERIODIC && c->bc != LBM_BC_BOUNCEBACK) {
+    why = "D1Q3 supports periodic and bounce-back ends only"; return false;
+  }
+  if (c->bc < 0 || c->bc > 3) { why = "unknown boundary"; return false; }
+  if (c->collision < 0 || c->collision > 2) { why = "unknown collision"; return false; }
+  if (c->collision == LBM_MRT && c->lattice != LBM_D2Q9) { why = "MRT is defined for D2Q9"; return false; }
+  if (c->storage < 0 || c->storage > 3) { why = "unknown storage"; return false; }
+  if (c->nu < 0 && !(c->omega > 0 && c->omega < 2.0000001)) { why = "omega must lie in (0, 2]"; return false; }
+  if ((c->limiters & LBM_LIM_EHRENFEST) && (c->ehr_k < 0 || !(c->ehr_delta >= 0))) {
+    why = "ehr_k and ehr_delta must be >= 0"; return false;
+  }
+  if (c->collision == LBM_ELBM && c->elbm_max_iter < 1) { why = "elbm_max_iter must be >= 1"; return false; }
+  if (c->checkpoint_every < 0 || c->max_steps < 0) { why = "checkpoint_every/max_steps must be >= 0"; return false; }
+  return true;
+}
+
+Layout make_layout(const lbm_config* c) {
+  Layout L;
+  L.Q = c->lattice == LBM_D2Q9 ? 9 : 3;
+  L.pitch = (c->nx + 63) / 64 * 64;
+  L.qs = (long long)c->ny * L.pitch;
+  L.n_sites = (long long)c->nx * c->ny;
+  L.lat_bytes = (size_t)L.Q * L.qs * elem_bytes(c->storage);
+  const size_t rb = is_f64(c->storage) ? 8 : 4;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
+  L.off_lat[0] = take(L.lat_bytes);
+  L.off_lat[1] = take(L.lat_bytes);
+  L.off_omega = c->omega_field ? take((size_t)L.qs * rb) : 0;
+  L.off_sel = take(sizeof(SelState));
+  L.off_cnt = take(CNT_N * sizeof(unsigned long long));
+  L.off_partial = take(stats_partial_doubles(c->nx, c->ny) * sizeof(double));
+  L.off_stats = take(8 * sizeof(double));
+  L.off_div = take(sizeof(long long));
+  if (c->limiters & LBM_LIM_EHRENFEST) {
+    L.k = c->ehr_k < L.n_sites ? c->ehr_k : L.n_sites;
+    long long cap = c->select_capacity;
+    if (cap <= 0) {
+      cap = L.n_sites <= (1ll << 20) ? L.n_sites : std::max(4 * L.k, 1ll << 20);
+    }
+    if (cap > L.n_sites) cap = L.n_sites;
+    L.cap = cap;
+    L.off_ckey = take((size_t)cap * rb);
+    L.off_cidx = take((size_t)cap * 4);
+    L.off_cmom = take((size_t)cap * 3 * rb);
+    L.off_hist = take(kBuckets * 4);
+    L.off_coarse = take(kCoarse * 4);
+    L.off_blist = take((size_t)kBoundaryCap * 4);
+    L.off_selected = take((size_t)std::max<long long>(L.k, 1) * 4);
+  }
+  L.adj = adjoint_layout(c, L.lat_bytes, L.qs, L.k, o);
+  o = L.adj.end;
+  L.total = o;
+  return L;
+}
+
+double omega_of(const lbm_config* c) { return c->nu >= 0 ? 1.0 / (3.0 * c->nu + 0.5) : c->omega; }
+
+// MRT change of basis (section 5), rebuilt from its velocity polynomials in
+// tensor order; inverse by Gauss-Jordan elimination with partial pivoting.
+void mrt_matrices(int basis, double M[81], double Minv[81]) {
+  for (int i = 0; i < 9; ++i) {
+    const double vx = (i % 3) - 1, vy = (i / 3) - 1, v2 = vx * vx + vy * vy;
+    double r[9];
+    if (basis == LBM_MRT_M1) {
+      r[0] = 1; r[1] = -4 + 3 * v2; r[2] = 4 - 10.5 * v2 + 4.5 * v2 * v2; r[3] = vx;
+      r[4] = (-5 + 3 * v2) * vx; r[5] = vy; r[6] = (-5 + 3 * v2) * vy; r[7] = vx * vx - vy * vy;
+      r[8] = vx * vy;
+    } else {
+      r[0] = 1; r[1] = vx; r[2] = vy; r[3] = v2; r[4] = vx * vx - vy * vy; r[5] = vx * vy;
+      r[6] = vx * vx * vy; r[7] = vx * vy * vy; r[8] = vx * vx * vy * vy;
+    }
+    for (int k = 0; k < 9; ++k) M[k * 9 + i] = r[k];
+  }
+  double a[9][18];
+  for (int r = 0; r < 9; ++r)
+    for (int c = 0; c < 18; ++c) a[r][c] = c < 9 ? M[r * 9 + c] : (c - 9 == r ? 1.0 : 0.0);
+  for (int c = 0; c < 9; ++c) {
+    int p = c;
+    for (int r = c + 1; r < 9; ++r) if (std::fabs(a[r][c]) > std::fabs(a[p][c])) p = r;
+    if (p != c) for (int k = 0; k < 18; ++k) std::swap(a[p][k], a[c][k]);
+    const double piv = a[c][c];
+    for (int k = 0; k < 18; ++k) a[c][k] /= piv;
+    for (int r = 0; r < 9; ++r) {
+      if (r == c) continue;
+      const double f = a[r][c];
+      if (f != 0.0) for (int k = 0; k < 18; ++k) a[r][k] -= f * a[c][k];
+    }
+  }
+  for (int r = 0; r < 9; ++r)
+    for (int c = 0; c < 9; ++c) Minv[r * 9 + c] = a[r][c + 9];
+}
+
+template <class R>
+void fill_args(StepArgs<R>& A, const lbm_config* c, const Layout& L, char* ws) {
+  std::memset((void*)&A, 0, sizeof(A));
+  A.qs = L.qs; A.nx = c->nx; A.ny = c->ny; A.pitch = L.pitch;
+  const TileShape ts = tile_shape(L.Q, (c->limiters & LBM_LIM_MEDIAN) != 0, c->nx);
+  A.tiles_x = (c->nx + ts.tx - 1) / ts.tx;
+  A.tiles_y = (c->ny + ts.ty - 1) / ts.ty;
+  A.bc = c->bc;
+  A.eq_kind = c->collision == LBM_ELBM ? LBM_EQ_ENTROPIC : c->equilibrium;
+  A.positivity = (c->limiters & LBM_LIM_POSITIVITY) ? 1 : 0;
+  A.ehrenfest = (c->limiters & LBM_LIM_EHRENFEST) ? 1 : 0;
+  A.count_events = 1;
+  A.rho0 = (R)c->rho0;
+  const double om = omega_of(c);
+  A.omega = (R)om;
+  A.omega_field = c->omega_field ? (const R*)(ws + L.off_omega) : nullptr;
+  for (int i = 0; i < 9; ++i) A.lid[i] = 0;
+  if (c->bc == LBM_BC_CAVITY || c->bc == LBM_BC_COUETTE) {
+    for (int i = 0; i < L.Q; ++i) {
+      const int a = L.Q == 9 ? (i % 3) - 1 : i - 1;
+      const int b = L.Q == 9 ? (i / 3) - 1 : 0;
+      const double w = (L.Q == 9 ? (a == 0 ? 2.0 / 3.0 : 1.0 / 6.0) * (b == 0 ? 2.0 / 3.0 : 1.0 / 6.0)
+                                 : (a == 0 ? 2.0 / 3.0 : 1.0 / 6.0));
+      A.lid[i] = (R)(6.0 * w * c->rho_wall * a * c->u_lid);
+    }
+  }
+  if (c->collision == LBM_MRT) {
+    double M[81], Mi[81];
+    mrt_matrices(c->mrt_basis, M, Mi);
+    for (int i = 0; i < 81; ++i) { A.M[i] = (R)M[i]; A.Minv[i] = (R)Mi[i]; }
+    double rates[9];
+    if (c->mrt_basis == LBM_MRT_M1) {
+      const double r1[9] = {1, c->s_e, c->s_eps, 1, c->s_q, 1, c->s_q, om, om};
+      std::memcpy(rates, r1, sizeof(rates));
+      A.nu_rows = (1u << 7) | (1u << 8);
+    } else {
+      const double r2[9] = {1, 1, 1, 1, om, om, 1, 1, 1};
+      std::memcpy(rates, r2, sizeof(rates));
+      A.nu_rows = (1u << 4) | (1u << 5);
+    }
+    for (int i = 0; i < 9; ++i) A.rates[i] = (R)rates[i];
+  }
+  A.eps = (R)c->elbm_eps;
+  A.atol = sizeof(R) == 4 ? (R)5e-7 : (R)0;
+  A.dS_cut = (R)c->elbm_dS_cut;
+  A.max_iter = c->elbm_max_iter;
+  A.norm = c->elbm_norm;
+  A.fallback = c->elbm_fallback;
+  A.eps64 = c->elbm_eps;
+  A.dS_cut64 = c->elbm_dS_cut;
+  A.f64_below = (R)c->elbm_f64_below;
+  A.med_delta = (R)c->med_delta;
+  A.ehr_delta = (R)c->ehr_delta;
+  A.sel = (SelState*)(ws + L.off_sel);
+  A.counters = (unsigned long long*)(ws + L.off_cnt);
+  if (A.ehrenfest) {
+    A.cand_key = (typename KeyOf<R>::T*)(ws + L.off_ckey);
+    A.cand_idx = (uint32_t*)(ws + L.off_cidx);
+    A.cand_mom = (R*)(ws + L.off_cmom);
+    A.cap = L.cap;
+  }
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_config cfg;
+  Layout L;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  int cur = 0;               // lattice holding the current state
+  long long steps = 0;
+  bool recorded = false;     // a rollout usable by lbm_backward exists
+  StepArgs<double> a64;
+  StepArgs<float> a32;
+  void* lat(int i) { return ws + L.off_lat[i]; }
+  bool f64() const { return cfg.storage == LBM_F64; }
+};
+
+extern "C" {
+
+void lbm_config_default(lbm_config* c) {
+  if (!c) return;
+  std::memset(c, 0, sizeof(*c));
+  c->lattice = LBM_D2Q9; c->nx = 64; c->ny = 64; c->bc = LBM_BC_PERIODIC;
+  c->rho_wall = 1.0; c->collision = LBM_LBGK; c->equilibrium = LBM_EQ_POLY;
+  c->nu = -1.0; c->omega = 1.0; c->mrt_basis = LBM_MRT_M1;
+  c->s_e = 1.64; c->s_eps = 1.54; c->s_q = 1.9;
+  c->med_delta = 1e-3; c->elbm_norm = LBM_NORM_ENTROPIC; c->elbm_fallback = LBM_FB_POSITIVITY;
+  c->elbm_eps = 1e-14; c->elbm_max_iter = 32; c->elbm_dS_cut = 1e-15; c->elbm_f64_below = 3.0;
+  c->storage = LBM_F32; c->rho0 = 1.0;
+}
+
+size_t lbm_workspace_bytes(const lbm_config* cfg) {
+  std::string why;
+  if (!validate(cfg, why)) { g_err = why; return 0; }
+  return make_layout(cfg).total;
+}
+
+lbm_status lbm_init(const lbm_config* cfg, void* ws, size_t ws_bytes, void* stream,
+                    lbm_ctx** out) {
+  g_err.clear();
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  std::string why;
+  if (!validate(cfg, why)) return fail(LBM_EINVAL, why);
+  Layout L = make_layout(cfg);
+  if (!ws || ws_bytes < L.total)
+    return fail(LBM_EWORKSPACE, "workspace needs " + std::to_string(L.total) + " bytes");
+  if (((uintptr_t)ws & 255) != 0) return fail(LBM_EWORKSPACE, "workspace must be 256-byte aligned");
+  lbm_ctx* c = new lbm_ctx();
+  c->cfg = *cfg;
+  c->L = L;
+  c->ws = (char*)ws;
+  c->stream = (hipStream_t)stream;
+  if (c->f64()) fill_args<double>(c->a64, cfg, L, c->ws);
+  else fill_args<float>(c->a32, cfg, L, c->ws);
+  // zero the selection state, counters and divergence flag
+  hipError_t e = hipMemsetAsync(c->ws + L.off_sel, 0, sizeof(SelState), c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.off_cnt, 0, CNT_N * 8, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.off_div, 0xff, sizeof(long long), c->stream);
+  if (e == hipSuccess && (cfg->limiters & LBM_LIM_EHRENFEST)) {
+    e = hipMemsetAsync(c->ws + L.off_hist, 0, kBuckets * 4, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.off_coarse, 0, kCoarse * 4, c->stream);
+  }
+  if (e != hipSuccess) { delete c; return hip_fail(e, "lbm_init"); }
+  *out = c;
+  return LBM_OK;
+}
+
+static lbm_status reset_rollout(lbm_ctx* c) {
+  c->steps = 0;
+  c->recorded = false;
+  hipError_t e = hipMemsetAsync(c->ws + c->L.off_div, 0xff, sizeof(long long), c->stream);
+  if (e != hipSuccess) return hip_fail(e, "reset");
+  if (c->cfg.checkpoint_every > 0) {
+    e = adjoint_begin_record(c->L.adj, c->ws, c->lat(c->cur), c->L.lat_bytes, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "checkpoint");
+    c->recorded = true;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_set_equilibrium(lbm_ctx* c, const void* rho, const void* ux, const void* uy,
+                               int dtype) {
+  g_err.clear();
+  if (!c || !rho || !ux) return fail(LBM_EINVAL, "NULL argument");
+  if (dtype != LBM_F64 && dtype != LBM_F32) return fail(LBM_EINVAL, "dtype must be LBM_F64 or LBM_F32");
+  if (c->L.Q == 9 && !uy) return fail(LBM_EINVAL, "uy is required for D2Q9");
+  const int kind = c->cfg.collision == LBM_ELBM ? LBM_EQ_ENTROPIC : c->cfg.equilibrium;
+  hipError_t e = launch_set_eq(c->cfg.storage, c->L.Q, rho, ux, uy, dtype == LBM_F64,
+                               c->lat(c->cur), c->L.qs, c->cfg.nx, c->cfg.ny, c->L.pitch, kind,
+                               c->cfg.rho0, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "lbm_set_equilibrium");
+  return reset_rollout(c);
+}
+
+lbm_status lbm_set_populations(lbm_ctx* c, const void* f, int dtype) {
+  g_err.clear();
+  if (!c || !f) return fail(LBM_EINVAL, "NULL argument");
+  if (dtype != LBM_F64 && dtype != LBM_F32) return fail(LBM_EINVAL, "dtype must be LBM_F64 or LBM_F32");
+  hipError_t e = launch_set_pop(c->cfg.storage, c->L.Q, f, dtype == LBM_F64, c->lat(c->cur),
+                                c->L.qs, c->cfg.nx, c->cfg.ny, c->L.pitch, c->cfg.rho0, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "lbm_set_populations");
+  return reset_rollout(c);
+}
+
+lbm_status lbm_get_populations(lbm_ctx* c, void* f, int dtype) {
+  g_err.clear();
+  if (!c || !f) return fail(LBM_EINVAL, "NULL argument");
+  if (dtype != LBM_F64 && dtype != LBM_F32) return fail(LBM_EINVAL, "dtype must be LBM_F64 or LBM_F32");
+  hipError_t e = launch_get_pop(c->cfg.storage, c->L.Q, f, dtype == LBM_F64, c->lat(c->cur),
+                                c->L.qs, c->cfg.nx, c->cfg.ny, c->L.pitch, c->cfg.rho0, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "lbm_get_populations");
+  return LBM_OK;
+}
+
+lbm_status lbm_set_omega(lbm_ctx* c, const void* omega, int dtype) {
+  g_err.clear();
+  if (!c || !omega) return fail(LBM_EINVAL, "NULL argument");
+  if (!c->cfg.omega_field) return fail(LBM_EINVAL, "config has omega_field = 0");
+  if (dtype != LBM_F64 && dtype != LBM_F32) return fail(LBM_EINVAL, "dtype must be LBM_F64 or LBM_F32");
+  const size_t rb = c->f64() ? 8 : 4;
+  const size_t eb = dtype == LBM_F64 ? 8 : 4;
+  char* dst = c->ws + c->L.off_omega;
+  if (rb == eb) {
+    hipError_t e = hipMemcpy2DAsync(dst, c->L.pitch * rb, omega, c->cfg.nx * eb, c->cfg.nx * eb,
+                                    c->cfg.ny, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "lbm_set_omega");
+    return LBM_OK;
+  }
+  hipError_t e = launch_convert_field(omega, dtype == LBM_F64, dst, c->f64(), c->cfg.nx, c->cfg.ny,
+                                      c->L.pitch, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "lbm_set_omega");
+  return LBM_OK;
+}
+
+static hipError_t one_step(lbm_ctx* c) {
+  const int src = c->cur, dst = 1 - c->cur;
+  const bool med = (c->cfg.limiters & LBM_LIM_MEDIAN) != 0;
+  const void* args;
+  if (c->f64()) { c->a64.src = c->lat(src); c->a64.dst = c->lat(dst); args = &c->a64; }
+  else { c->a32.src = c->lat(src); c->a32.dst = c->lat(dst); args = &c->a32; }
+  hipError_t e = launch_step(c->cfg.storage, c->L.Q, c->cfg.collision, med, args, c->stream);
+  if (e != hipSuccess) return e;
+  if (c->cfg.limiters & LBM_LIM_EHRENFEST) {
+    SelectArgs sa;
+    sa.storage = c->cfg.storage; sa.Q = c->L.Q; sa.coll = c->cfg.collision; sa.step_args = args;
+    sa.k = c->L.k; sa.n_sites = c->L.n_sites;
+    sa.selected = adjoint_selected_slot(c->L.adj, c->ws, c->steps,
+                                        (int32_t*)(c->ws + c->L.off_selected));
+    sa.boundary_idx = (int32_t*)(c->ws + c->L.off_blist);
+    sa.boundary_key = nullptr;
+    sa.hist = (unsigned int*)(c->ws + c->L.off_hist);
+    sa.coarse = (unsigned int*)(c->ws + c->L.off_coarse);
+    sa.n_sel_out = adjoint_count_slot(c->L.adj, c->ws, c->steps);
+    e = launch_select(sa, c->stream);
+    if (e != hipSuccess) return e;
+  }
+  c->cur = dst;
+  c->steps += 1;
+  return hipSuccess;
+}
+
+lbm_status lbm_step(lbm_ctx* c, long long n) {
+  g_err.clear();
+  if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+  if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+  for (long long s = 0; s < n; ++s) {
+    if (c->recorded && c->steps >= c->cfg.max_steps)
+      return fail(LBM_ESTATE, "rollout longer than cfg.max_steps; lbm_backward could not cover it");
+    hipError_t e = one_step(c);
+    if (e != hipSuccess) return hip_fail(e, "lbm_step");
+    if (c->recorded) {
+      e = adjoint_after_step(c->L.adj, c->ws, c->steps, c->lat(c->cur), c->L.lat_bytes, c->stream);
+      if (e != hipSuccess) return hip_fail(e, "checkpoint");
+    }
+    if (c->cfg.check_interval > 0 && c->steps % c->cfg.check_interval == 0) {
+      e = launch_stats(c->cfg.storage, c->L.Q, c->lat(c->cur), c->L.qs, c->cfg.nx, c->cfg.ny,
+                       c->L.pitch, c->cfg.rho0, (double*)(c->ws + c->L.off_partial),
+                       (double*)(c->ws + c->L.off_stats), (long long*)(c->ws + c->L.off_div),
+                       c->steps, c->stream);
+      if (e != hipSuccess) return hip_fail(e, "check");
+    }
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_moments(lbm_ctx* c, void* rho, void* ux, void* uy, int dtype) {
+  g_err.clear();
+  if (!c || !rho || !ux) return fail(LBM_EINVAL, "NULL argument");
+  if (dtype != LBM_F64 && dtype != LBM_F32) return fail(LBM_EINVAL, "dtype must be LBM_F64 or LBM_F32");
+  hipError_t e = launch_moments(c->cfg.storage, c->L.Q, c->lat(c->cur), c->L.qs, c->cfg.nx,
+                                c->cfg.ny, c->L.pitch, c->cfg.rho0, rho, ux, uy,
+                                dtype == LBM_F64, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "lbm_moments");
+  return LBM_OK;
+}
+
+lbm_status lbm_stats_get(lbm_ctx* c, lbm_stats* out) {
+  g_err.clear();
+  if (!c || !out) return fail(LBM_EINVAL, "NULL argument");
+  hipError_t e = launch_stats(c->cfg.storage, c->L.Q, c->lat(c->cur), c->L.qs, c->cfg.nx,
+                              c->cfg.ny, c->L.pitch, c->cfg.rho0,
+                              (double*)(c->ws + c->L.off_partial),
+                              (double*)(c->ws + c->L.off_stats),
+                              (long long*)(c->ws + c->L.off_div), c->steps, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "lbm_stats");
+  double st[8];
+  long long div = -1;
+  SelState sel;
+  std::memset(&sel, 0, sizeof(sel));
+  e = hipMemcpyAsync(st, c->ws + c->L.off_stats, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&div, c->ws + c->L.off_div, sizeof(div), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&sel, c->ws + c->L.off_sel, sizeof(sel), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(e, "lbm_stats");
+  std::memset(out, 0, sizeof(*out));
+  out->mass = st[0]; out->mom_x = st[1]; out->mom_y = st[2]; out->entropy = st[3];
+  out->min_rho = st[4]; out->nonfinite = st[5] != 0.0;
+  out->steps = c->steps;
+  out->diverged_step = div;
+  out->n_selected = sel.n_sel;
+  out->select_fallbacks = (long long)sel.fallbacks;
+  out->select_overflow = (long long)sel.overflows;
+  if (div >= 0) return fail(LBM_EDIVERGED, "non-finite value or rho <= 0 found at step " + std::to_string(div));
+  if (sel.overflows) return fail(LBM_ESELECT, "Ehrenfest candidate buffer overflowed; raise select_capacity");
+  return LBM_OK;
+}
+
+lbm_status lbm_counters(lbm_ctx* c, unsigned long long* out, int n) {
+  g_err.clear();
+  if (!c || !out || n < 1) return fail(LBM_EINVAL, "bad argument");
+  const int m = n < CNT_N ? n : CNT_N;
+  hipError_t e = hipMemcpyAsync(out, c->ws + c->L.off_cnt, m * 8, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(e, "lbm_counters");
+  return LBM_OK;
+}
+
+lbm_status lbm_selected(lbm_ctx* c, long long* idx, long long cap, long long* count) {
+  g_err.clear();
+  if (!c || !count) return fail(LBM_EINVAL, "NULL argument");
+  *count = 0;
+  if (!(c->cfg.limiters & LBM_LIM_EHRENFEST)) return LBM_OK;
+  SelState sel;
+  hipError_t e = hipMemcpyAsync(&sel, c->ws + c->L.off_sel, sizeof(sel), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(e, "lbm_selected");
+  const long long n = sel.n_sel;
+  *count = n;
+  if (!idx || n == 0) return LBM_OK;
+  std::vector<int32_t> tmp((size_t)n);
+  const int32_t* src = adjoint_selected_slot(c->L.adj, c->ws, c->steps - 1,
+                                             (int32_t*)(c->ws + c->L.off_selected));
+  e = hipMemcpy(tmp.data(), src, (size_t)n * 4, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "lbm_selected");
+  std::sort(tmp.begin(), tmp.end());
+  for (long long i = 0; i < n && i < cap; ++i) idx[i] = tmp[(size_t)i];
+  return LBM_OK;
+}
+
+lbm_status lbm_backward(lbm_ctx* c, const void* dL_dfT, void* dL_df0, void* dL_domega, int dtype) {
+  g_err.clear();
+  if (!c || !dL_dfT || !dL_df0) return fail(LBM_EINVAL, "NULL argument");
+  if (dtype != LBM_F64 && dtype != LBM_F32) return fail(LBM_EINVAL, "dtype must be LBM_F64 or LBM_F32");
+  if (c->cfg.checkpoint_every <= 0 || !c->recorded)
+    return fail(LBM_ESTATE, "no recorded rollout (set checkpoint_every > 0 and call lbm_set_* first)");
+  if (c->cfg.limiters & LBM_LIM_MEDIAN)
+    return fail(LBM_EUNSUPPORTED, "the adjoint of the median filter is not implemented");
+  if (dL_domega && !c->cfg.omega_field)
+    return fail(LBM_EINVAL, "dL_domega needs a per-site omega field");
+  return fail(LBM_EUNSUPPORTED, "backward pass not built yet");
+}
+
+void lbm_destroy(lbm_ctx* c) { delete c; }
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

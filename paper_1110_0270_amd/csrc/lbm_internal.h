@@ -1,0 +1,122 @@
+// Parameter blocks and launch entry points shared by the host API
+// (lbm_api.hip) and the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// Device-resident state of the Ehrenfest top-k selection (section 4,
+// Ehrenfests' regularisation with a budget of k sites per step).
+struct SelState {
+  unsigned long long count;      // candidates appended this step
+  unsigned long long max_key;    // largest candidate key this step
+  unsigned long long floor_key;  // a site is a candidate iff eligible and key >= floor_key
+  unsigned long long base_key;   // bucket origin of this step's histogram
+  unsigned long long bcount;     // length of the boundary-bucket list
+  unsigned long long fallbacks;  // steps that needed a full rescan (cumulative)
+  unsigned long long overflows;  // steps whose rescan overflowed (cumulative)
+  long long n_sel;               // sites selected in the last step
+  long long take;                // candidates to take from the boundary bucket
+  unsigned int shift;            // bucket width is 2^shift keys
+  unsigned int ticket;           // last-block ticket
+  int boundary;                  // boundary bucket, -1: take every candidate
+  int fallback;                  // 1: this step's candidates are unusable
+  int fb_bin;                    // coarse bin chosen by the rescan
+  int floor_raised;              // floor_key is above the eligibility threshold
+  int pad[2];
+};
+
+constexpr int kBuckets = 4096;        // fine histogram of candidate keys
+constexpr int kCoarse = 4096;         // coarse histogram: top 12 bits of the FP32 key
+constexpr int kBoundaryCap = 1 << 16; // boundary-bucket list entries
+
+// Counters of limiter activity (cumulative since the last reset).
+enum Counter : int {
+  CNT_POSITIVITY = 0, CNT_MEDIAN = 1, CNT_ELBM_NOROOT = 2, CNT_ELBM_F64 = 3,
+  CNT_ELBM_NONPOS = 4, CNT_N = 8
+};
+
+template <class R> struct KeyOf;
+template <> struct KeyOf<float> { using T = uint32_t; };
+template <> struct KeyOf<double> { using T = unsigned long long; };
+
+template <class R>
+struct StepArgs {
+  const void* src;
+  void* dst;
+  long long qs;          // elements between populations = ny * pitch
+  int nx, ny, pitch;
+  int tiles_x, tiles_y;
+  int bc;
+  int eq_kind;
+  int positivity;
+  int ehrenfest;
+  int count_events;
+  R rho0;
+  R omega;
+  const R* omega_field;  // [ny][pitch] or nullptr
+  R lid[9];              // moving-wall term 6 w_i rho_wall (v_i . u_wall)
+  // MRT (moment space): F = f + Minv (rates .* (M (f* - f)))
+  R M[81];
+  R Minv[81];
+  R rates[9];
+  unsigned nu_rows;      // bit mask of rows whose rate is the shear rate
+  // ELBM
+  R eps, atol, dS_cut;
+  int max_iter, norm, fallback;
+  double eps64, dS_cut64;
+  R f64_below;
+  // median
+  R med_delta;
+  // Ehrenfest
+  R ehr_delta;
+  SelState* sel;
+  typename KeyOf<R>::T* cand_key;
+  uint32_t* cand_idx;
+  R* cand_mom;           // [3][cap]: rho (or rho - rho0 when shifted), ux, uy
+  long long cap;
+  unsigned long long* counters;
+};
+
+// Launchers (one per translation unit); return hipSuccess or the error.
+// storage: 0 f64, 1 f32, 2 f16 shifted, 3 bf16 shifted.
+hipError_t launch_step(int storage, int Q, int coll, bool median, const void* args,
+                       hipStream_t s);
+hipError_t launch_set_eq(int storage, int Q, const void* rho, const void* ux,
+                         const void* uy, int in_f64, void* lat, long long qs, int nx,
+                         int ny, int pitch, int eq_kind, double rho0, hipStream_t s);
+hipError_t launch_set_pop(int storage, int Q, const void* f, int in_f64, void* lat,
+                          long long qs, int nx, int ny, int pitch, double rho0,
+                          hipStream_t s);
+hipError_t launch_get_pop(int storage, int Q, void* f, int out_f64, const void* lat,
+                          long long qs, int nx, int ny, int pitch, double rho0,
+                          hipStream_t s);
+hipError_t launch_moments(int storage, int Q, const void* lat, long long qs, int nx, int ny,
+                          int pitch, double rho0, void* rho, void* ux, void* uy,
+                          int out_f64, hipStream_t s);
+// Whole-lattice FP64 reduction into out[0..7] = mass, mom_x, mom_y, entropy,
+// min_rho, nonfinite, -, -.  partial: workspace of stats_partial_doubles().
+long long stats_partial_doubles(int nx, int ny);
+hipError_t launch_stats(int storage, int Q, const void* lat, long long qs, int nx, int ny,
+                        int pitch, double rho0, double* partial, double* out,
+                        long long* diverged_step, long long step, hipStream_t s);
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+
+// Ehrenfest selection after a step (selection kernels).
+struct SelectArgs {
+  int storage, Q, coll;
+  const void* step_args;   // StepArgs<R> of the step (for rescans)
+  long long k;
+  long long n_sites;
+  int32_t* selected;       // out: selected site indices, ascending not guaranteed
+  int32_t* boundary_idx;   // scratch lists
+  unsigned long long* boundary_key;
+  unsigned int* hist;      // kBuckets
+  unsigned int* coarse;    // kCoarse
+  long long* n_sel_out;    // optional: the step's selection count is copied here
+};
+hipError_t launch_select(const SelectArgs& a, hipStream_t s);
+
+}  // namespace lbm

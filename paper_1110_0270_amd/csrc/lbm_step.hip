@@ -1,0 +1,309 @@
+// Fused per-site step of the regularised LBM for gfx950 (one thread per
+// site, 256-thread workgroups of 64-wide wavefronts):
+//   pull-stream with boundaries (section 2, free flight)
+//   -> moments and equilibrium (sections 2, 6, 8)
+//   -> nonequilibrium entropy (section 4, eq. DelS) when a limiter needs it
+//   -> median entropy filter (section 4), Delta S of the tile and a one-site
+//      halo staged in LDS
+//   -> collision: LBGK (eq. CollisionIntegral), MRT (section 5) or ELBM
+//      (section 3)
+//   -> positivity rule (section 4)
+//   -> store into the second lattice, and append Ehrenfest candidates
+//      (section 4) for the selection kernels.
+#include "lbm_device.h"
+#include "lbm_internal.h"
+#include "lbm_site.h"
+
+namespace lbm {
+
+__device__ __forceinline__ void count_event(bool ev, unsigned long long* ctr) {
+  const unsigned long long m = __ballot(ev);
+  if (m && __lane_id() == (unsigned)(__ffsll((long long)m) - 1))
+    atomicAdd(ctr, (unsigned long long)__popcll(m));
+}
+
+template <class R>
+__device__ __forceinline__ void sort_net9(R a[9]) {
+#pragma unroll
+  for (int pass = 0; pass < 9; ++pass) {
+#pragma unroll
+    for (int j = pass & 1; j + 1 < 9; j += 2) {
+      const R lo = fmin(a[j], a[j + 1]), hi = fmax(a[j], a[j + 1]);
+      a[j] = lo;
+      a[j + 1] = hi;
+    }
+  }
+}
+
+template <class S, int Q, int COLL, bool MEDIAN, int TX, int TY>
+__global__ __launch_bounds__(256) void k_step(const StepArgs<typename StoreT<S>::R> A) {
+  using R = typename StoreT<S>::R;
+  constexpr bool SH = StoreT<S>::shifted;
+  static_assert(TX * TY == 256, "tile must hold 256 sites");
+
+  // XCD-aware tile order: consecutive workgroups are dealt round-robin to the
+  // 8 XCDs; give each XCD a contiguous band of tiles so that the rows above
+  // and below a tile sit in the same L2.
+  const int T = A.tiles_x * A.tiles_y;
+  const int b = blockIdx.x;
+  const int t = (T % 8 == 0) ? (b % 8) * (T / 8) + b / 8 : b;
+  const int tile_x = t % A.tiles_x, tile_y = t / A.tiles_x;
+  const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+  const int x = tile_x * TX + lx, y = tile_y * TY + ly;
+  const bool valid = x < A.nx && y < A.ny;
+
+  const bool need_dS = MEDIAN || A.ehrenfest;
+  R v[Q], feq[Q], d[Q], m0 = R(0), ux = R(0), uy = R(0), dS = R(0);
+  if (valid) dS = site_prep<S, Q>(A, x, y, v, feq, d, m0, ux, uy, need_dS);
+
+  if constexpr (MEDIAN) {
+    // Median entropy filter: Delta S of the tile plus a one-site halo in LDS.
+    constexpr int HY = (Q == 9) ? 1 : 0;
+    constexpr int SW = TX + 2, SH_ = TY + 2 * HY;
+    __shared__ R sdS[SH_ * SW];
+    sdS[(ly + HY) * SW + lx + 1] = valid ? dS : slot_dS<S, Q>(A, x, y);
+    constexpr int NHALO = SH_ * SW - TX * TY;
+    for (int s = threadIdx.x; s < NHALO; s += 256) {
+      // halo slot s -> LDS coordinates: top row, bottom row, then the left
+      // and right columns (2D); the two end slots of the single row (1D)
+      int hx, hy;
+      if constexpr (HY == 1) {
+        if (s < SW) { hx = s; hy = 0; }
+        else if (s < 2 * SW) { hx = s - SW; hy = SH_ - 1; }
+        else { const int r = s - 2 * SW; hy = 1 + r / 2; hx = (r & 1) ? SW - 1 : 0; }
+      } else {
+        hy = 0;
+        hx = (s == 0) ? 0 : SW - 1;
+      }
+      sdS[hy * SW + hx] = slot_dS<S, Q>(A, tile_x * TX + hx - 1, tile_y * TY + hy - HY);
+    }
+    __syncthreads();
+    if (valid) {
+      R nb[9];
+      int n = 0;
+      constexpr int NN = (Q == 9) ? 9 : 3;
+#pragma unroll
+      for (int k = 0; k < NN; ++k) {
+        const int dy = (Q == 9) ? k / 3 - 1 : 0, dx = (Q == 9) ? k % 3 - 1 : k - 1;
+        const R val = sdS[(ly + HY + dy) * SW + lx + 1 + dx];
+        const bool in = !(val != val);
+        n += in ? 1 : 0;
+        nb[k] = in ? val : r_inf<R>();
+      }
+      R med;
+      if constexpr (Q == 9) {
+        sort_net9<R>(nb);
+        const int rank = (n + 1) / 2 - 1;
+        med = nb[0];
+#pragma unroll
+        for (int k = 1; k < 9; ++k) med = rank == k ? nb[k] : med;
+      } else {
+        R a0 = fmin(nb[0], nb[1]), a1 = fmax(nb[0], nb[1]);
+        const R a2 = fmax(a1, nb[2]);
+        a1 = fmin(a1, nb[2]);
+        const R b0 = fmin(a0, a1), b1 = fmax(a0, a1);
+        (void)a2;
+        med = ((n + 1) / 2 - 1) == 0 ? b0 : b1;
+      }
+      const bool acc = (dS > A.med_delta) & (med < dS) & (dS < r_inf<R>());
+      if (acc) {
+        const R c = sqrt(med / dS);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          v[i] = feq[i] + c * (v[i] - feq[i]);
+          d[i] = feq[i] - v[i];
+        }
+      }
+      if (A.count_events) count_event(acc, A.counters + CNT_MEDIAN);
+    } else if (A.count_events) {
+      count_event(false, A.counters + CNT_MEDIAN);
+    }
+  }
+
+  // Ehrenfest candidates: eligible (Delta S > delta) and above the floor.
+  if (A.ehrenfest) {
+    using K = typename KeyOf<R>::T;
+    const K key = key_of<R>(dS);
+    const bool is_c = valid && (dS > A.ehr_delta) && (key >= (K)A.sel->floor_key);
+    const unsigned long long mask = __ballot(is_c);
+    if (mask) {
+      const int lane = __lane_id();
+      const int leader = __ffsll((long long)mask) - 1;
+      unsigned long long kmax = is_c ? (unsigned long long)key : 0ull;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(kmax, off);
+        kmax = o > kmax ? o : kmax;
+      }
+      unsigned long long base = 0;
+      if (lane == leader) {
+        base = atomicAdd(&A.sel->count, (unsigned long long)__popcll(mask));
+        atomicMax(&A.sel->max_key, kmax);
+      }
+      base = __shfl(base, leader);
+      if (is_c) {
+        const unsigned long long pos =
+            base + (unsigned long long)__popcll(mask & ((1ull << lane) - 1ull));
+        if (pos < (unsigned long long)A.cap) {
+          A.cand_key[pos] = key;
+          A.cand_idx[pos] = (uint32_t)(y * A.nx + x);
+          A.cand_mom[pos] = m0;
+          A.cand_mom[A.cap + pos] = ux;
+          A.cand_mom[2 * A.cap + pos] = uy;
+        }
+      }
+    }
+  }
+
+  R post[Q];
+  bool pos_event = false;
+  if (valid) {
+    const R om = A.omega_field ? A.omega_field[(long long)y * A.pitch + x] : A.omega;
+    if constexpr (COLL == COLL_LBGK) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) post[i] = v[i] + om * d[i];
+    } else if constexpr (COLL == COLL_MRT) {
+      R m[Q];
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        R s = R(0);
+#pragma unroll
+        for (int j = 0; j < Q; ++j) s += A.M[k * Q + j] * d[j];
+        m[k] = s * (((A.nu_rows >> k) & 1u) ? om : A.rates[k]);
+      }
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        R s = R(0);
+#pragma unroll
+        for (int k = 0; k < Q; ++k) s += A.Minv[i * Q + k] * m[k];
+        post[i] = v[i] + s;
+      }
+    } else {  // ELBM
+      R fa[Q], qa[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const R sh = SH ? wt<R, Q>(i) * A.rho0 : R(0);
+        fa[i] = v[i] + sh;
+        qa[i] = feq[i] + sh;
+      }
+      const R dSe = delta_s<R, Q>(fa, qa, d);
+      const R amax = alpha_max<R, Q>(fa, d);
+      int br = EB_ROOT;
+      R alpha;
+      ElbmParams<R> ep{A.eps, A.atol, A.dS_cut, A.max_iter, A.norm, A.fallback};
+      bool f64 = false;
+      if constexpr (sizeof(R) == 4) {
+        if (amax < A.f64_below) {
+          // FP64 solve near the no-root (degenerate) branch.
+          double fd[Q], qd[Q], Dd[Q];
+#pragma unroll
+          for (int i = 0; i < Q; ++i) {
+            fd[i] = (double)fa[i];
+            qd[i] = (double)qa[i];
+            Dd[i] = qd[i] - fd[i];
+          }
+          const double dSd = delta_s<double, Q>(fd, qd, Dd);
+          ElbmParams<double> e64{A.eps64, 0.0, A.dS_cut64, A.max_iter, A.norm, A.fallback};
+          alpha = (R)elbm_alpha<double, Q>(fd, qd, Dd, dSd, alpha_max<double, Q>(fd, Dd), e64, br);
+          f64 = true;
+        } else {
+          alpha = elbm_alpha<R, Q>(fa, qa, d, dSe, amax, ep, br);
+        }
+      } else {
+        alpha = elbm_alpha<R, Q>(fa, qa, d, dSe, amax, ep, br);
+      }
+      const R ab = alpha * (om * R(0.5));
+#pragma unroll
+      for (int i = 0; i < Q; ++i) post[i] = v[i] + ab * d[i];
+      if (A.count_events) {
+        count_event(br == EB_NOROOT, A.counters + CNT_ELBM_NOROOT);
+        count_event(f64, A.counters + CNT_ELBM_F64);
+        count_event(br == EB_NONPOS, A.counters + CNT_ELBM_NONPOS);
+      }
+    }
+    if (A.positivity) {
+      R phi = r_inf<R>();
+      int arg = -1;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const R sh = SH ? wt<R, Q>(i) * A.rho0 : R(0);
+        const R pa = post[i] + sh, qa = feq[i] + sh;
+        if (pa < R(0) && qa > R(0)) {
+          const R r = qa / (qa - pa);
+          if (r < phi) { phi = r; arg = i; }
+        }
+      }
+      if (arg >= 0) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          const R sh = SH ? wt<R, Q>(i) * A.rho0 : R(0);
+          post[i] = (i == arg) ? -sh : feq[i] + phi * (post[i] - feq[i]);
+        }
+        pos_event = true;
+      }
+    }
+    S* dst = (S*)A.dst;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      StoreT<S>::st(dst + (long long)i * A.qs + (long long)y * A.pitch + x, post[i]);
+  } else if constexpr (COLL == COLL_ELBM) {
+    if (A.count_events) {
+      count_event(false, A.counters + CNT_ELBM_NOROOT);
+      count_event(false, A.counters + CNT_ELBM_F64);
+      count_event(false, A.counters + CNT_ELBM_NONPOS);
+    }
+  }
+  if (A.positivity && A.count_events) count_event(pos_event, A.counters + CNT_POSITIVITY);
+}
+
+// ---------------------------------------------------------------------------
+// Launch dispatch.
+// ---------------------------------------------------------------------------
+template <class S, int Q, int COLL, bool MEDIAN>
+static hipError_t launch_t(const void* args, hipStream_t s) {
+  using R = typename StoreT<S>::R;
+  const StepArgs<R>& A = *(const StepArgs<R>*)args;
+  const dim3 grid(A.tiles_x * A.tiles_y), block(256);
+  if constexpr (Q == 3) {
+    hipLaunchKernelGGL((k_step<S, Q, COLL, MEDIAN, 256, 1>), grid, block, 0, s, A);
+  } else if constexpr (MEDIAN) {
+    hipLaunchKernelGGL((k_step<S, Q, COLL, MEDIAN, 64, 4>), grid, block, 0, s, A);
+  } else {
+    if (tile_shape(Q, MEDIAN, A.nx).tx == 256)
+      hipLaunchKernelGGL((k_step<S, Q, COLL, MEDIAN, 256, 1>), grid, block, 0, s, A);
+    else
+      hipLaunchKernelGGL((k_step<S, Q, COLL, MEDIAN, 64, 4>), grid, block, 0, s, A);
+  }
+  return hipGetLastError();
+}
+
+template <class S>
+static hipError_t launch_s(int Q, int coll, bool median, const void* args, hipStream_t s) {
+  if (Q == 3) {
+    if (coll == COLL_LBGK)
+      return median ? launch_t<S, 3, COLL_LBGK, true>(args, s) : launch_t<S, 3, COLL_LBGK, false>(args, s);
+    if (coll == COLL_ELBM)
+      return median ? launch_t<S, 3, COLL_ELBM, true>(args, s) : launch_t<S, 3, COLL_ELBM, false>(args, s);
+    return hipErrorInvalidValue;
+  }
+  switch (coll) {
+    case COLL_LBGK:
+      return median ? launch_t<S, 9, COLL_LBGK, true>(args, s) : launch_t<S, 9, COLL_LBGK, false>(args, s);
+    case COLL_MRT:
+      return median ? launch_t<S, 9, COLL_MRT, true>(args, s) : launch_t<S, 9, COLL_MRT, false>(args, s);
+    default:
+      return median ? launch_t<S, 9, COLL_ELBM, true>(args, s) : launch_t<S, 9, COLL_ELBM, false>(args, s);
+  }
+}
+
+hipError_t launch_step(int storage, int Q, int coll, bool median, const void* args,
+                       hipStream_t s) {
+  switch (storage) {
+    case 0: return launch_s<double>(Q, coll, median, args, s);
+    case 1: return launch_s<float>(Q, coll, median, args, s);
+    case 2: return launch_s<_Float16>(Q, coll, median, args, s);
+    default: return launch_s<bf16_t>(Q, coll, median, args, s);
+  }
+}
+
+}  // namespace lbm

@@ -1,0 +1,76 @@
+"""The C-ABI library loads on a machine without a GPU, exports every entry
+point that include/lbm.h declares, and its host-side logic (configuration
+checks, workspace sizing) behaves as documented.  No kernel is launched."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1110_0270_amd import lbm as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.library()
+    names = declared_symbols()
+    assert "lbm_step" in names and "lbm_backward" in names
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in include/lbm.h but not exported"
+
+
+def test_config_struct_matches_header_field_order():
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    body = src[src.index("typedef struct lbm_config {"):src.index("} lbm_config;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = []
+    for decl in body.split(";")[:-1]:
+        decl = decl.split("{")[-1].strip()
+        if not decl:
+            continue
+        toks = decl.replace(",", " ").split()
+        typ_len = 2 if toks[0] in ("long", "unsigned") and toks[1] in ("long",) else 1
+        if toks[0] == "long" and toks[1] == "long":
+            typ_len = 2
+        fields += toks[typ_len:]
+    assert fields == [f for f, _ in B.lbm_config._fields_]
+
+
+def test_workspace_sizing_and_validation():
+    c = B.make_config(nx=256, ny=128, storage="f32", nu=0.01)
+    n = B.lbm_workspace_bytes(c)
+    pitch = 256
+    assert n >= 2 * 9 * 128 * pitch * 4          # two FP32 lattices
+    c64 = B.make_config(nx=256, ny=128, storage="f64", nu=0.01)
+    assert B.lbm_workspace_bytes(c64) > n
+    ce = B.make_config(nx=256, ny=128, storage="f32", nu=0.01, ehrenfest=True, ehr_k=100)
+    assert B.lbm_workspace_bytes(ce) > n
+    ca = B.make_config(nx=64, ny=64, storage="f32", nu=0.01, checkpoint_every=16, max_steps=64)
+    assert B.lbm_workspace_bytes(ca) > B.lbm_workspace_bytes(B.make_config(nx=64, ny=64, nu=0.01))
+    for bad in (dict(lattice="D1Q3", nx=16, ny=4), dict(nx=0, ny=4),
+                dict(collision="mrt", lattice="D1Q3", nx=16, ny=1),
+                dict(lattice="D1Q3", nx=16, ny=1, bc="cavity"),
+                dict(nu=None, omega=2.5)):
+        cfg = B.make_config(**{"nu": 0.01, **bad})
+        assert B.library().lbm_workspace_bytes(ctypes.byref(cfg)) == 0
+        assert B.library().lbm_last_error().decode() != ""
+
+
+def test_init_rejects_small_or_missing_workspace_without_touching_the_device():
+    c = B.make_config(nx=64, ny=64, nu=0.01)
+    ctx = ctypes.c_void_p()
+    lib = B.library()
+    st = lib.lbm_init(ctypes.byref(c), None, 0, None, ctypes.byref(ctx))
+    assert st == B.LBM_EWORKSPACE and not ctx.value
+    bad = B.make_config(nx=-3, ny=64, nu=0.01)
+    st = lib.lbm_init(ctypes.byref(bad), None, 0, None, ctypes.byref(ctx))
+    assert st == B.LBM_EINVAL
+    assert lib.lbm_step(None, 1) == B.LBM_EINVAL
+    lib.lbm_destroy(None)
