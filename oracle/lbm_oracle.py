@@ -191,8 +191,8 @@ def stream(lat: Lattice, g: torch.Tensor, bc: str, u_lid: float = 0.0,
         refl = g[lat.opp[i]]
         if bc in ("cavity", "couette"):
             from_lid = (sy >= ny).expand(ny, nx)
-            lid = 6.0 * float(lat.w[i]) * rho_wall * a * u_lid
-            refl = refl + torch.where(from_lid, lid, 0.0).to(DT)
+            lid = torch.tensor(6.0 * float(lat.w[i]) * rho_wall * a * u_lid, dtype=DT)
+            refl = refl + torch.where(from_lid, lid, torch.zeros((), dtype=DT))
         elif bc != "bounceback":
             raise ValueError(bc)
         out.append(torch.where(outside, refl, shifted))
