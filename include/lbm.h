@@ -21,8 +21,9 @@
  *   (a, b) in {-1,0,1}^2, so the opposite of i is 8 - i and i = 4 is rest;
  *   D1Q3 i = a + 1 for a in {-1, 0, 1}, with ny = 1.
  *   The site index used for ties is y * nx + x.
- *   Caller populations are always unshifted f_i; the library may store them
- *   internally as shifted deviations f_i - w_i rho0 (LBM_F16S, LBM_BF16S).
+ *   Caller populations are always unshifted f_i; the library stores the
+ *   FP32, FP16 and BF16 forms internally as shifted deviations
+ *   f_i - w_i rho0 (LBM_F32, LBM_F16S, LBM_BF16S).
  *
  * Ownership: the caller allocates every device buffer, including the
  * workspace (lbm_workspace_bytes); the library never allocates device
@@ -117,6 +118,7 @@ typedef struct lbm_stats {
   long long n_selected;   /* Ehrenfest sites chosen in the last step            */
   long long select_fallbacks; /* steps whose selection needed a full rescan     */
   long long select_overflow;  /* steps whose candidate buffer overflowed        */
+  long long select_candidates;/* Ehrenfest candidates examined, all steps      */
   int nonfinite;          /* 1 if the last check found NaN or Inf               */
 } lbm_stats;
 
@@ -190,10 +192,18 @@ lbm_status lbm_stats_get(lbm_ctx* ctx, lbm_stats* out);
 lbm_status lbm_selected(lbm_ctx* ctx, long long* idx, long long cap, long long* count);
 
 /* Synchronise and copy the cumulative limiter counters into out[0..n-1]:
- * positivity-rule activations, median-filter corrections, ELBM sites with no
- * nontrivial root, ELBM sites solved in FP64, ELBM sites with a
- * non-positive population. */
+ * positivity-rule activations in the collision (sites that the Ehrenfest
+ * limiter then sends to equilibrium included), median-filter corrections,
+ * ELBM sites with no nontrivial root, ELBM sites solved in FP64, ELBM sites
+ * with a non-positive population. */
 lbm_status lbm_counters(lbm_ctx* ctx, unsigned long long* out, int n);
+
+/* Advance n steps exactly as lbm_step does, bracketing each step's fused
+ * collide-stream kernel with HIP events on the context's stream, then
+ * synchronise.  out[0] = summed duration of those kernels (ms), out[1] =
+ * duration from the first kernel's start to the end of the last step's
+ * work (ms).  For measurement; the events add a few microseconds per step. */
+lbm_status lbm_profile_step(lbm_ctx* ctx, long long n, double out[2]);
 
 /* Free the context (not the caller's buffers). NULL is allowed. */
 void lbm_destroy(lbm_ctx* ctx);

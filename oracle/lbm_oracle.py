@@ -532,6 +532,10 @@ def step(lat: Lattice, cfg: Config, g: torch.Tensor,
         info["branch"] = branch.reshape(rho.shape)
     else:
         raise ValueError(cfg.collision)
+    if cfg.positivity:
+        # diagnostic only: where the collided state (before any Ehrenfest
+        # step) has a negative population the rule acts
+        info["positivity_collided"] = ((post < 0) & (feq > 0)).any(0)
     selmask = torch.zeros(rho.numel(), dtype=torch.bool)
     if sel is not None and sel.numel() > 0:
         selmask[sel] = True

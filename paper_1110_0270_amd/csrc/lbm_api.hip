@@ -35,7 +35,7 @@ bool is_f64(int storage) { return storage == LBM_F64; }
 
 struct Layout {
   int Q = 0, pitch = 0;
-  long long qs = 0, n_sites = 0, cap = 0, k = 0;
+  long long qs = 0, n_sites = 0, cap = 0, k = 0, bcap = 0;
   size_t lat_bytes = 0;
   size_t off_lat[2] = {0, 0}, off_omega = 0, off_sel = 0, off_cnt = 0, off_partial = 0,
          off_stats = 0, off_div = 0, off_ckey = 0, off_cidx = 0, off_cmom = 0, off_hist = 0,
@@ -97,7 +97,8 @@ Layout make_layout(const lbm_config* c) {
     L.off_cmom = take((size_t)cap * 3 * rb);
     L.off_hist = take(kBuckets * 4);
     L.off_coarse = take(kCoarse * 4);
-    L.off_blist = take((size_t)kBoundaryCap * 4);
+    L.bcap = std::min<long long>(cap, 1ll << 20);
+    L.off_blist = take((size_t)L.bcap * 4);
     L.off_selected = take((size_t)std::max<long long>(L.k, 1) * 4);
   }
   L.adj = adjoint_layout(c, L.lat_bytes, L.qs, L.k, o);
@@ -203,6 +204,7 @@ void fill_args(StepArgs<R>& A, const lbm_config* c, const Layout& L, char* ws) {
     A.cand_idx = (uint32_t*)(ws + L.off_cidx);
     A.cand_mom = (R*)(ws + L.off_cmom);
     A.cap = L.cap;
+    A.hist = (unsigned int*)(ws + L.off_hist);
   }
 }
 
@@ -260,8 +262,11 @@ lbm_status lbm_init(const lbm_config* cfg, void* ws, size_t ws_bytes, void* stre
   c->stream = (hipStream_t)stream;
   if (c->f64()) fill_args<double>(c->a64, cfg, L, c->ws);
   else fill_args<float>(c->a32, cfg, L, c->ws);
-  // zero the selection state, counters and divergence flag
-  hipError_t e = hipMemsetAsync(c->ws + L.off_sel, 0, sizeof(SelState), c->stream);
+  // selection state, counters and divergence flag
+  SelState s0;
+  init_select_state(&s0, c->f64());
+  hipError_t e = hipMemcpyAsync(c->ws + L.off_sel, &s0, sizeof(SelState), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.off_cnt, 0, CNT_N * 8, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.off_div, 0xff, sizeof(long long), c->stream);
   if (e == hipSuccess && (cfg->limiters & LBM_LIM_EHRENFEST)) {
@@ -340,13 +345,18 @@ lbm_status lbm_set_omega(lbm_ctx* c, const void* omega, int dtype) {
   return LBM_OK;
 }
 
-static hipError_t one_step(lbm_ctx* c) {
+static hipError_t one_step(lbm_ctx* c, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
   const int src = c->cur, dst = 1 - c->cur;
   const bool med = (c->cfg.limiters & LBM_LIM_MEDIAN) != 0;
   const void* args;
   if (c->f64()) { c->a64.src = c->lat(src); c->a64.dst = c->lat(dst); args = &c->a64; }
   else { c->a32.src = c->lat(src); c->a32.dst = c->lat(dst); args = &c->a32; }
-  hipError_t e = launch_step(c->cfg.storage, c->L.Q, c->cfg.collision, med, args, c->stream);
+  hipError_t e = hipSuccess;
+  if (ev0) e = hipEventRecord(ev0, c->stream);
+  if (e != hipSuccess) return e;
+  e = launch_step(c->cfg.storage, c->L.Q, c->cfg.collision, med, args, c->stream);
+  if (e != hipSuccess) return e;
+  if (ev1) e = hipEventRecord(ev1, c->stream);
   if (e != hipSuccess) return e;
   if (c->cfg.limiters & LBM_LIM_EHRENFEST) {
     SelectArgs sa;
@@ -354,9 +364,8 @@ static hipError_t one_step(lbm_ctx* c) {
     sa.k = c->L.k; sa.n_sites = c->L.n_sites;
     sa.selected = adjoint_selected_slot(c->L.adj, c->ws, c->steps,
                                         (int32_t*)(c->ws + c->L.off_selected));
-    sa.boundary_idx = (int32_t*)(c->ws + c->L.off_blist);
-    sa.boundary_key = nullptr;
-    sa.hist = (unsigned int*)(c->ws + c->L.off_hist);
+    sa.blist = (uint32_t*)(c->ws + c->L.off_blist);
+    sa.bcap = c->L.bcap;
     sa.coarse = (unsigned int*)(c->ws + c->L.off_coarse);
     sa.n_sel_out = adjoint_count_slot(c->L.adj, c->ws, c->steps);
     e = launch_select(sa, c->stream);
@@ -367,14 +376,11 @@ static hipError_t one_step(lbm_ctx* c) {
   return hipSuccess;
 }
 
-lbm_status lbm_step(lbm_ctx* c, long long n) {
-  g_err.clear();
-  if (!c) return fail(LBM_EINVAL, "ctx is NULL");
-  if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+static lbm_status run_steps(lbm_ctx* c, long long n, hipEvent_t* ev) {
   for (long long s = 0; s < n; ++s) {
     if (c->recorded && c->steps >= c->cfg.max_steps)
       return fail(LBM_ESTATE, "rollout longer than cfg.max_steps; lbm_backward could not cover it");
-    hipError_t e = one_step(c);
+    hipError_t e = ev ? one_step(c, ev[2 * s], ev[2 * s + 1]) : one_step(c);
     if (e != hipSuccess) return hip_fail(e, "lbm_step");
     if (c->recorded) {
       e = adjoint_after_step(c->L.adj, c->ws, c->steps, c->lat(c->cur), c->L.lat_bytes, c->stream);
@@ -388,6 +394,51 @@ lbm_status lbm_step(lbm_ctx* c, long long n) {
       if (e != hipSuccess) return hip_fail(e, "check");
     }
   }
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx* c, long long n) {
+  g_err.clear();
+  if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+  if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+  return run_steps(c, n, nullptr);
+}
+
+lbm_status lbm_profile_step(lbm_ctx* c, long long n, double out[2]) {
+  g_err.clear();
+  if (!c || !out) return fail(LBM_EINVAL, "NULL argument");
+  if (n < 1) return fail(LBM_EINVAL, "n must be >= 1");
+  std::vector<hipEvent_t> ev((size_t)(2 * n + 1), nullptr);
+  hipError_t e = hipSuccess;
+  for (auto& x : ev) {
+    e = hipEventCreate(&x);
+    if (e != hipSuccess) break;
+  }
+  lbm_status st = LBM_OK;
+  if (e == hipSuccess) {
+    st = run_steps(c, n, ev.data());
+    if (st == LBM_OK) {
+      e = hipEventRecord(ev[2 * n], c->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(ev[2 * n]);
+    }
+  }
+  double kern = 0.0, total = 0.0;
+  if (e == hipSuccess && st == LBM_OK) {
+    for (long long s = 0; s < n && e == hipSuccess; ++s) {
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, ev[2 * s], ev[2 * s + 1]);
+      kern += ms;
+    }
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[2 * n]);
+    total = ms;
+  }
+  for (auto& x : ev)
+    if (x) hipEventDestroy(x);
+  if (st != LBM_OK) return st;
+  if (e != hipSuccess) return hip_fail(e, "lbm_profile_step");
+  out[0] = kern;
+  out[1] = total;
   return LBM_OK;
 }
 
@@ -428,6 +479,7 @@ lbm_status lbm_stats_get(lbm_ctx* c, lbm_stats* out) {
   out->n_selected = sel.n_sel;
   out->select_fallbacks = (long long)sel.fallbacks;
   out->select_overflow = (long long)sel.overflows;
+  out->select_candidates = (long long)sel.cand_total;
   if (div >= 0) return fail(LBM_EDIVERGED, "non-finite value or rho <= 0 found at step " + std::to_string(div));
   if (sel.overflows) return fail(LBM_ESELECT, "Ehrenfest candidate buffer overflowed; raise select_capacity");
   return LBM_OK;

@@ -33,8 +33,9 @@ enum EqKind : int { EQ_POLY = 0, EQ_ENTROPIC = 1 };
 enum ElbmBranch : int { EB_ROOT = 0, EB_CUTOFF = 1, EB_NOROOT = 2, EB_NONPOS = 3, EB_F64 = 4 };
 
 // ---------------------------------------------------------------------------
-// Storage forms.  FP64 and FP32 hold f_i.  FP16 and BF16 hold the shifted
-// deviation g_i = f_i - w_i rho0, rounded to nearest even.
+// Storage forms.  FP64 holds f_i.  FP32, FP16 and BF16 hold the shifted
+// deviation g_i = f_i - w_i rho0, rounded to nearest even, so that their
+// precision is spent on the small deviations from rest.
 // ---------------------------------------------------------------------------
 struct bf16_t { uint16_t bits; };
 
@@ -47,7 +48,7 @@ template <> struct StoreT<double> {
 };
 template <> struct StoreT<float> {
   using R = float;
-  static constexpr bool shifted = false;
+  static constexpr bool shifted = true;
   static __device__ __forceinline__ float ld(const float* p) { return *p; }
   static __device__ __forceinline__ void st(float* p, float v) { __builtin_nontemporal_store(v, p); }
 };
@@ -77,28 +78,32 @@ template <> struct StoreT<bf16_t> {
 };
 
 // ---------------------------------------------------------------------------
-// 1D equilibrium factors divided by their weight, minus one:
-//   polynomial (section 6): P_a(u) = phi_a(u) / w_a, phi_-(u) = (1-3u+3u^2)/6,
-//     phi_0 = (2/3)(1 - 3u^2/2), phi_+ = (1+3u+3u^2)/6;
-//   entropic (section 6): phi_- = (-3u - 1 + 2 s)/6, phi_0 = (2/3)(2 - s),
-//     phi_+ = (3u - 1 + 2 s)/6 with s = sqrt(1 + 3u^2).
-// Returning P_a - 1 keeps the shifted form accurate.
+// 1D equilibria (section 6), scaled by 6 so that the weights become the
+// integers c = (1, 4, 1), and written as deviations dt_a = 6 phi_a(u) - c_a:
+//   polynomial: phi_0 = (2/3)(1 - 3u^2/2)  ->  dt_0 = -6 u^2
+//   entropic:   phi_0 = (2/3)(2 - s), s = sqrt(1 + 3u^2)  ->  dt_0 = -4 (s - 1)
+//   both:       phi_+- = (1 - phi_0)/2 +- u/2  ->  dt_+- = -dt_0/2 +- 3u
+// (the same identities as the printed phi_-, phi_+).  With exact integer
+// weights, sum_a (c_a + dt_a) = 6 and sum_a a (c_a + dt_a) = 6u hold up to
+// unbiased rounding, so the discrete equilibrium adds no systematic mass or
+// momentum drift in FP32.
 // ---------------------------------------------------------------------------
 template <class R>
-__device__ __forceinline__ void eq_factors_m1(R u, int kind, R pm1[3]) {
+__device__ __forceinline__ void eq_dev6(R u, int kind, R dt[3]) {
+  R d0;
   if (kind == EQ_POLY) {
-    R u2 = R(3) * u * u;
-    pm1[0] = -R(3) * u + u2;
-    pm1[1] = -R(0.5) * u2;
-    pm1[2] = R(3) * u + u2;
+    d0 = R(-6) * u * u;
   } else {
-    R t = R(3) * u * u;
-    R sm1 = t / (sqrt(R(1) + t) + R(1));  // s - 1 without cancellation
-    pm1[0] = -R(3) * u + R(2) * sm1;
-    pm1[1] = -sm1;
-    pm1[2] = R(3) * u + R(2) * sm1;
+    const R t = R(3) * u * u;
+    d0 = R(-4) * (t / (sqrt(R(1) + t) + R(1)));  // -4 (s - 1) without cancellation
   }
+  const R h = R(-0.5) * d0;
+  dt[0] = h - R(3) * u;
+  dt[1] = d0;
+  dt[2] = h + R(3) * u;
 }
+
+__device__ __forceinline__ int c1(int a) { return a == 0 ? 4 : 1; }  // 6 w_a
 
 // h(x) = (1 + x) ln(1 + x) - x, h(-1) = 1; Taylor series for |x| < 0.1.
 template <class R>

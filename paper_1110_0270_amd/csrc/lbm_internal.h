@@ -11,26 +11,25 @@ namespace lbm {
 // Ehrenfests' regularisation with a budget of k sites per step).
 struct SelState {
   unsigned long long count;      // candidates appended this step
-  unsigned long long max_key;    // largest candidate key this step
+  unsigned long long max_key;    // largest finite candidate key this step
   unsigned long long floor_key;  // a site is a candidate iff eligible and key >= floor_key
-  unsigned long long base_key;   // bucket origin of this step's histogram
+  unsigned long long base_key;   // histogram frame: bucket = (key - base_key) >> shift
   unsigned long long bcount;     // length of the boundary-bucket list
+  unsigned long long sel_acc;    // sites selected so far in the running step
   unsigned long long fallbacks;  // steps that needed a full rescan (cumulative)
-  unsigned long long overflows;  // steps whose rescan overflowed (cumulative)
-  long long n_sel;               // sites selected in the last step
-  long long take;                // candidates to take from the boundary bucket
+  unsigned long long overflows;  // steps whose buffers overflowed (cumulative)
+  unsigned long long cand_total; // candidates over all steps (cumulative)
+  long long n_sel;               // sites selected in the last completed step
   unsigned int shift;            // bucket width is 2^shift keys
-  unsigned int ticket;           // last-block ticket
-  int boundary;                  // boundary bucket, -1: take every candidate
-  int fallback;                  // 1: this step's candidates are unusable
+  unsigned int ticket;           // last-workgroup ticket
+  int fallback;                  // 1: this step's candidates came from a rescan
   int fb_bin;                    // coarse bin chosen by the rescan
   int floor_raised;              // floor_key is above the eligibility threshold
-  int pad[2];
+  int pad[3];
 };
 
-constexpr int kBuckets = 4096;        // fine histogram of candidate keys
-constexpr int kCoarse = 4096;         // coarse histogram: top 12 bits of the FP32 key
-constexpr int kBoundaryCap = 1 << 16; // boundary-bucket list entries
+constexpr int kBuckets = 4096;        // histogram of candidate keys
+constexpr int kCoarse = 4096;         // rescan histogram: top 12 bits of the FP32 key
 
 // Counters of limiter activity (cumulative since the last reset).
 enum Counter : int {
@@ -77,6 +76,7 @@ struct StepArgs {
   uint32_t* cand_idx;
   R* cand_mom;           // [3][cap]: rho (or rho - rho0 when shifted), ux, uy
   long long cap;
+  unsigned int* hist;    // kBuckets counts of this step's candidates
   unsigned long long* counters;
 };
 
@@ -111,12 +111,12 @@ struct SelectArgs {
   long long k;
   long long n_sites;
   int32_t* selected;       // out: selected site indices, ascending not guaranteed
-  int32_t* boundary_idx;   // scratch lists
-  unsigned long long* boundary_key;
-  unsigned int* hist;      // kBuckets
+  uint32_t* blist;         // boundary-bucket list (positions in the candidate buffer)
+  long long bcap;          // its capacity
   unsigned int* coarse;    // kCoarse
   long long* n_sel_out;    // optional: the step's selection count is copied here
 };
 hipError_t launch_select(const SelectArgs& a, hipStream_t s);
+void init_select_state(SelState* h, int f64);
 
 }  // namespace lbm

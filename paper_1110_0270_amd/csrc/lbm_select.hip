@@ -1,24 +1,24 @@
 // Ehrenfest regularisation with a budget (section 4): after the collision,
 // the k sites of largest nonequilibrium entropy Delta S > delta (ties to the
-// lower site index) are sent to their equilibrium f*.  Since every collision
-// keeps rho and u, f* is rebuilt from the moments that the step kernel
-// recorded with each candidate and written over the collided state.
+// lower site index) are sent to their equilibrium f*.  Every collision keeps
+// rho and u, so f* is rebuilt from the moments that the step kernel recorded
+// with each candidate and written over the collided state.
 //
-// The step kernel appends only sites whose key (the bit pattern of Delta S,
-// monotone for non-negative floats) is at least a floor carried over from
-// the previous step, so selection works on a short candidate list instead
-// of the whole lattice:
-//   k_fb_scan   (only if the candidates cannot contain the answer: too few
-//                above a raised floor, or more than the buffer holds) rescans
-//                the lattice, builds a coarse Delta S histogram and picks a
-//                safe floor bin;
-//   k_fb_append (same condition) rescans and appends from that bin up;
-//   k_hist      builds a 4096-bucket histogram of the candidate keys and
-//                finds the boundary bucket holding the k-th largest key;
-//   k_fix       writes f* at candidates above the boundary bucket and
-//                resolves the boundary bucket exactly by a radix select on
-//                (key descending, site index ascending).
-// The last workgroup of each kernel (atomic ticket) does its serial part.
+// The step kernel appends only sites whose key (the bit pattern of Delta S)
+// is at least a floor carried over from the previous step, and counts them
+// in a 4096-bucket histogram whose frame also comes from the previous step.
+// Selection then touches the short candidate list only:
+//   k_fb_scan   only when the candidates cannot hold the answer (fewer than
+//               k above a raised floor, or more than the buffer holds):
+//               rescans the lattice, histograms the top 12 bits of Delta S
+//               and picks a floor bin that holds at least k sites;
+//   k_fb_append same condition: rescans and appends from that bin up;
+//   k_fix       every workgroup finds the boundary bucket (holding the k-th
+//               largest key) from the histogram, writes f* at candidates
+//               above it and lists those inside it; the last workgroup
+//               resolves the boundary bucket exactly by an MSD radix select on
+//               (key descending, site index ascending), sets the next step's
+//               floor and frame, and resets the counters.
 #include "lbm_site.h"
 
 namespace lbm {
@@ -26,11 +26,11 @@ namespace lbm {
 template <class R> struct KeyTraits;
 template <> struct KeyTraits<float> {
   static constexpr int bits = 32;
-  static constexpr unsigned long long quarter = 2ull << 23;   // Delta S / 4
+  static constexpr unsigned long long quarter = 1ull << 21;   // a quarter octave of Delta S
 };
 template <> struct KeyTraits<double> {
   static constexpr int bits = 64;
-  static constexpr unsigned long long quarter = 2ull << 52;
+  static constexpr unsigned long long quarter = 1ull << 50;
 };
 
 __device__ __forceinline__ unsigned int coarse_bin(float v) {
@@ -38,14 +38,19 @@ __device__ __forceinline__ unsigned int coarse_bin(float v) {
   const uint32_t b = u >> 19;  // exponent and 4 mantissa bits: 0 .. 4080 for v >= 0
   return b < (uint32_t)kCoarse ? b : 0u;
 }
-__device__ __forceinline__ unsigned long long ld_acq(const unsigned long long* p) {
+template <class R>
+__device__ __forceinline__ unsigned long long coarse_edge_key(int bin) {
+  const float edge = __uint_as_float(((uint32_t)bin) << 19);
+  return (unsigned long long)key_of<R>((R)edge);
+}
+__device__ __forceinline__ unsigned long long ld_rlx(const unsigned long long* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ unsigned int ld_acq(const unsigned int* p) {
+__device__ __forceinline__ unsigned int ld_rlx(const unsigned int* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Returns true in every thread of the last workgroup to arrive.
+// True in every thread of the last workgroup to arrive.
 __device__ __forceinline__ bool last_block(unsigned int* ticket) {
   __shared__ bool is_last;
   __threadfence();
@@ -56,15 +61,63 @@ __device__ __forceinline__ bool last_block(unsigned int* ticket) {
   return is_last;
 }
 
-template <class R>
-__device__ __forceinline__ bool need_rescan(const SelState* st, long long k, long long cap) {
-  const unsigned long long n = st->count;
-  return n > (unsigned long long)cap || ((long long)n < k && st->floor_raised);
+// Block-wide search of an LDS histogram h[0..NB) from the top bin down: *bin
+// receives the bin where the running count first reaches `need` (-1 if the
+// histogram holds fewer), *above the count in the bins above it.  Every
+// thread of the block calls it (blockDim.x <= 1024).
+template <int NB>
+__device__ void find_from_top(const unsigned int* h, unsigned long long need, int* bin,
+                              unsigned long long* above) {
+  __shared__ unsigned long long part[1024];
+  __shared__ int s_bin;
+  __shared__ unsigned long long s_above;
+  const int T = blockDim.x, t = threadIdx.x;
+  const int C = (NB + T - 1) / T;
+  const int hi = NB - t * C;
+  const int lo = hi - C > 0 ? hi - C : 0;
+  unsigned long long s = 0;
+  for (int b = lo; b < hi; ++b) s += h[b];
+  part[t] = s;
+  if (t == 0) { s_bin = -1; s_above = 0; }
+  __syncthreads();
+  for (int off = 1; off < T; off <<= 1) {
+    const unsigned long long v = t >= off ? part[t - off] : 0ull;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  const unsigned long long incl = part[t], excl = incl - s;
+  if (s > 0 && need > 0 && excl < need && need <= incl) {
+    unsigned long long c = excl;
+    for (int b = hi - 1; b >= lo; --b) {
+      if (c + h[b] >= need) { s_bin = b; s_above = c; break; }
+      c += h[b];
+    }
+  }
+  __syncthreads();
+  *bin = s_bin;
+  *above = s_above;
+  __syncthreads();
 }
 
 template <class R>
 __device__ __forceinline__ unsigned long long delta_key(R delta) {
   return delta <= R(0) ? 0ull : (unsigned long long)key_of<R>(delta);
+}
+
+// Frame for a histogram of keys in [base, top): about 2048 buckets, leaving
+// half of the 4096 as margin for keys that grow in the next step.
+__device__ __forceinline__ unsigned int frame_shift(unsigned long long base, unsigned long long top) {
+  const unsigned long long span = top > base ? top - base : 0ull;
+  unsigned int sh = 0;
+  while (sh < 62 && (span >> sh) >= (unsigned long long)(kBuckets / 2)) ++sh;
+  return sh;
+}
+
+template <class R>
+__device__ __forceinline__ bool need_rescan(const SelState* st, long long k, long long cap) {
+  const unsigned long long n = st->count;
+  return n > (unsigned long long)cap || ((long long)n < k && st->floor_raised);
 }
 
 // ---------------------------------------------------------------------------
@@ -89,31 +142,41 @@ __global__ __launch_bounds__(256) void k_fb_scan(const StepArgs<typename StoreT<
   for (int i = threadIdx.x; i < kCoarse; i += blockDim.x)
     if (h[i]) atomicAdd(&coarse[i], h[i]);
   if (!last_block(&st->ticket)) return;
-  // Serial part: the coarse bin that holds the k-th largest Delta S.
+  // The coarse bin that holds the k-th largest Delta S, and the frame of the
+  // fallback candidates' histogram.
+  for (int i = threadIdx.x; i < kCoarse; i += blockDim.x) h[i] = ld_rlx(&coarse[i]);
+  __syncthreads();
+  int b;
+  unsigned long long above;
+  find_from_top<kCoarse>(h, (unsigned long long)(k > 0 ? k : 1), &b, &above);
+  if (b < 0) b = 0;                                   // fewer than k eligible: take all
+  __shared__ int top;
+  if (threadIdx.x == 0) top = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < kCoarse - 16; i += blockDim.x)   // highest finite bin
+    if (h[i]) atomicMax(&top, i);
+  __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned long long cum = 0;
-    int b = kCoarse - 1;
-    for (; b > 0; --b) {
-      cum += ld_acq(&coarse[b]);
-      if (cum >= (unsigned long long)k) break;
-    }
-    if (b == 0) cum += ld_acq(&coarse[0]);
+    unsigned long long total = 0;
+    for (int i = b; i < kCoarse; ++i) total += h[i];
     st->fb_bin = b;
     st->fallback = 1;
     st->fallbacks += 1;
-    if (cum > (unsigned long long)A.cap) st->overflows += 1;
+    if (total > (unsigned long long)A.cap) st->overflows += 1;
     st->count = 0;
     st->max_key = 0;
+    st->base_key = coarse_edge_key<R>(b);
+    st->shift = frame_shift(st->base_key, coarse_edge_key<R>(top + 1));
     st->ticket = 0;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < kCoarse; i += blockDim.x) coarse[i] = 0;
+  for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) A.hist[i] = 0;
 }
 
 template <class S, int Q>
 __global__ __launch_bounds__(256) void k_fb_append(const StepArgs<typename StoreT<S>::R> A) {
   using R = typename StoreT<S>::R;
-  using K = typename KeyOf<R>::T;
   SelState* st = A.sel;
   if (!st->fallback) return;
   const unsigned int fb = (unsigned int)st->fb_bin;
@@ -132,122 +195,8 @@ __global__ __launch_bounds__(256) void k_fb_append(const StepArgs<typename Store
       dS = site_prep<S, Q>(A, x, y, v, feq, d, m0, ux, uy, true);
       is_c = (dS > A.ehr_delta) && coarse_bin((float)dS) >= fb;
     }
-    const unsigned long long mask = __ballot(is_c);
-    if (!mask) continue;
-    const int lane = __lane_id();
-    const int leader = __ffsll((long long)mask) - 1;
-    const K key = key_of<R>(dS);
-    unsigned long long kmax = is_c ? (unsigned long long)key : 0ull;
-    for (int off = 32; off > 0; off >>= 1) {
-      const unsigned long long o = __shfl_xor(kmax, off);
-      kmax = o > kmax ? o : kmax;
-    }
-    unsigned long long base = 0;
-    if (lane == leader) {
-      base = atomicAdd(&st->count, (unsigned long long)__popcll(mask));
-      atomicMax(&st->max_key, kmax);
-    }
-    base = __shfl(base, leader);
-    if (is_c) {
-      const unsigned long long pos =
-          base + (unsigned long long)__popcll(mask & ((1ull << lane) - 1ull));
-      if (pos < (unsigned long long)A.cap) {
-        A.cand_key[pos] = key;
-        A.cand_idx[pos] = (uint32_t)(y * A.nx + x);
-        A.cand_mom[pos] = m0;
-        A.cand_mom[A.cap + pos] = ux;
-        A.cand_mom[2 * A.cap + pos] = uy;
-      }
-    }
+    append_candidates<R>(A, is_c, key_of<R>(dS), (uint32_t)(y * A.nx + x), m0, ux, uy);
   }
-}
-
-// Lower edge of the candidate keys and the bucket width for this step.
-template <class R>
-__device__ __forceinline__ void bucket_frame(const SelState* st, R delta,
-                                             unsigned long long& base, unsigned int& shift) {
-  if (st->fallback) {
-    const float edge = __uint_as_float(((uint32_t)st->fb_bin) << 19);
-    base = (unsigned long long)key_of<R>((R)edge);
-  } else {
-    base = st->floor_raised ? st->floor_key : delta_key<R>(delta);
-  }
-  const unsigned long long mx = st->max_key;
-  const unsigned long long span = mx > base ? mx - base : 0ull;
-  shift = 0;
-  while (shift < 62 && (span >> shift) >= (unsigned long long)kBuckets) ++shift;
-}
-
-__device__ __forceinline__ int bucket_of(unsigned long long key, unsigned long long base,
-                                         unsigned int shift) {
-  if (key < base) return 0;
-  const unsigned long long b = (key - base) >> shift;
-  return b >= (unsigned long long)kBuckets ? kBuckets - 1 : (int)b;
-}
-
-template <class R>
-__global__ __launch_bounds__(256) void k_hist(const StepArgs<R> A, long long k,
-                                              long long n_sites, unsigned int* hist) {
-  SelState* st = A.sel;
-  const unsigned long long nc_all = st->count;
-  const long long nc = (long long)(nc_all < (unsigned long long)A.cap ? nc_all : A.cap);
-  unsigned long long base;
-  unsigned int shift;
-  bucket_frame<R>(st, A.ehr_delta, base, shift);
-  __shared__ unsigned int h[kBuckets];
-  for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) h[i] = 0;
-  __syncthreads();
-  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < nc;
-       p += (long long)gridDim.x * blockDim.x)
-    atomicAdd(&h[bucket_of((unsigned long long)A.cand_key[p], base, shift)], 1u);
-  __syncthreads();
-  for (int i = threadIdx.x; i < kBuckets; i += blockDim.x)
-    if (h[i]) atomicAdd(&hist[i], h[i]);
-  if (!last_block(&st->ticket)) return;
-  if (threadIdx.x == 0) {
-    const long long need = k < nc ? k : nc;
-    int boundary = -1;
-    long long take = 0;
-    if (nc > k && k > 0) {
-      unsigned long long cum = 0;
-      for (int b = kBuckets - 1; b >= 0; --b) {
-        const unsigned long long c = ld_acq(&hist[b]);
-        if (cum + c >= (unsigned long long)need) {
-          boundary = b;
-          take = need - (long long)cum;
-          break;
-        }
-        cum += c;
-      }
-    } else if (k <= 0) {
-      boundary = kBuckets;  // take nothing
-    }
-    st->boundary = boundary;
-    st->take = take;
-    st->base_key = base;
-    st->shift = shift;
-    // Floor for the next step: keep about 2k candidates (never raised when
-    // the buffer can hold every site).
-    const unsigned long long dk = delta_key<R>(A.ehr_delta);
-    unsigned long long fnext = dk;
-    if (A.cap < n_sites && k > 0) {
-      const unsigned long long target = 2ull * (unsigned long long)k;
-      unsigned long long cum = 0;
-      int t = -1;
-      for (int b = kBuckets - 1; b >= 0; --b) {
-        cum += ld_acq(&hist[b]);
-        if (cum >= target) { t = b; break; }
-      }
-      if (t >= 0) fnext = base + ((unsigned long long)t << shift);
-      else fnext = base > KeyTraits<R>::quarter ? base - KeyTraits<R>::quarter : 0ull;
-      if (fnext < dk) fnext = dk;
-    }
-    st->floor_key = fnext;
-    st->floor_raised = fnext > dk ? 1 : 0;
-    st->ticket = 0;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) hist[i] = 0;
 }
 
 template <class S, int Q>
@@ -265,122 +214,186 @@ __device__ __forceinline__ void write_feq(const StepArgs<typename StoreT<S>::R>&
     StoreT<S>::st(dst + (long long)i * A.qs + (long long)y * A.pitch + x, feq[i]);
 }
 
+// Wave-aggregated reservation of one slot per set lane.
+__device__ __forceinline__ unsigned long long wave_slot(bool on, unsigned long long* ctr) {
+  const unsigned long long mask = __ballot(on);
+  if (!mask) return 0;
+  const int lane = __lane_id();
+  const int leader = __ffsll((long long)mask) - 1;
+  unsigned long long base = 0;
+  if (lane == leader) base = atomicAdd(ctr, (unsigned long long)__popcll(mask));
+  base = __shfl(base, leader);
+  return base + (unsigned long long)__popcll(mask & ((1ull << lane) - 1ull));
+}
+
 template <class S, int Q>
 __global__ __launch_bounds__(1024) void k_fix(const StepArgs<typename StoreT<S>::R> A,
-                                              long long k, int32_t* selected, uint32_t* blist,
+                                              long long k, long long n_sites, int32_t* selected,
+                                              uint32_t* blist, long long bcap,
                                               long long* n_sel_out) {
   using R = typename StoreT<S>::R;
   SelState* st = A.sel;
+  __shared__ unsigned int h[kBuckets];
   const unsigned long long nc_all = st->count;
   const long long nc = (long long)(nc_all < (unsigned long long)A.cap ? nc_all : A.cap);
-  const int boundary = st->boundary;
   const unsigned long long base = st->base_key;
   const unsigned int shift = st->shift;
-  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < nc;
-       p += (long long)gridDim.x * blockDim.x) {
-    const int b = bucket_of((unsigned long long)A.cand_key[p], base, shift);
-    if (boundary < 0 || b > boundary) {
-      write_feq<S, Q>(A, p);
-      const unsigned long long slot = atomicAdd((unsigned long long*)&st->n_sel, 1ull);
-      if (slot < (unsigned long long)k) selected[slot] = (int32_t)A.cand_idx[p];
-    } else if (b == boundary) {
-      const unsigned long long q = atomicAdd(&st->bcount, 1ull);
-      if (q < (unsigned long long)kBoundaryCap) blist[q] = (uint32_t)p;
+  const long long need = k < nc ? k : nc;
+  for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) h[i] = ld_rlx(&A.hist[i]);
+  __syncthreads();
+  int boundary;
+  unsigned long long above;
+  if (k <= 0) {
+    boundary = kBuckets;                 // take nothing
+    above = 0;
+  } else if (nc <= k) {
+    boundary = -1;                       // take every candidate
+    above = 0;
+  } else {
+    find_from_top<kBuckets>(h, (unsigned long long)need, &boundary, &above);
+    if (boundary < 0) boundary = -1;
+  }
+  const long long take = (boundary >= 0 && boundary < kBuckets) ? need - (long long)above : 0;
+
+  const long long nthreads = (long long)gridDim.x * blockDim.x;
+  const long long iters = (nc + nthreads - 1) / nthreads;
+  for (long long it = 0; it < iters; ++it) {
+    const long long p = it * nthreads + (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    bool sel = false, bnd = false;
+    if (p < nc) {
+      const int b = bucket_of<R>((unsigned long long)A.cand_key[p], base, shift);
+      sel = boundary < 0 || b > boundary;
+      bnd = b == boundary;
     }
+    if (sel) write_feq<S, Q>(A, p);
+    const unsigned long long slot = wave_slot(sel, &st->sel_acc);
+    if (sel && slot < (unsigned long long)k) selected[slot] = (int32_t)A.cand_idx[p];
+    const unsigned long long q = wave_slot(bnd, &st->bcount);
+    if (bnd && q < (unsigned long long)bcap) blist[q] = (uint32_t)p;
   }
   if (!last_block(&st->ticket)) return;
 
-  // Boundary bucket: take the `take` largest (key desc, index asc) by an MSD
-  // radix select over 8-bit digits of the key, then of the complemented index.
+  // --- boundary bucket: the `take` largest by (key desc, index asc) --------
   __shared__ unsigned int dh[256];
-  __shared__ unsigned long long s_key_pref;
+  __shared__ unsigned long long s_off_pref;
   __shared__ uint32_t s_idx_pref;
-  __shared__ long long s_need;
-  const long long m_all = (long long)ld_acq(&st->bcount);
-  const long long m = m_all < kBoundaryCap ? m_all : kBoundaryCap;
-  long long take = st->take;
-  if (boundary >= 0 && boundary < kBuckets && take > 0) {
-    if (threadIdx.x == 0) { s_key_pref = 0; s_idx_pref = 0; s_need = take; }
-    constexpr int KB = KeyTraits<R>::bits;
-    // digits: KB/8 of the key then 4 of ~index, most significant first
-    for (int dgt = 0; dgt < KB / 8 + 4; ++dgt) {
+  const long long m_all = (long long)ld_rlx(&st->bcount);
+  const long long m = m_all < bcap ? m_all : bcap;
+  if (take > 0 && m > 0) {
+    // keys of the bucket differ only in their offset from the bucket's lower
+    // edge: `shift` bits, or all bits in the open-ended top bucket
+    const unsigned long long edge = base + ((unsigned long long)boundary << shift);
+    const int nb = boundary == kBuckets - 1 ? KeyTraits<R>::bits : (int)shift;
+    const int kd = (nb + 7) / 8;
+    unsigned long long need_left = (unsigned long long)take;
+    if (threadIdx.x == 0) { s_off_pref = 0; s_idx_pref = 0; }
+    __syncthreads();
+    for (int dgt = 0; dgt < kd + 4; ++dgt) {
       for (int i = threadIdx.x; i < 256; i += blockDim.x) dh[i] = 0;
       __syncthreads();
-      const bool on_key = dgt < KB / 8;
-      const int shiftb = on_key ? KB - 8 * (dgt + 1) : 32 - 8 * (dgt - KB / 8 + 1);
-      const unsigned long long kp = s_key_pref;
+      const bool on_key = dgt < kd;
+      const int sb = on_key ? 8 * (kd - 1 - dgt) : 8 * (3 - (dgt - kd));
+      const unsigned long long op = s_off_pref;
       const uint32_t ip = s_idx_pref;
       for (long long q = threadIdx.x; q < m; q += blockDim.x) {
         const uint32_t p = blist[q];
         const unsigned long long key = (unsigned long long)A.cand_key[p];
+        const unsigned long long off = key >= edge ? key - edge : 0ull;
         const uint32_t ni = ~A.cand_idx[p];
         bool match;
         unsigned int digit;
+        const int top = sb + 8;
         if (on_key) {
-          const unsigned long long hi_mask = dgt == 0 ? 0ull : (~0ull << (shiftb + 8)) & (KB == 64 ? ~0ull : 0xffffffffull);
-          match = (key & hi_mask) == (kp & hi_mask);
-          digit = (unsigned int)((key >> shiftb) & 0xffu);
+          const unsigned long long hm = top >= 64 ? 0ull : (~0ull << top);
+          match = (off & hm) == (op & hm);
+          digit = (unsigned int)((off >> sb) & 0xffu);
         } else {
-          const uint32_t hi_mask = (shiftb + 8 >= 32) ? 0u : (~0u << (shiftb + 8));
-          match = key == kp && (ni & hi_mask) == (ip & hi_mask);
-          digit = (ni >> shiftb) & 0xffu;
+          const uint32_t hm = top >= 32 ? 0u : (~0u << top);
+          match = off == op && (ni & hm) == (ip & hm);
+          digit = (ni >> sb) & 0xffu;
         }
         if (match) atomicAdd(&dh[digit], 1u);
       }
       __syncthreads();
+      int dsel;
+      unsigned long long dabove;
+      find_from_top<256>(dh, need_left, &dsel, &dabove);
+      if (dsel < 0) dsel = 0;
+      need_left -= dabove;
       if (threadIdx.x == 0) {
-        long long need = s_need, cum = 0;
-        int dsel = 0;
-        for (int dd = 255; dd >= 0; --dd) {
-          if (cum + (long long)dh[dd] >= need) { dsel = dd; break; }
-          cum += dh[dd];
-        }
-        s_need = need - cum;
-        if (on_key) s_key_pref |= ((unsigned long long)dsel) << shiftb;
-        else s_idx_pref |= ((uint32_t)dsel) << shiftb;
+        if (on_key) s_off_pref |= ((unsigned long long)dsel) << sb;
+        else s_idx_pref |= ((uint32_t)dsel) << sb;
       }
       __syncthreads();
     }
-    const unsigned long long tk = s_key_pref;
+    const unsigned long long to = s_off_pref;
     const uint32_t ti = s_idx_pref;
-    for (long long q = threadIdx.x; q < m; q += blockDim.x) {
-      const uint32_t p = blist[q];
-      const unsigned long long key = (unsigned long long)A.cand_key[p];
-      const uint32_t ni = ~A.cand_idx[p];
-      if (key > tk || (key == tk && ni >= ti)) {
-        write_feq<S, Q>(A, p);
-        const unsigned long long slot = atomicAdd((unsigned long long*)&st->n_sel, 1ull);
-        if (slot < (unsigned long long)k) selected[slot] = (int32_t)A.cand_idx[p];
+    for (long long q0 = 0; q0 < m; q0 += blockDim.x) {
+      const long long q = q0 + threadIdx.x;
+      bool sel = false;
+      uint32_t p = 0;
+      if (q < m) {
+        p = blist[q];
+        const unsigned long long key = (unsigned long long)A.cand_key[p];
+        const unsigned long long off = key >= edge ? key - edge : 0ull;
+        const uint32_t ni = ~A.cand_idx[p];
+        sel = off > to || (off == to && ni >= ti);
       }
+      if (sel) write_feq<S, Q>(A, p);
+      const unsigned long long slot = wave_slot(sel, &st->sel_acc);
+      if (sel && slot < (unsigned long long)k) selected[slot] = (int32_t)A.cand_idx[p];
     }
   }
   __syncthreads();
+
+  // --- floor and frame of the next step ------------------------------------
+  // Keep roughly 2k candidates, with hysteresis; the floor is never raised
+  // when the buffer can hold every site.
+  const unsigned long long dk = delta_key<R>(A.ehr_delta);
+  unsigned long long fnext = dk;
+  if (A.cap < n_sites && k > 0) {
+    const bool keep = st->floor_raised && !st->fallback && nc >= k + k / 4 && nc <= 4 * k;
+    if (keep) {
+      fnext = st->floor_key;
+    } else {
+      int t2;
+      unsigned long long a2;
+      find_from_top<kBuckets>(h, 2ull * (unsigned long long)k, &t2, &a2);
+      if (t2 >= 0 && t2 < kBuckets - 1) fnext = base + ((unsigned long long)t2 << shift);
+      else if (t2 < 0) fnext = base > KeyTraits<R>::quarter ? base - KeyTraits<R>::quarter : 0ull;
+      else fnext = st->floor_key;
+    }
+    if (fnext < dk) fnext = dk;
+  }
   if (threadIdx.x == 0) {
-    if (n_sel_out) *n_sel_out = ld_acq((const unsigned long long*)&st->n_sel);
-    if (m_all > kBoundaryCap) st->overflows += 1;
+    const unsigned long long mx = ld_rlx(&st->max_key);
+    st->floor_key = fnext;
+    st->floor_raised = fnext > dk ? 1 : 0;
+    st->base_key = fnext;
+    st->shift = frame_shift(fnext, mx > fnext ? fnext + 2 * (mx - fnext) : fnext + 1);
+    const unsigned long long ns = ld_rlx(&st->sel_acc);
+    st->n_sel = (long long)ns;
+    if (n_sel_out) *n_sel_out = (long long)ns;
+    if (m_all > bcap) st->overflows += 1;
+    st->cand_total += (unsigned long long)nc;
     st->count = 0;
     st->max_key = 0;
     st->bcount = 0;
+    st->sel_acc = 0;
     st->fallback = 0;
     st->ticket = 0;
   }
-}
-
-// Reset of the per-step selection counter before a step's fix-up.
-__global__ void k_sel_begin(SelState* st) {
-  st->n_sel = 0;
+  for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) A.hist[i] = 0;
 }
 
 template <class S, int Q>
 static hipError_t launch_select_t(const SelectArgs& a, hipStream_t s) {
   using R = typename StoreT<S>::R;
   const StepArgs<R>& A = *(const StepArgs<R>*)a.step_args;
-  hipLaunchKernelGGL((k_fb_scan<S, Q>), dim3(512), dim3(256), 0, s, A, a.k, a.coarse);
-  hipLaunchKernelGGL((k_fb_append<S, Q>), dim3(512), dim3(256), 0, s, A);
-  hipLaunchKernelGGL((k_hist<R>), dim3(128), dim3(256), 0, s, A, a.k, a.n_sites, a.hist);
-  hipLaunchKernelGGL(k_sel_begin, dim3(1), dim3(1), 0, s, A.sel);
-  hipLaunchKernelGGL((k_fix<S, Q>), dim3(64), dim3(1024), 0, s, A, a.k, a.selected,
-                     (uint32_t*)a.boundary_idx, a.n_sel_out);
+  hipLaunchKernelGGL((k_fb_scan<S, Q>), dim3(1024), dim3(256), 0, s, A, a.k, a.coarse);
+  hipLaunchKernelGGL((k_fb_append<S, Q>), dim3(1024), dim3(256), 0, s, A);
+  hipLaunchKernelGGL((k_fix<S, Q>), dim3(64), dim3(1024), 0, s, A, a.k, a.n_sites, a.selected,
+                     a.blist, a.bcap, a.n_sel_out);
   return hipGetLastError();
 }
 
@@ -395,6 +408,13 @@ hipError_t launch_select(const SelectArgs& a, hipStream_t s) {
     case 3 * 16 + 9: return launch_select_t<bf16_t, 9>(a, s);
     default: return launch_select_t<bf16_t, 3>(a, s);
   }
+}
+
+// Initial selection state: floor at the threshold, a frame spanning every
+// positive key (bucket = the top 12 bits of the key).
+void init_select_state(SelState* h, int f64) {
+  *h = SelState{};
+  h->shift = f64 ? 51u : 19u;
 }
 
 }  // namespace lbm

@@ -25,23 +25,30 @@ template <class R, int Q> __device__ __forceinline__ R wt(int i) {
 }
 
 // Equilibrium in the storage representation (unshifted f*_i, or the
-// deviation f*_i - w_i rho0) from m0 (rho, or rho - rho0 when shifted).
+// deviation f*_i - w_i rho0) from m0 (rho, or rho - rho0 when shifted):
+// the product of the 1D equilibria (section 8), f*_ab = rho phi_a phi_b,
+// evaluated as (rho/36) (c_a + dt_a)(c_b + dt_b) with integer weights.
 template <class R, int Q, bool SH>
 __device__ __forceinline__ void equilibrium_v(R m0, R rho0, R ux, R uy, int kind, R feq[Q]) {
-  R px[3], py[3];
-  eq_factors_m1<R>(ux, kind, px);
-  if constexpr (Q == 9) eq_factors_m1<R>(uy, kind, py);
+  R dx[3], dy[3];
+  eq_dev6<R>(ux, kind, dx);
+  if constexpr (Q == 9) eq_dev6<R>(uy, kind, dy);
   const R rho = SH ? rho0 + m0 : m0;
+  constexpr R S = Q == 9 ? R(36) : R(6);
+  const R rs = rho / S;
+  const R ms = m0 / S;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    R p;
     if constexpr (Q == 9) {
-      const R a = px[vx_of<Q>(i) + 1], b = py[vy_of<Q>(i) + 1];
-      p = a + b + a * b;
+      const int a = vx_of<Q>(i), b = vy_of<Q>(i);
+      const R ca = (R)c1(a), cb = (R)c1(b);
+      const R da = dx[a + 1], db = dy[b + 1];
+      feq[i] = SH ? ms * (ca * cb) + rs * (ca * db + da * cb + da * db)
+                  : rs * ((ca + da) * (cb + db));
     } else {
-      p = px[i];
+      const R ca = (R)c1(i - 1);
+      feq[i] = SH ? ms * ca + rs * dx[i] : rs * (ca + dx[i]);
     }
-    feq[i] = SH ? wt<R, Q>(i) * (m0 + rho * p) : wt<R, Q>(i) * (rho + rho * p);
   }
 }
 
@@ -103,6 +110,8 @@ __device__ __forceinline__ R site_dS(const R v[Q], const R feq[Q], const R d[Q],
   return delta_s<R, Q>(fa, qa, d);
 }
 
+// Ranking key of a non-negative Delta S: its bit pattern (monotone in the
+// value); NaN ranks as +inf.
 template <class R> __device__ __forceinline__ typename KeyOf<R>::T key_of(R x);
 template <> __device__ __forceinline__ uint32_t key_of<float>(float x) {
   return x != x ? 0x7f800000u : __float_as_uint(x);   // NaN ranks as +inf
@@ -126,6 +135,63 @@ __device__ __forceinline__ typename StoreT<S>::R site_prep(
 #pragma unroll
   for (int i = 0; i < Q; ++i) d[i] = feq[i] - v[i];
   return need_dS ? site_dS<R, Q, SH>(v, feq, d, A.rho0) : R(0);
+}
+
+template <class R> struct KeyInf;
+template <> struct KeyInf<float> { static constexpr unsigned long long v = 0x7f800000ull; };
+template <> struct KeyInf<double> { static constexpr unsigned long long v = 0x7ff0000000000000ull; };
+
+// Histogram bucket of a key in the frame (base, shift); +inf keys and keys
+// beyond the frame go to the top bucket.
+template <class R>
+__device__ __forceinline__ int bucket_of(unsigned long long key, unsigned long long base,
+                                         unsigned int shift) {
+  if (key >= KeyInf<R>::v) return kBuckets - 1;
+  if (key < base) return 0;
+  const unsigned long long b = (key - base) >> shift;
+  return b >= (unsigned long long)kBuckets ? kBuckets - 1 : (int)b;
+}
+
+// Wave-aggregated append of Ehrenfest candidates (all lanes of the wave must
+// call it): one atomic per wave reserves the slots; the candidate's key, site
+// index and moments go to the buffer and its bucket count to the histogram.
+template <class R>
+__device__ __forceinline__ void append_candidates(const StepArgs<R>& A, bool is_c,
+                                                  typename KeyOf<R>::T key, uint32_t idx,
+                                                  R m0, R ux, R uy) {
+  const unsigned long long mask = __ballot(is_c);
+  if (!mask) return;
+  SelState* st = A.sel;
+  const int lane = __lane_id();
+  const int leader = __ffsll((long long)mask) - 1;
+  unsigned long long kmax = (is_c && (unsigned long long)key < KeyInf<R>::v) ? (unsigned long long)key : 0ull;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(kmax, off);
+    kmax = o > kmax ? o : kmax;
+  }
+  unsigned long long base = ~0ull;
+  if (lane == leader) {
+    // once the buffer has overflowed the step goes to a rescan anyway; stop
+    // contending for the counter
+    const unsigned long long seen = __hip_atomic_load(&st->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (seen <= (unsigned long long)A.cap) {
+      base = atomicAdd(&st->count, (unsigned long long)__popcll(mask));
+      if (kmax) atomicMax(&st->max_key, kmax);
+    }
+  }
+  base = __shfl(base, leader);
+  if (is_c && base != ~0ull) {
+    const unsigned long long pos = base + (unsigned long long)__popcll(mask & ((1ull << lane) - 1ull));
+    if (pos < (unsigned long long)A.cap) {
+      A.cand_key[pos] = key;
+      A.cand_idx[pos] = idx;
+      A.cand_mom[pos] = m0;
+      A.cand_mom[A.cap + pos] = ux;
+      A.cand_mom[2 * A.cap + pos] = uy;
+      atomicAdd(&A.hist[bucket_of<R>((unsigned long long)key, st->base_key, st->shift)], 1u);
+    }
+  }
 }
 
 template <class S, int Q>

@@ -125,34 +125,7 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<typename StoreT<S>:
     using K = typename KeyOf<R>::T;
     const K key = key_of<R>(dS);
     const bool is_c = valid && (dS > A.ehr_delta) && (key >= (K)A.sel->floor_key);
-    const unsigned long long mask = __ballot(is_c);
-    if (mask) {
-      const int lane = __lane_id();
-      const int leader = __ffsll((long long)mask) - 1;
-      unsigned long long kmax = is_c ? (unsigned long long)key : 0ull;
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const unsigned long long o = __shfl_xor(kmax, off);
-        kmax = o > kmax ? o : kmax;
-      }
-      unsigned long long base = 0;
-      if (lane == leader) {
-        base = atomicAdd(&A.sel->count, (unsigned long long)__popcll(mask));
-        atomicMax(&A.sel->max_key, kmax);
-      }
-      base = __shfl(base, leader);
-      if (is_c) {
-        const unsigned long long pos =
-            base + (unsigned long long)__popcll(mask & ((1ull << lane) - 1ull));
-        if (pos < (unsigned long long)A.cap) {
-          A.cand_key[pos] = key;
-          A.cand_idx[pos] = (uint32_t)(y * A.nx + x);
-          A.cand_mom[pos] = m0;
-          A.cand_mom[A.cap + pos] = ux;
-          A.cand_mom[2 * A.cap + pos] = uy;
-        }
-      }
-    }
+    append_candidates<R>(A, is_c, key, (uint32_t)(y * A.nx + x), m0, ux, uy);
   }
 
   R post[Q];

@@ -32,8 +32,8 @@ LBM_F64, LBM_F32, LBM_F16S, LBM_BF16S = 0, 1, 2, 3
 EXPORTED = [
     "lbm_config_default", "lbm_workspace_bytes", "lbm_init", "lbm_set_equilibrium",
     "lbm_set_populations", "lbm_get_populations", "lbm_set_omega", "lbm_step",
-    "lbm_moments", "lbm_backward", "lbm_stats_get", "lbm_selected", "lbm_destroy",
-    "lbm_last_error",
+    "lbm_moments", "lbm_backward", "lbm_stats_get", "lbm_selected", "lbm_counters",
+    "lbm_profile_step", "lbm_destroy", "lbm_last_error",
 ]
 
 
@@ -62,7 +62,8 @@ class lbm_stats(ctypes.Structure):
         ("entropy", ctypes.c_double), ("min_rho", ctypes.c_double),
         ("steps", ctypes.c_longlong), ("diverged_step", ctypes.c_longlong),
         ("n_selected", ctypes.c_longlong), ("select_fallbacks", ctypes.c_longlong),
-        ("select_overflow", ctypes.c_longlong), ("nonfinite", ctypes.c_int),
+        ("select_overflow", ctypes.c_longlong), ("select_candidates", ctypes.c_longlong),
+        ("nonfinite", ctypes.c_int),
     ]
 
 
@@ -93,6 +94,7 @@ def library() -> ctypes.CDLL:
         "lbm_stats_get": (I, [P, ctypes.POINTER(lbm_stats)]),
         "lbm_selected": (I, [P, ctypes.POINTER(LL), LL, ctypes.POINTER(LL)]),
         "lbm_counters": (I, [P, ctypes.POINTER(ctypes.c_ulonglong), I]),
+        "lbm_profile_step": (I, [P, LL, ctypes.POINTER(ctypes.c_double)]),
         "lbm_destroy": (None, [P]),
         "lbm_last_error": (ctypes.c_char_p, []),
     }
@@ -208,6 +210,13 @@ def lbm_counters(ctx, n: int = 8):
     return list(arr)
 
 
+def lbm_profile_step(ctx, n: int):
+    """(ms in the fused step kernels, ms for the n steps) via HIP events."""
+    out = (ctypes.c_double * 2)()
+    _check(library().lbm_profile_step(ctx, int(n), out), "lbm_profile_step")
+    return out[0], out[1]
+
+
 def lbm_destroy(ctx):
     library().lbm_destroy(ctx)
 
@@ -313,6 +322,9 @@ class Simulation:
 
     def counters(self):
         return lbm_counters(self.ctx)
+
+    def profile_step(self, n: int):
+        return lbm_profile_step(self.ctx, n)
 
     def backward(self, dL_dfT, dL_df0, dL_domega=None):
         lbm_backward(self.ctx, dL_dfT, dL_df0, dL_domega)
