@@ -99,7 +99,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--forms", default="f64,f16s,bf16s")
     ap.add_argument("--form-steps", type=int, default=300)
@@ -120,7 +120,7 @@ def main():
         f"= {main_res['kernel_gbs']:.0f} GB/s")
     forms = {args.storage: main_res}
     for s in [x for x in args.forms.split(",") if x and x != args.storage]:
-        r = run_form(w, s, args.form_steps, 20)
+        r = run_form(w, s, args.form_steps, 100)
         forms[s] = r
         log(f"[bench] {s}: {r['mlups']:.0f} MLUPS, kernel {r['kernel_gbs']:.0f} GB/s")
     cpu = None

@@ -58,7 +58,7 @@ typedef enum {
   LBM_EDIVERGED = -4,     /* a check found a non-finite value or rho <= 0   */
   LBM_ESTATE = -5,        /* call out of order (e.g. backward w/o forward)  */
   LBM_EUNSUPPORTED = -6,  /* valid but not implemented combination          */
-  LBM_ESELECT = -7        /* Ehrenfest candidate buffer overflowed          */
+  LBM_ESELECT = -7        /* Ehrenfest selection could not be resolved exactly */
 } lbm_status;
 
 enum { LBM_D1Q3 = 1, LBM_D2Q9 = 2 };
@@ -105,7 +105,6 @@ typedef struct lbm_config {
   int checkpoint_every;   /* K > 0: record a rollout for lbm_backward           */
   long long max_steps;    /* longest rollout lbm_backward must cover            */
   int check_interval;     /* steps between divergence checks (0: only on lbm_stats) */
-  long long select_capacity; /* Ehrenfest candidate buffer entries (0: automatic) */
 } lbm_config;
 
 typedef struct lbm_stats {
@@ -117,7 +116,7 @@ typedef struct lbm_stats {
   long long diverged_step;/* first step at which a check failed, or -1          */
   long long n_selected;   /* Ehrenfest sites chosen in the last step            */
   long long select_fallbacks; /* steps whose selection needed a full rescan     */
-  long long select_overflow;  /* steps whose candidate buffer overflowed        */
+  long long select_overflow;  /* steps whose boundary list overflowed          */
   long long select_candidates;/* Ehrenfest candidates examined, all steps      */
   int nonfinite;          /* 1 if the last check found NaN or Inf               */
 } lbm_stats;

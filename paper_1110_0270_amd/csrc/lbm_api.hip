@@ -39,7 +39,8 @@ struct Layout {
   size_t lat_bytes = 0;
   size_t off_lat[2] = {0, 0}, off_omega = 0, off_sel = 0, off_cnt = 0, off_partial = 0,
          off_stats = 0, off_div = 0, off_ckey = 0, off_cidx = 0, off_cmom = 0, off_hist = 0,
-         off_coarse = 0, off_blist = 0, off_selected = 0;
+         off_coarse = 0, off_wcount = 0, off_ccount = 0, off_stage = 0, off_blist = 0,
+         off_selected = 0;
   AdjointLayout adj;
   size_t total = 0;
 };
@@ -86,18 +87,20 @@ Layout make_layout(const lbm_config* c) {
   L.off_div = take(sizeof(long long));
   if (c->limiters & LBM_LIM_EHRENFEST) {
     L.k = c->ehr_k < L.n_sites ? c->ehr_k : L.n_sites;
-    long long cap = c->select_capacity;
-    if (cap <= 0) {
-      cap = L.n_sites <= (1ll << 20) ? L.n_sites : std::max(4 * L.k, 1ll << 20);
-    }
-    if (cap > L.n_sites) cap = L.n_sites;
-    L.cap = cap;
-    L.off_ckey = take((size_t)cap * rb);
-    L.off_cidx = take((size_t)cap * 4);
-    L.off_cmom = take((size_t)cap * 3 * rb);
+    // every wavefront of the step kernel owns 64 candidate entries
+    const TileShape ts = tile_shape(L.Q, (c->limiters & LBM_LIM_MEDIAN) != 0, c->nx);
+    const long long tiles = (long long)((c->nx + ts.tx - 1) / ts.tx) * ((c->ny + ts.ty - 1) / ts.ty);
+    L.cap = tiles * 256;
+    L.off_ckey = take((size_t)L.cap * rb);
+    L.off_cidx = take((size_t)L.cap * 4);
+    L.off_cmom = take((size_t)L.cap * 3 * rb);
+    L.off_wcount = take((size_t)tiles * 4 * 4);
     L.off_hist = take(kBuckets * 4);
     L.off_coarse = take(kCoarse * 4);
-    L.bcap = std::min<long long>(cap, 1ll << 20);
+    L.off_ccount = take((size_t)kCountSlots * kCountStride * 8);
+    // 256 regions x 64 entries per k_fix_regions workgroup
+    L.off_stage = take((size_t)((tiles * 4 + 255) / 256) * 256 * 64 * 4);
+    L.bcap = std::min<long long>(L.cap, 1ll << 20);
     L.off_blist = take((size_t)L.bcap * 4);
     L.off_selected = take((size_t)std::max<long long>(L.k, 1) * 4);
   }
@@ -151,6 +154,7 @@ void fill_args(StepArgs<R>& A, const lbm_config* c, const Layout& L, char* ws) {
   const TileShape ts = tile_shape(L.Q, (c->limiters & LBM_LIM_MEDIAN) != 0, c->nx);
   A.tiles_x = (c->nx + ts.tx - 1) / ts.tx;
   A.tiles_y = (c->ny + ts.ty - 1) / ts.ty;
+  A.tile_tx = ts.tx;
   A.bc = c->bc;
   A.eq_kind = c->collision == LBM_ELBM ? LBM_EQ_ENTROPIC : c->equilibrium;
   A.positivity = (c->limiters & LBM_LIM_POSITIVITY) ? 1 : 0;
@@ -204,6 +208,8 @@ void fill_args(StepArgs<R>& A, const lbm_config* c, const Layout& L, char* ws) {
     A.cand_idx = (uint32_t*)(ws + L.off_cidx);
     A.cand_mom = (R*)(ws + L.off_cmom);
     A.cap = L.cap;
+    A.wcount = (uint32_t*)(ws + L.off_wcount);
+    A.ccount = (unsigned long long*)(ws + L.off_ccount);
     A.hist = (unsigned int*)(ws + L.off_hist);
   }
 }
@@ -223,6 +229,8 @@ struct lbm_ctx {
   void* lat(int i) { return ws + L.off_lat[i]; }
   bool f64() const { return cfg.storage == LBM_F64; }
 };
+
+static SelectArgs select_args(lbm_ctx* c, const void* args);
 
 extern "C" {
 
@@ -272,6 +280,8 @@ lbm_status lbm_init(const lbm_config* cfg, void* ws, size_t ws_bytes, void* stre
   if (e == hipSuccess && (cfg->limiters & LBM_LIM_EHRENFEST)) {
     e = hipMemsetAsync(c->ws + L.off_hist, 0, kBuckets * 4, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.off_coarse, 0, kCoarse * 4, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.off_wcount, 0, (size_t)(L.cap / 64) * 4, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.off_ccount, 0, (size_t)kCountSlots * kCountStride * 8, c->stream);
   }
   if (e != hipSuccess) { delete c; return hip_fail(e, "lbm_init"); }
   *out = c;
@@ -283,6 +293,14 @@ static lbm_status reset_rollout(lbm_ctx* c) {
   c->recorded = false;
   hipError_t e = hipMemsetAsync(c->ws + c->L.off_div, 0xff, sizeof(long long), c->stream);
   if (e != hipSuccess) return hip_fail(e, "reset");
+  if (c->cfg.limiters & LBM_LIM_EHRENFEST) {
+    const void* args;
+    if (c->f64()) { c->a64.src = c->lat(c->cur); c->a64.dst = c->lat(1 - c->cur); args = &c->a64; }
+    else { c->a32.src = c->lat(c->cur); c->a32.dst = c->lat(1 - c->cur); args = &c->a32; }
+    SelectArgs sa = select_args(c, args);
+    e = launch_select_calibrate(sa, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "selection calibration");
+  }
   if (c->cfg.checkpoint_every > 0) {
     e = adjoint_begin_record(c->L.adj, c->ws, c->lat(c->cur), c->L.lat_bytes, c->stream);
     if (e != hipSuccess) return hip_fail(e, "checkpoint");
@@ -351,29 +369,31 @@ static hipError_t one_step(lbm_ctx* c, hipEvent_t ev0 = nullptr, hipEvent_t ev1 
   const void* args;
   if (c->f64()) { c->a64.src = c->lat(src); c->a64.dst = c->lat(dst); args = &c->a64; }
   else { c->a32.src = c->lat(src); c->a32.dst = c->lat(dst); args = &c->a32; }
-  hipError_t e = hipSuccess;
-  if (ev0) e = hipEventRecord(ev0, c->stream);
-  if (e != hipSuccess) return e;
-  e = launch_step(c->cfg.storage, c->L.Q, c->cfg.collision, med, args, c->stream);
-  if (e != hipSuccess) return e;
-  if (ev1) e = hipEventRecord(ev1, c->stream);
+  hipError_t e = launch_step(c->cfg.storage, c->L.Q, c->cfg.collision, med, args, c->stream,
+                             ev0, ev1);
   if (e != hipSuccess) return e;
   if (c->cfg.limiters & LBM_LIM_EHRENFEST) {
-    SelectArgs sa;
-    sa.storage = c->cfg.storage; sa.Q = c->L.Q; sa.coll = c->cfg.collision; sa.step_args = args;
-    sa.k = c->L.k; sa.n_sites = c->L.n_sites;
-    sa.selected = adjoint_selected_slot(c->L.adj, c->ws, c->steps,
-                                        (int32_t*)(c->ws + c->L.off_selected));
-    sa.blist = (uint32_t*)(c->ws + c->L.off_blist);
-    sa.bcap = c->L.bcap;
-    sa.coarse = (unsigned int*)(c->ws + c->L.off_coarse);
-    sa.n_sel_out = adjoint_count_slot(c->L.adj, c->ws, c->steps);
+    SelectArgs sa = select_args(c, args);
     e = launch_select(sa, c->stream);
     if (e != hipSuccess) return e;
   }
   c->cur = dst;
   c->steps += 1;
   return hipSuccess;
+}
+
+static SelectArgs select_args(lbm_ctx* c, const void* args) {
+    SelectArgs sa;
+    sa.storage = c->cfg.storage; sa.Q = c->L.Q; sa.coll = c->cfg.collision; sa.step_args = args;
+    sa.k = c->L.k; sa.n_sites = c->L.n_sites;
+    sa.selected = adjoint_selected_slot(c->L.adj, c->ws, c->steps,
+                                        (int32_t*)(c->ws + c->L.off_selected));
+    sa.segsel = (int32_t*)(c->ws + c->L.off_stage);
+    sa.blist = (uint32_t*)(c->ws + c->L.off_blist);
+    sa.bcap = c->L.bcap;
+    sa.coarse = (unsigned int*)(c->ws + c->L.off_coarse);
+    sa.n_sel_out = adjoint_count_slot(c->L.adj, c->ws, c->steps);
+    return sa;
 }
 
 static lbm_status run_steps(lbm_ctx* c, long long n, hipEvent_t* ev) {
@@ -481,7 +501,7 @@ lbm_status lbm_stats_get(lbm_ctx* c, lbm_stats* out) {
   out->select_overflow = (long long)sel.overflows;
   out->select_candidates = (long long)sel.cand_total;
   if (div >= 0) return fail(LBM_EDIVERGED, "non-finite value or rho <= 0 found at step " + std::to_string(div));
-  if (sel.overflows) return fail(LBM_ESELECT, "Ehrenfest candidate buffer overflowed; raise select_capacity");
+  if (sel.overflows) return fail(LBM_ESELECT, "Ehrenfest boundary list overflowed: more than 2^20 sites tie within one histogram bucket");
   return LBM_OK;
 }
 

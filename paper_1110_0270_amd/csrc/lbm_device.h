@@ -125,9 +125,10 @@ __device__ __forceinline__ double h_fn<double>(double x) {
 template <>
 __device__ __forceinline__ float h_fn<float>(float x) {
   if (fabsf(x) < 0.1f) {
+    // terms up to x^8: truncation below 4e-8 of the leading term
     float acc = 0.0f;
 #pragma unroll
-    for (int n = 9; n >= 3; --n) {
+    for (int n = 8; n >= 3; --n) {
       float c = ((n & 1) ? -1.0f : 1.0f) / (float)(n * (n - 1));
       acc = (acc + c) * x;
     }
@@ -136,6 +137,10 @@ __device__ __forceinline__ float h_fn<float>(float x) {
   if (x <= -1.0f) return 1.0f;
   return (1.0f + x) * log1pf(x) - x;
 }
+
+template <class R> __device__ __forceinline__ R rcp(R x);
+template <> __device__ __forceinline__ double rcp<double>(double x) { return 1.0 / x; }
+template <> __device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
 template <class R> __device__ __forceinline__ R lg1p(R x);
 template <> __device__ __forceinline__ double lg1p<double>(double x) { return log1p(x); }

@@ -10,14 +10,13 @@ namespace lbm {
 // Device-resident state of the Ehrenfest top-k selection (section 4,
 // Ehrenfests' regularisation with a budget of k sites per step).
 struct SelState {
-  unsigned long long count;      // candidates appended this step
-  unsigned long long max_key;    // largest finite candidate key this step
   unsigned long long floor_key;  // a site is a candidate iff eligible and key >= floor_key
+  unsigned long long floor_prev; // floor suggested by the previous step (0: none)
   unsigned long long base_key;   // histogram frame: bucket = (key - base_key) >> shift
   unsigned long long bcount;     // length of the boundary-bucket list
   unsigned long long sel_acc;    // sites selected so far in the running step
   unsigned long long fallbacks;  // steps that needed a full rescan (cumulative)
-  unsigned long long overflows;  // steps whose buffers overflowed (cumulative)
+  unsigned long long overflows;  // steps whose boundary list overflowed (cumulative)
   unsigned long long cand_total; // candidates over all steps (cumulative)
   long long n_sel;               // sites selected in the last completed step
   unsigned int shift;            // bucket width is 2^shift keys
@@ -30,6 +29,8 @@ struct SelState {
 
 constexpr int kBuckets = 4096;        // histogram of candidate keys
 constexpr int kCoarse = 4096;         // rescan histogram: top 12 bits of the FP32 key
+constexpr int kCountSlots = 64;       // candidate counters, 128 bytes apart
+constexpr int kCountStride = 16;      // in unsigned long long
 
 // Counters of limiter activity (cumulative since the last reset).
 enum Counter : int {
@@ -48,6 +49,7 @@ struct StepArgs {
   long long qs;          // elements between populations = ny * pitch
   int nx, ny, pitch;
   int tiles_x, tiles_y;
+  int tile_tx;           // sites per tile row (256 or 64); tiles hold 256 sites
   int bc;
   int eq_kind;
   int positivity;
@@ -72,18 +74,23 @@ struct StepArgs {
   // Ehrenfest
   R ehr_delta;
   SelState* sel;
+  // Candidate buffer: wavefront w of tile t owns entries [64 (4t + w), +64);
+  // wcount[4t + w] holds how many it filled this step (0 where none).
   typename KeyOf<R>::T* cand_key;
   uint32_t* cand_idx;
   R* cand_mom;           // [3][cap]: rho (or rho - rho0 when shifted), ux, uy
-  long long cap;
+  long long cap;         // 256 * number of tiles
+  uint32_t* wcount;
+  unsigned long long* ccount;  // kCountSlots partial candidate counts (spread atomics)
   unsigned int* hist;    // kBuckets counts of this step's candidates
   unsigned long long* counters;
 };
 
 // Launchers (one per translation unit); return hipSuccess or the error.
 // storage: 0 f64, 1 f32, 2 f16 shifted, 3 bf16 shifted.
+// e0/e1 (optional): events recorded at the step kernel's start and end.
 hipError_t launch_step(int storage, int Q, int coll, bool median, const void* args,
-                       hipStream_t s);
+                       hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_set_eq(int storage, int Q, const void* rho, const void* ux,
                          const void* uy, int in_f64, void* lat, long long qs, int nx,
                          int ny, int pitch, int eq_kind, double rho0, hipStream_t s);
@@ -111,12 +118,17 @@ struct SelectArgs {
   long long k;
   long long n_sites;
   int32_t* selected;       // out: selected site indices, ascending not guaranteed
-  uint32_t* blist;         // boundary-bucket list (positions in the candidate buffer)
-  long long bcap;          // its capacity
+  int32_t* segsel;         // per-workgroup staging of selected indices (cap entries)
+  uint32_t* blist;         // boundary-bucket candidate positions
+  long long bcap;          // capacity of blist
   unsigned int* coarse;    // kCoarse
   long long* n_sel_out;    // optional: the step's selection count is copied here
 };
 hipError_t launch_select(const SelectArgs& a, hipStream_t s);
+// Place the first candidate floor of a freshly set lattice at the 3k-th
+// largest Delta S of its next step (one rescan).
+hipError_t launch_select_calibrate(const SelectArgs& a, hipStream_t s);
 void init_select_state(SelState* h, int f64);
+
 
 }  // namespace lbm

@@ -114,20 +114,56 @@ __device__ __forceinline__ unsigned int frame_shift(unsigned long long base, uns
   return sh;
 }
 
-template <class R>
-__device__ __forceinline__ bool need_rescan(const SelState* st, long long k, long long cap) {
-  const unsigned long long n = st->count;
-  return n > (unsigned long long)cap || ((long long)n < k && st->floor_raised);
+// Sum of an LDS histogram h[0..NB) over the block.
+template <int NB>
+__device__ unsigned long long block_sum(const unsigned int* h) {
+  __shared__ unsigned long long red[1024];
+  unsigned long long s = 0;
+  for (int i = threadIdx.x; i < NB; i += blockDim.x) s += h[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  const unsigned long long r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// The rescan is needed when the floor was raised and fewer than k sites
+// reached it.
+__device__ __forceinline__ bool need_rescan(unsigned long long nc, long long k, const SelState* st) {
+  return (long long)nc < k && st->floor_raised;
+}
+
+// Site of lane `lane` of wavefront w in logical tile t (the step kernel's
+// layout).
+__device__ __forceinline__ void tile_site(int t, int w, int lane, int tiles_x, int tx, int& x, int& y) {
+  const int tid = w * 64 + lane;
+  x = (t % tiles_x) * tx + tid % tx;
+  y = (t / tiles_x) * (256 / tx) + tid / tx;
 }
 
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long candidate_count(const unsigned long long* cc) {
+  unsigned long long n = 0;
+  for (int i = 0; i < kCountSlots; ++i) n += ld_rlx(&cc[i * kCountStride]);
+  return n;
+}
+
+// calibrate = 0: the step's fallback; 1: first floor of a freshly set lattice.
 template <class S, int Q>
 __global__ __launch_bounds__(256) void k_fb_scan(const StepArgs<typename StoreT<S>::R> A,
-                                                 long long k, unsigned int* coarse) {
+                                                 long long k, unsigned int* coarse,
+                                                 int calibrate) {
   using R = typename StoreT<S>::R;
   SelState* st = A.sel;
-  if (!need_rescan<R>(st, k, A.cap)) return;
   __shared__ unsigned int h[kCoarse];
+  __shared__ unsigned long long s_nc;
+  if (threadIdx.x == 0) s_nc = candidate_count(A.ccount);
+  __syncthreads();
+  if (!calibrate && !need_rescan(s_nc, k, st)) return;
   for (int i = threadIdx.x; i < kCoarse; i += blockDim.x) h[i] = 0;
   __syncthreads();
   const long long n = (long long)A.nx * A.ny;
@@ -148,8 +184,9 @@ __global__ __launch_bounds__(256) void k_fb_scan(const StepArgs<typename StoreT<
   __syncthreads();
   int b;
   unsigned long long above;
-  find_from_top<kCoarse>(h, (unsigned long long)(k > 0 ? k : 1), &b, &above);
-  if (b < 0) b = 0;                                   // fewer than k eligible: take all
+  const unsigned long long want = calibrate ? 3ull * (unsigned long long)k : (unsigned long long)k;
+  find_from_top<kCoarse>(h, want > 0 ? want : 1ull, &b, &above);
+  if (b < 0) b = 0;                                   // fewer eligible sites: take all
   __shared__ int top;
   if (threadIdx.x == 0) top = 0;
   __syncthreads();
@@ -157,45 +194,67 @@ __global__ __launch_bounds__(256) void k_fb_scan(const StepArgs<typename StoreT<
     if (h[i]) atomicMax(&top, i);
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned long long total = 0;
-    for (int i = b; i < kCoarse; ++i) total += h[i];
-    st->fb_bin = b;
-    st->fallback = 1;
-    st->fallbacks += 1;
-    if (total > (unsigned long long)A.cap) st->overflows += 1;
-    st->count = 0;
-    st->max_key = 0;
-    st->base_key = coarse_edge_key<R>(b);
+    const unsigned long long edge = coarse_edge_key<R>(b);
+    if (calibrate) {
+      const unsigned long long dk = delta_key<R>(A.ehr_delta);
+      const unsigned long long f = edge > dk ? edge : dk;
+      st->floor_key = f;
+      st->floor_prev = 0;
+      st->floor_raised = f > dk ? 1 : 0;
+      st->fallback = 0;
+      st->base_key = f;
+    } else {
+      st->fb_bin = b;
+      st->fallback = 1;
+      st->fallbacks += 1;
+      st->base_key = edge;
+    }
     st->shift = frame_shift(st->base_key, coarse_edge_key<R>(top + 1));
     st->ticket = 0;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < kCoarse; i += blockDim.x) coarse[i] = 0;
   for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) A.hist[i] = 0;
+  for (int i = threadIdx.x; i < kCountSlots; i += blockDim.x) A.ccount[i * kCountStride] = 0;
 }
 
+// Rescan append, in the step kernel's tile layout so that every wavefront
+// region is rewritten (stale counts of the step kernel included).
 template <class S, int Q>
 __global__ __launch_bounds__(256) void k_fb_append(const StepArgs<typename StoreT<S>::R> A) {
   using R = typename StoreT<S>::R;
   SelState* st = A.sel;
   if (!st->fallback) return;
   const unsigned int fb = (unsigned int)st->fb_bin;
-  const long long n = (long long)A.nx * A.ny;
-  const long long nthreads = (long long)gridDim.x * blockDim.x;
-  const long long iters = (n + nthreads - 1) / nthreads;
-  for (long long it = 0; it < iters; ++it) {
-    const long long s = it * nthreads + (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int T = A.tiles_x * A.tiles_y;
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  for (int t = blockIdx.x; t < T; t += gridDim.x) {
+    int x, y;
+    tile_site(t, w, lane, A.tiles_x, A.tile_tx, x, y);
+    const bool valid = x < A.nx && y < A.ny;
     bool is_c = false;
     R dS = R(0), m0 = R(0), ux = R(0), uy = R(0);
-    int x = 0, y = 0;
-    if (s < n) {
-      y = (int)(s / A.nx);
-      x = (int)(s % A.nx);
+    if (valid) {
       R v[Q], feq[Q], d[Q];
       dS = site_prep<S, Q>(A, x, y, v, feq, d, m0, ux, uy, true);
       is_c = (dS > A.ehr_delta) && coarse_bin((float)dS) >= fb;
     }
-    append_candidates<R>(A, is_c, key_of<R>(dS), (uint32_t)(y * A.nx + x), m0, ux, uy);
+    const long long region = (long long)t * 4 + w;
+    const unsigned long long mask = __ballot(is_c);
+    if (lane == 0) {
+      A.wcount[region] = (uint32_t)__popcll(mask);
+      if (mask)
+        atomicAdd(&A.ccount[(region & (kCountSlots - 1)) * kCountStride], (unsigned long long)__popcll(mask));
+    }
+    if (is_c) {
+      const long long pos = region * 64 + __popcll(mask & ((1ull << lane) - 1ull));
+      A.cand_key[pos] = key_of<R>(dS);
+      A.cand_idx[pos] = (uint32_t)(y * A.nx + x);
+      A.cand_mom[pos] = m0;
+      A.cand_mom[A.cap + pos] = ux;
+      A.cand_mom[2 * A.cap + pos] = uy;
+      atomicAdd(&A.hist[bucket_of<R>((unsigned long long)key_of<R>(dS), st->base_key, st->shift)], 1u);
+    }
   }
 }
 
@@ -214,33 +273,38 @@ __device__ __forceinline__ void write_feq(const StepArgs<typename StoreT<S>::R>&
     StoreT<S>::st(dst + (long long)i * A.qs + (long long)y * A.pitch + x, feq[i]);
 }
 
-// Wave-aggregated reservation of one slot per set lane.
-__device__ __forceinline__ unsigned long long wave_slot(bool on, unsigned long long* ctr) {
+// Wave-aggregated reservation of one slot per set lane on an LDS counter.
+__device__ __forceinline__ unsigned int lds_slot(bool on, unsigned int* ctr) {
   const unsigned long long mask = __ballot(on);
   if (!mask) return 0;
   const int lane = __lane_id();
   const int leader = __ffsll((long long)mask) - 1;
-  unsigned long long base = 0;
-  if (lane == leader) base = atomicAdd(ctr, (unsigned long long)__popcll(mask));
+  unsigned int base = 0;
+  if (lane == leader) base = atomicAdd(ctr, (unsigned int)__popcll(mask));
   base = __shfl(base, leader);
-  return base + (unsigned long long)__popcll(mask & ((1ull << lane) - 1ull));
+  return base + (unsigned int)__popcll(mask & ((1ull << lane) - 1ull));
 }
 
+// Selection: k_fix_regions sends every candidate above the boundary bucket to
+// equilibrium and lists the boundary bucket; k_fix_tail (one workgroup)
+// resolves the boundary bucket exactly and prepares the next step.
 template <class S, int Q>
-__global__ __launch_bounds__(1024) void k_fix(const StepArgs<typename StoreT<S>::R> A,
-                                              long long k, long long n_sites, int32_t* selected,
-                                              uint32_t* blist, long long bcap,
-                                              long long* n_sel_out) {
+__global__ __launch_bounds__(256) void k_fix_regions(const StepArgs<typename StoreT<S>::R> A,
+                                                     long long k, int32_t* selected,
+                                                     int32_t* stage, uint32_t* blist,
+                                                     long long bcap) {
   using R = typename StoreT<S>::R;
   SelState* st = A.sel;
   __shared__ unsigned int h[kBuckets];
-  const unsigned long long nc_all = st->count;
-  const long long nc = (long long)(nc_all < (unsigned long long)A.cap ? nc_all : A.cap);
+  __shared__ unsigned int s_sel, s_bnd;
+  __shared__ unsigned long long s_nc, s_base_sel, s_base_bnd;
   const unsigned long long base = st->base_key;
   const unsigned int shift = st->shift;
-  const long long need = k < nc ? k : nc;
   for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) h[i] = ld_rlx(&A.hist[i]);
+  if (threadIdx.x == 0) { s_sel = 0; s_bnd = 0; s_nc = candidate_count(A.ccount); }
   __syncthreads();
+  const long long nc = (long long)s_nc;
+  const long long need = k < nc ? k : nc;
   int boundary;
   unsigned long long above;
   if (k <= 0) {
@@ -253,42 +317,94 @@ __global__ __launch_bounds__(1024) void k_fix(const StepArgs<typename StoreT<S>:
     find_from_top<kBuckets>(h, (unsigned long long)need, &boundary, &above);
     if (boundary < 0) boundary = -1;
   }
-  const long long take = (boundary >= 0 && boundary < kBuckets) ? need - (long long)above : 0;
-
-  const long long nthreads = (long long)gridDim.x * blockDim.x;
-  const long long iters = (nc + nthreads - 1) / nthreads;
-  for (long long it = 0; it < iters; ++it) {
-    const long long p = it * nthreads + (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  // 64 regions per wavefront, spread over the whole lattice with a stride of
+  // the wavefront count (candidates crowd into whole rows of a shear layer;
+  // a contiguous assignment would hand one wavefront an entire dense row).
+  // One read of the 64 counts, then the non-empty regions in turn with one
+  // lane per entry.
+  const long long nreg = (long long)A.tiles_x * A.tiles_y * 4;
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const long long g = (long long)blockIdx.x * 4 + w, nwave = (long long)gridDim.x * 4;
+  const long long my_r = (long long)lane * nwave + g;
+  int32_t* my_stage = stage + (long long)blockIdx.x * 256 * 64;
+  uint32_t cnt = 0;
+  if (my_r < nreg) cnt = A.wcount[my_r];
+  unsigned long long nz = __ballot(cnt != 0);
+  while (nz) {
+    const int j = __ffsll((long long)nz) - 1;
+    nz &= nz - 1;
+    const uint32_t c = __shfl(cnt, j);
+    const long long rj = __shfl(my_r, j);
+    const long long p = rj * 64 + lane;
     bool sel = false, bnd = false;
-    if (p < nc) {
+    if ((uint32_t)lane < c) {
       const int b = bucket_of<R>((unsigned long long)A.cand_key[p], base, shift);
       sel = boundary < 0 || b > boundary;
       bnd = b == boundary;
     }
     if (sel) write_feq<S, Q>(A, p);
-    const unsigned long long slot = wave_slot(sel, &st->sel_acc);
-    if (sel && slot < (unsigned long long)k) selected[slot] = (int32_t)A.cand_idx[p];
-    const unsigned long long q = wave_slot(bnd, &st->bcount);
-    if (bnd && q < (unsigned long long)bcap) blist[q] = (uint32_t)p;
+    const unsigned int slot = lds_slot(sel, &s_sel);
+    if (sel) my_stage[slot] = (int32_t)A.cand_idx[p];
+    const unsigned int q = lds_slot(bnd, &s_bnd);
+    if (bnd) my_stage[256 * 64 - 1 - q] = (int32_t)p;   // boundary entries fill from the end
   }
-  if (!last_block(&st->ticket)) return;
+  if (cnt) A.wcount[my_r] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s_base_sel = s_sel ? atomicAdd(&st->sel_acc, (unsigned long long)s_sel) : 0ull;
+    s_base_bnd = s_bnd ? atomicAdd(&st->bcount, (unsigned long long)s_bnd) : 0ull;
+  }
+  __syncthreads();
+  for (unsigned int i = threadIdx.x; i < s_sel; i += blockDim.x)
+    if ((long long)(s_base_sel + i) < k) selected[s_base_sel + i] = my_stage[i];
+  for (unsigned int i = threadIdx.x; i < s_bnd; i += blockDim.x)
+    if ((long long)(s_base_bnd + i) < bcap) blist[s_base_bnd + i] = (uint32_t)my_stage[256 * 64 - 1 - i];
+}
 
-  // --- boundary bucket: the `take` largest by (key desc, index asc) --------
+template <class S, int Q>
+__global__ __launch_bounds__(1024) void k_fix_tail(const StepArgs<typename StoreT<S>::R> A,
+                                                   long long k, long long n_sites,
+                                                   int32_t* selected, uint32_t* blist,
+                                                   long long bcap, long long* n_sel_out) {
+  using R = typename StoreT<S>::R;
+  SelState* st = A.sel;
+  __shared__ unsigned int h[kBuckets];
   __shared__ unsigned int dh[256];
-  __shared__ unsigned long long s_off_pref;
+  __shared__ unsigned long long s_off_pref, s_nc;
   __shared__ uint32_t s_idx_pref;
+  __shared__ unsigned int s_tot;
+  const unsigned long long base = st->base_key;
+  const unsigned int shift = st->shift;
+  for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) h[i] = ld_rlx(&A.hist[i]);
+  if (threadIdx.x == 0) {
+    s_nc = candidate_count(A.ccount);
+    s_tot = (unsigned int)ld_rlx(&st->sel_acc);
+  }
+  __syncthreads();
+  const long long nc = (long long)s_nc;
+  const long long need = k < nc ? k : nc;
+  int boundary = -1;
+  unsigned long long above = 0;
+  if (k > 0 && nc > k) {
+    find_from_top<kBuckets>(h, (unsigned long long)need, &boundary, &above);
+  }
+  const long long take = (boundary >= 0 && k > 0 && nc > k) ? need - (long long)above : 0;
   const long long m_all = (long long)ld_rlx(&st->bcount);
   const long long m = m_all < bcap ? m_all : bcap;
   if (take > 0 && m > 0) {
-    // keys of the bucket differ only in their offset from the bucket's lower
-    // edge: `shift` bits, or all bits in the open-ended top bucket
+    // keys of the bucket differ only in their offset from its lower edge:
+    // `shift` bits, or all bits in the open-ended top bucket
     const unsigned long long edge = base + ((unsigned long long)boundary << shift);
     const int nb = boundary == kBuckets - 1 ? KeyTraits<R>::bits : (int)shift;
     const int kd = (nb + 7) / 8;
     unsigned long long need_left = (unsigned long long)take;
-    if (threadIdx.x == 0) { s_off_pref = 0; s_idx_pref = 0; }
+    __shared__ unsigned int s_last_cnt;
+    if (threadIdx.x == 0) { s_off_pref = 0; s_idx_pref = 0; s_last_cnt = (unsigned int)m; }
     __syncthreads();
     for (int dgt = 0; dgt < kd + 4; ++dgt) {
+      // after the key digits: if every entry sharing the threshold key is
+      // taken, the site-index digits cannot change the set
+      if (dgt == kd && s_last_cnt == need_left) break;
       for (int i = threadIdx.x; i < 256; i += blockDim.x) dh[i] = 0;
       __syncthreads();
       const bool on_key = dgt < kd;
@@ -302,13 +418,13 @@ __global__ __launch_bounds__(1024) void k_fix(const StepArgs<typename StoreT<S>:
         const uint32_t ni = ~A.cand_idx[p];
         bool match;
         unsigned int digit;
-        const int top = sb + 8;
+        const int topb = sb + 8;
         if (on_key) {
-          const unsigned long long hm = top >= 64 ? 0ull : (~0ull << top);
+          const unsigned long long hm = topb >= 64 ? 0ull : (~0ull << topb);
           match = (off & hm) == (op & hm);
           digit = (unsigned int)((off >> sb) & 0xffu);
         } else {
-          const uint32_t hm = top >= 32 ? 0u : (~0u << top);
+          const uint32_t hm = topb >= 32 ? 0u : (~0u << topb);
           match = off == op && (ni & hm) == (ip & hm);
           digit = (ni >> sb) & 0xffu;
         }
@@ -323,6 +439,7 @@ __global__ __launch_bounds__(1024) void k_fix(const StepArgs<typename StoreT<S>:
       if (threadIdx.x == 0) {
         if (on_key) s_off_pref |= ((unsigned long long)dsel) << sb;
         else s_idx_pref |= ((uint32_t)dsel) << sb;
+        s_last_cnt = dh[dsel];
       }
       __syncthreads();
     }
@@ -340,61 +457,102 @@ __global__ __launch_bounds__(1024) void k_fix(const StepArgs<typename StoreT<S>:
         sel = off > to || (off == to && ni >= ti);
       }
       if (sel) write_feq<S, Q>(A, p);
-      const unsigned long long slot = wave_slot(sel, &st->sel_acc);
-      if (sel && slot < (unsigned long long)k) selected[slot] = (int32_t)A.cand_idx[p];
+      const unsigned int slot = lds_slot(sel, &s_tot);
+      if (sel && (long long)slot < k) selected[slot] = (int32_t)A.cand_idx[p];
     }
   }
   __syncthreads();
 
   // --- floor and frame of the next step ------------------------------------
-  // Keep roughly 2k candidates, with hysteresis; the floor is never raised
-  // when the buffer can hold every site.
+  // Keep between 2k and 6k candidates (aim at 3k); the floor is never raised
+  // when k is at least a tenth of the lattice.  The lower of this step's and
+  // the previous step's suggestions is used: with omega near 2 the
+  // nonequilibrium part changes sign every step, and the two parities can
+  // rank different sites.  The frame spans twice the current candidates'
+  // range above the floor.
   const unsigned long long dk = delta_key<R>(A.ehr_delta);
-  unsigned long long fnext = dk;
-  if (A.cap < n_sites && k > 0) {
-    const bool keep = st->floor_raised && !st->fallback && nc >= k + k / 4 && nc <= 4 * k;
+  unsigned long long fnext = dk, fsugg = dk;
+  if (10 * k < n_sites && k > 0) {
+    const bool keep = st->floor_raised && !st->fallback && nc >= 2 * k && nc <= 6 * k;
     if (keep) {
-      fnext = st->floor_key;
+      fsugg = st->floor_key;
     } else {
       int t2;
       unsigned long long a2;
-      find_from_top<kBuckets>(h, 2ull * (unsigned long long)k, &t2, &a2);
-      if (t2 >= 0 && t2 < kBuckets - 1) fnext = base + ((unsigned long long)t2 << shift);
-      else if (t2 < 0) fnext = base > KeyTraits<R>::quarter ? base - KeyTraits<R>::quarter : 0ull;
-      else fnext = st->floor_key;
+      find_from_top<kBuckets>(h, 3ull * (unsigned long long)k, &t2, &a2);
+      if (t2 >= 0 && t2 < kBuckets - 1) fsugg = base + ((unsigned long long)t2 << shift);
+      else if (t2 < 0) fsugg = base > 2 * KeyTraits<R>::quarter ? base - 2 * KeyTraits<R>::quarter : 0ull;
+      else fsugg = st->floor_key;
     }
-    if (fnext < dk) fnext = dk;
+    if (fsugg < dk) fsugg = dk;
+    fnext = (keep || st->floor_prev == 0 || st->floor_prev > fsugg) ? fsugg : st->floor_prev;
   }
+  __shared__ int s_top;
+  if (threadIdx.x == 0) s_top = -1;
+  __syncthreads();
+  for (int i = threadIdx.x; i < kBuckets; i += blockDim.x)
+    if (h[i]) atomicMax(&s_top, i);
+  __syncthreads();
   if (threadIdx.x == 0) {
-    const unsigned long long mx = ld_rlx(&st->max_key);
+    // upper end of this step's keys: the top nonempty bucket's upper edge,
+    // or twice the frame when keys ran past it
+    const unsigned long long span = (unsigned long long)kBuckets << shift;
+    const unsigned long long hi_key = s_top < 0 ? fnext + 1
+        : (s_top < kBuckets - 1 ? base + ((unsigned long long)(s_top + 1) << shift) : base + 2 * span);
     st->floor_key = fnext;
+    st->floor_prev = fsugg;
     st->floor_raised = fnext > dk ? 1 : 0;
     st->base_key = fnext;
-    st->shift = frame_shift(fnext, mx > fnext ? fnext + 2 * (mx - fnext) : fnext + 1);
-    const unsigned long long ns = ld_rlx(&st->sel_acc);
+    st->shift = frame_shift(fnext, hi_key > fnext ? fnext + 2 * (hi_key - fnext) : fnext + 1);
+    const unsigned int ns = s_tot < (unsigned int)k ? s_tot : (unsigned int)k;
     st->n_sel = (long long)ns;
     if (n_sel_out) *n_sel_out = (long long)ns;
     if (m_all > bcap) st->overflows += 1;
     st->cand_total += (unsigned long long)nc;
-    st->count = 0;
-    st->max_key = 0;
-    st->bcount = 0;
-    st->sel_acc = 0;
     st->fallback = 0;
-    st->ticket = 0;
+    st->sel_acc = 0;
+    st->bcount = 0;
   }
   for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) A.hist[i] = 0;
+  for (int i = threadIdx.x; i < kCountSlots; i += blockDim.x) A.ccount[i * kCountStride] = 0;
 }
 
 template <class S, int Q>
 static hipError_t launch_select_t(const SelectArgs& a, hipStream_t s) {
   using R = typename StoreT<S>::R;
   const StepArgs<R>& A = *(const StepArgs<R>*)a.step_args;
-  hipLaunchKernelGGL((k_fb_scan<S, Q>), dim3(1024), dim3(256), 0, s, A, a.k, a.coarse);
+  hipLaunchKernelGGL((k_fb_scan<S, Q>), dim3(1024), dim3(256), 0, s, A, a.k, a.coarse, 0);
   hipLaunchKernelGGL((k_fb_append<S, Q>), dim3(1024), dim3(256), 0, s, A);
-  hipLaunchKernelGGL((k_fix<S, Q>), dim3(64), dim3(1024), 0, s, A, a.k, a.n_sites, a.selected,
-                     a.blist, a.bcap, a.n_sel_out);
+  const long long nreg = (long long)A.tiles_x * A.tiles_y * 4;
+  const int gfix = (int)((nreg + 255) / 256);
+  hipLaunchKernelGGL((k_fix_regions<S, Q>), dim3(gfix), dim3(256), 0, s, A, a.k, a.selected,
+                     a.segsel, a.blist, a.bcap);
+  hipLaunchKernelGGL((k_fix_tail<S, Q>), dim3(1), dim3(1024), 0, s, A, a.k, a.n_sites,
+                     a.selected, a.blist, a.bcap, a.n_sel_out);
   return hipGetLastError();
+}
+
+template <class S, int Q>
+static hipError_t launch_calibrate_t(const SelectArgs& a, hipStream_t s) {
+  using R = typename StoreT<S>::R;
+  const StepArgs<R>& A = *(const StepArgs<R>*)a.step_args;
+  // the floor is only ever raised when k is below a tenth of the lattice
+  if (!(10 * a.k < a.n_sites && a.k > 0)) return hipSuccess;
+  hipLaunchKernelGGL((k_fb_scan<S, Q>), dim3(1024), dim3(256), 0, s, A, a.k, a.coarse, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_calibrate(const SelectArgs& a, hipStream_t s) {
+  switch (a.storage * 16 + a.Q) {
+    case 0 * 16 + 9: return launch_calibrate_t<double, 9>(a, s);
+    case 0 * 16 + 3: return launch_calibrate_t<double, 3>(a, s);
+    case 1 * 16 + 9: return launch_calibrate_t<float, 9>(a, s);
+    case 1 * 16 + 3: return launch_calibrate_t<float, 3>(a, s);
+    case 2 * 16 + 9: return launch_calibrate_t<_Float16, 9>(a, s);
+    case 2 * 16 + 3: return launch_calibrate_t<_Float16, 3>(a, s);
+    case 3 * 16 + 9: return launch_calibrate_t<bf16_t, 9>(a, s);
+    default: return launch_calibrate_t<bf16_t, 3>(a, s);
+  }
 }
 
 hipError_t launch_select(const SelectArgs& a, hipStream_t s) {

@@ -98,16 +98,60 @@ __device__ __forceinline__ void moments_v(const R v[Q], R rho0, R& m0, R& ux, R&
   uy = jy / rho;
 }
 
+// Nonequilibrium entropy of a site (section 4, eq. DelS), sum_i f_i
+// ln(f_i / f*_i), evaluated as sum_i f*_i h((f_i - f*_i) / f*_i) (same value
+// because f and f* share rho).  With the product form of f*, 1/f*_ab =
+// (S/rho) / ((c_a + dt_a)(c_b + dt_b)), so 1 + 2*3 reciprocals replace nine
+// divisions.  +inf if some f_i < 0 or f*_i <= 0.
+//
+// Screening: h(x) <= x^2 for x >= -1/2, so U = sum_i f*_i x_i^2 bounds Delta S
+// from above.  When U < screen (and every x_i >= -1/2) the exact sum is
+// skipped and U is returned: the caller only needs to know that Delta S is
+// below `screen`.  screen = 0 always evaluates the exact sum.
 template <class R, int Q, bool SH>
-__device__ __forceinline__ R site_dS(const R v[Q], const R feq[Q], const R d[Q], R rho0) {
-  R fa[Q], qa[Q];
+__device__ __forceinline__ R site_dS(const R v[Q], const R d[Q], R m0, R rho0, R ux, R uy,
+                                     int kind, R screen = R(0)) {
+  R dx[3], dy[3], fx[3], fy[3], rx[3], ry[3];
+  eq_dev6<R>(ux, kind, dx);
+  if constexpr (Q == 9) eq_dev6<R>(uy, kind, dy);
+  bool bad = false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    fx[a] = (R)c1(a - 1) + dx[a];
+    rx[a] = rcp<R>(fx[a]);
+    bad |= fx[a] <= R(0);
+    if constexpr (Q == 9) {
+      fy[a] = (R)c1(a - 1) + dy[a];
+      ry[a] = rcp<R>(fy[a]);
+      bad |= fy[a] <= R(0);
+    }
+  }
+  const R rho = SH ? rho0 + m0 : m0;
+  constexpr R S = Q == 9 ? R(36) : R(6);
+  const R irs = S * rcp<R>(rho);
+  bad |= rho <= R(0);
+  R x[Q], fq[Q];
+  R ub = R(0);
+  bool far = false;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
+    const int a = vx_of<Q>(i) + 1, b = vy_of<Q>(i) + 1;
     const R sh = SH ? wt<R, Q>(i) * rho0 : R(0);
-    fa[i] = v[i] + sh;
-    qa[i] = feq[i] + sh;
+    bad |= (v[i] + sh) < R(0);
+    R inv;
+    if constexpr (Q == 9) { fq[i] = fx[a] * fy[b]; inv = irs * (rx[a] * ry[b]); }
+    else { fq[i] = fx[a]; inv = irs * rx[a]; }
+    x[i] = -d[i] * inv;
+    far |= x[i] < R(-0.5);
+    ub += fq[i] * (x[i] * x[i]);
   }
-  return delta_s<R, Q>(fa, qa, d);
+  if (bad) return r_inf<R>();
+  ub *= rho / S;
+  if (!far && ub < screen) return ub;
+  R acc = R(0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) acc += fq[i] * h_fn<R>(x[i]);
+  return acc * (rho / S);
 }
 
 // Ranking key of a non-negative Delta S: its bit pattern (monotone in the
@@ -119,6 +163,14 @@ template <> __device__ __forceinline__ uint32_t key_of<float>(float x) {
 template <> __device__ __forceinline__ unsigned long long key_of<double>(double x) {
   return x != x ? 0x7ff0000000000000ull : (unsigned long long)__double_as_longlong(x);
 }
+// The Delta S value whose key is k.
+template <class R> __device__ __forceinline__ R value_of_key(unsigned long long k);
+template <> __device__ __forceinline__ float value_of_key<float>(unsigned long long k) {
+  return __uint_as_float((uint32_t)k);
+}
+template <> __device__ __forceinline__ double value_of_key<double>(unsigned long long k) {
+  return __longlong_as_double((long long)k);
+}
 
 // Everything up to Delta S for one site: used by the step, the median halo
 // and the selection rescans, so that all of them see bit-identical values.
@@ -126,7 +178,8 @@ template <class S, int Q>
 __device__ __forceinline__ typename StoreT<S>::R site_prep(
     const StepArgs<typename StoreT<S>::R>& A, int x, int y, typename StoreT<S>::R v[Q],
     typename StoreT<S>::R feq[Q], typename StoreT<S>::R d[Q], typename StoreT<S>::R& m0,
-    typename StoreT<S>::R& ux, typename StoreT<S>::R& uy, bool need_dS) {
+    typename StoreT<S>::R& ux, typename StoreT<S>::R& uy, bool need_dS,
+    typename StoreT<S>::R screen = typename StoreT<S>::R(0)) {
   using R = typename StoreT<S>::R;
   constexpr bool SH = StoreT<S>::shifted;
   pull<S, Q>((const S*)A.src, A.qs, A.pitch, A.nx, A.ny, A.bc, x, y, A.lid, v);
@@ -134,7 +187,7 @@ __device__ __forceinline__ typename StoreT<S>::R site_prep(
   equilibrium_v<R, Q, SH>(m0, A.rho0, ux, uy, A.eq_kind, feq);
 #pragma unroll
   for (int i = 0; i < Q; ++i) d[i] = feq[i] - v[i];
-  return need_dS ? site_dS<R, Q, SH>(v, feq, d, A.rho0) : R(0);
+  return need_dS ? site_dS<R, Q, SH>(v, d, m0, A.rho0, ux, uy, A.eq_kind, screen) : R(0);
 }
 
 template <class R> struct KeyInf;
@@ -152,45 +205,30 @@ __device__ __forceinline__ int bucket_of(unsigned long long key, unsigned long l
   return b >= (unsigned long long)kBuckets ? kBuckets - 1 : (int)b;
 }
 
-// Wave-aggregated append of Ehrenfest candidates (all lanes of the wave must
-// call it): one atomic per wave reserves the slots; the candidate's key, site
-// index and moments go to the buffer and its bucket count to the histogram.
+// Append of Ehrenfest candidates by one wavefront (all its lanes call it):
+// the wavefront owns 64 entries of the candidate buffer (its region), so a
+// ballot gives every candidate its slot without a global counter; the
+// region's count goes to wcount and each key's bucket count to the
+// histogram.
 template <class R>
-__device__ __forceinline__ void append_candidates(const StepArgs<R>& A, bool is_c,
+__device__ __forceinline__ void append_candidates(const StepArgs<R>& A, long long region, bool is_c,
                                                   typename KeyOf<R>::T key, uint32_t idx,
                                                   R m0, R ux, R uy) {
   const unsigned long long mask = __ballot(is_c);
   if (!mask) return;
-  SelState* st = A.sel;
   const int lane = __lane_id();
-  const int leader = __ffsll((long long)mask) - 1;
-  unsigned long long kmax = (is_c && (unsigned long long)key < KeyInf<R>::v) ? (unsigned long long)key : 0ull;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const unsigned long long o = __shfl_xor(kmax, off);
-    kmax = o > kmax ? o : kmax;
+  if (lane == __ffsll((long long)mask) - 1) {
+    A.wcount[region] = (uint32_t)__popcll(mask);
+    atomicAdd(&A.ccount[(region & (kCountSlots - 1)) * kCountStride], (unsigned long long)__popcll(mask));
   }
-  unsigned long long base = ~0ull;
-  if (lane == leader) {
-    // once the buffer has overflowed the step goes to a rescan anyway; stop
-    // contending for the counter
-    const unsigned long long seen = __hip_atomic_load(&st->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (seen <= (unsigned long long)A.cap) {
-      base = atomicAdd(&st->count, (unsigned long long)__popcll(mask));
-      if (kmax) atomicMax(&st->max_key, kmax);
-    }
-  }
-  base = __shfl(base, leader);
-  if (is_c && base != ~0ull) {
-    const unsigned long long pos = base + (unsigned long long)__popcll(mask & ((1ull << lane) - 1ull));
-    if (pos < (unsigned long long)A.cap) {
-      A.cand_key[pos] = key;
-      A.cand_idx[pos] = idx;
-      A.cand_mom[pos] = m0;
-      A.cand_mom[A.cap + pos] = ux;
-      A.cand_mom[2 * A.cap + pos] = uy;
-      atomicAdd(&A.hist[bucket_of<R>((unsigned long long)key, st->base_key, st->shift)], 1u);
-    }
+  if (is_c) {
+    const long long pos = region * 64 + __popcll(mask & ((1ull << lane) - 1ull));
+    A.cand_key[pos] = key;
+    A.cand_idx[pos] = idx;
+    A.cand_mom[pos] = m0;
+    A.cand_mom[A.cap + pos] = ux;
+    A.cand_mom[2 * A.cap + pos] = uy;
+    atomicAdd(&A.hist[bucket_of<R>((unsigned long long)key, A.sel->base_key, A.sel->shift)], 1u);
   }
 }
 

@@ -12,6 +12,8 @@
 //      (section 4) for the selection kernels.
 #include "lbm_device.h"
 #include "lbm_internal.h"
+#include <hip/hip_ext.h>
+
 #include "lbm_site.h"
 
 namespace lbm {
@@ -53,8 +55,11 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<typename StoreT<S>:
   const bool valid = x < A.nx && y < A.ny;
 
   const bool need_dS = MEDIAN || A.ehrenfest;
+  // Without the median filter, Delta S only decides Ehrenfest candidacy:
+  // sites provably below the floor skip its exact evaluation.
+  const R screen = (!MEDIAN && A.ehrenfest) ? value_of_key<R>(A.sel->floor_key) : R(0);
   R v[Q], feq[Q], d[Q], m0 = R(0), ux = R(0), uy = R(0), dS = R(0);
-  if (valid) dS = site_prep<S, Q>(A, x, y, v, feq, d, m0, ux, uy, need_dS);
+  if (valid) dS = site_prep<S, Q>(A, x, y, v, feq, d, m0, ux, uy, need_dS, screen);
 
   if constexpr (MEDIAN) {
     // Median entropy filter: Delta S of the tile plus a one-site halo in LDS.
@@ -125,7 +130,8 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<typename StoreT<S>:
     using K = typename KeyOf<R>::T;
     const K key = key_of<R>(dS);
     const bool is_c = valid && (dS > A.ehr_delta) && (key >= (K)A.sel->floor_key);
-    append_candidates<R>(A, is_c, key, (uint32_t)(y * A.nx + x), m0, ux, uy);
+    append_candidates<R>(A, (long long)t * 4 + threadIdx.x / 64, is_c, key,
+                         (uint32_t)(y * A.nx + x), m0, ux, uy);
   }
 
   R post[Q];
@@ -232,50 +238,58 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<typename StoreT<S>:
 // ---------------------------------------------------------------------------
 // Launch dispatch.
 // ---------------------------------------------------------------------------
+template <class S, int Q, int COLL, bool MEDIAN, int TX, int TY>
+static void launch_k(const StepArgs<typename StoreT<S>::R>& A, hipStream_t s, hipEvent_t e0,
+                     hipEvent_t e1) {
+  const dim3 grid(A.tiles_x * A.tiles_y), block(256);
+  if (e0 && e1)  // events taken at the kernel's own start and end
+    hipExtLaunchKernelGGL((k_step<S, Q, COLL, MEDIAN, TX, TY>), grid, block, 0, s, e0, e1, 0, A);
+  else
+    hipLaunchKernelGGL((k_step<S, Q, COLL, MEDIAN, TX, TY>), grid, block, 0, s, A);
+}
+
 template <class S, int Q, int COLL, bool MEDIAN>
-static hipError_t launch_t(const void* args, hipStream_t s) {
+static hipError_t launch_t(const void* args, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   using R = typename StoreT<S>::R;
   const StepArgs<R>& A = *(const StepArgs<R>*)args;
-  const dim3 grid(A.tiles_x * A.tiles_y), block(256);
   if constexpr (Q == 3) {
-    hipLaunchKernelGGL((k_step<S, Q, COLL, MEDIAN, 256, 1>), grid, block, 0, s, A);
+    launch_k<S, Q, COLL, MEDIAN, 256, 1>(A, s, e0, e1);
   } else if constexpr (MEDIAN) {
-    hipLaunchKernelGGL((k_step<S, Q, COLL, MEDIAN, 64, 4>), grid, block, 0, s, A);
+    launch_k<S, Q, COLL, MEDIAN, 64, 4>(A, s, e0, e1);
   } else {
-    if (tile_shape(Q, MEDIAN, A.nx).tx == 256)
-      hipLaunchKernelGGL((k_step<S, Q, COLL, MEDIAN, 256, 1>), grid, block, 0, s, A);
-    else
-      hipLaunchKernelGGL((k_step<S, Q, COLL, MEDIAN, 64, 4>), grid, block, 0, s, A);
+    if (tile_shape(Q, MEDIAN, A.nx).tx == 256) launch_k<S, Q, COLL, MEDIAN, 256, 1>(A, s, e0, e1);
+    else launch_k<S, Q, COLL, MEDIAN, 64, 4>(A, s, e0, e1);
   }
   return hipGetLastError();
 }
 
 template <class S>
-static hipError_t launch_s(int Q, int coll, bool median, const void* args, hipStream_t s) {
+static hipError_t launch_s(int Q, int coll, bool median, const void* args, hipStream_t s,
+                           hipEvent_t e0, hipEvent_t e1) {
   if (Q == 3) {
     if (coll == COLL_LBGK)
-      return median ? launch_t<S, 3, COLL_LBGK, true>(args, s) : launch_t<S, 3, COLL_LBGK, false>(args, s);
+      return median ? launch_t<S, 3, COLL_LBGK, true>(args, s, e0, e1) : launch_t<S, 3, COLL_LBGK, false>(args, s, e0, e1);
     if (coll == COLL_ELBM)
-      return median ? launch_t<S, 3, COLL_ELBM, true>(args, s) : launch_t<S, 3, COLL_ELBM, false>(args, s);
+      return median ? launch_t<S, 3, COLL_ELBM, true>(args, s, e0, e1) : launch_t<S, 3, COLL_ELBM, false>(args, s, e0, e1);
     return hipErrorInvalidValue;
   }
   switch (coll) {
     case COLL_LBGK:
-      return median ? launch_t<S, 9, COLL_LBGK, true>(args, s) : launch_t<S, 9, COLL_LBGK, false>(args, s);
+      return median ? launch_t<S, 9, COLL_LBGK, true>(args, s, e0, e1) : launch_t<S, 9, COLL_LBGK, false>(args, s, e0, e1);
     case COLL_MRT:
-      return median ? launch_t<S, 9, COLL_MRT, true>(args, s) : launch_t<S, 9, COLL_MRT, false>(args, s);
+      return median ? launch_t<S, 9, COLL_MRT, true>(args, s, e0, e1) : launch_t<S, 9, COLL_MRT, false>(args, s, e0, e1);
     default:
-      return median ? launch_t<S, 9, COLL_ELBM, true>(args, s) : launch_t<S, 9, COLL_ELBM, false>(args, s);
+      return median ? launch_t<S, 9, COLL_ELBM, true>(args, s, e0, e1) : launch_t<S, 9, COLL_ELBM, false>(args, s, e0, e1);
   }
 }
 
 hipError_t launch_step(int storage, int Q, int coll, bool median, const void* args,
-                       hipStream_t s) {
+                       hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   switch (storage) {
-    case 0: return launch_s<double>(Q, coll, median, args, s);
-    case 1: return launch_s<float>(Q, coll, median, args, s);
-    case 2: return launch_s<_Float16>(Q, coll, median, args, s);
-    default: return launch_s<bf16_t>(Q, coll, median, args, s);
+    case 0: return launch_s<double>(Q, coll, median, args, s, e0, e1);
+    case 1: return launch_s<float>(Q, coll, median, args, s, e0, e1);
+    case 2: return launch_s<_Float16>(Q, coll, median, args, s, e0, e1);
+    default: return launch_s<bf16_t>(Q, coll, median, args, s, e0, e1);
   }
 }
 

@@ -52,7 +52,6 @@ class lbm_config(ctypes.Structure):
         ("storage", ctypes.c_int), ("rho0", ctypes.c_double),
         ("omega_field", ctypes.c_int), ("checkpoint_every", ctypes.c_int),
         ("max_steps", ctypes.c_longlong), ("check_interval", ctypes.c_int),
-        ("select_capacity", ctypes.c_longlong),
     ]
 
 
@@ -238,7 +237,7 @@ def make_config(*, lattice="D2Q9", nx=64, ny=64, bc="periodic", u_lid=0.0, rho_w
                 elbm_fallback="positivity", elbm_eps=1e-14, elbm_max_iter=32,
                 elbm_dS_cut=1e-15, elbm_f64_below=3.0, storage="f32", rho0=1.0,
                 omega_field=False, checkpoint_every=0, max_steps=0, check_interval=0,
-                select_capacity=0, **_ignored) -> lbm_config:
+                **_ignored) -> lbm_config:
     c = lbm_config_default()
     c.lattice = LBM_D2Q9 if lattice == "D2Q9" else LBM_D1Q3
     c.nx, c.ny = int(nx), int(ny)
@@ -264,7 +263,6 @@ def make_config(*, lattice="D2Q9", nx=64, ny=64, bc="periodic", u_lid=0.0, rho_w
     c.omega_field = 1 if omega_field else 0
     c.checkpoint_every, c.max_steps = int(checkpoint_every), int(max_steps)
     c.check_interval = int(check_interval)
-    c.select_capacity = int(select_capacity)
     return c
 
 
