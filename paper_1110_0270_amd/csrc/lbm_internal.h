@@ -9,21 +9,24 @@ namespace lbm {
 
 // Device-resident state of the Ehrenfest top-k selection (section 4,
 // Ehrenfests' regularisation with a budget of k sites per step).
+// Floors and histogram frames are kept per step parity: with omega near 2
+// the nonequilibrium part changes sign every step, and the steps of one
+// parity resemble each other more than consecutive steps do.
 struct SelState {
-  unsigned long long floor_key;  // a site is a candidate iff eligible and key >= floor_key
-  unsigned long long floor_prev; // floor suggested by the previous step (0: none)
-  unsigned long long base_key;   // histogram frame: bucket = (key - base_key) >> shift
+  unsigned long long floor_key[2]; // candidate iff eligible and key >= floor_key[parity]
+  unsigned long long base_key[2];  // histogram frame: bucket = (key - base_key) >> shift
+  unsigned long long step;         // steps selected so far (parity = step & 1)
   unsigned long long bcount;     // length of the boundary-bucket list
   unsigned long long sel_acc;    // sites selected so far in the running step
   unsigned long long fallbacks;  // steps that needed a full rescan (cumulative)
   unsigned long long overflows;  // steps whose boundary list overflowed (cumulative)
   unsigned long long cand_total; // candidates over all steps (cumulative)
   long long n_sel;               // sites selected in the last completed step
-  unsigned int shift;            // bucket width is 2^shift keys
+  unsigned int shift[2];         // bucket width is 2^shift keys
   unsigned int ticket;           // last-workgroup ticket
   int fallback;                  // 1: this step's candidates came from a rescan
   int fb_bin;                    // coarse bin chosen by the rescan
-  int floor_raised;              // floor_key is above the eligibility threshold
+  int floor_raised[2];           // floor_key is above the eligibility threshold
   int pad[3];
 };
 

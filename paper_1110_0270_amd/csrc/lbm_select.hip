@@ -134,7 +134,7 @@ __device__ unsigned long long block_sum(const unsigned int* h) {
 // The rescan is needed when the floor was raised and fewer than k sites
 // reached it.
 __device__ __forceinline__ bool need_rescan(unsigned long long nc, long long k, const SelState* st) {
-  return (long long)nc < k && st->floor_raised;
+  return (long long)nc < k && st->floor_raised[st->step & 1ull];
 }
 
 // Site of lane `lane` of wavefront w in logical tile t (the step kernel's
@@ -195,21 +195,25 @@ __global__ __launch_bounds__(256) void k_fb_scan(const StepArgs<typename StoreT<
   __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned long long edge = coarse_edge_key<R>(b);
+    const int par = (int)(st->step & 1ull);
     if (calibrate) {
       const unsigned long long dk = delta_key<R>(A.ehr_delta);
       const unsigned long long f = edge > dk ? edge : dk;
-      st->floor_key = f;
-      st->floor_prev = 0;
-      st->floor_raised = f > dk ? 1 : 0;
+      const unsigned int sh = frame_shift(f, coarse_edge_key<R>(top + 1));
+      for (int q = 0; q < 2; ++q) {
+        st->floor_key[q] = f;
+        st->floor_raised[q] = f > dk ? 1 : 0;
+        st->base_key[q] = f;
+        st->shift[q] = sh;
+      }
       st->fallback = 0;
-      st->base_key = f;
     } else {
       st->fb_bin = b;
       st->fallback = 1;
       st->fallbacks += 1;
-      st->base_key = edge;
+      st->base_key[par] = edge;
+      st->shift[par] = frame_shift(edge, coarse_edge_key<R>(top + 1));
     }
-    st->shift = frame_shift(st->base_key, coarse_edge_key<R>(top + 1));
     st->ticket = 0;
   }
   __syncthreads();
@@ -253,7 +257,8 @@ __global__ __launch_bounds__(256) void k_fb_append(const StepArgs<typename Store
       A.cand_mom[pos] = m0;
       A.cand_mom[A.cap + pos] = ux;
       A.cand_mom[2 * A.cap + pos] = uy;
-      atomicAdd(&A.hist[bucket_of<R>((unsigned long long)key_of<R>(dS), st->base_key, st->shift)], 1u);
+      const int par = (int)(st->step & 1ull);
+      atomicAdd(&A.hist[bucket_of<R>((unsigned long long)key_of<R>(dS), st->base_key[par], st->shift[par])], 1u);
     }
   }
 }
@@ -298,8 +303,9 @@ __global__ __launch_bounds__(256) void k_fix_regions(const StepArgs<typename Sto
   __shared__ unsigned int h[kBuckets];
   __shared__ unsigned int s_sel, s_bnd;
   __shared__ unsigned long long s_nc, s_base_sel, s_base_bnd;
-  const unsigned long long base = st->base_key;
-  const unsigned int shift = st->shift;
+  const int par = (int)(st->step & 1ull);
+  const unsigned long long base = st->base_key[par];
+  const unsigned int shift = st->shift[par];
   for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) h[i] = ld_rlx(&A.hist[i]);
   if (threadIdx.x == 0) { s_sel = 0; s_bnd = 0; s_nc = candidate_count(A.ccount); }
   __syncthreads();
@@ -373,8 +379,9 @@ __global__ __launch_bounds__(1024) void k_fix_tail(const StepArgs<typename Store
   __shared__ unsigned long long s_off_pref, s_nc;
   __shared__ uint32_t s_idx_pref;
   __shared__ unsigned int s_tot;
-  const unsigned long long base = st->base_key;
-  const unsigned int shift = st->shift;
+  const int par = (int)(st->step & 1ull);
+  const unsigned long long base = st->base_key[par];
+  const unsigned int shift = st->shift[par];
   for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) h[i] = ld_rlx(&A.hist[i]);
   if (threadIdx.x == 0) {
     s_nc = candidate_count(A.ccount);
@@ -463,29 +470,25 @@ __global__ __launch_bounds__(1024) void k_fix_tail(const StepArgs<typename Store
   }
   __syncthreads();
 
-  // --- floor and frame of the next step ------------------------------------
+  // --- floor and frame for the next step of this parity --------------------
   // Keep between 2k and 6k candidates (aim at 3k); the floor is never raised
-  // when k is at least a tenth of the lattice.  The lower of this step's and
-  // the previous step's suggestions is used: with omega near 2 the
-  // nonequilibrium part changes sign every step, and the two parities can
-  // rank different sites.  The frame spans twice the current candidates'
-  // range above the floor.
+  // when k is at least a tenth of the lattice.  The frame spans twice the
+  // current candidates' range above the floor.
   const unsigned long long dk = delta_key<R>(A.ehr_delta);
-  unsigned long long fnext = dk, fsugg = dk;
+  unsigned long long fnext = dk;
   if (10 * k < n_sites && k > 0) {
-    const bool keep = st->floor_raised && !st->fallback && nc >= 2 * k && nc <= 6 * k;
+    const bool keep = st->floor_raised[par] && !st->fallback && nc >= 2 * k && nc <= 6 * k;
     if (keep) {
-      fsugg = st->floor_key;
+      fnext = st->floor_key[par];
     } else {
       int t2;
       unsigned long long a2;
       find_from_top<kBuckets>(h, 3ull * (unsigned long long)k, &t2, &a2);
-      if (t2 >= 0 && t2 < kBuckets - 1) fsugg = base + ((unsigned long long)t2 << shift);
-      else if (t2 < 0) fsugg = base > 2 * KeyTraits<R>::quarter ? base - 2 * KeyTraits<R>::quarter : 0ull;
-      else fsugg = st->floor_key;
+      if (t2 >= 0 && t2 < kBuckets - 1) fnext = base + ((unsigned long long)t2 << shift);
+      else if (t2 < 0) fnext = base > 2 * KeyTraits<R>::quarter ? base - 2 * KeyTraits<R>::quarter : 0ull;
+      else fnext = st->floor_key[par];
     }
-    if (fsugg < dk) fsugg = dk;
-    fnext = (keep || st->floor_prev == 0 || st->floor_prev > fsugg) ? fsugg : st->floor_prev;
+    if (fnext < dk) fnext = dk;
   }
   __shared__ int s_top;
   if (threadIdx.x == 0) s_top = -1;
@@ -499,11 +502,10 @@ __global__ __launch_bounds__(1024) void k_fix_tail(const StepArgs<typename Store
     const unsigned long long span = (unsigned long long)kBuckets << shift;
     const unsigned long long hi_key = s_top < 0 ? fnext + 1
         : (s_top < kBuckets - 1 ? base + ((unsigned long long)(s_top + 1) << shift) : base + 2 * span);
-    st->floor_key = fnext;
-    st->floor_prev = fsugg;
-    st->floor_raised = fnext > dk ? 1 : 0;
-    st->base_key = fnext;
-    st->shift = frame_shift(fnext, hi_key > fnext ? fnext + 2 * (hi_key - fnext) : fnext + 1);
+    st->floor_key[par] = fnext;
+    st->floor_raised[par] = fnext > dk ? 1 : 0;
+    st->base_key[par] = fnext;
+    st->shift[par] = frame_shift(fnext, hi_key > fnext ? fnext + 2 * (hi_key - fnext) : fnext + 1);
     const unsigned int ns = s_tot < (unsigned int)k ? s_tot : (unsigned int)k;
     st->n_sel = (long long)ns;
     if (n_sel_out) *n_sel_out = (long long)ns;
@@ -512,6 +514,7 @@ __global__ __launch_bounds__(1024) void k_fix_tail(const StepArgs<typename Store
     st->fallback = 0;
     st->sel_acc = 0;
     st->bcount = 0;
+    st->step += 1;
   }
   for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) A.hist[i] = 0;
   for (int i = threadIdx.x; i < kCountSlots; i += blockDim.x) A.ccount[i * kCountStride] = 0;
@@ -572,7 +575,7 @@ hipError_t launch_select(const SelectArgs& a, hipStream_t s) {
 // positive key (bucket = the top 12 bits of the key).
 void init_select_state(SelState* h, int f64) {
   *h = SelState{};
-  h->shift = f64 ? 51u : 19u;
+  h->shift[0] = h->shift[1] = f64 ? 51u : 19u;
 }
 
 }  // namespace lbm

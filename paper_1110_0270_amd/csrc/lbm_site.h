@@ -228,7 +228,8 @@ __device__ __forceinline__ void append_candidates(const StepArgs<R>& A, long lon
     A.cand_mom[pos] = m0;
     A.cand_mom[A.cap + pos] = ux;
     A.cand_mom[2 * A.cap + pos] = uy;
-    atomicAdd(&A.hist[bucket_of<R>((unsigned long long)key, A.sel->base_key, A.sel->shift)], 1u);
+    const int par = (int)(A.sel->step & 1ull);
+    atomicAdd(&A.hist[bucket_of<R>((unsigned long long)key, A.sel->base_key[par], A.sel->shift[par])], 1u);
   }
 }
 

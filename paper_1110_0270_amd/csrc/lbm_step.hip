@@ -57,7 +57,8 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<typename StoreT<S>:
   const bool need_dS = MEDIAN || A.ehrenfest;
   // Without the median filter, Delta S only decides Ehrenfest candidacy:
   // sites provably below the floor skip its exact evaluation.
-  const R screen = (!MEDIAN && A.ehrenfest) ? value_of_key<R>(A.sel->floor_key) : R(0);
+  const int par = A.ehrenfest ? (int)(A.sel->step & 1ull) : 0;
+  const R screen = (!MEDIAN && A.ehrenfest) ? value_of_key<R>(A.sel->floor_key[par]) : R(0);
   R v[Q], feq[Q], d[Q], m0 = R(0), ux = R(0), uy = R(0), dS = R(0);
   if (valid) dS = site_prep<S, Q>(A, x, y, v, feq, d, m0, ux, uy, need_dS, screen);
 
@@ -129,7 +130,7 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<typename StoreT<S>:
   if (A.ehrenfest) {
     using K = typename KeyOf<R>::T;
     const K key = key_of<R>(dS);
-    const bool is_c = valid && (dS > A.ehr_delta) && (key >= (K)A.sel->floor_key);
+    const bool is_c = valid && (dS > A.ehr_delta) && (key >= (K)A.sel->floor_key[par]);
     append_candidates<R>(A, (long long)t * 4 + threadIdx.x / 64, is_c, key,
                          (uint32_t)(y * A.nx + x), m0, ux, uy);
   }
