@@ -171,12 +171,21 @@ lbm_status lbm_moments(lbm_ctx* ctx, void* rho, void* ux, void* uy, int dtype);
 /* Adjoint of the rollout recorded since the last lbm_set_* (requires
  * cfg.checkpoint_every > 0 and at most cfg.max_steps steps).  dL_dfT: the
  * gradient of a loss with respect to the final populations f[Q][ny][nx]
- * (device, dtype).  Writes dL/df0 into dL_df0 and, when dL_domega is not
- * NULL, dL/d omega(x) into dL_domega (ny*nx).  Gradients pass through the
- * limiters as subgradients along the branch the forward pass took, and
- * through the ELBM root by implicit differentiation.  The lattice is left
- * in its final state.  Errors: LBM_ESTATE without a recorded rollout;
- * LBM_EUNSUPPORTED for the median filter. */
+ * (device, dtype, dense).  Writes dL/df0 into dL_df0 (same layout) and,
+ * when dL_domega is not NULL, dL/d omega(x) into dL_domega (ny*nx): the
+ * gradient with respect to a per-site relaxation rate (with a uniform
+ * omega, its sum over sites is dL/d omega).  Gradients pass through the
+ * limiters along the branch the forward pass took (a site the Ehrenfest
+ * limiter sent to equilibrium through the Jacobian of f*; the positivity rule through
+ * its coefficient and the component that set it), through the ELBM root by
+ * implicit differentiation of the entropy condition (section 3), and
+ * through storage rounding as the identity.  The rollout is recomputed
+ * from the checkpoints taken every cfg.checkpoint_every steps, with the
+ * recorded Ehrenfest selections, so the recompute takes the forward pass's
+ * branches bit for bit.  Work runs in the compute precision (FP64 for
+ * LBM_F64 storage, FP32 otherwise).  The lattice is left in its final
+ * state.  Errors: LBM_ESTATE without a recorded rollout; LBM_EUNSUPPORTED
+ * for the median filter (its adjoint is not provided). */
 lbm_status lbm_backward(lbm_ctx* ctx, const void* dL_dfT, void* dL_df0,
                         void* dL_domega, int dtype);
 

@@ -25,6 +25,7 @@ struct AdjointLayout {
   size_t off_gom = 0;        // per-site omega gradient accumulator
   size_t off_tape_sel = 0;   // max_steps * k site indices
   size_t off_tape_cnt = 0;   // max_steps counts
+  size_t off_mask = 0;       // one byte per site: sent to f* in the step being reversed
   size_t end = 0;
 };
 
@@ -38,10 +39,25 @@ hipError_t adjoint_after_step(const AdjointLayout& L, char* ws, long long steps_
 int32_t* adjoint_selected_slot(const AdjointLayout& L, char* ws, long long t, int32_t* dflt);
 long long* adjoint_count_slot(const AdjointLayout& L, char* ws, long long t);
 
+// Adjoint kernels (lbm_adjoint.hip).  step_args points at the StepArgs of
+// the compute precision (double for LBM_F64 storage, float otherwise) with
+// src = the state the step read; lam_in/lam_out/gom use the same precision
+// and the pitched layout of the lattice.
+hipError_t launch_adjoint(int storage, int Q, int coll, const void* step_args, const void* lam_in,
+                          void* lam_out, void* gom, const unsigned char* mask, hipStream_t s);
+// f* written into step_args->dst at the first *count sites of list (<= k).
+hipError_t launch_tape_fix(int storage, int Q, const void* step_args, const int32_t* list,
+                           const long long* count, long long k, hipStream_t s);
+hipError_t launch_mark(unsigned char* mask, const int32_t* list, const long long* count,
+                       long long k, unsigned char val, hipStream_t s);
+// Dense [nf][ny][nx] (FP64 or FP32) <-> pitched [nf][ny][pitch] (FP64 or FP32).
+hipError_t launch_to_pitch(const void* src, int src_f64, void* dst, int dst_f64, int nf, int nx,
+                           int ny, int pitch, long long qs, hipStream_t s);
+hipError_t launch_from_pitch(const void* src, int src_f64, void* dst, int dst_f64, int nf, int nx,
+                             int ny, int pitch, long long qs, hipStream_t s);
+
 hipError_t launch_convert_field(const void* src, int src_f64, void* dst, int dst_f64, int nx,
                                 int ny, int pitch, hipStream_t s);
 
 }  // namespace lbm
 
-struct lbm_ctx;
-// Backward pass over the recorded rollout; implemented in lbm_api.hip.

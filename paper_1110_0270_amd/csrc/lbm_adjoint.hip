@@ -1,0 +1,378 @@
+// Adjoint of the regularised LBM step (reverse mode).
+//
+// A step maps the stored lattice g_t to g_{t+1}(x) = C(p(x); omega(x)), where
+// p = pull(g_t) is the streamed pre-collision state (section 2) and C the
+// site-local collision with its limiters.  The pull with periodic wrap and
+// halfway bounce-back is a permutation of the populations (plus constants
+// from the moving wall), so its transpose is a push that writes every entry
+// of the adjoint lattice exactly once: with mu(x) = J(x)^T lambda_{t+1}(x),
+//   lambda_t[i](x - v_i) = mu_i(x)   when x - v_i is the pull source,
+//   lambda_t[opp(i)](x)  = mu_i(x)   when the pull bounced back.
+// J(x) is differentiated along the branch the forward step took: a site
+// sent to equilibrium by the Ehrenfest limiter contributes d f*/d p; the
+// positivity rule through its homothety coefficient and the component that
+// attained it; ELBM through alpha, by implicit differentiation of
+// S(p + alpha (f* - p)) = S(p) on the root branch (section 3) or through the
+// attaining component of alpha_max on the positivity branch.
+#include "lbm_adjoint.h"
+#include "lbm_collide.h"
+
+namespace lbm {
+
+// 1D equilibrium factors phi_a(u) and their derivatives (section 6):
+//   polynomial: phi_0 = 2/3 - u^2, phi_+- = 1/6 +- u/2 + u^2/2;
+//   entropic:   phi_0 = (2/3)(2 - s), phi_+- = +-u/2 + (2s - 1)/6, s = sqrt(1+3u^2).
+template <class R>
+__device__ __forceinline__ void eq_phi(R u, int kind, R phi[3], R dphi[3]) {
+  R dt[3];
+  eq_dev6<R>(u, kind, dt);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) phi[a] = ((R)c1(a - 1) + dt[a]) / R(6);
+  const R g = kind == EQ_POLY ? u : u / sqrt(R(1) + R(3) * u * u);
+  dphi[0] = R(-0.5) + g;
+  dphi[1] = R(-2) * g;
+  dphi[2] = R(0.5) + g;
+}
+
+// out = (d f*/d p)^T a for f*_i = rho phi_a(u_x) phi_b(u_y), rho = sum p,
+// rho u = sum v p: out_k = a0 + v_kx ax + v_ky ay with
+// ax = sum_i a_i phi_a' phi_b, ay = sum_i a_i phi_a phi_b',
+// a0 = sum_i a_i phi_a phi_b - u_x ax - u_y ay.
+template <class R, int Q>
+__device__ __forceinline__ void feq_vjp(const R a[Q], R ux, R uy, int kind, R out[Q]) {
+  R px[3], dpx[3], py[3], dpy[3];
+  eq_phi<R>(ux, kind, px, dpx);
+  if constexpr (Q == 9) eq_phi<R>(uy, kind, py, dpy);
+  R s0 = R(0), sx = R(0), sy = R(0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int ia = vx_of<Q>(i) + 1, ib = vy_of<Q>(i) + 1;
+    if constexpr (Q == 9) {
+      s0 += a[i] * (px[ia] * py[ib]);
+      sx += a[i] * (dpx[ia] * py[ib]);
+      sy += a[i] * (px[ia] * dpy[ib]);
+    } else {
+      s0 += a[i] * px[ia];
+      sx += a[i] * dpx[ia];
+    }
+  }
+  const R a0 = s0 - ux * sx - uy * sy;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) out[k] = a0 + (R)vx_of<Q>(k) * sx + (R)vy_of<Q>(k) * sy;
+}
+
+template <class R>
+struct AdjArgs {
+  const R* lam_in;          // lambda_{t+1}, [Q][ny][pitch]
+  R* lam_out;               // lambda_t
+  R* gom;                   // dL/d omega accumulator [ny][pitch] or nullptr
+  const unsigned char* mask;// 1 at sites the Ehrenfest limiter sent to f* (or nullptr)
+};
+
+template <class S, int Q, int COLL>
+__global__ __launch_bounds__(256) void k_adjoint(const StepArgs<typename StoreT<S>::R> A,
+                                                 const AdjArgs<typename StoreT<S>::R> B) {
+  using R = typename StoreT<S>::R;
+  constexpr bool SH = StoreT<S>::shifted;
+  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= (long long)A.nx * A.ny) return;
+  const int y = (int)(s / A.nx), x = (int)(s % A.nx);
+  R v[Q], feq[Q], d[Q], m0, ux, uy;
+  site_prep<S, Q>(A, x, y, v, feq, d, m0, ux, uy, false);
+  const long long o = (long long)y * A.pitch + x;
+  const R om = A.omega_field ? A.omega_field[o] : A.omega;
+  R lam[Q], mu[Q], lf[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    lam[i] = B.lam_in[(long long)i * A.qs + o];
+    lf[i] = R(0);
+  }
+  R gw = R(0);
+  if (B.mask && B.mask[s]) {
+    // Ehrenfest step: g' = f*(p)
+#pragma unroll
+    for (int i = 0; i < Q; ++i) { lf[i] = lam[i]; mu[i] = R(0); }
+  } else {
+    R q[Q];
+    CollInfo<R> ci;
+    collide_site<S, Q, COLL>(A, v, feq, d, om, q, ci);
+    // positivity rule: g'' = f* + phi (q - f*), phi = f*_a / (f*_a - q_a)
+    R lq[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) lq[i] = lam[i];
+    if (A.positivity) {
+      R q2[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) q2[i] = q[i];
+      CollInfo<R> cp;
+      positivity_site<S, Q>(A, feq, q2, cp);
+      if (cp.pos_arg >= 0) {
+        const int a = cp.pos_arg;
+        const R phi = cp.phi;
+        R se = R(0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) se += (q[i] - feq[i]) * lam[i];
+        const R sha = SH ? wt<R, Q>(a) * A.rho0 : R(0);
+        const R qa = q[a] + sha, fa = feq[a] + sha;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          lq[i] = phi * lam[i];
+          lf[i] = (R(1) - phi) * lam[i];
+        }
+        lq[a] += se * phi * phi / fa;
+        lf[a] -= se * phi * phi * qa / (fa * fa);
+      }
+    }
+    if constexpr (COLL == COLL_LBGK) {
+      // q = p + omega (f* - p)
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        mu[i] = (R(1) - om) * lq[i];
+        lf[i] += om * lq[i];
+        gw += lq[i] * d[i];
+      }
+    } else if constexpr (COLL == COLL_MRT) {
+      // q = p + B (f* - p), B = Minv diag(rates) M
+      R z[Q], m[Q];
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        R sz = R(0), sm = R(0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          sz += A.Minv[i * Q + k] * lq[i];
+          sm += A.M[k * Q + i] * d[i];
+        }
+        z[k] = sz;
+        m[k] = sm;
+        if ((A.nu_rows >> k) & 1u) gw += sz * sm;
+      }
+#pragma unroll
+      for (int k = 0; k < Q; ++k) z[k] *= ((A.nu_rows >> k) & 1u) ? om : A.rates[k];
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        R w = R(0);
+#pragma unroll
+        for (int k = 0; k < Q; ++k) w += A.M[k * Q + j] * z[k];
+        mu[j] = lq[j] - w;
+        lf[j] += w;
+      }
+    } else {
+      // q = p + alpha beta (f* - p), beta = omega / 2
+      const R alpha = ci.alpha, ab = alpha * (om * R(0.5));
+      R lal = R(0);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        mu[i] = (R(1) - ab) * lq[i];
+        lf[i] += ab * lq[i];
+        gw += lq[i] * (alpha * R(0.5)) * d[i];
+        lal += lq[i] * d[i];
+      }
+      lal *= om * R(0.5);                       // dL/d alpha
+      R fa[Q], qa[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const R sh = SH ? wt<R, Q>(i) * A.rho0 : R(0);
+        fa[i] = v[i] + sh;
+        qa[i] = feq[i] + sh;
+      }
+      if (ci.branch == EB_ROOT) {
+        // implicit derivative: d alpha = -(dS_f/dp dp + dS_f/df* df*) / S_f'
+        R d1 = R(0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          const R xx = alpha * d[i] / fa[i];
+          d1 -= d[i] * (lg1p<R>(xx < R(-1) ? R(-1) : xx) + lg1p<R>(-d[i] / qa[i]));
+        }
+        const R c = -lal / d1;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          const R w = wt<R, Q>(i);
+          const R gs = -(log((fa[i] + alpha * d[i]) / w) + R(1));   // dS/dy at p + alpha D
+          const R ps = -(log(fa[i] / w) + R(1));                     // dS/dy at p
+          mu[i] += c * ((R(1) - alpha) * gs - ps);
+          lf[i] += c * (alpha * gs);
+        }
+      } else if (ci.branch == EB_NOROOT && A.fallback == 0) {
+        // alpha = alpha_max = p_a / (p_a - f*_a) at the attaining component
+        R amin = r_inf<R>();
+        int a = -1;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          if (d[i] < R(0)) {
+            const R r = fa[i] / (-d[i]);
+            if (r < amin) { amin = r; a = i; }
+          }
+        }
+        if (a >= 0) {
+          const R den = fa[a] - qa[a];
+          mu[a] += lal * (-qa[a] / (den * den));
+          lf[a] += lal * (fa[a] / (den * den));
+        }
+      }
+    }
+  }
+  R tf[Q];
+  feq_vjp<R, Q>(lf, ux, uy, A.eq_kind, tf);
+  // transpose of the pull: push mu_i to the population it was pulled from
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const R val = mu[i] + tf[i];
+    int sx = x - vx_of<Q>(i), sy = y - vy_of<Q>(i);
+    bool out;
+    if (A.bc == BC_PERIODIC) {
+      sx = sx < 0 ? sx + A.nx : (sx >= A.nx ? sx - A.nx : sx);
+      sy = sy < 0 ? sy + A.ny : (sy >= A.ny ? sy - A.ny : sy);
+      out = false;
+    } else if (A.bc == BC_COUETTE) {
+      sx = sx < 0 ? sx + A.nx : (sx >= A.nx ? sx - A.nx : sx);
+      out = (sy < 0) | (sy >= A.ny);
+    } else {
+      out = (sx < 0) | (sx >= A.nx) | (sy < 0) | (sy >= A.ny);
+    }
+    if (!out) B.lam_out[(long long)i * A.qs + (long long)sy * A.pitch + sx] = val;
+    else B.lam_out[(long long)(Q - 1 - i) * A.qs + o] = val;
+  }
+  if (B.gom) B.gom[o] += gw;
+}
+
+// Recompute of an Ehrenfest step from its tape: f* at the listed sites,
+// from the pulled state exactly as the step kernel computed it.
+template <class S, int Q>
+__global__ void k_tape_fix(const StepArgs<typename StoreT<S>::R> A, const int32_t* list,
+                           const long long* count, long long k) {
+  using R = typename StoreT<S>::R;
+  const long long n = *count < k ? *count : k;
+  for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+       j += (long long)gridDim.x * blockDim.x) {
+    const int idx = list[j];
+    const int y = idx / A.nx, x = idx % A.nx;
+    R v[Q], feq[Q], d[Q], m0, ux, uy;
+    site_prep<S, Q>(A, x, y, v, feq, d, m0, ux, uy, false);
+    S* dst = (S*)A.dst;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      StoreT<S>::st(dst + (long long)i * A.qs + (long long)y * A.pitch + x, feq[i]);
+  }
+}
+
+__global__ void k_mark(unsigned char* mask, const int32_t* list, const long long* count,
+                       long long k, unsigned char val) {
+  const long long n = *count < k ? *count : k;
+  for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+       j += (long long)gridDim.x * blockDim.x)
+    mask[list[j]] = val;
+}
+
+// Dense caller arrays <-> pitched compute-precision arrays.
+template <class R>
+__global__ void k_to_pitch(const void* src, int src_f64, R* dst, int nf, int nx, int ny,
+                           int pitch, long long qs) {
+  const long long n = (long long)nx * ny;
+  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n * nf;
+       s += (long long)gridDim.x * blockDim.x) {
+    const int f = (int)(s / n);
+    const long long r = s % n;
+    const int y = (int)(r / nx), x = (int)(r % nx);
+    const double v = src_f64 ? ((const double*)src)[s] : (double)((const float*)src)[s];
+    dst[(long long)f * qs + (long long)y * pitch + x] = (R)v;
+  }
+}
+template <class R>
+__global__ void k_from_pitch(const R* src, void* dst, int dst_f64, int nf, int nx, int ny,
+                             int pitch, long long qs) {
+  const long long n = (long long)nx * ny;
+  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n * nf;
+       s += (long long)gridDim.x * blockDim.x) {
+    const int f = (int)(s / n);
+    const long long r = s % n;
+    const int y = (int)(r / nx), x = (int)(r % nx);
+    const double v = (double)src[(long long)f * qs + (long long)y * pitch + x];
+    if (dst_f64) ((double*)dst)[s] = v;
+    else ((float*)dst)[s] = (float)v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+static int grid_of(long long n) {
+  long long g = (n + 255) / 256;
+  return (int)(g < 1 ? 1 : (g > 65535 * 16 ? 65535 * 16 : g));
+}
+
+template <class S, int Q>
+static hipError_t launch_adj_q(int coll, const void* sargs, const void* aargs, hipStream_t s) {
+  using R = typename StoreT<S>::R;
+  const StepArgs<R>& A = *(const StepArgs<R>*)sargs;
+  const AdjArgs<R>& B = *(const AdjArgs<R>*)aargs;
+  const int g = (int)(((long long)A.nx * A.ny + 255) / 256);
+  if (coll == COLL_LBGK) hipLaunchKernelGGL((k_adjoint<S, Q, COLL_LBGK>), dim3(g), dim3(256), 0, s, A, B);
+  else if (coll == COLL_ELBM) hipLaunchKernelGGL((k_adjoint<S, Q, COLL_ELBM>), dim3(g), dim3(256), 0, s, A, B);
+  else if constexpr (Q == 9) hipLaunchKernelGGL((k_adjoint<S, Q, COLL_MRT>), dim3(g), dim3(256), 0, s, A, B);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <class S>
+static hipError_t launch_adj_s(int Q, int coll, const void* sargs, const void* aargs, hipStream_t s) {
+  return Q == 9 ? launch_adj_q<S, 9>(coll, sargs, aargs, s) : launch_adj_q<S, 3>(coll, sargs, aargs, s);
+}
+
+hipError_t launch_adjoint(int storage, int Q, int coll, const void* step_args, const void* lam_in,
+                          void* lam_out, void* gom, const unsigned char* mask, hipStream_t s) {
+  if (storage == 0) {
+    AdjArgs<double> B{(const double*)lam_in, (double*)lam_out, (double*)gom, mask};
+    return launch_adj_s<double>(Q, coll, step_args, &B, s);
+  }
+  AdjArgs<float> B{(const float*)lam_in, (float*)lam_out, (float*)gom, mask};
+  if (storage == 1) return launch_adj_s<float>(Q, coll, step_args, &B, s);
+  if (storage == 2) return launch_adj_s<_Float16>(Q, coll, step_args, &B, s);
+  return launch_adj_s<bf16_t>(Q, coll, step_args, &B, s);
+}
+
+template <class S, int Q>
+static void tape_fix_q(const void* sargs, const int32_t* list, const long long* cnt, long long k,
+                       hipStream_t s) {
+  using R = typename StoreT<S>::R;
+  const StepArgs<R>& A = *(const StepArgs<R>*)sargs;
+  hipLaunchKernelGGL((k_tape_fix<S, Q>), dim3(grid_of(k)), dim3(256), 0, s, A, list, cnt, k);
+}
+
+hipError_t launch_tape_fix(int storage, int Q, const void* step_args, const int32_t* list,
+                           const long long* count, long long k, hipStream_t s) {
+  if (k <= 0) return hipSuccess;
+  switch (storage * 16 + Q) {
+    case 0 * 16 + 9: tape_fix_q<double, 9>(step_args, list, count, k, s); break;
+    case 0 * 16 + 3: tape_fix_q<double, 3>(step_args, list, count, k, s); break;
+    case 1 * 16 + 9: tape_fix_q<float, 9>(step_args, list, count, k, s); break;
+    case 1 * 16 + 3: tape_fix_q<float, 3>(step_args, list, count, k, s); break;
+    case 2 * 16 + 9: tape_fix_q<_Float16, 9>(step_args, list, count, k, s); break;
+    case 2 * 16 + 3: tape_fix_q<_Float16, 3>(step_args, list, count, k, s); break;
+    case 3 * 16 + 9: tape_fix_q<bf16_t, 9>(step_args, list, count, k, s); break;
+    default: tape_fix_q<bf16_t, 3>(step_args, list, count, k, s); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_mark(unsigned char* mask, const int32_t* list, const long long* count,
+                       long long k, unsigned char val, hipStream_t s) {
+  if (k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mark, dim3(grid_of(k)), dim3(256), 0, s, mask, list, count, k, val);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_pitch(const void* src, int src_f64, void* dst, int dst_f64, int nf, int nx,
+                           int ny, int pitch, long long qs, hipStream_t s) {
+  const int g = grid_of((long long)nf * nx * ny);
+  if (dst_f64) hipLaunchKernelGGL((k_to_pitch<double>), dim3(g), dim3(256), 0, s, src, src_f64, (double*)dst, nf, nx, ny, pitch, qs);
+  else hipLaunchKernelGGL((k_to_pitch<float>), dim3(g), dim3(256), 0, s, src, src_f64, (float*)dst, nf, nx, ny, pitch, qs);
+  return hipGetLastError();
+}
+
+hipError_t launch_from_pitch(const void* src, int src_f64, void* dst, int dst_f64, int nf, int nx,
+                             int ny, int pitch, long long qs, hipStream_t s) {
+  const int g = grid_of((long long)nf * nx * ny);
+  if (src_f64) hipLaunchKernelGGL((k_from_pitch<double>), dim3(g), dim3(256), 0, s, (const double*)src, dst, dst_f64, nf, nx, ny, pitch, qs);
+  else hipLaunchKernelGGL((k_from_pitch<float>), dim3(g), dim3(256), 0, s, (const float*)src, dst, dst_f64, nf, nx, ny, pitch, qs);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -30,6 +30,7 @@ AdjointLayout adjoint_layout(const lbm_config* c, size_t lat_bytes, long long qs
   if (L.k > 0) {
     L.off_tape_sel = take((size_t)L.max_steps * L.k * 4);
     L.off_tape_cnt = take((size_t)L.max_steps * 8);
+    L.off_mask = take((size_t)c->nx * c->ny);
   }
   L.end = o;
   return L;

@@ -545,9 +545,61 @@ lbm_status lbm_backward(lbm_ctx* c, const void* dL_dfT, void* dL_df0, void* dL_d
     return fail(LBM_ESTATE, "no recorded rollout (set checkpoint_every > 0 and call lbm_set_* first)");
   if (c->cfg.limiters & LBM_LIM_MEDIAN)
     return fail(LBM_EUNSUPPORTED, "the adjoint of the median filter is not implemented");
-  if (dL_domega && !c->cfg.omega_field)
-    return fail(LBM_EINVAL, "dL_domega needs a per-site omega field");
-  return fail(LBM_EUNSUPPORTED, "backward pass not built yet");
+  const AdjointLayout& A = c->L.adj;
+  const long long T = c->steps;
+  const int Q = c->L.Q, nx = c->cfg.nx, ny = c->cfg.ny, pitch = c->L.pitch;
+  const long long qs = c->L.qs;
+  const bool r64 = c->f64();
+  const int din = dtype == LBM_F64;
+  hipStream_t st = c->stream;
+  char* ws = c->ws;
+  void* lam[2] = {ws + A.off_lam[0], ws + A.off_lam[1]};
+  void* gom = ws + A.off_gom;
+  unsigned char* mask = A.k > 0 ? (unsigned char*)(ws + A.off_mask) : nullptr;
+  auto seg = [&](long long j) { return (void*)(ws + A.off_seg + (size_t)j * align256(c->L.lat_bytes)); };
+  auto ckpt = [&](long long s) { return (const void*)(ws + A.off_ckpt + (size_t)s * align256(c->L.lat_bytes)); };
+  // Step arguments of the recompute: no selection, no counters.
+  StepArgs<double> a64 = c->a64;
+  StepArgs<float> a32 = c->a32;
+  a64.ehrenfest = a32.ehrenfest = 0;
+  a64.count_events = a32.count_events = 0;
+  auto args_for = [&](const void* src, void* dst) -> const void* {
+    if (r64) { a64.src = src; a64.dst = dst; return &a64; }
+    a32.src = src; a32.dst = dst; return &a32;
+  };
+  hipError_t e = launch_to_pitch(dL_dfT, din, lam[0], r64, Q, nx, ny, pitch, qs, st);
+  if (e == hipSuccess) e = hipMemsetAsync(gom, 0, (size_t)qs * (r64 ? 8 : 4), st);
+  if (e == hipSuccess && mask) e = hipMemsetAsync(mask, 0, (size_t)nx * ny, st);
+  int cur = 0;
+  for (long long s = T > 0 ? (T - 1) / A.K : -1; s >= 0 && e == hipSuccess; --s) {
+    const long long t0 = s * A.K, t1 = std::min(T, t0 + A.K);
+    // states g_t0 .. g_{t1-1} of the segment, from its checkpoint
+    e = hipMemcpyAsync(seg(0), ckpt(s), c->L.lat_bytes, hipMemcpyDeviceToDevice, st);
+    for (long long t = t0; t + 1 < t1 && e == hipSuccess; ++t) {
+      const void* args = args_for(seg(t - t0), seg(t + 1 - t0));
+      e = launch_step(c->cfg.storage, Q, c->cfg.collision, false, args, st);
+      if (e == hipSuccess && A.k > 0)
+        e = launch_tape_fix(c->cfg.storage, Q, args, adjoint_selected_slot(A, ws, t, nullptr),
+                            adjoint_count_slot(A, ws, t), A.k, st);
+    }
+    // reverse sweep over the segment
+    for (long long t = t1 - 1; t >= t0 && e == hipSuccess; --t) {
+      const int32_t* list = A.k > 0 ? adjoint_selected_slot(A, ws, t, nullptr) : nullptr;
+      const long long* cnt = A.k > 0 ? adjoint_count_slot(A, ws, t) : nullptr;
+      if (mask) e = launch_mark(mask, list, cnt, A.k, 1, st);
+      const void* args = args_for(seg(t - t0), nullptr);
+      if (e == hipSuccess)
+        e = launch_adjoint(c->cfg.storage, Q, c->cfg.collision, args, lam[cur], lam[1 - cur],
+                           dL_domega ? gom : nullptr, mask, st);
+      if (e == hipSuccess && mask) e = launch_mark(mask, list, cnt, A.k, 0, st);
+      cur = 1 - cur;
+    }
+  }
+  if (e == hipSuccess) e = launch_from_pitch(lam[cur], r64, dL_df0, din, Q, nx, ny, pitch, qs, st);
+  if (e == hipSuccess && dL_domega)
+    e = launch_from_pitch(gom, r64, dL_domega, din, 1, nx, ny, pitch, qs, st);
+  if (e != hipSuccess) return hip_fail(e, "lbm_backward");
+  return LBM_OK;
 }
 
 void lbm_destroy(lbm_ctx* c) { delete c; }

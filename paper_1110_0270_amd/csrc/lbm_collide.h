@@ -1,0 +1,125 @@
+// Collision of one site (LBGK, MRT, ELBM) and the positivity rule, shared by
+// the step kernel, the adjoint's recompute and the adjoint kernel so that all
+// of them take bit-identical branches.
+#pragma once
+
+#include "lbm_site.h"
+
+namespace lbm {
+
+template <class R>
+struct CollInfo {
+  R alpha = R(2);   // ELBM alpha (2 elsewhere)
+  int branch = EB_ROOT;
+  bool f64 = false; // ELBM root solved in FP64
+  int pos_arg = -1; // positivity rule: component set to 0, -1 if inactive
+  R phi = R(1);     // positivity rule: homothety coefficient
+};
+
+// Collision (eq. CollisionIntegral; section 5 MRT in moment space; section
+// 3 ELBM), in the storage representation: d = f* - f, om the relaxation rate
+// (LBGK omega, MRT shear rate s_nu, ELBM 2 beta).
+template <class S, int Q, int COLL>
+__device__ __forceinline__ void collide_site(const StepArgs<typename StoreT<S>::R>& A,
+                                             const typename StoreT<S>::R v[Q],
+                                             const typename StoreT<S>::R feq[Q],
+                                             const typename StoreT<S>::R d[Q],
+                                             typename StoreT<S>::R om,
+                                             typename StoreT<S>::R post[Q],
+                                             CollInfo<typename StoreT<S>::R>& ci) {
+  using R = typename StoreT<S>::R;
+  constexpr bool SH = StoreT<S>::shifted;
+  if constexpr (COLL == COLL_LBGK) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) post[i] = v[i] + om * d[i];
+  } else if constexpr (COLL == COLL_MRT) {
+    R m[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      R s = R(0);
+#pragma unroll
+      for (int j = 0; j < Q; ++j) s += A.M[k * Q + j] * d[j];
+      m[k] = s * (((A.nu_rows >> k) & 1u) ? om : A.rates[k]);
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      R s = R(0);
+#pragma unroll
+      for (int k = 0; k < Q; ++k) s += A.Minv[i * Q + k] * m[k];
+      post[i] = v[i] + s;
+    }
+  } else {  // ELBM
+    R fa[Q], qa[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const R sh = SH ? wt<R, Q>(i) * A.rho0 : R(0);
+      fa[i] = v[i] + sh;
+      qa[i] = feq[i] + sh;
+    }
+    const R dSe = delta_s<R, Q>(fa, qa, d);
+    const R amax = alpha_max<R, Q>(fa, d);
+    int br = EB_ROOT;
+    R alpha;
+    ElbmParams<R> ep{A.eps, A.atol, A.dS_cut, A.max_iter, A.norm, A.fallback};
+    bool f64 = false;
+    if constexpr (sizeof(R) == 4) {
+      if (amax < A.f64_below) {
+        // FP64 solve near the no-root (degenerate) branch.
+        double fd[Q], qd[Q], Dd[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          fd[i] = (double)fa[i];
+          qd[i] = (double)qa[i];
+          Dd[i] = qd[i] - fd[i];
+        }
+        const double dSd = delta_s<double, Q>(fd, qd, Dd);
+        ElbmParams<double> e64{A.eps64, 0.0, A.dS_cut64, A.max_iter, A.norm, A.fallback};
+        alpha = (R)elbm_alpha<double, Q>(fd, qd, Dd, dSd, alpha_max<double, Q>(fd, Dd), e64, br);
+        f64 = true;
+      } else {
+        alpha = elbm_alpha<R, Q>(fa, qa, d, dSe, amax, ep, br);
+      }
+    } else {
+      alpha = elbm_alpha<R, Q>(fa, qa, d, dSe, amax, ep, br);
+    }
+    const R ab = alpha * (om * R(0.5));
+#pragma unroll
+    for (int i = 0; i < Q; ++i) post[i] = v[i] + ab * d[i];
+    ci.alpha = alpha;
+    ci.branch = br;
+    ci.f64 = f64;
+  }
+}
+
+// Positivity rule (section 4): a collided state with a negative component
+// moves along the line to f* until the first component reaches 0.
+template <class S, int Q>
+__device__ __forceinline__ void positivity_site(const StepArgs<typename StoreT<S>::R>& A,
+                                                const typename StoreT<S>::R feq[Q],
+                                                typename StoreT<S>::R post[Q],
+                                                CollInfo<typename StoreT<S>::R>& ci) {
+  using R = typename StoreT<S>::R;
+  constexpr bool SH = StoreT<S>::shifted;
+  R phi = r_inf<R>();
+  int arg = -1;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const R sh = SH ? wt<R, Q>(i) * A.rho0 : R(0);
+    const R pa = post[i] + sh, qa = feq[i] + sh;
+    if (pa < R(0) && qa > R(0)) {
+      const R r = qa / (qa - pa);
+      if (r < phi) { phi = r; arg = i; }
+    }
+  }
+  if (arg >= 0) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const R sh = SH ? wt<R, Q>(i) * A.rho0 : R(0);
+      post[i] = (i == arg) ? -sh : feq[i] + phi * (post[i] - feq[i]);
+    }
+    ci.pos_arg = arg;
+    ci.phi = phi;
+  }
+}
+
+}  // namespace lbm

@@ -14,7 +14,7 @@
 #include "lbm_internal.h"
 #include <hip/hip_ext.h>
 
-#include "lbm_site.h"
+#include "lbm_collide.h"
 
 namespace lbm {
 
@@ -139,88 +139,18 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<typename StoreT<S>:
   bool pos_event = false;
   if (valid) {
     const R om = A.omega_field ? A.omega_field[(long long)y * A.pitch + x] : A.omega;
-    if constexpr (COLL == COLL_LBGK) {
-#pragma unroll
-      for (int i = 0; i < Q; ++i) post[i] = v[i] + om * d[i];
-    } else if constexpr (COLL == COLL_MRT) {
-      R m[Q];
-#pragma unroll
-      for (int k = 0; k < Q; ++k) {
-        R s = R(0);
-#pragma unroll
-        for (int j = 0; j < Q; ++j) s += A.M[k * Q + j] * d[j];
-        m[k] = s * (((A.nu_rows >> k) & 1u) ? om : A.rates[k]);
-      }
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        R s = R(0);
-#pragma unroll
-        for (int k = 0; k < Q; ++k) s += A.Minv[i * Q + k] * m[k];
-        post[i] = v[i] + s;
-      }
-    } else {  // ELBM
-      R fa[Q], qa[Q];
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const R sh = SH ? wt<R, Q>(i) * A.rho0 : R(0);
-        fa[i] = v[i] + sh;
-        qa[i] = feq[i] + sh;
-      }
-      const R dSe = delta_s<R, Q>(fa, qa, d);
-      const R amax = alpha_max<R, Q>(fa, d);
-      int br = EB_ROOT;
-      R alpha;
-      ElbmParams<R> ep{A.eps, A.atol, A.dS_cut, A.max_iter, A.norm, A.fallback};
-      bool f64 = false;
-      if constexpr (sizeof(R) == 4) {
-        if (amax < A.f64_below) {
-          // FP64 solve near the no-root (degenerate) branch.
-          double fd[Q], qd[Q], Dd[Q];
-#pragma unroll
-          for (int i = 0; i < Q; ++i) {
-            fd[i] = (double)fa[i];
-            qd[i] = (double)qa[i];
-            Dd[i] = qd[i] - fd[i];
-          }
-          const double dSd = delta_s<double, Q>(fd, qd, Dd);
-          ElbmParams<double> e64{A.eps64, 0.0, A.dS_cut64, A.max_iter, A.norm, A.fallback};
-          alpha = (R)elbm_alpha<double, Q>(fd, qd, Dd, dSd, alpha_max<double, Q>(fd, Dd), e64, br);
-          f64 = true;
-        } else {
-          alpha = elbm_alpha<R, Q>(fa, qa, d, dSe, amax, ep, br);
-        }
-      } else {
-        alpha = elbm_alpha<R, Q>(fa, qa, d, dSe, amax, ep, br);
-      }
-      const R ab = alpha * (om * R(0.5));
-#pragma unroll
-      for (int i = 0; i < Q; ++i) post[i] = v[i] + ab * d[i];
+    CollInfo<R> ci;
+    collide_site<S, Q, COLL>(A, v, feq, d, om, post, ci);
+    if constexpr (COLL == COLL_ELBM) {
       if (A.count_events) {
-        count_event(br == EB_NOROOT, A.counters + CNT_ELBM_NOROOT);
-        count_event(f64, A.counters + CNT_ELBM_F64);
-        count_event(br == EB_NONPOS, A.counters + CNT_ELBM_NONPOS);
+        count_event(ci.branch == EB_NOROOT, A.counters + CNT_ELBM_NOROOT);
+        count_event(ci.f64, A.counters + CNT_ELBM_F64);
+        count_event(ci.branch == EB_NONPOS, A.counters + CNT_ELBM_NONPOS);
       }
     }
     if (A.positivity) {
-      R phi = r_inf<R>();
-      int arg = -1;
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const R sh = SH ? wt<R, Q>(i) * A.rho0 : R(0);
-        const R pa = post[i] + sh, qa = feq[i] + sh;
-        if (pa < R(0) && qa > R(0)) {
-          const R r = qa / (qa - pa);
-          if (r < phi) { phi = r; arg = i; }
-        }
-      }
-      if (arg >= 0) {
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-          const R sh = SH ? wt<R, Q>(i) * A.rho0 : R(0);
-          post[i] = (i == arg) ? -sh : feq[i] + phi * (post[i] - feq[i]);
-        }
-        pos_event = true;
-      }
+      positivity_site<S, Q>(A, feq, post, ci);
+      pos_event = ci.pos_arg >= 0;
     }
     S* dst = (S*)A.dst;
 #pragma unroll

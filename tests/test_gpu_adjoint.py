@@ -1,0 +1,259 @@
+"""GPU parity of the adjoint (lbm_backward, called through the C ABI)
+against the FP64 oracle's autograd gradient on the same seeded inputs.
+
+Loss L = sum(w * f_T) with seeded weights w, so dL/df_T = w.  The library's
+dL/df0 and per-site dL/d omega are compared with the oracle's gradients:
+FP64 storage max |gpu - oracle| <= tol * max |oracle| with tol = 1e-11
+(1e-9 through ELBM roots, which carry the root solve's 1e-14 tolerance
+through the implicit derivative); FP32 storage 1e-4 (1e-3 ELBM), the
+accumulated FP32 rounding of a few steps of forward recompute and adjoint.
+Rollouts span several checkpoint segments with a ragged last one, so the
+recompute from checkpoints and the selection tape are exercised."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from tests.parity_util import lattice, make_sim, oracle_config, random_state
+
+pytestmark = pytest.mark.gpu
+
+NARROW = dict(nx=70, ny=37)
+CASES = {
+    "lbgk_periodic": dict(bc="periodic", omega=1.7),
+    "lbgk_cavity_ehrenfest_pos": dict(bc="cavity", u_lid=0.1, omega=1.98, ehrenfest=True,
+                                      ehr_k=9, ehr_delta=0.0, positivity=True, _amp=0.4),
+    "lbgk_couette": dict(bc="couette", u_lid=0.05, nu=0.02),
+    "lbgk_bounceback_entropic_eq": dict(bc="bounceback", nu=0.01, equilibrium="entropic"),
+    "lbgk_positivity": dict(bc="periodic", omega=1.95, positivity=True, _amp=0.6),
+    "mrt_m1_field_cavity": dict(bc="cavity", u_lid=0.1, collision="mrt", s_e=1.64,
+                                s_eps=1.54, s_q=1.9, _field=True),
+    "mrt_m2_periodic": dict(bc="periodic", nu=0.002, collision="mrt", mrt_basis="M2"),
+    "mrt_ehrenfest_pos": dict(bc="cavity", u_lid=0.1, nu=1e-3, collision="mrt", s_e=1.64,
+                              s_eps=1.64, s_q=1.9, ehrenfest=True, ehr_k=9, ehr_delta=1e-4,
+                              positivity=True, _amp=0.3),
+    "elbm_periodic": dict(bc="periodic", nu=1e-4, collision="elbm"),
+    "elbm_field_cavity": dict(bc="cavity", u_lid=0.1, collision="elbm", _field=True),
+    "elbm_far_positivity": dict(bc="periodic", nu=1e-4, collision="elbm", positivity=True,
+                                _amp=0.6),
+    "elbm_far_ehrenfest_rule": dict(bc="periodic", nu=1e-4, collision="elbm",
+                                    elbm_fallback="ehrenfest", _amp=0.6),
+    "elbm_ehrenfest": dict(bc="periodic", nu=1e-4, collision="elbm", ehrenfest=True,
+                           ehr_k=12, ehr_delta=0.0, _amp=0.2),
+    "d1q3_shock_ehrenfest": dict(lattice="D1Q3", nx=300, ny=1, bc="bounceback", nu=1e-4,
+                                 ehrenfest=True, ehr_k=4, ehr_delta=0.0, _amp=0.2),
+    "d1q3_elbm_periodic": dict(lattice="D1Q3", nx=300, ny=1, bc="periodic", nu=1e-4,
+                               collision="elbm", _amp=0.2),
+}
+
+
+def _params(name):
+    p = {"lattice": "D2Q9", **NARROW, **CASES[name]}
+    amp = p.pop("_amp", 0.05)
+    field = p.pop("_field", False)
+    return p, amp, field
+
+
+def _kind(p):
+    return "entropic" if (p.get("collision") == "elbm" or p.get("equilibrium") == "entropic") else "poly"
+
+
+def _omega_of(p):
+    return O.relaxation_rate(oracle_config(p))
+
+
+def _weights(shape, seed):
+    return torch.tensor(np.random.default_rng(seed).normal(size=shape), dtype=torch.float64)
+
+
+def _oracle_grad(p, f0, n, omega, w):
+    """Gradients of sum(w * f_n) by the oracle's autograd; omega is a per-site
+    tensor (a uniform one when the case has a scalar rate)."""
+    lat, cfg = lattice(p), oracle_config(p)
+    g0 = f0.clone().requires_grad_(True)
+    om = omega.clone().requires_grad_(True)
+    g = g0
+    infos = []
+    for _ in range(n):
+        g, info = O.step(lat, cfg, g, om)
+        infos.append(info)
+    (g * w).sum().backward()
+    return g.detach(), g0.grad, om.grad, infos
+
+
+def _gpu_grad(p, f0, n, K, w, field, storage="f64", max_steps=None):
+    sim = make_sim({**p, "checkpoint_every": K, "max_steps": max_steps or n,
+                    "omega_field": field is not None}, storage)
+    sim.set_populations(f0.to("cuda"))
+    if field is not None:
+        sim.set_omega(field.to("cuda"))
+    sim.step(n)
+    fT = sim.populations().cpu()
+    g0 = torch.empty(sim.shape, dtype=torch.float64, device="cuda")
+    gw = torch.empty((p["ny"], p["nx"]), dtype=torch.float64, device="cuda")
+    sim.backward(w.to("cuda"), g0, gw)
+    torch.cuda.synchronize()
+    return sim, fT, g0.cpu(), gw.cpu()
+
+
+def _field_for(p, field):
+    if not field:
+        return None
+    from lbm_inputs import generators as G
+    return torch.tensor(G.smooth_omega_field(p["nx"], p["ny"], seed=41), dtype=torch.float64)
+
+
+def _rel(a, b):
+    return float((a - b).abs().max() / b.abs().max().clamp(min=1e-300))
+
+
+def _check_case(name, storage, n, K, tol64, tol32):
+    p, amp, want_field = _params(name)
+    field = _field_for(p, want_field)
+    f0 = random_state(p, 23, amp=amp, kind=_kind(p))
+    w = _weights(f0.shape, 29)
+    omega = field if field is not None else torch.full((p["ny"], p["nx"]), _omega_of(p),
+                                                       dtype=torch.float64)
+    fT_o, g0_o, gw_o, infos = _oracle_grad(p, f0, n, omega, w)
+    sim, fT, g0, gw = _gpu_grad(p, f0, n, K, w, field, storage)
+    tol = tol64 if storage == "f64" else tol32
+    e0, ew = _rel(g0, g0_o), _rel(gw, gw_o)
+    assert e0 <= tol, f"dL/df0: {e0:.3e} > {tol:.0e}"
+    assert ew <= tol, f"dL/domega: {ew:.3e} > {tol:.0e}"
+    return sim, infos, fT, fT_o
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_adjoint_fp64_matches_oracle_gradient(name):
+    elbm = CASES[name].get("collision") == "elbm"
+    sim, infos, fT, fT_o = _check_case(name, "f64", 5, 2, 1e-9 if elbm else 1e-11, None)
+    # the branches the case is meant to exercise were taken
+    if CASES[name].get("ehrenfest"):
+        assert sum(int(i["selected"].numel()) for i in infos) > 0
+    if CASES[name].get("positivity") and CASES[name].get("collision") != "elbm":
+        assert sum(int(i["positivity_mask"].sum()) for i in infos) > 0
+    if name.startswith("elbm_far"):
+        assert any(bool((i["branch"] == O.ELBM_NOROOT).any()) for i in infos)
+    # the backward pass leaves the final state in place
+    assert torch.equal(sim.populations().cpu(), fT)
+
+
+@pytest.mark.parametrize("name", ["lbgk_periodic", "mrt_m1_field_cavity",
+                                  "lbgk_cavity_ehrenfest_pos", "elbm_periodic"])
+def test_adjoint_fp32_storage(name):
+    elbm = CASES[name].get("collision") == "elbm"
+    _check_case(name, "f32", 4, 3, None, 1e-3 if elbm else 1e-4)
+
+
+@pytest.mark.parametrize("n,K", [(1, 1), (6, 6), (7, 3), (9, 4)])
+def test_adjoint_checkpoint_intervals(n, K):
+    """Any interval gives the same gradient: full segments, one segment, and
+    ragged last segments."""
+    _check_case("mrt_ehrenfest_pos", "f64", n, K, 1e-11, None)
+
+
+def test_adjoint_zero_steps_is_identity():
+    p, amp, _ = _params("lbgk_periodic")
+    f0 = random_state(p, 3, amp=amp)
+    w = _weights(f0.shape, 5)
+    sim, fT, g0, gw = _gpu_grad(p, f0, 0, 4, w, None, max_steps=4)
+    assert torch.equal(g0, w)
+    assert torch.equal(gw, torch.zeros_like(gw))
+
+
+def test_adjoint_repeatable_and_after_more_steps():
+    """Two backward calls on one rollout agree bit for bit; stepping further
+    extends the recorded rollout."""
+    p, amp, _ = _params("lbgk_cavity_ehrenfest_pos")
+    f0 = random_state(p, 7, amp=amp)
+    w = _weights(f0.shape, 9)
+    sim = make_sim({**p, "checkpoint_every": 3, "max_steps": 8}, "f64")
+    sim.set_populations(f0.to("cuda"))
+    sim.step(2)
+    sim.step(3)
+    a = torch.empty(sim.shape, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    sim.backward(w.to("cuda"), a)
+    sim.backward(w.to("cuda"), b)
+    assert torch.equal(a, b)
+    omega = torch.full((p["ny"], p["nx"]), _omega_of(p), dtype=torch.float64)
+    _, g0_o, _, _ = _oracle_grad(p, f0, 5, omega, w)
+    assert _rel(a.cpu(), g0_o) <= 1e-11
+
+
+def test_adjoint_errors():
+    from paper_1110_0270_amd import lbm as B
+    p, amp, _ = _params("lbgk_periodic")
+    f0 = random_state(p, 3, amp=amp).to("cuda")
+    g = torch.empty_like(f0)
+    sim = make_sim(p, "f64")                      # no checkpointing
+    sim.set_populations(f0)
+    sim.step(1)
+    with pytest.raises(B.LBMError) as e:
+        sim.backward(f0, g)
+    assert e.value.status == B.LBM_ESTATE
+    sim = make_sim({**p, "checkpoint_every": 2, "max_steps": 3}, "f64")
+    sim.set_populations(f0)
+    with pytest.raises(B.LBMError) as e:
+        sim.step(4)                               # longer than max_steps
+    assert e.value.status == B.LBM_ESTATE
+    pm = {**p, "median": True, "checkpoint_every": 2, "max_steps": 3}
+    sim = make_sim(pm, "f64")
+    sim.set_populations(f0)
+    sim.step(1)
+    with pytest.raises(B.LBMError) as e:
+        sim.backward(f0, g)
+    assert e.value.status == B.LBM_EUNSUPPORTED
+
+
+def test_rollout_autograd_function():
+    """LBMRollout (torch.autograd.Function over the library) returns the
+    oracle's gradient for f0 and the omega field."""
+    from paper_1110_0270_amd import lbm as B
+    p, amp, _ = _params("mrt_m1_field_cavity")
+    field = _field_for(p, True)
+    f0 = random_state(p, 31, amp=amp)
+    w = _weights(f0.shape, 37)
+    sim = make_sim({**p, "checkpoint_every": 2, "max_steps": 4, "omega_field": True}, "f64")
+    f0d = f0.to("cuda").requires_grad_(True)
+    omd = field.to("cuda").requires_grad_(True)
+    fT = B.LBMRollout.apply(f0d, omd, sim, 4)
+    (fT * w.to("cuda")).sum().backward()
+    _, g0_o, gw_o, _ = _oracle_grad(p, f0, 4, field, w)
+    assert _rel(f0d.grad.cpu(), g0_o) <= 1e-11
+    assert _rel(omd.grad.cpu(), gw_o) <= 1e-11
+
+
+def test_adjoint_full_size_directional_derivative():
+    """The cavity adjoint workload's configuration (512^2, MRT with an omega
+    field, Ehrenfest k = 9) in FP64 over 48 steps, checkpoints every 16:
+    <dL/df0, v> and <dL/domega, z> equal central differences of the
+    library's own forward pass (the oracle cannot run this size)."""
+    from lbm_inputs.workloads import workload
+    wl = workload("cavity_adjoint_512")
+    p = {k: wl[k] for k in ("lattice", "nx", "ny", "bc", "u_lid", "collision", "s_e", "s_eps",
+                            "s_q", "ehrenfest", "ehr_k", "ehr_delta")}
+    field = _field_for(p, True)
+    f0 = random_state(p, 43, amp=0.05)
+    rng = np.random.default_rng(47)
+    w = torch.tensor(rng.normal(size=f0.shape))
+    v = torch.tensor(rng.normal(size=f0.shape))
+    z = torch.tensor(rng.normal(size=field.shape))
+    n = 48
+    sim, fT, g0, gw = _gpu_grad(p, f0, n, 16, w, field)
+    wd = w.to("cuda")
+
+    def loss(f, om):
+        s = make_sim({**p, "omega_field": True}, "f64")
+        s.set_populations(f.to("cuda"))
+        s.set_omega(om.to("cuda"))
+        s.step(n)
+        return float((s.populations() * wd).sum())
+
+    h = 1e-6
+    fd = (loss(f0 + h * v, field) - loss(f0 - h * v, field)) / (2 * h)
+    ad = float((g0 * v).sum())
+    assert abs(ad - fd) <= 1e-6 * abs(ad)
+    fdw = (loss(f0, field + h * z) - loss(f0, field - h * z)) / (2 * h)
+    adw = float((gw * z).sum())
+    assert abs(adw - fdw) <= 1e-6 * abs(adw)
