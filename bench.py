@@ -1,7 +1,8 @@
 #!/usr/bin/env python3
 """Throughput of the fused D2Q9 collide-and-stream step with the Ehrenfest
 limiter on the periodic double shear layer (4096 x 4096, nu = 1e-5, LBGK,
-top 0.1 % of sites by nonequilibrium entropy sent to equilibrium each step).
+top 0.1 % of sites by nonequilibrium entropy sent to equilibrium each step),
+and of its adjoint.
 
 One JSON line on stdout:
   value     whole-step throughput in MLUPS (million lattice-site updates per
@@ -10,7 +11,16 @@ One JSON line on stdout:
             write 9, per site) over its average duration from HIP events
             recorded around each launch inside the timed region, against
             the MI355X HBM peak of 8 TB/s;
-  forms     the same workload with FP64 and shifted FP16/BF16 storage;
+  forms     the same workload with FP64 and shifted FP16/BF16 storage, each
+            run for the same number of steps as the FP32 line, with the
+            relative L2 error of rho and u against the FP64 run;
+  adjoint   the 512^2 lid-driven cavity (MRT with a per-site shear rate,
+            Ehrenfest k = 9), 8192 steps forward and the adjoint with
+            checkpoints every 256 steps, in FP32 and FP64; the FP32
+            gradients' error against the FP64 ones;
+  adjoint_scale  forward and adjoint of the shear-layer workload (FP32,
+            128 steps, checkpoints every 16), with the adjoint kernel's
+            bytes over its event-timed duration;
   cpu_baseline  the FP64 oracle timed on this host on two full steps.
 Progress goes to stderr.
 """
@@ -34,7 +44,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_form(w: dict, storage: str, steps: int, warmup: int) -> dict:
+def run_form(w: dict, storage: str, steps: int, warmup: int) -> tuple:
     import torch
 
     from lbm_inputs import generators as G
@@ -69,9 +79,78 @@ def run_form(w: dict, storage: str, steps: int, warmup: int) -> dict:
         "diverged_step": int(st.diverged_step),
         "mass": st.mass,
     }
+    mom = sim.moments()
     del sim
     torch.cuda.empty_cache()
-    return res
+    return res, mom
+
+
+def rel_l2(a, b) -> float:
+    return float(((a - b).norm() / b.norm().clamp(min=1e-300)).item())
+
+
+def velocity_loss_grad(f, tx, ty):
+    """L = sum_x |u(x) - u_t(x)|^2 of the final state and dL/df:
+    dL/df_i = 2 (u - u_t) . (v_i - u) / rho (velocity i = 3 (b+1) + (a+1))."""
+    import torch
+    rho = f.sum(0)
+    v = torch.tensor([[(i % 3) - 1, (i // 3) - 1] for i in range(9)], dtype=f.dtype,
+                     device=f.device)
+    ux = (v[:, 0].view(9, 1, 1) * f).sum(0) / rho
+    uy = (v[:, 1].view(9, 1, 1) * f).sum(0) / rho
+    ex, ey = ux - tx, uy - ty
+    loss = float((ex * ex + ey * ey).sum())
+    g = 2 * (ex * (v[:, 0].view(9, 1, 1) - ux) + ey * (v[:, 1].view(9, 1, 1) - uy)) / rho
+    return loss, g.contiguous()
+
+
+def run_adjoint(w: dict, storage: str, steps: int, K: int, init: str, dldomega: bool) -> dict:
+    """Forward `steps` steps with checkpoints every K, then the adjoint of the
+    velocity misfit to the seeded Fourier target."""
+    import torch
+
+    from lbm_inputs import generators as G
+    from paper_1110_0270_amd import lbm as B
+
+    nx, ny = w["nx"], w["ny"]
+    cfg = B.make_config(**{**w, "storage": storage, "checkpoint_every": K, "max_steps": steps})
+    sim = B.Simulation(cfg)
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")  # noqa: E731
+    if init == "uniform_rest":
+        rho, ux, uy = G.uniform_rest(nx, ny)
+    else:
+        rho, ux, uy = G.double_shear_layer(nx)
+    sim.set_equilibrium(t(rho), t(ux), t(uy))
+    if w.get("omega_field"):
+        sim.set_omega(t(G.smooth_omega_field(nx, ny, seed=w.get("omega_seed", 41))))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fwd_kern, _ = sim.profile_step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tx, ty = G.fourier_target(nx, ny, seed=w.get("target_seed", 4))
+    loss, g = velocity_loss_grad(sim.populations(), t(tx), t(ty))
+    g0 = torch.empty_like(g)
+    gw = torch.empty((ny, nx), dtype=torch.float64, device="cuda") if dldomega else None
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    adj_kern, _ = sim.profile_backward(g, g0, gw)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    n = nx * ny
+    fwd_s, bwd_s = t1 - t0, t3 - t2
+    res = {
+        "storage": storage, "steps": steps, "checkpoint_every": K, "loss": loss,
+        "fwd_ms": fwd_s * 1e3, "bwd_ms": bwd_s * 1e3,
+        "fwd_mlups": n * steps / fwd_s / 1e6, "bwd_mlups": n * steps / bwd_s / 1e6,
+        "fwd_adjoint_mlups": n * steps / (fwd_s + bwd_s) / 1e6,
+        "fwd_kernel_us": fwd_kern / steps * 1e3, "adjoint_kernel_us": adj_kern / steps * 1e3,
+        "workspace_gb": sim.workspace.numel() / 1e9,
+    }
+    out = (res, g0, gw)
+    del sim
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(w: dict, steps: int) -> dict:
@@ -95,6 +174,14 @@ def cpu_baseline(w: dict, steps: int) -> dict:
                       f"{dt:.1f} s"}
 
 
+def _round(x):
+    if isinstance(x, dict):
+        return {k: _round(v) for k, v in x.items()}
+    if isinstance(x, float):
+        return float(f"{x:.6g}")
+    return x
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,7 +189,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--forms", default="f64,f16s,bf16s")
-    ap.add_argument("--form-steps", type=int, default=300)
+    ap.add_argument("--adjoint-steps", type=int, default=8192)
+    ap.add_argument("--scale-adjoint-steps", type=int, default=128)
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -123,18 +211,59 @@ def main():
         print(json.dumps({"copy_bytes": args.copy_probe, "launches": 10}))
         return
 
+    import torch
+
     from lbm_inputs.workloads import workload
 
     w = workload("shear_layer_4096")
     log(f"[bench] {w['nx']}x{w['ny']} D2Q9 LBGK + Ehrenfest k={w['ehr_k']}, storage {args.storage}")
-    main_res = run_form(w, args.storage, args.steps, args.warmup)
+    main_res, main_mom = run_form(w, args.storage, args.steps, args.warmup)
     log(f"[bench] {args.storage}: {main_res['mlups']:.0f} MLUPS, kernel {main_res['kernel_ms']*1e3:.1f} us "
         f"= {main_res['kernel_gbs']:.0f} GB/s")
     forms = {args.storage: main_res}
+    moms = {args.storage: main_mom}
     for s in [x for x in args.forms.split(",") if x and x != args.storage]:
-        r = run_form(w, s, args.form_steps, 100)
-        forms[s] = r
+        r, m = run_form(w, s, args.steps, args.warmup)
+        forms[s], moms[s] = r, m
         log(f"[bench] {s}: {r['mlups']:.0f} MLUPS, kernel {r['kernel_gbs']:.0f} GB/s")
+    if "f64" in moms:
+        ref = moms["f64"]
+        for s, m in moms.items():
+            forms[s]["err_vs_f64_after_steps"] = args.steps + args.warmup
+            forms[s]["rel_l2_rho_minus_1"] = rel_l2(m[0] - 1.0, ref[0] - 1.0)
+            forms[s]["rel_l2_u"] = rel_l2(torch.stack(m[1:]), torch.stack(ref[1:]))
+    del moms, main_mom
+
+    adjoint = None
+    if args.adjoint_steps > 0:
+        wa = workload("cavity_adjoint_512")
+        adjoint = {"workload": "cavity_adjoint_512", "nx": wa["nx"], "ny": wa["ny"],
+                   "collision": "mrt", "omega_field": True, "limiters": "ehrenfest k=9 delta=1e-3"}
+        grads = {}
+        for s in ("f32", "f64"):
+            r, g0, gw = run_adjoint(wa, s, args.adjoint_steps, wa["checkpoint_every"],
+                                    "uniform_rest", True)
+            adjoint[s] = r
+            grads[s] = (g0, gw)
+            log(f"[bench] adjoint 512^2 {s}: fwd {r['fwd_mlups']:.0f} MLUPS, adjoint "
+                f"{r['bwd_mlups']:.0f} MLUPS, fwd+adjoint {r['fwd_adjoint_mlups']:.0f} MLUPS")
+        adjoint["f32"]["grad_rel_l2_f0_vs_f64"] = rel_l2(grads["f32"][0], grads["f64"][0])
+        adjoint["f32"]["grad_rel_l2_omega_vs_f64"] = rel_l2(grads["f32"][1], grads["f64"][1])
+        del grads
+
+    adjoint_scale = None
+    if args.scale_adjoint_steps > 0:
+        r, g0, gw = run_adjoint(w, "f32", args.scale_adjoint_steps, 16, "shear", True)
+        del g0, gw
+        n = w["nx"] * w["ny"]
+        adj_bytes = n * (9 * (4 + 4 + 4) + 2 * 4)     # lambda in/out, f, omega-gradient RMW
+        r["adjoint_alg_bytes_per_launch"] = adj_bytes
+        r["adjoint_kernel_gbs"] = adj_bytes / (r["adjoint_kernel_us"] * 1e-6) / 1e9
+        r["adjoint_frac_of_hbm_peak"] = r["adjoint_kernel_gbs"] / HBM_PEAK_GBS
+        adjoint_scale = {"workload": "shear_layer_4096", **r}
+        log(f"[bench] adjoint 4096^2 f32: fwd+adjoint {r['fwd_adjoint_mlups']:.0f} MLUPS, adjoint "
+            f"kernel {r['adjoint_kernel_us']:.1f} us = {r['adjoint_kernel_gbs']:.0f} GB/s")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host ...")
@@ -163,8 +292,9 @@ def main():
                      "traffic": None, "kernel": "k_step (fused collide-stream)",
                      "kernel_us": round(main_res["kernel_ms"] * 1e3, 2),
                      "alg_bytes_per_launch": main_res["alg_bytes_per_launch"]},
-        "forms": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
-                      for kk, vv in v.items()} for k, v in forms.items()},
+        "forms": _round(forms),
+        "adjoint": _round(adjoint),
+        "adjoint_scale": _round(adjoint_scale),
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -213,6 +213,13 @@ lbm_status lbm_counters(lbm_ctx* ctx, unsigned long long* out, int n);
  * work (ms).  For measurement; the events add a few microseconds per step. */
 lbm_status lbm_profile_step(lbm_ctx* ctx, long long n, double out[2]);
 
+/* lbm_backward with each step's adjoint kernel bracketed by HIP events,
+ * then synchronise.  out[0] = summed duration of those kernels (ms), out[1]
+ * = duration of the whole backward pass, recompute included (ms).  For
+ * measurement. */
+lbm_status lbm_profile_backward(lbm_ctx* ctx, const void* dL_dfT, void* dL_df0,
+                                void* dL_domega, int dtype, double out[2]);
+
 /* Free the context (not the caller's buffers). NULL is allowed. */
 void lbm_destroy(lbm_ctx* ctx);
 

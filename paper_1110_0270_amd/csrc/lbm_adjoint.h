@@ -43,8 +43,10 @@ long long* adjoint_count_slot(const AdjointLayout& L, char* ws, long long t);
 // the compute precision (double for LBM_F64 storage, float otherwise) with
 // src = the state the step read; lam_in/lam_out/gom use the same precision
 // and the pitched layout of the lattice.
+// e0/e1: optional events recorded right before and after the kernel.
 hipError_t launch_adjoint(int storage, int Q, int coll, const void* step_args, const void* lam_in,
-                          void* lam_out, void* gom, const unsigned char* mask, hipStream_t s);
+                          void* lam_out, void* gom, const unsigned char* mask, hipStream_t s,
+                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // f* written into step_args->dst at the first *count sites of list (<= k).
 hipError_t launch_tape_fix(int storage, int Q, const void* step_args, const int32_t* list,
                            const long long* count, long long k, hipStream_t s);

@@ -14,6 +14,8 @@
 // attained it; ELBM through alpha, by implicit differentiation of
 // S(p + alpha (f* - p)) = S(p) on the root branch (section 3) or through the
 // attaining component of alpha_max on the positivity branch.
+#include <hip/hip_ext.h>
+
 #include "lbm_adjoint.h"
 #include "lbm_collide.h"
 
@@ -298,34 +300,48 @@ static int grid_of(long long n) {
   return (int)(g < 1 ? 1 : (g > 65535 * 16 ? 65535 * 16 : g));
 }
 
+template <class S, int Q, int COLL>
+static void launch_adj_k(const StepArgs<typename StoreT<S>::R>& A,
+                         const AdjArgs<typename StoreT<S>::R>& B, int g, hipStream_t s,
+                         hipEvent_t e0, hipEvent_t e1) {
+  if (e0 || e1)
+    hipExtLaunchKernelGGL((k_adjoint<S, Q, COLL>), dim3(g), dim3(256), 0, s, e0, e1, 0, A, B);
+  else
+    hipLaunchKernelGGL((k_adjoint<S, Q, COLL>), dim3(g), dim3(256), 0, s, A, B);
+}
+
 template <class S, int Q>
-static hipError_t launch_adj_q(int coll, const void* sargs, const void* aargs, hipStream_t s) {
+static hipError_t launch_adj_q(int coll, const void* sargs, const void* aargs, hipStream_t s,
+                               hipEvent_t e0, hipEvent_t e1) {
   using R = typename StoreT<S>::R;
   const StepArgs<R>& A = *(const StepArgs<R>*)sargs;
   const AdjArgs<R>& B = *(const AdjArgs<R>*)aargs;
   const int g = (int)(((long long)A.nx * A.ny + 255) / 256);
-  if (coll == COLL_LBGK) hipLaunchKernelGGL((k_adjoint<S, Q, COLL_LBGK>), dim3(g), dim3(256), 0, s, A, B);
-  else if (coll == COLL_ELBM) hipLaunchKernelGGL((k_adjoint<S, Q, COLL_ELBM>), dim3(g), dim3(256), 0, s, A, B);
-  else if constexpr (Q == 9) hipLaunchKernelGGL((k_adjoint<S, Q, COLL_MRT>), dim3(g), dim3(256), 0, s, A, B);
+  if (coll == COLL_LBGK) launch_adj_k<S, Q, COLL_LBGK>(A, B, g, s, e0, e1);
+  else if (coll == COLL_ELBM) launch_adj_k<S, Q, COLL_ELBM>(A, B, g, s, e0, e1);
+  else if constexpr (Q == 9) launch_adj_k<S, Q, COLL_MRT>(A, B, g, s, e0, e1);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 template <class S>
-static hipError_t launch_adj_s(int Q, int coll, const void* sargs, const void* aargs, hipStream_t s) {
-  return Q == 9 ? launch_adj_q<S, 9>(coll, sargs, aargs, s) : launch_adj_q<S, 3>(coll, sargs, aargs, s);
+static hipError_t launch_adj_s(int Q, int coll, const void* sargs, const void* aargs, hipStream_t s,
+                               hipEvent_t e0, hipEvent_t e1) {
+  return Q == 9 ? launch_adj_q<S, 9>(coll, sargs, aargs, s, e0, e1)
+                : launch_adj_q<S, 3>(coll, sargs, aargs, s, e0, e1);
 }
 
 hipError_t launch_adjoint(int storage, int Q, int coll, const void* step_args, const void* lam_in,
-                          void* lam_out, void* gom, const unsigned char* mask, hipStream_t s) {
+                          void* lam_out, void* gom, const unsigned char* mask, hipStream_t s,
+                          hipEvent_t e0, hipEvent_t e1) {
   if (storage == 0) {
     AdjArgs<double> B{(const double*)lam_in, (double*)lam_out, (double*)gom, mask};
-    return launch_adj_s<double>(Q, coll, step_args, &B, s);
+    return launch_adj_s<double>(Q, coll, step_args, &B, s, e0, e1);
   }
   AdjArgs<float> B{(const float*)lam_in, (float*)lam_out, (float*)gom, mask};
-  if (storage == 1) return launch_adj_s<float>(Q, coll, step_args, &B, s);
-  if (storage == 2) return launch_adj_s<_Float16>(Q, coll, step_args, &B, s);
-  return launch_adj_s<bf16_t>(Q, coll, step_args, &B, s);
+  if (storage == 1) return launch_adj_s<float>(Q, coll, step_args, &B, s, e0, e1);
+  if (storage == 2) return launch_adj_s<_Float16>(Q, coll, step_args, &B, s, e0, e1);
+  return launch_adj_s<bf16_t>(Q, coll, step_args, &B, s, e0, e1);
 }
 
 template <class S, int Q>

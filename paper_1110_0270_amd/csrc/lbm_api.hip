@@ -537,8 +537,55 @@ lbm_status lbm_selected(lbm_ctx* c, long long* idx, long long cap, long long* co
   return LBM_OK;
 }
 
+static lbm_status backward_impl(lbm_ctx* c, const void* dL_dfT, void* dL_df0, void* dL_domega,
+                                int dtype, std::vector<hipEvent_t>* ev);
+
 lbm_status lbm_backward(lbm_ctx* c, const void* dL_dfT, void* dL_df0, void* dL_domega, int dtype) {
   g_err.clear();
+  return backward_impl(c, dL_dfT, dL_df0, dL_domega, dtype, nullptr);
+}
+
+lbm_status lbm_profile_backward(lbm_ctx* c, const void* dL_dfT, void* dL_df0, void* dL_domega,
+                                int dtype, double out[2]) {
+  g_err.clear();
+  if (!c || !out) return fail(LBM_EINVAL, "NULL argument");
+  const long long T = c->steps;
+  std::vector<hipEvent_t> ev((size_t)(2 * T + 2), nullptr);
+  hipError_t e = hipSuccess;
+  for (auto& x : ev) {
+    e = hipEventCreate(&x);
+    if (e != hipSuccess) break;
+  }
+  lbm_status st = e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_profile_backward");
+  if (st == LBM_OK) {
+    e = hipEventRecord(ev[2 * T], c->stream);
+    st = e == hipSuccess ? backward_impl(c, dL_dfT, dL_df0, dL_domega, dtype, &ev)
+                         : hip_fail(e, "lbm_profile_backward");
+  }
+  if (st == LBM_OK) {
+    e = hipEventRecord(ev[2 * T + 1], c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[2 * T + 1]);
+    double kern = 0.0;
+    for (long long s = 0; s < T && e == hipSuccess; ++s) {
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, ev[2 * s], ev[2 * s + 1]);
+      kern += ms;
+    }
+    float tot = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&tot, ev[2 * T], ev[2 * T + 1]);
+    if (e != hipSuccess) st = hip_fail(e, "lbm_profile_backward");
+    out[0] = kern;
+    out[1] = tot;
+  }
+  for (auto& x : ev)
+    if (x) hipEventDestroy(x);
+  return st;
+}
+
+}  // extern "C"
+
+static lbm_status backward_impl(lbm_ctx* c, const void* dL_dfT, void* dL_df0, void* dL_domega,
+                                int dtype, std::vector<hipEvent_t>* ev) {
   if (!c || !dL_dfT || !dL_df0) return fail(LBM_EINVAL, "NULL argument");
   if (dtype != LBM_F64 && dtype != LBM_F32) return fail(LBM_EINVAL, "dtype must be LBM_F64 or LBM_F32");
   if (c->cfg.checkpoint_every <= 0 || !c->recorded)
@@ -590,7 +637,8 @@ lbm_status lbm_backward(lbm_ctx* c, const void* dL_dfT, void* dL_df0, void* dL_d
       const void* args = args_for(seg(t - t0), nullptr);
       if (e == hipSuccess)
         e = launch_adjoint(c->cfg.storage, Q, c->cfg.collision, args, lam[cur], lam[1 - cur],
-                           dL_domega ? gom : nullptr, mask, st);
+                           dL_domega ? gom : nullptr, mask, st,
+                           ev ? (*ev)[2 * t] : nullptr, ev ? (*ev)[2 * t + 1] : nullptr);
       if (e == hipSuccess && mask) e = launch_mark(mask, list, cnt, A.k, 0, st);
       cur = 1 - cur;
     }
@@ -601,6 +649,8 @@ lbm_status lbm_backward(lbm_ctx* c, const void* dL_dfT, void* dL_df0, void* dL_d
   if (e != hipSuccess) return hip_fail(e, "lbm_backward");
   return LBM_OK;
 }
+
+extern "C" {
 
 void lbm_destroy(lbm_ctx* c) { delete c; }
 

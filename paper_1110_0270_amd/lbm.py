@@ -33,7 +33,7 @@ EXPORTED = [
     "lbm_config_default", "lbm_workspace_bytes", "lbm_init", "lbm_set_equilibrium",
     "lbm_set_populations", "lbm_get_populations", "lbm_set_omega", "lbm_step",
     "lbm_moments", "lbm_backward", "lbm_stats_get", "lbm_selected", "lbm_counters",
-    "lbm_profile_step", "lbm_destroy", "lbm_last_error",
+    "lbm_profile_step", "lbm_profile_backward", "lbm_destroy", "lbm_last_error",
 ]
 
 
@@ -94,6 +94,7 @@ def library() -> ctypes.CDLL:
         "lbm_selected": (I, [P, ctypes.POINTER(LL), LL, ctypes.POINTER(LL)]),
         "lbm_counters": (I, [P, ctypes.POINTER(ctypes.c_ulonglong), I]),
         "lbm_profile_step": (I, [P, LL, ctypes.POINTER(ctypes.c_double)]),
+        "lbm_profile_backward": (I, [P, P, P, P, I, ctypes.POINTER(ctypes.c_double)]),
         "lbm_destroy": (None, [P]),
         "lbm_last_error": (ctypes.c_char_p, []),
     }
@@ -216,6 +217,14 @@ def lbm_profile_step(ctx, n: int):
     return out[0], out[1]
 
 
+def lbm_profile_backward(ctx, dL_dfT, dL_df0, dL_domega=None):
+    """(summed adjoint-kernel ms, whole backward ms)."""
+    out = (ctypes.c_double * 2)()
+    _check(library().lbm_profile_backward(ctx, _ptr(dL_dfT), _ptr(dL_df0), _ptr(dL_domega),
+                                          _dtype_code(dL_dfT), out), "lbm_profile_backward")
+    return out[0], out[1]
+
+
 def lbm_destroy(ctx):
     library().lbm_destroy(ctx)
 
@@ -326,6 +335,9 @@ class Simulation:
 
     def backward(self, dL_dfT, dL_df0, dL_domega=None):
         lbm_backward(self.ctx, dL_dfT, dL_df0, dL_domega)
+
+    def profile_backward(self, dL_dfT, dL_df0, dL_domega=None):
+        return lbm_profile_backward(self.ctx, dL_dfT, dL_df0, dL_domega)
 
 
 class LBMRollout(torch.autograd.Function):
