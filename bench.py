@@ -174,6 +174,67 @@ def cpu_baseline(w: dict, steps: int) -> dict:
                       f"{dt:.1f} s"}
 
 
+def precision_study(w: dict, checkpoints: list) -> dict:
+    """Error of the FP32, FP16-shifted and BF16-shifted forms against FP64
+    over a long run of the shear-layer workload, next to an FP64 control
+    started from the FP32-rounded initial state (its error is what the
+    flow's own amplification makes of one rounding of the initial state)."""
+    import torch
+
+    from lbm_inputs import generators as G
+    from paper_1110_0270_amd import lbm as B
+
+    rho, ux, uy = G.double_shear_layer(w["nx"])
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")  # noqa: E731
+    rounded = None
+    runs = {}
+    for form in ("f64", "f32", "f64_from_f32_init", "f16s", "bf16s"):
+        storage = "f64" if form.startswith("f64") else form
+        sim = B.Simulation(B.make_config(**{**w, "storage": storage}))
+        if form == "f64_from_f32_init":
+            sim.set_populations(rounded)
+        else:
+            sim.set_equilibrium(t(rho), t(ux), t(uy))
+        if form == "f32":
+            rounded = sim.populations()
+        done, snaps = 0, {}
+        t0 = time.perf_counter()
+        for c in checkpoints:
+            sim.step(c - done)
+            done = c
+            st = sim.stats(allow_status=(B.LBM_OK, B.LBM_EDIVERGED, B.LBM_ESELECT))
+            snaps[c] = {"mom": sim.moments(), "sel": set(sim.selected()),
+                        "mass": st.mass, "entropy": st.entropy,
+                        "diverged_step": int(st.diverged_step)}
+        torch.cuda.synchronize()
+        log(f"[study] {form}: {checkpoints[-1]} steps in {time.perf_counter() - t0:.1f} s")
+        runs[form] = snaps
+        del sim
+        torch.cuda.empty_cache()
+    ref = runs["f64"]
+    out = {"workload": "shear_layer_4096", "reference": "f64", "checkpoints": checkpoints,
+           "forms": {}}
+    for form, snaps in runs.items():
+        rows = []
+        for c in checkpoints:
+            a, b = snaps[c], ref[c]
+            du = torch.stack(a["mom"][1:]) - torch.stack(b["mom"][1:])
+            sa, sb = a["sel"], b["sel"]
+            rows.append({
+                "step": c,
+                "rel_l2_u": rel_l2(torch.stack(a["mom"][1:]), torch.stack(b["mom"][1:])),
+                "max_abs_u": float(du.abs().max()),
+                "rel_l2_rho_minus_1": rel_l2(a["mom"][0] - 1.0, b["mom"][0] - 1.0),
+                "max_abs_rho": float((a["mom"][0] - b["mom"][0]).abs().max()),
+                "selection_jaccard": len(sa & sb) / max(1, len(sa | sb)),
+                "mass_drift": a["mass"] / (w["nx"] * w["ny"]) - 1.0,
+                "entropy": a["entropy"],
+                "diverged_step": a["diverged_step"],
+            })
+        out["forms"][form] = rows
+    return out
+
+
 def _round(x):
     if isinstance(x, dict):
         return {k: _round(v) for k, v in x.items()}
@@ -189,6 +250,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--forms", default="f64,f16s,bf16s")
+    ap.add_argument("--study", default="", help="'precision': error of the storage forms "
+                    "against FP64 over a long shear-layer run (one JSON document)")
+    ap.add_argument("--study-checkpoints", default="100,1000,5000,10000,20000")
     ap.add_argument("--adjoint-steps", type=int, default=8192)
     ap.add_argument("--scale-adjoint-steps", type=int, default=128)
     ap.add_argument("--cpu-steps", type=int, default=2)
@@ -196,6 +260,11 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run 10 device copies of this many bytes (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.study == "precision":
+        from lbm_inputs.workloads import workload
+        cps = [int(x) for x in args.study_checkpoints.split(",")]
+        print(json.dumps(_round(precision_study(workload("shear_layer_4096"), cps))), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU; this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)

@@ -257,3 +257,104 @@ def test_adjoint_full_size_directional_derivative():
     fdw = (loss(f0, field + h * z) - loss(f0, field - h * z)) / (2 * h)
     adw = float((gw * z).sum())
     assert abs(adw - fdw) <= 1e-6 * abs(adw)
+
+
+def _cavity_copy(n=64):
+    """The cavity adjoint workload's setup on an n x n copy: MRT with the
+    seeded per-site shear rate, Ehrenfest k = 9, delta = 1e-3, fluid at rest,
+    the seeded Fourier target velocity."""
+    from lbm_inputs import generators as G
+    from lbm_inputs.workloads import workload
+    wl = workload("cavity_adjoint_512")
+    p = {k: wl[k] for k in ("lattice", "bc", "u_lid", "collision", "s_e", "s_eps", "s_q",
+                            "ehrenfest", "ehr_k", "ehr_delta")}
+    p.update(nx=n, ny=n)
+    field = torch.tensor(G.smooth_omega_field(n, n, seed=wl["omega_seed"]))
+    rho, ux, uy = G.uniform_rest(n, n)
+    f0 = O.init_equilibrium(lattice(p), rho, ux, uy)
+    tx, ty = (torch.tensor(a) for a in G.fourier_target(n, n, seed=wl["target_seed"]))
+    return p, field, f0, tx, ty
+
+
+def _misfit(f, tx, ty):
+    rho = f.sum(0)
+    v = torch.tensor([[(i % 3) - 1, (i // 3) - 1] for i in range(9)], dtype=f.dtype,
+                     device=f.device)
+    ux = (v[:, 0].view(9, 1, 1) * f).sum(0) / rho
+    uy = (v[:, 1].view(9, 1, 1) * f).sum(0) / rho
+    return ((ux - tx.to(f.device)) ** 2 + (uy - ty.to(f.device)) ** 2).sum()
+
+
+def _misfit_grad(fT, tx, ty):
+    f = fT.clone().requires_grad_(True)
+    _misfit(f, tx, ty).backward()
+    return f.grad
+
+
+def test_cavity_copy_velocity_misfit_matches_oracle():
+    """64^2 copy of the cavity adjoint workload, 40 steps, checkpoints every
+    16: gradients of the velocity misfit equal the oracle's autograd."""
+    p, field, f0, tx, ty = _cavity_copy()
+    n = 40
+    lat, cfg = lattice(p), oracle_config(p)
+    g0 = f0.clone().requires_grad_(True)
+    om = field.clone().requires_grad_(True)
+    g = g0
+    for _ in range(n):
+        g, _ = O.step(lat, cfg, g, om)
+    _misfit(g, tx, ty).backward()
+    sim = make_sim({**p, "checkpoint_every": 16, "max_steps": n, "omega_field": True}, "f64")
+    sim.set_populations(f0.to("cuda"))
+    sim.set_omega(field.to("cuda"))
+    sim.step(n)
+    dLdfT = _misfit_grad(sim.populations(), tx, ty)
+    gf = torch.empty_like(dLdfT)
+    gw = torch.empty((p["ny"], p["nx"]), dtype=torch.float64, device="cuda")
+    sim.backward(dLdfT, gf, gw)
+    assert _rel(gf.cpu(), g0.grad) <= 1e-11
+    assert _rel(gw.cpu(), om.grad) <= 1e-11
+
+
+def test_cavity_copy_8192_steps_central_differences():
+    """64^2 copy of the cavity adjoint workload over the full 8192 steps in
+    FP64 with checkpoints every 256: directional derivatives of the velocity
+    misfit along seeded directions in f0 and omega equal central
+    differences of the library's forward pass (h = 1e-6; the final
+    Ehrenfest sets of the +-h runs are equal).  The rest state is perturbed
+    by a seeded relative 1e-3: at rest the two lid corners tie exactly in
+    Delta S at the first step, where the loss is not differentiable.  From
+    the perturbed start the oracle's smallest selection margin over the
+    8192 steps (k-th against (k+1)-th Delta S, or against delta) is 7e-5
+    relative, far above what the 1e-8 perturbations move."""
+    p, field, f0, tx, ty = _cavity_copy()
+    f0 = f0 * (1 + 1e-3 * torch.tensor(np.random.default_rng(59).uniform(-1, 1, f0.shape)))
+    n = 8192
+    rng = np.random.default_rng(53)
+    v = torch.tensor(rng.normal(size=f0.shape)) * 1e-2
+    z = torch.tensor(rng.normal(size=field.shape)) * 1e-2
+    sim = make_sim({**p, "checkpoint_every": 256, "max_steps": n, "omega_field": True}, "f64")
+    sim.set_populations(f0.to("cuda"))
+    sim.set_omega(field.to("cuda"))
+    sim.step(n)
+    dLdfT = _misfit_grad(sim.populations(), tx, ty)
+    gf = torch.empty_like(dLdfT)
+    gw = torch.empty((p["ny"], p["nx"]), dtype=torch.float64, device="cuda")
+    sim.backward(dLdfT, gf, gw)
+    sel_ref = sim.selected()
+
+    def loss(f, om):
+        s = make_sim({**p, "omega_field": True}, "f64")
+        s.set_populations(f.to("cuda"))
+        s.set_omega(om.to("cuda"))
+        s.step(n)
+        return float(_misfit(s.populations(), tx, ty)), s.selected()
+
+    h = 1e-6
+    (lp, sp), (lm, sm) = loss(f0 + h * v, field), loss(f0 - h * v, field)
+    assert sp == sel_ref and sm == sel_ref
+    ad = float((gf.cpu() * v).sum())
+    assert abs(ad - (lp - lm) / (2 * h)) <= 1e-6 * abs(ad)
+    (lp, sp), (lm, sm) = loss(f0, field + h * z), loss(f0, field - h * z)
+    assert sp == sel_ref and sm == sel_ref
+    adw = float((gw.cpu() * z).sum())
+    assert abs(adw - (lp - lm) / (2 * h)) <= 1e-6 * abs(adw)
