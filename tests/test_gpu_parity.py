@@ -90,12 +90,33 @@ def test_one_step_fp64_narrow(name):
         assert cnt[4] == int((br == O.ELBM_NONPOS).sum())
 
 
-@pytest.mark.parametrize("name", ["lbgk_periodic", "lbgk_cavity", "mrt_m1_cavity",
-                                  "elbm_periodic", "lbgk_median_cavity", "lbgk_ehrenfest_k20",
-                                  "lbgk_positivity"])
+# Row tiles of 256 sites; 300 = 256 + 44 puts the right domain edge inside
+# a wavefront.
+WIDE_CASES = ["lbgk_periodic", "lbgk_cavity", "lbgk_couette", "lbgk_bounceback",
+              "mrt_m1_cavity", "mrt_m2_periodic", "elbm_periodic", "lbgk_median_cavity",
+              "lbgk_ehrenfest_k20", "lbgk_ehrenfest_delta", "lbgk_positivity",
+              "mrt_ehrenfest_pos"]
+
+
+@pytest.mark.parametrize("name", WIDE_CASES)
 def test_one_step_fp64_wide(name):
     p, amp = _params(name, WIDE)
     _compare(p, amp, 1, 12, 1e-12)
+
+
+@pytest.mark.parametrize("name", ["lbgk_cavity", "lbgk_couette", "lbgk_ehrenfest_k20",
+                                  "mrt_ehrenfest_pos"])
+def test_twenty_steps_fp64_wide(name):
+    p, amp = _params(name, WIDE)
+    _compare(p, amp, 20, 17, 1e-10)
+
+
+@pytest.mark.parametrize("coll", ["lbgk", "mrt"])
+def test_omega_field_fp64_wide(coll):
+    p = {"lattice": "D2Q9", **WIDE, "bc": "cavity", "u_lid": 0.1, "nu": 0.01,
+         "collision": coll, "omega_field": True, "s_e": 1.64, "s_eps": 1.64, "s_q": 1.9}
+    om = torch.tensor(G.smooth_omega_field(p["nx"], p["ny"], seed=41))
+    _compare(p, 0.05, 3, 18, 1e-12, omega_field=om)
 
 
 @pytest.mark.parametrize("name", ["lbgk_cavity", "mrt_m1_cavity", "elbm_periodic",
@@ -211,9 +232,13 @@ def storage_bound(ora: torch.Tensor, storage: str, lat: O.Lattice) -> torch.Tens
 
 @pytest.mark.parametrize("storage", ["f32", "f16s", "bf16s"])
 @pytest.mark.parametrize("name", ["lbgk_cavity", "mrt_m1_cavity", "elbm_periodic",
-                                  "lbgk_median_cavity", "lbgk_ehrenfest_k20"])
+                                  "lbgk_median_cavity", "lbgk_ehrenfest_k20",
+                                  "wide:lbgk_couette", "wide:mrt_m1_cavity",
+                                  "wide:lbgk_ehrenfest_k20"])
 def test_low_precision_one_step(storage, name):
-    p, amp = _params(name, NARROW)
+    size = WIDE if name.startswith("wide:") else NARROW
+    name = name.split(":")[-1]
+    p, amp = _params(name, size)
     f0 = random_state(p, 21, amp=amp, kind=_kind(p))
     f_in, f_gpu, sim = gpu_run(p, f0, 1, storage)
     f_ora, infos = oracle_run(p, f_in, 1)
