@@ -21,6 +21,10 @@ One JSON line on stdout:
   adjoint_scale  forward and adjoint of the shear-layer workload (FP32,
             128 steps, checkpoints every 16), with the adjoint kernel's
             bytes over its event-timed duration;
+  elbm_8192 the 8192^2 ELBM workload (positivity, Ehrenfest 0.1 %, FP16
+            shifted storage): forward MLUPS and branch statistics, forward +
+            adjoint over 32 steps, and the workspace of its full 5000-step
+            adjoint;
   cpu_baseline  the FP64 oracle timed on this host on two full steps.
 Progress goes to stderr.
 """
@@ -174,6 +178,155 @@ def cpu_baseline(w: dict, steps: int) -> dict:
                       f"{dt:.1f} s"}
 
 
+def run_elbm_8192(steps: int, warmup: int, adj_steps: int, adj_K: int) -> dict:
+    """The 8192^2 periodic ELBM workload (positivity fallback and rule,
+    Ehrenfest on 0.1 %, FP16 shifted storage): forward throughput and the
+    ELBM branch statistics, then forward + adjoint over adj_steps steps, and
+    the workspace the full 5000-step adjoint needs with checkpoints every
+    71 steps (about sqrt(5000): checkpoint store and segment store equal)."""
+    import torch
+
+    from lbm_inputs import generators as G
+    from lbm_inputs.workloads import workload
+    from paper_1110_0270_amd import lbm as B
+
+    w = workload("elbm_8192")
+    n = w["nx"] * w["ny"]
+    r0, ux, uy = G.spectral_velocity(w["nx"], seed=w["seed"])
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")  # noqa: E731
+    rho, uxd, uyd = t(r0), t(ux), t(uy)
+    del r0, ux, uy
+    sim = B.Simulation(B.make_config(**{**w, "storage": "f16s", "checkpoint_every": 0}))
+    sim.set_equilibrium(rho, uxd, uyd)
+    sim.step(warmup)
+    c0 = sim.counters()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kern_ms, _ = sim.profile_step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    c1 = sim.counters()
+    st = sim.stats(allow_status=(B.LBM_OK, B.LBM_EDIVERGED, B.LBM_ESELECT))
+    upd = n * steps
+    res = {
+        "workload": "elbm_8192", "storage": "f16s", "steps": steps, "warmup": warmup,
+        "mlups": upd / (t1 - t0) / 1e6,
+        "kernel_us": kern_ms / steps * 1e3,
+        "kernel_gbs": 2 * 9 * 2 * n / (kern_ms / steps * 1e-3) / 1e9,
+        "positivity_per_update": (c1[0] - c0[0]) / upd,
+        "elbm_noroot_per_update": (c1[2] - c0[2]) / upd,
+        "elbm_fp64_solve_per_update": (c1[3] - c0[3]) / upd,
+        "elbm_nonpositive_per_update": (c1[4] - c0[4]) / upd,
+        "n_selected": int(st.n_selected), "diverged_step": int(st.diverged_step),
+        "mass_per_site": st.mass / n,
+    }
+    del sim
+    torch.cuda.empty_cache()
+    log(f"[bench] elbm 8192^2 f16s: {res['mlups']:.0f} MLUPS, kernel {res['kernel_us']:.0f} us")
+    if adj_steps > 0:
+        sim = B.Simulation(B.make_config(**{**w, "storage": "f16s", "checkpoint_every": adj_K,
+                                            "max_steps": adj_steps}))
+        sim.set_equilibrium(rho, uxd, uyd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(adj_steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        tx, ty = G.fourier_target(w["nx"], w["ny"], seed=w["target_seed"])
+        loss, g = velocity_loss_grad(sim.populations(), t(tx), t(ty))
+        del tx, ty
+        g0 = torch.empty_like(g)
+        gw = torch.empty((w["ny"], w["nx"]), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        adj_kern, _ = sim.profile_backward(g, g0, gw)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        adj_bytes = n * (9 * (4 + 4 + 2) + 2 * 4)
+        res["adjoint"] = {
+            "steps": adj_steps, "checkpoint_every": adj_K, "loss": loss,
+            "fwd_ms": (t1 - t0) * 1e3, "bwd_ms": (t3 - t2) * 1e3,
+            "fwd_adjoint_mlups": n * adj_steps / (t3 - t2 + t1 - t0) / 1e6,
+            "adjoint_kernel_us": adj_kern / adj_steps * 1e3,
+            "adjoint_kernel_gbs": adj_bytes / (adj_kern / adj_steps * 1e-3) / 1e9,
+            "adjoint_alg_bytes_per_launch": adj_bytes,
+            "grad_finite": bool(torch.isfinite(g0).all()) and bool(torch.isfinite(gw).all()),
+            "workspace_gb": sim.workspace.numel() / 1e9,
+        }
+        del sim, g, g0, gw
+        torch.cuda.empty_cache()
+        log(f"[bench] elbm 8192^2 adjoint: fwd+adjoint {res['adjoint']['fwd_adjoint_mlups']:.0f} "
+            f"MLUPS, adjoint kernel {res['adjoint']['adjoint_kernel_us']:.0f} us")
+    full = B.make_config(**{**w, "storage": "f16s", "checkpoint_every": 71, "max_steps": 5000})
+    res["full_adjoint_5000_steps_workspace_gb"] = B.lbm_workspace_bytes(full) / 1e9
+    return res
+
+
+def cavity_study(steps: int, checkpoints: list) -> dict:
+    """The 256^2 lid-driven cavity at Re 5000 (lid 0.1): LBGK, ELBM, MRT and
+    LBGK with the median filter, each in FP64 and FP32, from rest;
+    throughput, divergence (checked every 100 steps), total entropy, ELBM
+    branch and iteration counts, and the FP32 run's error against the FP64
+    one at the checkpoints, next to an FP64 control whose relaxation rate is
+    rounded to FP32 (the flow's own sensitivity to a perturbation of that
+    size)."""
+    import numpy as np
+    import torch
+
+    from lbm_inputs import generators as G
+    from lbm_inputs.workloads import workload
+    from paper_1110_0270_amd import lbm as B
+
+    w = workload("cavity_256")
+    omega = 1.0 / (3.0 * w["nu"] + 0.5)
+    runs = {"lbgk": {}, "elbm": {"collision": "elbm"}, "mrt": {"collision": "mrt"},
+            "lbgk_median": {"median": True, "med_delta": 1e-3}}
+    forms = {"f64": {"storage": "f64"}, "f32": {"storage": "f32"},
+             "f64_omega_rounded_to_f32": {"storage": "f64", "nu": None,
+                                          "omega": float(np.float32(omega))}}
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")  # noqa: E731
+    rho, ux, uy = (t(a) for a in G.uniform_rest(w["nx"], w["ny"]))
+    n = w["nx"] * w["ny"]
+    cps = [c for c in checkpoints if c <= steps]
+    out = {"workload": "cavity_256", "steps": steps, "nu": w["nu"], "omega": omega,
+           "checkpoints": cps, "runs": {}}
+    for name, over in runs.items():
+        res, moms = {}, {}
+        for form, fo in forms.items():
+            sim = B.Simulation(B.make_config(**{**w, **over, **fo, "check_interval": 100}))
+            sim.set_equilibrium(rho, ux, uy)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            done, div, snaps = 0, -1, {}
+            for c in cps:
+                sim.step(c - done)
+                done = c
+                st = sim.stats(allow_status=(B.LBM_OK, B.LBM_EDIVERGED, B.LBM_ESELECT))
+                div = int(st.diverged_step)
+                if div >= 0:
+                    break
+                snaps[c] = torch.stack(sim.moments()[1:])
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            c = sim.counters()
+            res[form] = {"mlups": n * done / dt / 1e6, "steps_run": done, "diverged_step": div,
+                         "entropy": st.entropy, "mass_drift": st.mass / n - 1.0,
+                         "median_corrections_per_update": c[1] / (n * done),
+                         "elbm_noroot_per_update": c[2] / (n * done),
+                         "elbm_fp64_solves_per_update": c[3] / (n * done),
+                         "elbm_iterations_per_update": c[5] / (n * done)}
+            moms[form] = snaps
+            del sim
+        for form in ("f32", "f64_omega_rounded_to_f32"):
+            res[form]["rel_l2_u_vs_f64"] = {
+                c: rel_l2(moms[form][c], moms["f64"][c]) for c in cps
+                if c in moms[form] and c in moms["f64"]}
+        out["runs"][name] = res
+        log(f"[study] cavity {name}: " + ", ".join(
+            f"{k} {v['mlups']:.0f} MLUPS div {v['diverged_step']}" for k, v in res.items()))
+    return out
+
+
 def precision_study(w: dict, checkpoints: list) -> dict:
     """Error of the FP32, FP16-shifted and BF16-shifted forms against FP64
     over a long run of the shear-layer workload, next to an FP64 control
@@ -251,15 +404,23 @@ def main():
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--forms", default="f64,f16s,bf16s")
     ap.add_argument("--study", default="", help="'precision': error of the storage forms "
-                    "against FP64 over a long shear-layer run (one JSON document)")
+                    "against FP64 over a long shear-layer run; 'cavity': the four 256^2 "
+                    "cavity runs in FP64 and FP32 (one JSON document each)")
     ap.add_argument("--study-checkpoints", default="100,1000,5000,10000,20000")
+    ap.add_argument("--study-steps", type=int, default=50000)
     ap.add_argument("--adjoint-steps", type=int, default=8192)
     ap.add_argument("--scale-adjoint-steps", type=int, default=128)
+    ap.add_argument("--elbm-steps", type=int, default=50)
+    ap.add_argument("--elbm-adjoint-steps", type=int, default=32)
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run 10 device copies of this many bytes (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.study == "cavity":
+        cps = [1000, 5000, 10000, 20000, 50000]
+        print(json.dumps(_round(cavity_study(args.study_steps, cps))), flush=True)
+        return
     if args.study == "precision":
         from lbm_inputs.workloads import workload
         cps = [int(x) for x in args.study_checkpoints.split(",")]
@@ -333,6 +494,10 @@ def main():
         log(f"[bench] adjoint 4096^2 f32: fwd+adjoint {r['fwd_adjoint_mlups']:.0f} MLUPS, adjoint "
             f"kernel {r['adjoint_kernel_us']:.1f} us = {r['adjoint_kernel_gbs']:.0f} GB/s")
 
+    elbm = None
+    if args.elbm_steps > 0:
+        elbm = run_elbm_8192(args.elbm_steps, 20, args.elbm_adjoint_steps, 8)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host ...")
@@ -364,6 +529,7 @@ def main():
         "forms": _round(forms),
         "adjoint": _round(adjoint),
         "adjoint_scale": _round(adjoint_scale),
+        "elbm_8192": _round(elbm),
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

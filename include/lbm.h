@@ -203,7 +203,8 @@ lbm_status lbm_selected(lbm_ctx* ctx, long long* idx, long long cap, long long* 
  * positivity-rule activations in the collision (sites that the Ehrenfest
  * limiter then sends to equilibrium included), median-filter corrections,
  * ELBM sites with no nontrivial root, ELBM sites solved in FP64, ELBM sites
- * with a non-positive population. */
+ * with a non-positive population, ELBM root iterations (summed over
+ * sites). */
 lbm_status lbm_counters(lbm_ctx* ctx, unsigned long long* out, int n);
 
 /* Advance n steps exactly as lbm_step does, bracketing each step's fused

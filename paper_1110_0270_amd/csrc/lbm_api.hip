@@ -64,6 +64,7 @@ bool validate(const lbm_config* c, std::string& why) {
   }
   if (c->collision == LBM_ELBM && c->elbm_max_iter < 1) { why = "elbm_max_iter must be >= 1"; return false; }
   if (c->checkpoint_every < 0 || c->max_steps < 0) { why = "checkpoint_every/max_steps must be >= 0"; return false; }
+  if (c->checkpoint_every > 0 && c->max_steps < 1) { why = "checkpoint_every > 0 needs max_steps >= 1"; return false; }
   return true;
 }
 
@@ -81,7 +82,7 @@ Layout make_layout(const lbm_config* c) {
   L.off_lat[1] = take(L.lat_bytes);
   L.off_omega = c->omega_field ? take((size_t)L.qs * rb) : 0;
   L.off_sel = take(sizeof(SelState));
-  L.off_cnt = take(CNT_N * sizeof(unsigned long long));
+  L.off_cnt = take((size_t)kCntSlots * CNT_N * sizeof(unsigned long long));
   L.off_partial = take(stats_partial_doubles(c->nx, c->ny) * sizeof(double));
   L.off_stats = take(8 * sizeof(double));
   L.off_div = take(sizeof(long long));
@@ -275,7 +276,7 @@ lbm_status lbm_init(const lbm_config* cfg, void* ws, size_t ws_bytes, void* stre
   init_select_state(&s0, c->f64());
   hipError_t e = hipMemcpyAsync(c->ws + L.off_sel, &s0, sizeof(SelState), hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.off_cnt, 0, CNT_N * 8, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.off_cnt, 0, (size_t)kCntSlots * CNT_N * 8, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.off_div, 0xff, sizeof(long long), c->stream);
   if (e == hipSuccess && (cfg->limiters & LBM_LIM_EHRENFEST)) {
     e = hipMemsetAsync(c->ws + L.off_hist, 0, kBuckets * 4, c->stream);
@@ -508,10 +509,17 @@ lbm_status lbm_stats_get(lbm_ctx* c, lbm_stats* out) {
 lbm_status lbm_counters(lbm_ctx* c, unsigned long long* out, int n) {
   g_err.clear();
   if (!c || !out || n < 1) return fail(LBM_EINVAL, "bad argument");
-  const int m = n < CNT_N ? n : CNT_N;
-  hipError_t e = hipMemcpyAsync(out, c->ws + c->L.off_cnt, m * 8, hipMemcpyDeviceToHost, c->stream);
+  std::vector<unsigned long long> all((size_t)kCntSlots * CNT_N);
+  hipError_t e = hipMemcpyAsync(all.data(), c->ws + c->L.off_cnt, all.size() * 8,
+                                hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(e, "lbm_counters");
+  for (int k = 0; k < n; ++k) {
+    unsigned long long sum = 0;
+    if (k < CNT_N)
+      for (int slot = 0; slot < kCntSlots; ++slot) sum += all[(size_t)slot * CNT_N + k];
+    out[k] = sum;
+  }
   return LBM_OK;
 }
 

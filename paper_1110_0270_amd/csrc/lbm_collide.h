@@ -7,6 +7,28 @@
 
 namespace lbm {
 
+struct ElbmF64Site { float f[9], q[9]; };
+struct ElbmF64Result { float alpha; int branch; int iters; };
+
+// The FP64 root solve for a site of an FP32 lattice, out of line: the FP32
+// kernels carry its code once, away from their hot path (few sites take it).
+template <int Q>
+__device__ __noinline__ ElbmF64Result elbm_alpha_fp64(ElbmF64Site s, double eps, double dS_cut,
+                                                      int max_iter, int norm, int fallback) {
+  double fd[Q], qd[Q], Dd[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    fd[i] = (double)s.f[i];
+    qd[i] = (double)s.q[i];
+    Dd[i] = qd[i] - fd[i];
+  }
+  ElbmParams<double> e64{eps, 0.0, dS_cut, max_iter, norm, fallback};
+  ElbmF64Result r;
+  r.alpha = (float)elbm_alpha<double, Q>(fd, qd, Dd, alpha_max<double, Q>(fd, Dd), e64,
+                                         r.branch, r.iters);
+  return r;
+}
+
 template <class R>
 struct CollInfo {
   R alpha = R(2);   // ELBM alpha (2 elsewhere)
@@ -14,6 +36,7 @@ struct CollInfo {
   bool f64 = false; // ELBM root solved in FP64
   int pos_arg = -1; // positivity rule: component set to 0, -1 if inactive
   R phi = R(1);     // positivity rule: homothety coefficient
+  int iters = 0;    // ELBM root iterations
 };
 
 // Collision (eq. CollisionIntegral; section 5 MRT in moment space; section
@@ -56,7 +79,6 @@ __device__ __forceinline__ void collide_site(const StepArgs<typename StoreT<S>::
       fa[i] = v[i] + sh;
       qa[i] = feq[i] + sh;
     }
-    const R dSe = delta_s<R, Q>(fa, qa, d);
     const R amax = alpha_max<R, Q>(fa, d);
     int br = EB_ROOT;
     R alpha;
@@ -65,22 +87,23 @@ __device__ __forceinline__ void collide_site(const StepArgs<typename StoreT<S>::
     if constexpr (sizeof(R) == 4) {
       if (amax < A.f64_below) {
         // FP64 solve near the no-root (degenerate) branch.
-        double fd[Q], qd[Q], Dd[Q];
+        ElbmF64Site st;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-          fd[i] = (double)fa[i];
-          qd[i] = (double)qa[i];
-          Dd[i] = qd[i] - fd[i];
+          st.f[i] = fa[i];
+          st.q[i] = qa[i];
         }
-        const double dSd = delta_s<double, Q>(fd, qd, Dd);
-        ElbmParams<double> e64{A.eps64, 0.0, A.dS_cut64, A.max_iter, A.norm, A.fallback};
-        alpha = (R)elbm_alpha<double, Q>(fd, qd, Dd, dSd, alpha_max<double, Q>(fd, Dd), e64, br);
+        const ElbmF64Result r =
+            elbm_alpha_fp64<Q>(st, A.eps64, A.dS_cut64, A.max_iter, A.norm, A.fallback);
+        alpha = r.alpha;
+        br = r.branch;
+        ci.iters = r.iters;
         f64 = true;
       } else {
-        alpha = elbm_alpha<R, Q>(fa, qa, d, dSe, amax, ep, br);
+        alpha = elbm_alpha<R, Q>(fa, qa, d, amax, ep, br, ci.iters);
       }
     } else {
-      alpha = elbm_alpha<R, Q>(fa, qa, d, dSe, amax, ep, br);
+      alpha = elbm_alpha<R, Q>(fa, qa, d, amax, ep, br, ci.iters);
     }
     const R ab = alpha * (om * R(0.5));
 #pragma unroll

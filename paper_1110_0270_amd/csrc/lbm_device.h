@@ -106,64 +106,84 @@ __device__ __forceinline__ void eq_dev6(R u, int kind, R dt[3]) {
 __device__ __forceinline__ int c1(int a) { return a == 0 ? 4 : 1; }  // 6 w_a
 
 // h(x) = (1 + x) ln(1 + x) - x, h(-1) = 1; Taylor series for |x| < 0.1.
+// h_series is the series part; h_log(x, l) takes l = ln(1 + x) from the
+// caller (so that a sum that also needs ln(1 + x) evaluates it once).
 template <class R>
-__device__ __forceinline__ R h_fn(R x);
+__device__ __forceinline__ R h_series(R x);
 template <>
-__device__ __forceinline__ double h_fn<double>(double x) {
-  if (fabs(x) < 0.1) {
-    double acc = 0.0;
+__device__ __forceinline__ double h_series<double>(double x) {
+  double acc = 0.0;
 #pragma unroll
-    for (int n = 16; n >= 3; --n) {
-      double c = ((n & 1) ? -1.0 : 1.0) / (double)(n * (n - 1));
-      acc = (acc + c) * x;
-    }
-    return (acc + 0.5) * x * x;
+  for (int n = 16; n >= 3; --n) {
+    double c = ((n & 1) ? -1.0 : 1.0) / (double)(n * (n - 1));
+    acc = (acc + c) * x;
   }
-  if (x <= -1.0) return 1.0;
-  return (1.0 + x) * log1p(x) - x;
+  return (acc + 0.5) * x * x;
 }
 template <>
-__device__ __forceinline__ float h_fn<float>(float x) {
-  if (fabsf(x) < 0.1f) {
-    // terms up to x^8: truncation below 4e-8 of the leading term
-    float acc = 0.0f;
+__device__ __forceinline__ float h_series<float>(float x) {
+  // terms up to x^8: truncation below 4e-8 of the leading term
+  float acc = 0.0f;
 #pragma unroll
-    for (int n = 8; n >= 3; --n) {
-      float c = ((n & 1) ? -1.0f : 1.0f) / (float)(n * (n - 1));
-      acc = (acc + c) * x;
-    }
-    return (acc + 0.5f) * x * x;
+  for (int n = 8; n >= 3; --n) {
+    float c = ((n & 1) ? -1.0f : 1.0f) / (float)(n * (n - 1));
+    acc = (acc + c) * x;
   }
-  if (x <= -1.0f) return 1.0f;
-  return (1.0f + x) * log1pf(x) - x;
+  return (acc + 0.5f) * x * x;
+}
+// Branch-free selects: both forms are evaluated and one is kept, so that the
+// nine components of a site interleave instead of running as nine divergent
+// branches one after another.
+template <class R>
+__device__ __forceinline__ R h_log(R x, R l) {
+  const R ser = h_series<R>(x);
+  const R lgv = (R(1) + x) * l - x;
+  return fabs(x) < R(0.1) ? ser : (x <= R(-1) ? R(1) : lgv);
+}
+// ln(1 + x) for x >= -1.  FP64: the library log1p.  FP32: for |x| < 0.1 its
+// Taylor series to x^8 (truncation below 1.2e-9 relative); otherwise the
+// hardware logarithm of u = 1 + x times x / (u - 1), which removes the
+// rounding of u (D. Goldberg, What every computer scientist should know
+// about floating-point arithmetic, 1991, theorem 4): a few units in the last
+// place, against the several hundred instructions of the extended-precision
+// library routine.
+template <class R> __device__ __forceinline__ R lg1p(R x);
+template <> __device__ __forceinline__ double lg1p<double>(double x) { return log1p(x); }
+template <> __device__ __forceinline__ float lg1p<float>(float x) {
+  float acc = 0.0f;
+#pragma unroll
+  for (int n = 8; n >= 2; --n) acc = (acc + ((n & 1) ? 1.0f : -1.0f) / (float)n) * x;
+  const float ser = (acc + 1.0f) * x;
+  const float u = 1.0f + x;
+  const float lgv = __logf(u) * (x * __builtin_amdgcn_rcpf(u - 1.0f));
+  return fabsf(x) < 0.1f ? ser : lgv;
+}
+
+// a / b: correctly rounded in FP64; in FP32 a times the hardware reciprocal
+// (within 2 units in the last place).
+template <class R> __device__ __forceinline__ R fdiv(R a, R b);
+template <> __device__ __forceinline__ double fdiv<double>(double a, double b) { return a / b; }
+template <> __device__ __forceinline__ float fdiv<float>(float a, float b) {
+  return a * __builtin_amdgcn_rcpf(b);
+}
+template <class R>
+__device__ __forceinline__ R h_fn(R x) {
+  if constexpr (sizeof(R) == 4) {
+    return h_log<R>(x, lg1p<R>(x < R(-1) ? R(-1) : x));
+  } else {
+    if (fabs(x) < R(0.1)) return h_series<R>(x);
+    if (x <= R(-1)) return R(1);
+    return (R(1) + x) * lg1p<R>(x) - x;
+  }
 }
 
 template <class R> __device__ __forceinline__ R rcp(R x);
 template <> __device__ __forceinline__ double rcp<double>(double x) { return 1.0 / x; }
 template <> __device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
-template <class R> __device__ __forceinline__ R lg1p(R x);
-template <> __device__ __forceinline__ double lg1p<double>(double x) { return log1p(x); }
-template <> __device__ __forceinline__ float lg1p<float>(float x) { return log1pf(x); }
-
 template <class R> __device__ __forceinline__ R r_inf();
 template <> __device__ __forceinline__ double r_inf<double>() { return __builtin_huge_val(); }
 template <> __device__ __forceinline__ float r_inf<float>() { return __builtin_huge_valf(); }
-
-// Nonequilibrium entropy (section 4, eq. DelS): sum_i f_i ln(f_i / f*_i),
-// evaluated as sum_i f*_i h((f_i - f*_i) / f*_i) (same value since f and
-// f* share rho).  d = f* - f.  +inf if some f_i < 0 or f*_i <= 0.
-template <class R, int Q>
-__device__ __forceinline__ R delta_s(const R f[Q], const R feq[Q], const R d[Q]) {
-  R s = R(0);
-  bool bad = false;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    bad |= (f[i] < R(0)) | (feq[i] <= R(0));
-    s += feq[i] * h_fn<R>(-d[i] / feq[i]);
-  }
-  return bad ? r_inf<R>() : s;
-}
 
 // ---------------------------------------------------------------------------
 // ELBM root (section 3).  S_f(alpha) = S(f + alpha D) - S(f), D = f* - f,
@@ -178,12 +198,13 @@ __device__ __forceinline__ void sf_parts(const R f[Q], const R D[Q], const R lnr
   R s0 = R(0), s1 = R(0), t1 = R(0), t2 = R(0);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    R x = a * D[i] / f[i];
-    s0 += f[i] * h_fn<R>(x);
-    s1 += D[i] * lnr[i];
+    R x = fdiv<R>(a * D[i], f[i]);
     R xl = x < R(-1) ? R(-1) : x;
-    t1 += D[i] * (lg1p<R>(xl) + lnr[i]);
-    t2 += D[i] * D[i] / (f[i] + a * D[i]);
+    const R l = lg1p<R>(xl);
+    s0 += f[i] * h_log<R>(x, l);
+    s1 += D[i] * lnr[i];
+    t1 += D[i] * (l + lnr[i]);
+    t2 += fdiv<R>(D[i] * D[i], f[i] + a * D[i]);
   }
   sf = -s0 - a * s1;
   d1 = -t1;
@@ -201,49 +222,76 @@ struct ElbmParams {
 };
 
 // Returns alpha and the branch taken.  f: populations, feq: entropic
-// equilibrium, D = feq - f, dS: nonequilibrium entropy, amax: largest alpha
-// with f + alpha D >= 0 (computed by the caller).
+// equilibrium, D = feq - f, amax: largest alpha with f + alpha D >= 0
+// (computed by the caller).
+//
+// The cutoff test Delta S < dS_cut needs the exact Delta S =
+// sum f*_i h(x_i), x_i = (f_i - f*_i) / f*_i, only near equilibrium:
+// h(x) >= x^2 / (2 (1 + x/3)) for x >= -1 (the bound behind Bernstein's
+// inequality), so sum f*_i x_i^2 / (2 (1 + max x/3)) <= Delta S decides it
+// for every other site.  The same x_i give ln(f_i / f*_i) and the entropic
+// norm.
 template <class R, int Q>
-__device__ R elbm_alpha(const R f[Q], const R feq[Q], const R D[Q], R dS, R amax,
-                        const ElbmParams<R>& p, int& branch) {
+__device__ R elbm_alpha(const R f[Q], const R feq[Q], const R D[Q], R amax,
+                        const ElbmParams<R>& p, int& branch, int& iters) {
+  iters = 0;
   bool nonpos = false;
 #pragma unroll
   for (int i = 0; i < Q; ++i) nonpos |= (f[i] <= R(0));
   if (nonpos) { branch = EB_NONPOS; return R(1); }
-  if (dS < p.dS_cut) { branch = EB_CUTOFF; return R(2); }
+  R x[Q], U = R(0), xmax = R(-1);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    x[i] = fdiv<R>(-D[i], feq[i]);
+    U += feq[i] * x[i] * x[i];
+    xmax = fmax(xmax, x[i]);
+  }
+  if (U < R(2) * p.dS_cut * (R(1) + xmax / R(3))) {
+    R dS = R(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) dS += feq[i] * h_fn<R>(x[i]);
+    if (dS < p.dS_cut) { branch = EB_CUTOFF; return R(2); }
+  }
   R lnr[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) lnr[i] = lg1p<R>(-D[i] / feq[i]);
-  const bool finite = amax < r_inf<R>();
-  if (finite) {
-    R sf, d1, d2;
-    sf_parts<R, Q>(f, D, lnr, amax, sf, d1, d2);
-    if (sf >= R(0)) {
-      branch = EB_NOROOT;
-      return p.fallback == 0 ? amax : R(1);
-    }
-  }
+  for (int i = 0; i < Q; ++i) lnr[i] = lg1p<R>(x[i]);
   R nrm = R(0);
+  if (p.norm == 0) {
+    nrm = sqrt(U);
+  } else {
 #pragma unroll
-  for (int i = 0; i < Q; ++i) nrm += p.norm == 0 ? D[i] * D[i] / feq[i] : fabs(D[i]);
-  if (p.norm == 0) nrm = sqrt(nrm);
+    for (int i = 0; i < Q; ++i) nrm += fabs(D[i]);
+  }
+  // One evaluation site for S_f and its derivatives (the kernel's code size
+  // decides its speed): first the existence test S_f(alpha_max) < 0 when
+  // alpha_max is finite, then the iteration; the evaluation that stops the
+  // iteration also serves the final sign check.
+  bool probe = amax < r_inf<R>();
   R a = amax > R(2) ? R(2) : R(0.5) * (R(1) + amax);
-  for (int it = 0; it < p.max_iter; ++it) {
+  for (int it = 0;;) {
     R sf, d1, d2;
-    sf_parts<R, Q>(f, D, lnr, a, sf, d1, d2);
+    sf_parts<R, Q>(f, D, lnr, probe ? amax : a, sf, d1, d2);
+    if (probe) {
+      if (sf >= R(0)) {
+        branch = EB_NOROOT;
+        return p.fallback == 0 ? amax : R(1);
+      }
+      probe = false;
+      continue;
+    }
     const R step_est = fabs(sf / d1);
-    if (step_est * nrm < p.eps || step_est < p.atol) break;
+    if (step_est * nrm < p.eps || step_est < p.atol || it >= p.max_iter) {
+      if (sf < R(0)) a = a - R(2) * sf / d1;
+      break;
+    }
+    ++it;
+    ++iters;
     R disc = d1 * d1 - R(2) * sf * d2;
     R delta = disc >= R(0) ? R(2) * sf / (-d1 + sqrt(disc)) : -sf / d1;
     R an = a + delta;
     if (an >= amax) an = R(0.5) * (a + amax);
     if (an <= R(1)) an = R(0.5) * (a + R(1));
     a = an;
-  }
-  {
-    R sf, d1, d2;
-    sf_parts<R, Q>(f, D, lnr, a, sf, d1, d2);
-    if (sf < R(0)) a = a - R(2) * sf / d1;
   }
   branch = EB_ROOT;
   return a;

@@ -38,8 +38,12 @@ constexpr int kCountStride = 16;      // in unsigned long long
 // Counters of limiter activity (cumulative since the last reset).
 enum Counter : int {
   CNT_POSITIVITY = 0, CNT_MEDIAN = 1, CNT_ELBM_NOROOT = 2, CNT_ELBM_F64 = 3,
-  CNT_ELBM_NONPOS = 4, CNT_N = 8
+  CNT_ELBM_NONPOS = 4, CNT_ELBM_ITERS = 5, CNT_N = 8
 };
+// The limiter counters are spread over kCntSlots copies, one 64-byte line
+// each ([slot][CNT_N]); a workgroup adds to copy blockIdx.x % kCntSlots, so
+// one step's atomics do not queue on a single address.
+constexpr int kCntSlots = 64;
 
 template <class R> struct KeyOf;
 template <> struct KeyOf<float> { using T = uint32_t; };
@@ -86,7 +90,7 @@ struct StepArgs {
   uint32_t* wcount;
   unsigned long long* ccount;  // kCountSlots partial candidate counts (spread atomics)
   unsigned int* hist;    // kBuckets counts of this step's candidates
-  unsigned long long* counters;
+  unsigned long long* counters;  // [kCntSlots][CNT_N]
 };
 
 // Launchers (one per translation unit); return hipSuccess or the error.

@@ -24,6 +24,13 @@ __device__ __forceinline__ void count_event(bool ev, unsigned long long* ctr) {
     atomicAdd(ctr, (unsigned long long)__popcll(m));
 }
 
+// Sum of a per-lane count over the wavefront, added once.
+__device__ __forceinline__ void count_sum(int v, unsigned long long* ctr) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if (v && __lane_id() == 0) atomicAdd(ctr, (unsigned long long)v);
+}
+
 template <class R>
 __device__ __forceinline__ void sort_net9(R a[9]) {
 #pragma unroll
@@ -54,6 +61,7 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<typename StoreT<S>:
   const int x = tile_x * TX + lx, y = tile_y * TY + ly;
   const bool valid = x < A.nx && y < A.ny;
 
+  unsigned long long* const cnt = A.counters + (blockIdx.x % kCntSlots) * CNT_N;
   const bool need_dS = MEDIAN || A.ehrenfest;
   // Without the median filter, Delta S only decides Ehrenfest candidacy:
   // sites provably below the floor skip its exact evaluation.
@@ -120,9 +128,9 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<typename StoreT<S>:
           d[i] = feq[i] - v[i];
         }
       }
-      if (A.count_events) count_event(acc, A.counters + CNT_MEDIAN);
+      if (A.count_events) count_event(acc, cnt + CNT_MEDIAN);
     } else if (A.count_events) {
-      count_event(false, A.counters + CNT_MEDIAN);
+      count_event(false, cnt + CNT_MEDIAN);
     }
   }
 
@@ -143,9 +151,10 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<typename StoreT<S>:
     collide_site<S, Q, COLL>(A, v, feq, d, om, post, ci);
     if constexpr (COLL == COLL_ELBM) {
       if (A.count_events) {
-        count_event(ci.branch == EB_NOROOT, A.counters + CNT_ELBM_NOROOT);
-        count_event(ci.f64, A.counters + CNT_ELBM_F64);
-        count_event(ci.branch == EB_NONPOS, A.counters + CNT_ELBM_NONPOS);
+        count_event(ci.branch == EB_NOROOT, cnt + CNT_ELBM_NOROOT);
+        count_event(ci.f64, cnt + CNT_ELBM_F64);
+        count_event(ci.branch == EB_NONPOS, cnt + CNT_ELBM_NONPOS);
+        count_sum(ci.iters, cnt + CNT_ELBM_ITERS);
       }
     }
     if (A.positivity) {
@@ -158,12 +167,13 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<typename StoreT<S>:
       StoreT<S>::st(dst + (long long)i * A.qs + (long long)y * A.pitch + x, post[i]);
   } else if constexpr (COLL == COLL_ELBM) {
     if (A.count_events) {
-      count_event(false, A.counters + CNT_ELBM_NOROOT);
-      count_event(false, A.counters + CNT_ELBM_F64);
-      count_event(false, A.counters + CNT_ELBM_NONPOS);
+      count_event(false, cnt + CNT_ELBM_NOROOT);
+      count_event(false, cnt + CNT_ELBM_F64);
+      count_event(false, cnt + CNT_ELBM_NONPOS);
+      count_sum(0, cnt + CNT_ELBM_ITERS);
     }
   }
-  if (A.positivity && A.count_events) count_event(pos_event, A.counters + CNT_POSITIVITY);
+  if (A.positivity && A.count_events) count_event(pos_event, cnt + CNT_POSITIVITY);
 }
 
 // ---------------------------------------------------------------------------
