@@ -27,6 +27,10 @@ struct SelState {
   int fallback;                  // 1: this step's candidates came from a rescan
   int fb_bin;                    // coarse bin chosen by the rescan
   int floor_raised[2];           // floor_key is above the eligibility threshold
+  int b_bin;                     // this step's boundary bucket (-1: take every candidate)
+  unsigned long long b_nc;       // this step's candidate count
+  unsigned long long b_above;    // candidates in buckets above b_bin
+  int rescan;                    // this step's candidates cannot hold the answer
   int pad[3];
 };
 

@@ -8,17 +8,20 @@
 // is at least a floor carried over from the previous step, and counts them
 // in a 4096-bucket histogram whose frame also comes from the previous step.
 // Selection then touches the short candidate list only:
+//   k_decide    counts the candidates; unless a rescan is needed, finds the
+//               boundary bucket (holding the k-th largest key) from the
+//               histogram;
 //   k_fb_scan   only when the candidates cannot hold the answer (fewer than
 //               k above a raised floor, or more than the buffer holds):
 //               rescans the lattice, histograms the top 12 bits of Delta S
 //               and picks a floor bin that holds at least k sites;
 //   k_fb_append same condition: rescans and appends from that bin up;
-//   k_fix       every workgroup finds the boundary bucket (holding the k-th
-//               largest key) from the histogram, writes f* at candidates
-//               above it and lists those inside it; the last workgroup
-//               resolves the boundary bucket exactly by an MSD radix select on
-//               (key descending, site index ascending), sets the next step's
-//               floor and frame, and resets the counters.
+//               its last workgroup then finds the boundary bucket;
+//   k_fix_regions writes f* at candidates above the boundary bucket and
+//               lists those inside it;
+//   k_fix_tail  resolves the boundary bucket exactly by an MSD radix select
+//               on (key descending, site index ascending), sets the next
+//               step's floor and frame, and resets the counters.
 #include "lbm_site.h"
 
 namespace lbm {
@@ -146,9 +149,13 @@ __device__ __forceinline__ void tile_site(int t, int w, int lane, int tiles_x, i
 }
 
 // ---------------------------------------------------------------------------
+// Sum of the spread candidate counters; every lane of the calling wavefront
+// takes part (one counter per lane) and receives the sum.
 __device__ __forceinline__ unsigned long long candidate_count(const unsigned long long* cc) {
-  unsigned long long n = 0;
-  for (int i = 0; i < kCountSlots; ++i) n += ld_rlx(&cc[i * kCountStride]);
+  const int lane = __lane_id();
+  unsigned long long n = lane < kCountSlots ? ld_rlx(&cc[lane * kCountStride]) : 0ull;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o);
   return n;
 }
 
@@ -160,10 +167,7 @@ __global__ __launch_bounds__(256) void k_fb_scan(const StepArgs<typename StoreT<
   using R = typename StoreT<S>::R;
   SelState* st = A.sel;
   __shared__ unsigned int h[kCoarse];
-  __shared__ unsigned long long s_nc;
-  if (threadIdx.x == 0) s_nc = candidate_count(A.ccount);
-  __syncthreads();
-  if (!calibrate && !need_rescan(s_nc, k, st)) return;
+  if (!calibrate && !st->rescan) return;      // decided by k_decide
   for (int i = threadIdx.x; i < kCoarse; i += blockDim.x) h[i] = 0;
   __syncthreads();
   const long long n = (long long)A.nx * A.ny;
@@ -222,10 +226,41 @@ __global__ __launch_bounds__(256) void k_fb_scan(const StepArgs<typename StoreT<
   for (int i = threadIdx.x; i < kCountSlots; i += blockDim.x) A.ccount[i * kCountStride] = 0;
 }
 
+// The bucket holding the k-th largest candidate key, from the step's
+// histogram; stored in the selection state for the region sweep.  Every
+// thread of one workgroup calls it.
+template <class R>
+__device__ void find_boundary(const StepArgs<R>& A, long long k) {
+  SelState* st = A.sel;
+  __shared__ unsigned int h[kBuckets];
+  __shared__ unsigned long long s_nc;
+  for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) h[i] = ld_rlx(&A.hist[i]);
+  if (threadIdx.x < 64) {
+    const unsigned long long n = candidate_count(A.ccount);
+    if (threadIdx.x == 0) s_nc = n;
+  }
+  __syncthreads();
+  const long long nc = (long long)s_nc;
+  int boundary = -1;
+  unsigned long long above = 0;
+  if (k <= 0) {
+    boundary = kBuckets;                 // take nothing
+  } else if (nc > k) {
+    find_from_top<kBuckets>(h, (unsigned long long)k, &boundary, &above);
+    if (boundary < 0) boundary = -1;
+  }
+  if (threadIdx.x == 0) {
+    st->b_bin = boundary;
+    st->b_nc = (unsigned long long)nc;
+    st->b_above = above;
+  }
+}
+
 // Rescan append, in the step kernel's tile layout so that every wavefront
 // region is rewritten (stale counts of the step kernel included).
 template <class S, int Q>
-__global__ __launch_bounds__(256) void k_fb_append(const StepArgs<typename StoreT<S>::R> A) {
+__global__ __launch_bounds__(256) void k_fb_append(const StepArgs<typename StoreT<S>::R> A,
+                                                   long long k) {
   using R = typename StoreT<S>::R;
   SelState* st = A.sel;
   if (!st->fallback) return;
@@ -261,6 +296,29 @@ __global__ __launch_bounds__(256) void k_fb_append(const StepArgs<typename Store
       atomicAdd(&A.hist[bucket_of<R>((unsigned long long)key_of<R>(dS), st->base_key[par], st->shift[par])], 1u);
     }
   }
+  if (last_block(&st->ticket)) {
+    find_boundary<R>(A, k);
+    if (threadIdx.x == 0) st->ticket = 0;
+  }
+}
+
+// First selection kernel of a step (one workgroup): the candidate count,
+// and either the rescan flag or, when the candidates hold the answer, the
+// boundary bucket.
+template <class S, int Q>
+__global__ __launch_bounds__(1024) void k_decide(const StepArgs<typename StoreT<S>::R> A,
+                                                long long k) {
+  using R = typename StoreT<S>::R;
+  SelState* st = A.sel;
+  __shared__ unsigned long long s_nc;
+  if (threadIdx.x < 64) {
+    const unsigned long long n = candidate_count(A.ccount);
+    if (threadIdx.x == 0) s_nc = n;
+  }
+  __syncthreads();
+  const bool rescan = need_rescan(s_nc, k, st);
+  if (threadIdx.x == 0) st->rescan = rescan ? 1 : 0;
+  if (!rescan) find_boundary<R>(A, k);
 }
 
 template <class S, int Q>
@@ -290,88 +348,12 @@ __device__ __forceinline__ unsigned int lds_slot(bool on, unsigned int* ctr) {
   return base + (unsigned int)__popcll(mask & ((1ull << lane) - 1ull));
 }
 
-// Selection: k_fix_regions sends every candidate above the boundary bucket to
-// equilibrium and lists the boundary bucket; k_fix_tail (one workgroup)
-// resolves the boundary bucket exactly and prepares the next step.
+// Exact resolution of the boundary bucket and the next step's floor and
+// frame, by one workgroup.
 template <class S, int Q>
-__global__ __launch_bounds__(256) void k_fix_regions(const StepArgs<typename StoreT<S>::R> A,
-                                                     long long k, int32_t* selected,
-                                                     int32_t* stage, uint32_t* blist,
-                                                     long long bcap) {
-  using R = typename StoreT<S>::R;
-  SelState* st = A.sel;
-  __shared__ unsigned int h[kBuckets];
-  __shared__ unsigned int s_sel, s_bnd;
-  __shared__ unsigned long long s_nc, s_base_sel, s_base_bnd;
-  const int par = (int)(st->step & 1ull);
-  const unsigned long long base = st->base_key[par];
-  const unsigned int shift = st->shift[par];
-  for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) h[i] = ld_rlx(&A.hist[i]);
-  if (threadIdx.x == 0) { s_sel = 0; s_bnd = 0; s_nc = candidate_count(A.ccount); }
-  __syncthreads();
-  const long long nc = (long long)s_nc;
-  const long long need = k < nc ? k : nc;
-  int boundary;
-  unsigned long long above;
-  if (k <= 0) {
-    boundary = kBuckets;                 // take nothing
-    above = 0;
-  } else if (nc <= k) {
-    boundary = -1;                       // take every candidate
-    above = 0;
-  } else {
-    find_from_top<kBuckets>(h, (unsigned long long)need, &boundary, &above);
-    if (boundary < 0) boundary = -1;
-  }
-  // 64 regions per wavefront, spread over the whole lattice with a stride of
-  // the wavefront count (candidates crowd into whole rows of a shear layer;
-  // a contiguous assignment would hand one wavefront an entire dense row).
-  // One read of the 64 counts, then the non-empty regions in turn with one
-  // lane per entry.
-  const long long nreg = (long long)A.tiles_x * A.tiles_y * 4;
-  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const long long g = (long long)blockIdx.x * 4 + w, nwave = (long long)gridDim.x * 4;
-  const long long my_r = (long long)lane * nwave + g;
-  int32_t* my_stage = stage + (long long)blockIdx.x * 256 * 64;
-  uint32_t cnt = 0;
-  if (my_r < nreg) cnt = A.wcount[my_r];
-  unsigned long long nz = __ballot(cnt != 0);
-  while (nz) {
-    const int j = __ffsll((long long)nz) - 1;
-    nz &= nz - 1;
-    const uint32_t c = __shfl(cnt, j);
-    const long long rj = __shfl(my_r, j);
-    const long long p = rj * 64 + lane;
-    bool sel = false, bnd = false;
-    if ((uint32_t)lane < c) {
-      const int b = bucket_of<R>((unsigned long long)A.cand_key[p], base, shift);
-      sel = boundary < 0 || b > boundary;
-      bnd = b == boundary;
-    }
-    if (sel) write_feq<S, Q>(A, p);
-    const unsigned int slot = lds_slot(sel, &s_sel);
-    if (sel) my_stage[slot] = (int32_t)A.cand_idx[p];
-    const unsigned int q = lds_slot(bnd, &s_bnd);
-    if (bnd) my_stage[256 * 64 - 1 - q] = (int32_t)p;   // boundary entries fill from the end
-  }
-  if (cnt) A.wcount[my_r] = 0;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    s_base_sel = s_sel ? atomicAdd(&st->sel_acc, (unsigned long long)s_sel) : 0ull;
-    s_base_bnd = s_bnd ? atomicAdd(&st->bcount, (unsigned long long)s_bnd) : 0ull;
-  }
-  __syncthreads();
-  for (unsigned int i = threadIdx.x; i < s_sel; i += blockDim.x)
-    if ((long long)(s_base_sel + i) < k) selected[s_base_sel + i] = my_stage[i];
-  for (unsigned int i = threadIdx.x; i < s_bnd; i += blockDim.x)
-    if ((long long)(s_base_bnd + i) < bcap) blist[s_base_bnd + i] = (uint32_t)my_stage[256 * 64 - 1 - i];
-}
-
-template <class S, int Q>
-__global__ __launch_bounds__(1024) void k_fix_tail(const StepArgs<typename StoreT<S>::R> A,
-                                                   long long k, long long n_sites,
-                                                   int32_t* selected, uint32_t* blist,
-                                                   long long bcap, long long* n_sel_out) {
+__device__ void fix_tail(const StepArgs<typename StoreT<S>::R>& A, long long k, long long n_sites,
+                         int32_t* selected, uint32_t* blist, long long bcap,
+                         long long* n_sel_out) {
   using R = typename StoreT<S>::R;
   SelState* st = A.sel;
   __shared__ unsigned int h[kBuckets];
@@ -383,18 +365,20 @@ __global__ __launch_bounds__(1024) void k_fix_tail(const StepArgs<typename Store
   const unsigned long long base = st->base_key[par];
   const unsigned int shift = st->shift[par];
   for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) h[i] = ld_rlx(&A.hist[i]);
-  if (threadIdx.x == 0) {
-    s_nc = candidate_count(A.ccount);
-    s_tot = (unsigned int)ld_rlx(&st->sel_acc);
+  if (threadIdx.x < 64) {
+    const unsigned long long n = candidate_count(A.ccount);
+    if (threadIdx.x == 0) {
+      s_nc = n;
+      s_tot = (unsigned int)ld_rlx(&st->sel_acc);
+    }
   }
   __syncthreads();
   const long long nc = (long long)s_nc;
   const long long need = k < nc ? k : nc;
-  int boundary = -1;
-  unsigned long long above = 0;
-  if (k > 0 && nc > k) {
-    find_from_top<kBuckets>(h, (unsigned long long)need, &boundary, &above);
-  }
+  // boundary bucket and the count above it, as found by k_decide (or by the
+  // rescan's last workgroup)
+  const int boundary = (k > 0 && nc > k) ? st->b_bin : -1;
+  const unsigned long long above = (k > 0 && nc > k) ? st->b_above : 0ull;
   const long long take = (boundary >= 0 && k > 0 && nc > k) ? need - (long long)above : 0;
   const long long m_all = (long long)ld_rlx(&st->bcount);
   const long long m = m_all < bcap ? m_all : bcap;
@@ -520,12 +504,85 @@ __global__ __launch_bounds__(1024) void k_fix_tail(const StepArgs<typename Store
   for (int i = threadIdx.x; i < kCountSlots; i += blockDim.x) A.ccount[i * kCountStride] = 0;
 }
 
+// Selection: k_fix_regions sends every candidate above the boundary bucket to
+// equilibrium and lists the boundary bucket; k_fix_tail (one workgroup of
+// 1024: the exact resolution is a chain of dependent loads over the list)
+// resolves the boundary bucket exactly and prepares the next step.
+template <class S, int Q>
+__global__ __launch_bounds__(256) void k_fix_regions(const StepArgs<typename StoreT<S>::R> A,
+                                                     long long k, int32_t* selected,
+                                                     int32_t* stage, uint32_t* blist,
+                                                     long long bcap) {
+  using R = typename StoreT<S>::R;
+  SelState* st = A.sel;
+  __shared__ unsigned int s_sel, s_bnd;
+  __shared__ unsigned long long s_base_sel, s_base_bnd;
+  const int par = (int)(st->step & 1ull);
+  const unsigned long long base = st->base_key[par];
+  const unsigned int shift = st->shift[par];
+  const int boundary = st->b_bin;          // -1: take every candidate
+  if (threadIdx.x == 0) { s_sel = 0; s_bnd = 0; }
+  __syncthreads();
+  // 64 regions per wavefront, spread over the whole lattice with a stride of
+  // the wavefront count (candidates crowd into whole rows of a shear layer;
+  // a contiguous assignment would hand one wavefront an entire dense row).
+  // One read of the 64 counts, then the non-empty regions in turn with one
+  // lane per entry.
+  const long long nreg = (long long)A.tiles_x * A.tiles_y * 4;
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const long long g = (long long)blockIdx.x * 4 + w, nwave = (long long)gridDim.x * 4;
+  const long long my_r = (long long)lane * nwave + g;
+  int32_t* my_stage = stage + (long long)blockIdx.x * 256 * 64;
+  uint32_t cnt = 0;
+  if (my_r < nreg) cnt = A.wcount[my_r];
+  unsigned long long nz = __ballot(cnt != 0);
+  while (nz) {
+    const int j = __ffsll((long long)nz) - 1;
+    nz &= nz - 1;
+    const uint32_t c = __shfl(cnt, j);
+    const long long rj = __shfl(my_r, j);
+    const long long p = rj * 64 + lane;
+    bool sel = false, bnd = false;
+    if ((uint32_t)lane < c) {
+      const int b = bucket_of<R>((unsigned long long)A.cand_key[p], base, shift);
+      sel = boundary < 0 || b > boundary;
+      bnd = b == boundary;
+    }
+    if (sel) write_feq<S, Q>(A, p);
+    const unsigned int slot = lds_slot(sel, &s_sel);
+    if (sel) my_stage[slot] = (int32_t)A.cand_idx[p];
+    const unsigned int q = lds_slot(bnd, &s_bnd);
+    if (bnd) my_stage[256 * 64 - 1 - q] = (int32_t)p;   // boundary entries fill from the end
+  }
+  if (cnt) A.wcount[my_r] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s_base_sel = s_sel ? atomicAdd(&st->sel_acc, (unsigned long long)s_sel) : 0ull;
+    s_base_bnd = s_bnd ? atomicAdd(&st->bcount, (unsigned long long)s_bnd) : 0ull;
+  }
+  __syncthreads();
+  for (unsigned int i = threadIdx.x; i < s_sel; i += blockDim.x)
+    if ((long long)(s_base_sel + i) < k) selected[s_base_sel + i] = my_stage[i];
+  for (unsigned int i = threadIdx.x; i < s_bnd; i += blockDim.x)
+    if ((long long)(s_base_bnd + i) < bcap) blist[s_base_bnd + i] = (uint32_t)my_stage[256 * 64 - 1 - i];
+}
+
+template <class S, int Q>
+__global__ __launch_bounds__(1024) void k_fix_tail(const StepArgs<typename StoreT<S>::R> A,
+                                                   long long k, long long n_sites,
+                                                   int32_t* selected, uint32_t* blist,
+                                                   long long bcap, long long* n_sel_out) {
+  fix_tail<S, Q>(A, k, n_sites, selected, blist, bcap, n_sel_out);
+}
+
 template <class S, int Q>
 static hipError_t launch_select_t(const SelectArgs& a, hipStream_t s) {
   using R = typename StoreT<S>::R;
   const StepArgs<R>& A = *(const StepArgs<R>*)a.step_args;
-  hipLaunchKernelGGL((k_fb_scan<S, Q>), dim3(1024), dim3(256), 0, s, A, a.k, a.coarse, 0);
-  hipLaunchKernelGGL((k_fb_append<S, Q>), dim3(1024), dim3(256), 0, s, A);
+  hipLaunchKernelGGL((k_decide<S, Q>), dim3(1), dim3(1024), 0, s, A, a.k);
+  // one workgroup per CU: both return at once unless this step rescans (rare)
+  hipLaunchKernelGGL((k_fb_scan<S, Q>), dim3(256), dim3(256), 0, s, A, a.k, a.coarse, 0);
+  hipLaunchKernelGGL((k_fb_append<S, Q>), dim3(256), dim3(256), 0, s, A, a.k);
   const long long nreg = (long long)A.tiles_x * A.tiles_y * 4;
   const int gfix = (int)((nreg + 255) / 256);
   hipLaunchKernelGGL((k_fix_regions<S, Q>), dim3(gfix), dim3(256), 0, s, A, a.k, a.selected,
