@@ -43,27 +43,29 @@ template <class S> struct StoreT;
 template <> struct StoreT<double> {
   using R = double;
   static constexpr bool shifted = false;
+  static __device__ __forceinline__ double cvt(double v) { return v; }
   static __device__ __forceinline__ double ld(const double* p) { return *p; }
   static __device__ __forceinline__ void st(double* p, double v) { __builtin_nontemporal_store(v, p); }
 };
 template <> struct StoreT<float> {
   using R = float;
   static constexpr bool shifted = true;
+  static __device__ __forceinline__ float cvt(float v) { return v; }
   static __device__ __forceinline__ float ld(const float* p) { return *p; }
   static __device__ __forceinline__ void st(float* p, float v) { __builtin_nontemporal_store(v, p); }
 };
 template <> struct StoreT<_Float16> {
   using R = float;
   static constexpr bool shifted = true;
+  static __device__ __forceinline__ float cvt(_Float16 v) { return (float)v; }
   static __device__ __forceinline__ float ld(const _Float16* p) { return (float)*p; }
   static __device__ __forceinline__ void st(_Float16* p, float v) { *p = (_Float16)v; }
 };
 template <> struct StoreT<bf16_t> {
   using R = float;
   static constexpr bool shifted = true;
-  static __device__ __forceinline__ float ld(const bf16_t* p) {
-    return __uint_as_float(((uint32_t)p->bits) << 16);
-  }
+  static __device__ __forceinline__ float cvt(bf16_t v) { return __uint_as_float(((uint32_t)v.bits) << 16); }
+  static __device__ __forceinline__ float ld(const bf16_t* p) { return cvt(*p); }
   static __device__ __forceinline__ void st(bf16_t* p, float v) {
     uint32_t u = __float_as_uint(v);
     uint16_t r;

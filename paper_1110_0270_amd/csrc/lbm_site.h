@@ -34,9 +34,9 @@ __device__ __forceinline__ void equilibrium_v(R m0, R rho0, R ux, R uy, int kind
   eq_dev6<R>(ux, kind, dx);
   if constexpr (Q == 9) eq_dev6<R>(uy, kind, dy);
   const R rho = SH ? rho0 + m0 : m0;
-  constexpr R S = Q == 9 ? R(36) : R(6);
-  const R rs = rho / S;
-  const R ms = m0 / S;
+  constexpr R iS = Q == 9 ? R(1) / R(36) : R(1) / R(6);
+  const R rs = rho * iS;
+  const R ms = m0 * iS;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     if constexpr (Q == 9) {
@@ -50,6 +50,32 @@ __device__ __forceinline__ void equilibrium_v(R m0, R rho0, R ux, R uy, int kind
       feq[i] = SH ? ms * ca + rs * dx[i] : rs * (ca + dx[i]);
     }
   }
+}
+
+// Element `off` of an array whose base is the same for the whole wavefront:
+// a 32-bit byte offset on a scalar base (one vector register per address).
+template <class S>
+__device__ __forceinline__ const S* at(const S* base, unsigned off) {
+  return (const S*)((const char*)base + off * (unsigned)sizeof(S));
+}
+template <class S>
+__device__ __forceinline__ S* at(S* base, unsigned off) {
+  return (S*)((char*)base + off * (unsigned)sizeof(S));
+}
+
+// Pull on a periodic lattice, branch-free: three source rows and three source
+// columns per site, each population at a scalar base plus a 32-bit offset.
+template <class S, int Q>
+__device__ __forceinline__ void pull_periodic(const S* __restrict__ src, long long qs, int pitch,
+                                              int nx, int ny, int x, int y,
+                                              typename StoreT<S>::R v[Q]) {
+  const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+  const unsigned r[3] = {(unsigned)(yp * pitch), (unsigned)(y * pitch), (unsigned)(ym * pitch)};
+  const unsigned c[3] = {(unsigned)xp, (unsigned)x, (unsigned)xm};   // a = -1, 0, +1
+#pragma unroll
+  for (int i = 0; i < Q; ++i)
+    v[i] = StoreT<S>::ld(at(src + (long long)i * qs, r[vy_of<Q>(i) + 1] + c[vx_of<Q>(i) + 1]));
 }
 
 // Pull f_i(x) = f_i(x - v_i) with the boundary rules: periodic wrap, or
@@ -75,9 +101,9 @@ __device__ __forceinline__ void pull(const S* __restrict__ src, long long qs, in
       out = (sx < 0) | (sx >= nx) | (sy < 0) | (sy >= ny);
     }
     if (!out) {
-      v[i] = StoreT<S>::ld(src + (long long)i * qs + (long long)sy * pitch + sx);
+      v[i] = StoreT<S>::ld(at(src + (long long)i * qs, (unsigned)(sy * pitch + sx)));
     } else {
-      v[i] = StoreT<S>::ld(src + (long long)(Q - 1 - i) * qs + (long long)y * pitch + x);
+      v[i] = StoreT<S>::ld(at(src + (long long)(Q - 1 - i) * qs, (unsigned)(y * pitch + x)));
       if (sy >= ny) v[i] += lid[i];
     }
   }
@@ -94,8 +120,9 @@ __device__ __forceinline__ void moments_v(const R v[Q], R rho0, R& m0, R& ux, R&
   }
   m0 = s;
   const R rho = SH ? rho0 + s : s;
-  ux = jx / rho;
-  uy = jy / rho;
+  const R ir = rcp<R>(rho);
+  ux = jx * ir;
+  uy = jy * ir;
 }
 
 // Nonequilibrium entropy of a site (section 4, eq. DelS), sum_i f_i
@@ -104,9 +131,11 @@ __device__ __forceinline__ void moments_v(const R v[Q], R rho0, R& m0, R& ux, R&
 // (S/rho) / ((c_a + dt_a)(c_b + dt_b)), so 1 + 2*3 reciprocals replace nine
 // divisions.  +inf if some f_i < 0 or f*_i <= 0.
 //
-// Screening: h(x) <= x^2 for x >= -1/2, so U = sum_i f*_i x_i^2 bounds Delta S
-// from above.  When U < screen (and every x_i >= -1/2) the exact sum is
-// skipped and U is returned: the caller only needs to know that Delta S is
+// Screening: for x >= -1/2, h(x) <= x^2/2 + max(-x, 0)^3/3 (for x >= 0 since
+// h'' <= 1; for -1/2 <= x < 0 the series terms beyond the cubic one sum to
+// less than the cubic term), so U = sum_i f*_i (that bound at x_i) bounds
+// Delta S from above.  When U < screen (and every x_i >= -1/2) the exact sum
+// is skipped and U is returned: the caller only needs to know that Delta S is
 // below `screen`.  screen = 0 always evaluates the exact sum.
 template <class R, int Q, bool SH>
 __device__ __forceinline__ R site_dS(const R v[Q], const R d[Q], R m0, R rho0, R ux, R uy,
@@ -143,15 +172,17 @@ __device__ __forceinline__ R site_dS(const R v[Q], const R d[Q], R m0, R rho0, R
     else { fq[i] = fx[a]; inv = irs * rx[a]; }
     x[i] = -d[i] * inv;
     far |= x[i] < R(-0.5);
-    ub += fq[i] * (x[i] * x[i]);
+    const R xn = x[i] < R(0) ? -x[i] : R(0);
+    ub += fq[i] * (x[i] * x[i] * R(0.5) + xn * xn * xn * R(1.0 / 3.0));
   }
   if (bad) return r_inf<R>();
-  ub *= rho / S;
-  if (!far && ub < screen) return ub;
+  ub *= rho * (R(1) / S);
+  // the margin covers the rounding of the bound itself
+  if (!far && ub * R(1.0001) < screen) return ub;
   R acc = R(0);
 #pragma unroll
   for (int i = 0; i < Q; ++i) acc += fq[i] * h_fn<R>(x[i]);
-  return acc * (rho / S);
+  return acc * (rho * (R(1) / S));
 }
 
 // Ranking key of a non-negative Delta S: its bit pattern (monotone in the
@@ -174,7 +205,8 @@ template <> __device__ __forceinline__ double value_of_key<double>(unsigned long
 
 // Everything up to Delta S for one site: used by the step, the median halo
 // and the selection rescans, so that all of them see bit-identical values.
-template <class S, int Q>
+// PER: the caller knows the lattice is periodic (branch-free pull).
+template <class S, int Q, bool PER = false>
 __device__ __forceinline__ typename StoreT<S>::R site_prep(
     const StepArgs<typename StoreT<S>::R>& A, int x, int y, typename StoreT<S>::R v[Q],
     typename StoreT<S>::R feq[Q], typename StoreT<S>::R d[Q], typename StoreT<S>::R& m0,
@@ -182,7 +214,8 @@ __device__ __forceinline__ typename StoreT<S>::R site_prep(
     typename StoreT<S>::R screen = typename StoreT<S>::R(0)) {
   using R = typename StoreT<S>::R;
   constexpr bool SH = StoreT<S>::shifted;
-  pull<S, Q>((const S*)A.src, A.qs, A.pitch, A.nx, A.ny, A.bc, x, y, A.lid, v);
+  if constexpr (PER) pull_periodic<S, Q>((const S*)A.src, A.qs, A.pitch, A.nx, A.ny, x, y, v);
+  else pull<S, Q>((const S*)A.src, A.qs, A.pitch, A.nx, A.ny, A.bc, x, y, A.lid, v);
   moments_v<R, Q, SH>(v, A.rho0, m0, ux, uy);
   equilibrium_v<R, Q, SH>(m0, A.rho0, ux, uy, A.eq_kind, feq);
 #pragma unroll

@@ -44,8 +44,67 @@ __device__ __forceinline__ void sort_net9(R a[9]) {
   }
 }
 
-template <class S, int Q, int COLL, bool MEDIAN, int TX, int TY>
-__global__ __launch_bounds__(256) void k_step(const StepArgs<typename StoreT<S>::R> A) {
+// The step after the pull (and the median filter): Ehrenfest candidacy
+// (eligible, Delta S > delta, and above the floor), collision, positivity
+// rule, store into the second lattice, and the limiter counters.  Every lane
+// of the wavefront calls it.
+template <class S, int Q, int COLL>
+__device__ __forceinline__ void site_finish(const StepArgs<typename StoreT<S>::R>& A, int x, int y,
+                                            bool valid, long long region,
+                                            typename StoreT<S>::R v[Q],
+                                            typename StoreT<S>::R feq[Q],
+                                            typename StoreT<S>::R d[Q], typename StoreT<S>::R m0,
+                                            typename StoreT<S>::R ux, typename StoreT<S>::R uy,
+                                            typename StoreT<S>::R dS, int par,
+                                            unsigned long long* cnt) {
+  using R = typename StoreT<S>::R;
+  // Ehrenfest candidates: eligible (Delta S > delta) and above the floor.
+  if (A.ehrenfest) {
+    using K = typename KeyOf<R>::T;
+    const K key = key_of<R>(dS);
+    const bool is_c = valid && (dS > A.ehr_delta) && (key >= (K)A.sel->floor_key[par]);
+    append_candidates<R>(A, region, is_c, key, (uint32_t)(y * A.nx + x), m0, ux, uy);
+  }
+
+  R post[Q];
+  bool pos_event = false;
+  if (valid) {
+    const R om = A.omega_field ? A.omega_field[(long long)y * A.pitch + x] : A.omega;
+    CollInfo<R> ci;
+    collide_site<S, Q, COLL>(A, v, feq, d, om, post, ci);
+    if constexpr (COLL == COLL_ELBM) {
+      if (A.count_events) {
+        count_event(ci.branch == EB_NOROOT, cnt + CNT_ELBM_NOROOT);
+        count_event(ci.f64, cnt + CNT_ELBM_F64);
+        count_event(ci.branch == EB_NONPOS, cnt + CNT_ELBM_NONPOS);
+        count_sum(ci.iters, cnt + CNT_ELBM_ITERS);
+      }
+    }
+    if (A.positivity) {
+      positivity_site<S, Q>(A, feq, post, ci);
+      pos_event = ci.pos_arg >= 0;
+    }
+    S* dst = (S*)A.dst;
+    const unsigned o = (unsigned)(y * A.pitch + x);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) StoreT<S>::st(at(dst + (long long)i * A.qs, o), post[i]);
+  } else if constexpr (COLL == COLL_ELBM) {
+    if (A.count_events) {
+      count_event(false, cnt + CNT_ELBM_NOROOT);
+      count_event(false, cnt + CNT_ELBM_F64);
+      count_event(false, cnt + CNT_ELBM_NONPOS);
+      count_sum(0, cnt + CNT_ELBM_ITERS);
+    }
+  }
+  if (A.positivity && A.count_events) count_event(pos_event, cnt + CNT_POSITIVITY);
+}
+
+// LBGK in FP32/16-bit storage on row tiles fits 64 registers: keep the full
+// occupancy of 8 wavefronts per SIMD (the compiler would otherwise take a few
+// more).
+template <class S, int Q, int COLL, bool MEDIAN, int TX, int TY, bool PER>
+__global__ __launch_bounds__(256, ((COLL == COLL_LBGK && sizeof(S) <= 4 && !MEDIAN && TX == 256) ? 8 : 1))
+void k_step(const StepArgs<typename StoreT<S>::R> A) {
   using R = typename StoreT<S>::R;
   constexpr bool SH = StoreT<S>::shifted;
   static_assert(TX * TY == 256, "tile must hold 256 sites");
@@ -68,7 +127,7 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<typename StoreT<S>:
   const int par = A.ehrenfest ? (int)(A.sel->step & 1ull) : 0;
   const R screen = (!MEDIAN && A.ehrenfest) ? value_of_key<R>(A.sel->floor_key[par]) : R(0);
   R v[Q], feq[Q], d[Q], m0 = R(0), ux = R(0), uy = R(0), dS = R(0);
-  if (valid) dS = site_prep<S, Q>(A, x, y, v, feq, d, m0, ux, uy, need_dS, screen);
+  if (valid) dS = site_prep<S, Q, PER>(A, x, y, v, feq, d, m0, ux, uy, need_dS, screen);
 
   if constexpr (MEDIAN) {
     // Median entropy filter: Delta S of the tile plus a one-site halo in LDS.
@@ -134,59 +193,81 @@ __global__ __launch_bounds__(256) void k_step(const StepArgs<typename StoreT<S>:
     }
   }
 
-  // Ehrenfest candidates: eligible (Delta S > delta) and above the floor.
-  if (A.ehrenfest) {
-    using K = typename KeyOf<R>::T;
-    const K key = key_of<R>(dS);
-    const bool is_c = valid && (dS > A.ehr_delta) && (key >= (K)A.sel->floor_key[par]);
-    append_candidates<R>(A, (long long)t * 4 + threadIdx.x / 64, is_c, key,
-                         (uint32_t)(y * A.nx + x), m0, ux, uy);
-  }
+  site_finish<S, Q, COLL>(A, x, y, valid, (long long)t * 4 + threadIdx.x / 64, v, feq, d, m0, ux,
+                          uy, dS, par, cnt);
+}
 
-  R post[Q];
-  bool pos_event = false;
-  if (valid) {
-    const R om = A.omega_field ? A.omega_field[(long long)y * A.pitch + x] : A.omega;
-    CollInfo<R> ci;
-    collide_site<S, Q, COLL>(A, v, feq, d, om, post, ci);
-    if constexpr (COLL == COLL_ELBM) {
-      if (A.count_events) {
-        count_event(ci.branch == EB_NOROOT, cnt + CNT_ELBM_NOROOT);
-        count_event(ci.f64, cnt + CNT_ELBM_F64);
-        count_event(ci.branch == EB_NONPOS, cnt + CNT_ELBM_NONPOS);
-        count_sum(ci.iters, cnt + CNT_ELBM_ITERS);
-      }
-    }
-    if (A.positivity) {
-      positivity_site<S, Q>(A, feq, post, ci);
-      pos_event = ci.pos_arg >= 0;
-    }
-    S* dst = (S*)A.dst;
+// The step on a periodic lattice without the median filter, in rows of 256
+// sites: each workgroup takes ROWS consecutive rows of one 256-column strip,
+// and every thread issues the loads of its next row before it computes the
+// current one, so that each wavefront keeps two rows of loads in flight (the
+// one-site kernel waits on a full memory latency for every site).  Per-site
+// arithmetic is the one-site kernel's, so the results are bit-identical.
+// Used for the 16-bit storage forms and for ELBM in FP32.
+template <class S, int Q, int COLL, int ROWS>
+__global__ __launch_bounds__(256) void k_step_rows(const StepArgs<typename StoreT<S>::R> A) {
+  using R = typename StoreT<S>::R;
+  constexpr bool SH = StoreT<S>::shifted;
+  const int nyc = (A.ny + ROWS - 1) / ROWS;
+  const int T = A.tiles_x * nyc;
+  const int b = blockIdx.x;
+  const int t = (T % 8 == 0) ? (b % 8) * (T / 8) + b / 8 : b;   // XCD-aware order
+  const int tile_x = t % A.tiles_x, y0 = (t / A.tiles_x) * ROWS;
+  const int x = tile_x * 256 + (int)threadIdx.x;
+  const bool valid = x < A.nx;
+  const int xl = valid ? x : 0;
+  const unsigned c[3] = {(unsigned)(xl == A.nx - 1 ? 0 : xl + 1), (unsigned)xl,
+                         (unsigned)(xl == 0 ? A.nx - 1 : xl - 1)};   // source columns, a = -1, 0, +1
+  unsigned long long* const cnt = A.counters + (blockIdx.x % kCntSlots) * CNT_N;
+  const int par = A.ehrenfest ? (int)(A.sel->step & 1ull) : 0;
+  const R screen = A.ehrenfest ? value_of_key<R>(A.sel->floor_key[par]) : R(0);
+  const S* __restrict__ src = (const S*)A.src;
+
+  auto load_row = [&](int y, S raw[Q]) {
+    const int ym = y == 0 ? A.ny - 1 : y - 1, yp = y == A.ny - 1 ? 0 : y + 1;
+    const unsigned r[3] = {(unsigned)(yp * A.pitch), (unsigned)(y * A.pitch),
+                           (unsigned)(ym * A.pitch)};                // source rows, b = -1, 0, +1
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-      StoreT<S>::st(dst + (long long)i * A.qs + (long long)y * A.pitch + x, post[i]);
-  } else if constexpr (COLL == COLL_ELBM) {
-    if (A.count_events) {
-      count_event(false, cnt + CNT_ELBM_NOROOT);
-      count_event(false, cnt + CNT_ELBM_F64);
-      count_event(false, cnt + CNT_ELBM_NONPOS);
-      count_sum(0, cnt + CNT_ELBM_ITERS);
-    }
+      raw[i] = *at(src + (long long)i * A.qs, r[vy_of<Q>(i) + 1] + c[vx_of<Q>(i) + 1]);
+  };
+
+  S nxt[Q];
+  load_row(y0, nxt);
+#pragma unroll 1
+  for (int rr = 0; rr < ROWS; ++rr) {
+    const int y = y0 + rr;
+    if (y >= A.ny) break;                    // uniform over the workgroup
+    S cur[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) cur[i] = nxt[i];
+    if (rr + 1 < ROWS && y + 1 < A.ny) load_row(y + 1, nxt);
+    R v[Q], feq[Q], d[Q], m0, ux, uy;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) v[i] = StoreT<S>::cvt(cur[i]);
+    moments_v<R, Q, SH>(v, A.rho0, m0, ux, uy);
+    equilibrium_v<R, Q, SH>(m0, A.rho0, ux, uy, A.eq_kind, feq);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) d[i] = feq[i] - v[i];
+    const R dS = (A.ehrenfest && valid)
+                     ? site_dS<R, Q, SH>(v, d, m0, A.rho0, ux, uy, A.eq_kind, screen)
+                     : R(0);
+    const long long region = ((long long)y * A.tiles_x + tile_x) * 4 + threadIdx.x / 64;
+    site_finish<S, Q, COLL>(A, x, y, valid, region, v, feq, d, m0, ux, uy, dS, par, cnt);
   }
-  if (A.positivity && A.count_events) count_event(pos_event, cnt + CNT_POSITIVITY);
 }
 
 // ---------------------------------------------------------------------------
 // Launch dispatch.
 // ---------------------------------------------------------------------------
-template <class S, int Q, int COLL, bool MEDIAN, int TX, int TY>
+template <class S, int Q, int COLL, bool MEDIAN, int TX, int TY, bool PER = false>
 static void launch_k(const StepArgs<typename StoreT<S>::R>& A, hipStream_t s, hipEvent_t e0,
                      hipEvent_t e1) {
   const dim3 grid(A.tiles_x * A.tiles_y), block(256);
   if (e0 && e1)  // events taken at the kernel's own start and end
-    hipExtLaunchKernelGGL((k_step<S, Q, COLL, MEDIAN, TX, TY>), grid, block, 0, s, e0, e1, 0, A);
+    hipExtLaunchKernelGGL((k_step<S, Q, COLL, MEDIAN, TX, TY, PER>), grid, block, 0, s, e0, e1, 0, A);
   else
-    hipLaunchKernelGGL((k_step<S, Q, COLL, MEDIAN, TX, TY>), grid, block, 0, s, A);
+    hipLaunchKernelGGL((k_step<S, Q, COLL, MEDIAN, TX, TY, PER>), grid, block, 0, s, A);
 }
 
 template <class S, int Q, int COLL, bool MEDIAN>
@@ -198,8 +279,35 @@ static hipError_t launch_t(const void* args, hipStream_t s, hipEvent_t e0, hipEv
   } else if constexpr (MEDIAN) {
     launch_k<S, Q, COLL, MEDIAN, 64, 4>(A, s, e0, e1);
   } else {
-    if (tile_shape(Q, MEDIAN, A.nx).tx == 256) launch_k<S, Q, COLL, MEDIAN, 256, 1>(A, s, e0, e1);
-    else launch_k<S, Q, COLL, MEDIAN, 64, 4>(A, s, e0, e1);
+    if (tile_shape(Q, MEDIAN, A.nx).tx == 256) {
+      // 16-bit storage: one site per lane leaves the memory system idle
+      // (measured 2.4 TB/s against 4.2 TB/s for the row-pipelined kernel);
+      // FP32 and FP64 LBGK/MRT already keep enough loads in flight at full
+      // occupancy.  ELBM (two wavefronts per SIMD) gains from the pipelining
+      // in FP32 too.
+      bool rows = false;
+      if constexpr (sizeof(S) == 2 || (sizeof(S) == 4 && COLL == COLL_ELBM)) {
+        if (A.bc == BC_PERIODIC) {
+          constexpr int ROWS = 4;
+          const dim3 grid(A.tiles_x * ((A.ny + ROWS - 1) / ROWS)), block(256);
+          if (e0 && e1)
+            hipExtLaunchKernelGGL((k_step_rows<S, Q, COLL, ROWS>), grid, block, 0, s, e0, e1, 0, A);
+          else
+            hipLaunchKernelGGL((k_step_rows<S, Q, COLL, ROWS>), grid, block, 0, s, A);
+          rows = true;
+        }
+      }
+      if (!rows) {
+        if constexpr (COLL != COLL_ELBM) {
+          if (A.bc == BC_PERIODIC) launch_k<S, Q, COLL, MEDIAN, 256, 1, true>(A, s, e0, e1);
+          else launch_k<S, Q, COLL, MEDIAN, 256, 1>(A, s, e0, e1);
+        } else {
+          launch_k<S, Q, COLL, MEDIAN, 256, 1>(A, s, e0, e1);
+        }
+      }
+    } else {
+      launch_k<S, Q, COLL, MEDIAN, 64, 4>(A, s, e0, e1);
+    }
   }
   return hipGetLastError();
 }
