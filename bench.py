@@ -40,6 +40,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the FP32 step kernel on this workload (periodic
+# one-site kernel, LBGK + Ehrenfest): rocprofv3 FETCH_SIZE and WRITE_SIZE
+# medians over 25 launches, scaled by what the counters read for a device
+# copy of 1,207,959,552 bytes (FETCH x 2.0, WRITE x 1.0); summary in
+# profiles/hbm_traffic_k_step_shear_layer_4096_f32.md.  Retake after any
+# change of the kernel.
+HBM_TRAFFIC_F32 = 604_151_936 + 606_903_104
 ELEM = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}
 METRIC = "MLUPS and % HBM roofline, D2Q9 fwd+adjoint, FP64 vs FP32/FP16-storage at stated err"
 
@@ -523,7 +530,9 @@ def main():
                    "storage": args.storage},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "kernel": "k_step (fused collide-stream)",
+                     "traffic": (HBM_TRAFFIC_F32 if args.storage == "f32" else None),
+                     "traffic_unit": "bytes per launch",
+                     "kernel": "k_step (fused collide-stream)",
                      "kernel_us": round(main_res["kernel_ms"] * 1e3, 2),
                      "alg_bytes_per_launch": main_res["alg_bytes_per_launch"]},
         "forms": _round(forms),
