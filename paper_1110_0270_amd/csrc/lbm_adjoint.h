@@ -26,6 +26,9 @@ struct AdjointLayout {
   size_t off_tape_sel = 0;   // max_steps * k site indices
   size_t off_tape_cnt = 0;   // max_steps counts
   size_t off_mask = 0;       // one byte per site: sent to f* in the step being reversed
+  bool store_alpha = false;  // ELBM: the recompute keeps alpha and branch per site
+  size_t off_alpha = 0;      // K x [ny][pitch] alpha (compute precision)
+  size_t off_branch = 0;     // K x [ny][pitch] branch bytes
   size_t end = 0;
 };
 
@@ -43,9 +46,12 @@ long long* adjoint_count_slot(const AdjointLayout& L, char* ws, long long t);
 // the compute precision (double for LBM_F64 storage, float otherwise) with
 // src = the state the step read; lam_in/lam_out/gom use the same precision
 // and the pitched layout of the lattice.
-// e0/e1: optional events recorded right before and after the kernel.
+// alpha/branch: the step's ELBM alpha and branch per site, from the
+// recompute (required for ELBM, ignored otherwise).  e0/e1: optional events
+// recorded right before and after the kernel.
 hipError_t launch_adjoint(int storage, int Q, int coll, const void* step_args, const void* lam_in,
-                          void* lam_out, void* gom, const unsigned char* mask, hipStream_t s,
+                          void* lam_out, void* gom, const unsigned char* mask,
+                          const void* alpha, const unsigned char* branch, hipStream_t s,
                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // f* written into step_args->dst at the first *count sites of list (<= k).
 hipError_t launch_tape_fix(int storage, int Q, const void* step_args, const int32_t* list,

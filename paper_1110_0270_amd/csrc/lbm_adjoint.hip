@@ -69,6 +69,8 @@ struct AdjArgs {
   R* lam_out;               // lambda_t
   R* gom;                   // dL/d omega accumulator [ny][pitch] or nullptr
   const unsigned char* mask;// 1 at sites the Ehrenfest limiter sent to f* (or nullptr)
+  const R* alpha;           // ELBM: the step's alpha per site [ny][pitch]
+  const unsigned char* branch;  // ELBM: the step's branch per site
 };
 
 template <class S, int Q, int COLL>
@@ -97,7 +99,17 @@ __global__ __launch_bounds__(256) void k_adjoint(const StepArgs<typename StoreT<
   } else {
     R q[Q];
     CollInfo<R> ci;
-    collide_site<S, Q, COLL>(A, v, feq, d, om, q, ci);
+    if constexpr (COLL == COLL_ELBM) {
+      // alpha and branch of the forward step, kept by the recompute: the
+      // collided state is the forward's bit for bit without a second root solve
+      ci.alpha = B.alpha[o];
+      ci.branch = B.branch[o];
+      const R ab = ci.alpha * (om * R(0.5));
+#pragma unroll
+      for (int i = 0; i < Q; ++i) q[i] = v[i] + ab * d[i];
+    } else {
+      collide_site<S, Q, COLL>(A, v, feq, d, om, q, ci);
+    }
     // positivity rule: g'' = f* + phi (q - f*), phi = f*_a / (f*_a - q_a)
     R lq[Q];
 #pragma unroll
@@ -178,19 +190,21 @@ __global__ __launch_bounds__(256) void k_adjoint(const StepArgs<typename StoreT<
         qa[i] = feq[i] + sh;
       }
       if (ci.branch == EB_ROOT) {
-        // implicit derivative: d alpha = -(dS_f/dp dp + dS_f/df* df*) / S_f'
-        R d1 = R(0);
+        // implicit derivative: d alpha = -(dS_f/dp dp + dS_f/df* df*) / S_f',
+        // with ln((p + alpha D)/w) = ln(p/w) + ln(1 + alpha D/p)
+        R d1 = R(0), l1[Q], lw[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
           const R xx = alpha * d[i] / fa[i];
-          d1 -= d[i] * (lg1p<R>(xx < R(-1) ? R(-1) : xx) + lg1p<R>(-d[i] / qa[i]));
+          l1[i] = lg1p<R>(xx < R(-1) ? R(-1) : xx);
+          lw[i] = log(fa[i] / wt<R, Q>(i));
+          d1 -= d[i] * (l1[i] + lg1p<R>(-d[i] / qa[i]));
         }
         const R c = -lal / d1;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-          const R w = wt<R, Q>(i);
-          const R gs = -(log((fa[i] + alpha * d[i]) / w) + R(1));   // dS/dy at p + alpha D
-          const R ps = -(log(fa[i] / w) + R(1));                     // dS/dy at p
+          const R gs = -(lw[i] + l1[i] + R(1));   // dS/dy at p + alpha D
+          const R ps = -(lw[i] + R(1));           // dS/dy at p
           mu[i] += c * ((R(1) - alpha) * gs - ps);
           lf[i] += c * (alpha * gs);
         }
@@ -332,13 +346,17 @@ static hipError_t launch_adj_s(int Q, int coll, const void* sargs, const void* a
 }
 
 hipError_t launch_adjoint(int storage, int Q, int coll, const void* step_args, const void* lam_in,
-                          void* lam_out, void* gom, const unsigned char* mask, hipStream_t s,
+                          void* lam_out, void* gom, const unsigned char* mask,
+                          const void* alpha, const unsigned char* branch, hipStream_t s,
                           hipEvent_t e0, hipEvent_t e1) {
+  if (coll == COLL_ELBM && (!alpha || !branch)) return hipErrorInvalidValue;
   if (storage == 0) {
-    AdjArgs<double> B{(const double*)lam_in, (double*)lam_out, (double*)gom, mask};
+    AdjArgs<double> B{(const double*)lam_in, (double*)lam_out, (double*)gom, mask,
+                      (const double*)alpha, branch};
     return launch_adj_s<double>(Q, coll, step_args, &B, s, e0, e1);
   }
-  AdjArgs<float> B{(const float*)lam_in, (float*)lam_out, (float*)gom, mask};
+  AdjArgs<float> B{(const float*)lam_in, (float*)lam_out, (float*)gom, mask,
+                   (const float*)alpha, branch};
   if (storage == 1) return launch_adj_s<float>(Q, coll, step_args, &B, s, e0, e1);
   if (storage == 2) return launch_adj_s<_Float16>(Q, coll, step_args, &B, s, e0, e1);
   return launch_adj_s<bf16_t>(Q, coll, step_args, &B, s, e0, e1);

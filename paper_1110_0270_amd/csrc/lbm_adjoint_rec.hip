@@ -23,7 +23,14 @@ AdjointLayout adjoint_layout(const lbm_config* c, size_t lat_bytes, long long qs
   size_t o = offset;
   auto take = [&](size_t b) { size_t at = o; o += a256(b); return at; };
   L.off_ckpt = take((size_t)L.n_ckpt * a256(lat_bytes));
-  L.off_seg = take((size_t)L.K * a256(lat_bytes));
+  // ELBM: one more state slot, so that the last step of a segment can be
+  // recomputed for its alpha
+  L.store_alpha = c->collision == LBM_ELBM;
+  L.off_seg = take((size_t)(L.K + (L.store_alpha ? 1 : 0)) * a256(lat_bytes));
+  if (L.store_alpha) {
+    L.off_alpha = take((size_t)L.K * a256((size_t)qs * rb));
+    L.off_branch = take((size_t)L.K * a256((size_t)qs));
+  }
   L.off_lam[0] = take(L.lam_bytes);
   L.off_lam[1] = take(L.lam_bytes);
   L.off_gom = take((size_t)qs * rb);

@@ -618,9 +618,22 @@ static lbm_status backward_impl(lbm_ctx* c, const void* dL_dfT, void* dL_df0, vo
   StepArgs<float> a32 = c->a32;
   a64.ehrenfest = a32.ehrenfest = 0;
   a64.count_events = a32.count_events = 0;
-  auto args_for = [&](const void* src, void* dst) -> const void* {
-    if (r64) { a64.src = src; a64.dst = dst; return &a64; }
-    a32.src = src; a32.dst = dst; return &a32;
+  auto args_for = [&](const void* src, void* dst, void* alpha = nullptr,
+                      unsigned char* branch = nullptr) -> const void* {
+    if (r64) {
+      a64.src = src; a64.dst = dst; a64.alpha_out = (double*)alpha; a64.branch_out = branch;
+      return &a64;
+    }
+    a32.src = src; a32.dst = dst; a32.alpha_out = (float*)alpha; a32.branch_out = branch;
+    return &a32;
+  };
+  // ELBM: alpha and branch of step t0 + j of the segment being reversed
+  const size_t fbytes = align256((size_t)qs * (r64 ? 8 : 4)), bbytes = align256((size_t)qs);
+  auto alpha_slot = [&](long long j) -> void* {
+    return A.store_alpha ? (void*)(ws + A.off_alpha + (size_t)j * fbytes) : nullptr;
+  };
+  auto branch_slot = [&](long long j) -> unsigned char* {
+    return A.store_alpha ? (unsigned char*)(ws + A.off_branch + (size_t)j * bbytes) : nullptr;
   };
   hipError_t e = launch_to_pitch(dL_dfT, din, lam[0], r64, Q, nx, ny, pitch, qs, st);
   if (e == hipSuccess) e = hipMemsetAsync(gom, 0, (size_t)qs * (r64 ? 8 : 4), st);
@@ -628,12 +641,16 @@ static lbm_status backward_impl(lbm_ctx* c, const void* dL_dfT, void* dL_df0, vo
   int cur = 0;
   for (long long s = T > 0 ? (T - 1) / A.K : -1; s >= 0 && e == hipSuccess; --s) {
     const long long t0 = s * A.K, t1 = std::min(T, t0 + A.K);
-    // states g_t0 .. g_{t1-1} of the segment, from its checkpoint
+    // states g_t0 .. g_{t1-1} of the segment, from its checkpoint (ELBM: the
+    // last step too, into a spare slot, for its alpha)
     e = hipMemcpyAsync(seg(0), ckpt(s), c->L.lat_bytes, hipMemcpyDeviceToDevice, st);
-    for (long long t = t0; t + 1 < t1 && e == hipSuccess; ++t) {
-      const void* args = args_for(seg(t - t0), seg(t + 1 - t0));
+    const long long t_end = A.store_alpha ? t1 : t1 - 1;
+    for (long long t = t0; t < t_end && e == hipSuccess; ++t) {
+      const bool last = t + 1 == t1;
+      const void* args = args_for(seg(t - t0), last ? seg(A.K) : seg(t + 1 - t0),
+                                  alpha_slot(t - t0), branch_slot(t - t0));
       e = launch_step(c->cfg.storage, Q, c->cfg.collision, false, args, st);
-      if (e == hipSuccess && A.k > 0)
+      if (e == hipSuccess && A.k > 0 && !last)
         e = launch_tape_fix(c->cfg.storage, Q, args, adjoint_selected_slot(A, ws, t, nullptr),
                             adjoint_count_slot(A, ws, t), A.k, st);
     }
@@ -645,7 +662,8 @@ static lbm_status backward_impl(lbm_ctx* c, const void* dL_dfT, void* dL_df0, vo
       const void* args = args_for(seg(t - t0), nullptr);
       if (e == hipSuccess)
         e = launch_adjoint(c->cfg.storage, Q, c->cfg.collision, args, lam[cur], lam[1 - cur],
-                           dL_domega ? gom : nullptr, mask, st,
+                           dL_domega ? gom : nullptr, mask, alpha_slot(t - t0),
+                           branch_slot(t - t0), st,
                            ev ? (*ev)[2 * t] : nullptr, ev ? (*ev)[2 * t + 1] : nullptr);
       if (e == hipSuccess && mask) e = launch_mark(mask, list, cnt, A.k, 0, st);
       cur = 1 - cur;

@@ -95,6 +95,10 @@ struct StepArgs {
   unsigned long long* ccount;  // kCountSlots partial candidate counts (spread atomics)
   unsigned int* hist;    // kBuckets counts of this step's candidates
   unsigned long long* counters;  // [kCntSlots][CNT_N]
+  // ELBM recompute for the adjoint: alpha and branch of every site ([ny][pitch]),
+  // or nullptr
+  R* alpha_out;
+  unsigned char* branch_out;
 };
 
 // Launchers (one per translation unit); return hipSuccess or the error.

@@ -73,6 +73,11 @@ __device__ __forceinline__ void site_finish(const StepArgs<typename StoreT<S>::R
     CollInfo<R> ci;
     collide_site<S, Q, COLL>(A, v, feq, d, om, post, ci);
     if constexpr (COLL == COLL_ELBM) {
+      if (A.alpha_out) {
+        const long long o = (long long)y * A.pitch + x;
+        A.alpha_out[o] = ci.alpha;
+        A.branch_out[o] = (unsigned char)ci.branch;
+      }
       if (A.count_events) {
         count_event(ci.branch == EB_NOROOT, cnt + CNT_ELBM_NOROOT);
         count_event(ci.f64, cnt + CNT_ELBM_F64);
