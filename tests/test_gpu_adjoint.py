@@ -6,7 +6,9 @@ dL/df0 and per-site dL/d omega are compared with the oracle's gradients:
 FP64 storage max |gpu - oracle| <= tol * max |oracle| with tol = 1e-11
 (1e-9 through ELBM roots, which carry the root solve's 1e-14 tolerance
 through the implicit derivative); FP32 storage 1e-4 (1e-3 ELBM), the
-accumulated FP32 rounding of a few steps of forward recompute and adjoint.
+accumulated FP32 rounding of a few steps of forward recompute and adjoint;
+FP16 shifted storage 5e-3 (the adjoint treats storage rounding as the
+identity).
 Rollouts span several checkpoint segments with a ragged last one, so the
 recompute from checkpoints and the selection tape are exercised."""
 import numpy as np
@@ -358,3 +360,39 @@ def test_cavity_copy_8192_steps_central_differences():
     assert sp == sel_ref and sm == sel_ref
     adw = float((gw.cpu() * z).sum())
     assert abs(adw - (lp - lm) / (2 * h)) <= 1e-6 * abs(adw)
+
+
+@pytest.mark.parametrize("name,storage,tol", [
+    ("elbm_periodic", "f32", 1e-3),          # row-pipelined kernel keeps alpha in the recompute
+    ("elbm_periodic", "f64", 1e-9),
+    ("lbgk_cavity_ehrenfest_pos", "f32", 1e-4),
+    ("lbgk_periodic", "f16s", 5e-3),          # 16-bit storage: row kernel, storage rounding
+    ("mrt_m1_field_cavity", "f32", 1e-4),
+])
+def test_adjoint_row_tiles(name, storage, tol):
+    """The adjoint on 300 x 13 lattices (256-site row tiles; periodic 16-bit
+    and FP32 ELBM steps run the row-pipelined kernel), 6 steps with
+    checkpoints every 4, against the oracle's FP64 gradient from the state
+    the library stores."""
+    p, amp, want_field = _params(name)
+    p.update(nx=300, ny=13)
+    field = _field_for(p, want_field)
+    f0 = random_state(p, 67, amp=amp, kind=_kind(p))
+    w = _weights(f0.shape, 71)
+    sim = make_sim({**p, "checkpoint_every": 4, "max_steps": 6,
+                    "omega_field": field is not None}, storage)
+    sim.set_populations(f0.to("cuda"))
+    f_in = sim.populations().cpu()
+    if field is not None:
+        sim.set_omega(field.to("cuda"))
+    sim.step(6)
+    g0 = torch.empty(sim.shape, dtype=torch.float64, device="cuda")
+    gw = torch.empty((p["ny"], p["nx"]), dtype=torch.float64, device="cuda")
+    sim.backward(w.to("cuda"), g0, gw)
+    torch.cuda.synchronize()
+    omega = field if field is not None else torch.full((p["ny"], p["nx"]), _omega_of(p),
+                                                       dtype=torch.float64)
+    _, g0_o, gw_o, _ = _oracle_grad(p, f_in, 6, omega, w)
+    e0, ew = _rel(g0.cpu(), g0_o), _rel(gw.cpu(), gw_o)
+    assert e0 <= tol, f"dL/df0: {e0:.3e}"
+    assert ew <= tol, f"dL/domega: {ew:.3e}"
