@@ -217,6 +217,9 @@ void fill_args(StepArgs<R>& A, const lbm_config* c, const Layout& L, char* ws) {
 
 }  // namespace
 
+// Steps per captured graph (even: a replay starts and ends on the same lattice).
+constexpr int kGraphSteps = 16;
+
 struct lbm_ctx {
   lbm_config cfg;
   Layout L;
@@ -227,8 +230,17 @@ struct lbm_ctx {
   bool recorded = false;     // a rollout usable by lbm_backward exists
   StepArgs<double> a64;
   StepArgs<float> a32;
+  // kGraphSteps steps captured once per starting lattice and replayed by
+  // lbm_step (kernels only; every argument is the same at each replay)
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
   void* lat(int i) { return ws + L.off_lat[i]; }
   bool f64() const { return cfg.storage == LBM_F64; }
+  ~lbm_ctx() {
+    for (auto& g : graph)
+      if (g) hipGraphExecDestroy(g);
+    if (cap_stream) hipStreamDestroy(cap_stream);
+  }
 };
 
 static SelectArgs select_args(lbm_ctx* c, const void* args);
@@ -397,7 +409,48 @@ static SelectArgs select_args(lbm_ctx* c, const void* args) {
     return sa;
 }
 
+// Capture kGraphSteps steps from lattice c->cur on the library's own stream
+// (the caller's may be the legacy default stream, which cannot be
+// captured); the host-side step state is restored afterwards.
+static hipError_t capture_graph(lbm_ctx* c) {
+  hipError_t e = hipSuccess;
+  if (!c->cap_stream) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) return e;
+  const hipStream_t user = c->stream;
+  const int cur0 = c->cur;
+  const long long steps0 = c->steps;
+  c->stream = c->cap_stream;
+  hipGraph_t g = nullptr;
+  e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    for (int s = 0; s < kGraphSteps && e == hipSuccess; ++s) e = one_step(c);
+    const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+    if (e == hipSuccess) e = e2;
+  }
+  c->stream = user;
+  c->cur = cur0;
+  c->steps = steps0;
+  if (e == hipSuccess) e = hipGraphInstantiate(&c->graph[cur0], g, nullptr, nullptr, 0);
+  if (g) hipGraphDestroy(g);
+  return e;
+}
+
 static lbm_status run_steps(lbm_ctx* c, long long n, hipEvent_t* ev) {
+  // Launch-bound lattices gain most; any plain run of at least kGraphSteps
+  // steps replays the graph (no events, no rollout recording, no periodic
+  // checks, whose arguments change from step to step).
+  if (!ev && !c->recorded && !c->L.adj.on && c->cfg.check_interval <= 0) {
+    while (n >= kGraphSteps) {
+      if (!c->graph[c->cur]) {
+        const hipError_t e = capture_graph(c);
+        if (e != hipSuccess) return hip_fail(e, "graph capture");
+      }
+      const hipError_t e = hipGraphLaunch(c->graph[c->cur], c->stream);
+      if (e != hipSuccess) return hip_fail(e, "graph launch");
+      c->steps += kGraphSteps;
+      n -= kGraphSteps;
+    }
+  }
   for (long long s = 0; s < n; ++s) {
     if (c->recorded && c->steps >= c->cfg.max_steps)
       return fail(LBM_ESTATE, "rollout longer than cfg.max_steps; lbm_backward could not cover it");

@@ -1,0 +1,65 @@
+"""Replays of the captured step graph against eager stepping.
+
+A plain run of at least 16 steps (no rollout recording, no periodic
+checks) replays a HIP graph of 16 captured steps; single steps run eagerly.
+Two simulations start from the same state: one takes step(1) calls, the
+other step(n) calls that replay the graph.  After every call, with eager
+work (population and counter reads, torch arithmetic, synchronisation)
+between the replays, the populations, the Ehrenfest set and the limiter
+counters must agree bit for bit."""
+import pytest
+import torch
+
+from tests.parity_util import make_sim, random_state
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "cavity_f32_lbgk_ehr_pos": dict(nx=96, ny=80, bc="cavity", u_lid=0.1, collision="lbgk",
+                                    nu=0.002, ehrenfest=True, ehr_k=40, ehr_delta=1e-6,
+                                    positivity=True),
+    "periodic_f16s_elbm_ehr": dict(nx=256, ny=40, bc="periodic", collision="elbm", nu=1e-4,
+                                   ehrenfest=True, ehr_k=30, ehr_delta=1e-7, positivity=True),
+    "periodic_f64_mrt_median": dict(nx=70, ny=33, bc="periodic", collision="mrt", nu=0.001,
+                                    median=True, med_delta=1e-4, positivity=True),
+    "d1q3_bf16s_lbgk_ehr": dict(lattice="D1Q3", nx=1000, ny=1, bc="periodic", collision="lbgk",
+                                nu=0.01, ehrenfest=True, ehr_k=8, ehr_delta=1e-6),
+}
+STORAGE = {"cavity_f32_lbgk_ehr_pos": "f32", "periodic_f16s_elbm_ehr": "f16s",
+           "periodic_f64_mrt_median": "f64", "d1q3_bf16s_lbgk_ehr": "bf16s"}
+# step(n) calls of the replaying simulation: graphs of 16 plus eager remainders
+CALLS = [16, 32, 5, 16, 47, 16]
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_graph_replays_match_eager(name):
+    p = CASES[name]
+    storage = STORAGE[name]
+    f0 = random_state(p, seed=97, amp=0.04, umax=0.06)
+    eager = make_sim(p, storage)
+    graph = make_sim(p, storage)
+    for s in (eager, graph):
+        s.set_populations(f0.to("cuda"))
+    scratch = torch.zeros(1 << 16, device="cuda")
+    for i, n in enumerate(CALLS):
+        for _ in range(n):
+            eager.step(1)
+        graph.step(n)
+        # eager work between replays
+        scratch.add_(float(i + 1)).mul_(0.5)
+        torch.cuda.synchronize()
+        fe, fg = eager.populations(), graph.populations()
+        assert torch.equal(fe, fg), f"call {i} (step({n})): populations differ"
+        if p.get("ehrenfest"):
+            assert sorted(eager.selected()) == sorted(graph.selected()), f"call {i}: selection"
+        assert eager.counters() == graph.counters(), f"call {i}: counters"
+    assert torch.isfinite(graph.populations()).all()
+    # a fresh state set between replays restarts from the new lattice contents
+    f1 = random_state(p, seed=98, amp=0.04, umax=0.06)
+    for s in (eager, graph):
+        s.set_populations(f1.to("cuda"))
+    for _ in range(32):
+        eager.step(1)
+    graph.step(32)
+    torch.cuda.synchronize()
+    assert torch.equal(eager.populations(), graph.populations())
