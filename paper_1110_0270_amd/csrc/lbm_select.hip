@@ -67,29 +67,32 @@ __device__ __forceinline__ bool last_block(unsigned int* ticket) {
 // Block-wide search of an LDS histogram h[0..NB) from the top bin down: *bin
 // receives the bin where the running count first reaches `need` (-1 if the
 // histogram holds fewer), *above the count in the bins above it.  Every
-// thread of the block calls it (blockDim.x <= 1024).
+// thread of the block calls it (blockDim.x a multiple of 64, at most 1024).
+// Thread t sums a contiguous run of bins from the top; the running counts
+// come from a shuffle scan in each wavefront plus the wavefront totals.
 template <int NB>
 __device__ void find_from_top(const unsigned int* h, unsigned long long need, int* bin,
                               unsigned long long* above) {
-  __shared__ unsigned long long part[1024];
+  __shared__ unsigned long long wsum[16];
   __shared__ int s_bin;
   __shared__ unsigned long long s_above;
-  const int T = blockDim.x, t = threadIdx.x;
+  const int T = blockDim.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int C = (NB + T - 1) / T;
   const int hi = NB - t * C;
   const int lo = hi - C > 0 ? hi - C : 0;
   unsigned long long s = 0;
   for (int b = lo; b < hi; ++b) s += h[b];
-  part[t] = s;
+  unsigned long long incl = s;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned long long v = __shfl_up(incl, o);
+    if (lane >= o) incl += v;
+  }
+  if (lane == 63) wsum[wv] = incl;
   if (t == 0) { s_bin = -1; s_above = 0; }
   __syncthreads();
-  for (int off = 1; off < T; off <<= 1) {
-    const unsigned long long v = t >= off ? part[t - off] : 0ull;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  const unsigned long long incl = part[t], excl = incl - s;
+  for (int j = 0; j < wv; ++j) incl += wsum[j];
+  const unsigned long long excl = incl - s;
   if (s > 0 && need > 0 && excl < need && need <= incl) {
     unsigned long long c = excl;
     for (int b = hi - 1; b >= lo; --b) {
@@ -115,29 +118,6 @@ __device__ __forceinline__ unsigned int frame_shift(unsigned long long base, uns
   unsigned int sh = 0;
   while (sh < 62 && (span >> sh) >= (unsigned long long)(kBuckets / 2)) ++sh;
   return sh;
-}
-
-// Sum of an LDS histogram h[0..NB) over the block.
-template <int NB>
-__device__ unsigned long long block_sum(const unsigned int* h) {
-  __shared__ unsigned long long red[1024];
-  unsigned long long s = 0;
-  for (int i = threadIdx.x; i < NB; i += blockDim.x) s += h[i];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
-  }
-  const unsigned long long r = red[0];
-  __syncthreads();
-  return r;
-}
-
-// The rescan is needed when the floor was raised and fewer than k sites
-// reached it.
-__device__ __forceinline__ bool need_rescan(unsigned long long nc, long long k, const SelState* st) {
-  return (long long)nc < k && st->floor_raised[st->step & 1ull];
 }
 
 // Site of lane `lane` of wavefront w in logical tile t (the step kernel's
@@ -227,20 +207,10 @@ __global__ __launch_bounds__(256) void k_fb_scan(const StepArgs<typename StoreT<
 }
 
 // The bucket holding the k-th largest candidate key, from the step's
-// histogram; stored in the selection state for the region sweep.  Every
-// thread of one workgroup calls it.
+// histogram (in LDS) and candidate count; stored in the selection state
+// for the region sweep.  Every thread of one workgroup calls it.
 template <class R>
-__device__ void find_boundary(const StepArgs<R>& A, long long k) {
-  SelState* st = A.sel;
-  __shared__ unsigned int h[kBuckets];
-  __shared__ unsigned long long s_nc;
-  for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) h[i] = ld_rlx(&A.hist[i]);
-  if (threadIdx.x < 64) {
-    const unsigned long long n = candidate_count(A.ccount);
-    if (threadIdx.x == 0) s_nc = n;
-  }
-  __syncthreads();
-  const long long nc = (long long)s_nc;
+__device__ void boundary_from(const unsigned int* h, long long nc, long long k, SelState* st) {
   int boundary = -1;
   unsigned long long above = 0;
   if (k <= 0) {
@@ -254,6 +224,19 @@ __device__ void find_boundary(const StepArgs<R>& A, long long k) {
     st->b_nc = (unsigned long long)nc;
     st->b_above = above;
   }
+}
+
+template <class R>
+__device__ void find_boundary(const StepArgs<R>& A, long long k) {
+  __shared__ unsigned int h[kBuckets];
+  __shared__ unsigned long long s_nc;
+  for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) h[i] = ld_rlx(&A.hist[i]);
+  if (threadIdx.x < 64) {
+    const unsigned long long n = candidate_count(A.ccount);
+    if (threadIdx.x == 0) s_nc = n;
+  }
+  __syncthreads();
+  boundary_from<R>(h, (long long)s_nc, k, A.sel);
 }
 
 // Rescan append, in the step kernel's tile layout so that every wavefront
@@ -310,30 +293,47 @@ __global__ __launch_bounds__(1024) void k_decide(const StepArgs<typename StoreT<
                                                 long long k) {
   using R = typename StoreT<S>::R;
   SelState* st = A.sel;
+  // every load is issued before the first barrier: one memory round trip
+  __shared__ unsigned int h[kBuckets];
   __shared__ unsigned long long s_nc;
+  for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) h[i] = ld_rlx(&A.hist[i]);
   if (threadIdx.x < 64) {
     const unsigned long long n = candidate_count(A.ccount);
     if (threadIdx.x == 0) s_nc = n;
   }
+  const unsigned long long step = st->step;
+  const int fr0 = st->floor_raised[0], fr1 = st->floor_raised[1];
+  const bool raised = ((step & 1ull) ? fr1 : fr0) != 0;
   __syncthreads();
-  const bool rescan = need_rescan(s_nc, k, st);
+  // a rescan is needed when the floor was raised and fewer than k sites
+  // reached it
+  const long long nc = (long long)s_nc;
+  const bool rescan = nc < k && raised;
   if (threadIdx.x == 0) st->rescan = rescan ? 1 : 0;
-  if (!rescan) find_boundary<R>(A, k);
+  if (!rescan) boundary_from<R>(h, nc, k, st);
 }
 
+// f* of site idx from the moments recorded with its candidate entry,
+// written over the collided state.
 template <class S, int Q>
-__device__ __forceinline__ void write_feq(const StepArgs<typename StoreT<S>::R>& A, long long p) {
+__device__ __forceinline__ void write_feq_at(const StepArgs<typename StoreT<S>::R>& A,
+                                             uint32_t idx, typename StoreT<S>::R m0,
+                                             typename StoreT<S>::R ux, typename StoreT<S>::R uy) {
   using R = typename StoreT<S>::R;
   constexpr bool SH = StoreT<S>::shifted;
-  const uint32_t idx = A.cand_idx[p];
   const int y = (int)(idx / (uint32_t)A.nx), x = (int)(idx % (uint32_t)A.nx);
   R feq[Q];
-  equilibrium_v<R, Q, SH>(A.cand_mom[p], A.rho0, A.cand_mom[A.cap + p],
-                          A.cand_mom[2 * A.cap + p], A.eq_kind, feq);
+  equilibrium_v<R, Q, SH>(m0, A.rho0, ux, uy, A.eq_kind, feq);
   S* dst = (S*)A.dst;
 #pragma unroll
   for (int i = 0; i < Q; ++i)
     StoreT<S>::st(dst + (long long)i * A.qs + (long long)y * A.pitch + x, feq[i]);
+}
+
+template <class S, int Q>
+__device__ __forceinline__ void write_feq(const StepArgs<typename StoreT<S>::R>& A, long long p) {
+  write_feq_at<S, Q>(A, A.cand_idx[p], A.cand_mom[p], A.cand_mom[A.cap + p],
+                     A.cand_mom[2 * A.cap + p]);
 }
 
 // Wave-aggregated reservation of one slot per set lane on an LDS counter.
@@ -348,6 +348,11 @@ __device__ __forceinline__ unsigned int lds_slot(bool on, unsigned int* ctr) {
   return base + (unsigned int)__popcll(mask & ((1ull << lane) - 1ull));
 }
 
+// Boundary-bucket entries that the exact resolution stages in LDS; lists of
+// up to kTailRank entries are ranked directly.
+constexpr int kTailStage = 2048;
+constexpr int kTailRank = 256;
+
 // Exact resolution of the boundary bucket and the next step's floor and
 // frame, by one workgroup.
 template <class S, int Q>
@@ -358,36 +363,116 @@ __device__ void fix_tail(const StepArgs<typename StoreT<S>::R>& A, long long k, 
   SelState* st = A.sel;
   __shared__ unsigned int h[kBuckets];
   __shared__ unsigned int dh[256];
-  __shared__ unsigned long long s_off_pref, s_nc;
+  __shared__ unsigned long long s_off_pref;
   __shared__ uint32_t s_idx_pref;
   __shared__ unsigned int s_tot;
-  const int par = (int)(st->step & 1ull);
-  const unsigned long long base = st->base_key[par];
-  const unsigned int shift = st->shift[par];
+  __shared__ unsigned long long t_off[kTailStage];
+  __shared__ uint32_t t_ni[kTailStage], t_p[kTailStage];
+  // every load is issued before the first barrier; both parities' fields
+  // are loaded with the step count (one round trip)
+  const unsigned long long step = st->step;
+  const unsigned long long base_p[2] = {st->base_key[0], st->base_key[1]};
+  const unsigned int shift_p[2] = {st->shift[0], st->shift[1]};
+  const int raised_p[2] = {st->floor_raised[0], st->floor_raised[1]};
+  const unsigned long long floor_p[2] = {st->floor_key[0], st->floor_key[1]};
   for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) h[i] = ld_rlx(&A.hist[i]);
-  if (threadIdx.x < 64) {
-    const unsigned long long n = candidate_count(A.ccount);
-    if (threadIdx.x == 0) {
-      s_nc = n;
-      s_tot = (unsigned int)ld_rlx(&st->sel_acc);
-    }
-  }
+  // candidate count, boundary bucket and the count above it, as found by
+  // k_decide (or by the rescan's last workgroup)
+  const long long nc = (long long)st->b_nc;
+  const int b_bin = st->b_bin;
+  const unsigned long long b_above = st->b_above;
+  const long long m_all = (long long)st->bcount;
+  // state the epilogue updates
+  const bool fell_back = st->fallback != 0;
+  const unsigned long long overflows = st->overflows, cand_total = st->cand_total;
+  if (threadIdx.x == 0) s_tot = (unsigned int)st->sel_acc;
   __syncthreads();
-  const long long nc = (long long)s_nc;
+  const int par = (int)(step & 1ull);
+  const unsigned long long base = par ? base_p[1] : base_p[0];
+  const unsigned int shift = par ? shift_p[1] : shift_p[0];
+  const bool raised = (par ? raised_p[1] : raised_p[0]) != 0;
+  const unsigned long long floor_prev = par ? floor_p[1] : floor_p[0];
   const long long need = k < nc ? k : nc;
-  // boundary bucket and the count above it, as found by k_decide (or by the
-  // rescan's last workgroup)
-  const int boundary = (k > 0 && nc > k) ? st->b_bin : -1;
-  const unsigned long long above = (k > 0 && nc > k) ? st->b_above : 0ull;
+  const int boundary = (k > 0 && nc > k) ? b_bin : -1;
+  const unsigned long long above = (k > 0 && nc > k) ? b_above : 0ull;
   const long long take = (boundary >= 0 && k > 0 && nc > k) ? need - (long long)above : 0;
-  const long long m_all = (long long)ld_rlx(&st->bcount);
   const long long m = m_all < bcap ? m_all : bcap;
-  if (take > 0 && m > 0) {
+  if (take > 0 && m > 0 && m <= kTailRank && (int)blockDim.x >= 4 * kTailRank) {
+    // Short list: the rank of each entry in (key descending, site index
+    // ascending) order is the number of entries that beat it.  Entry q is
+    // counted by `slices` threads, each against a contiguous slice of the
+    // list in LDS; the entries of rank below `take` are selected.  The
+    // moments are loaded with the key, so f* needs no further round trip.
+    const unsigned long long edge = base + ((unsigned long long)boundary << shift);
+    const int mq = (int)((m + 63) & ~63ll);          // entries rounded up to whole wavefronts
+    const int slices = (int)blockDim.x / mq;         // >= 4
+    const int q = (int)threadIdx.x % mq, sl = (int)threadIdx.x / mq;
+    unsigned long long oq = 0;
+    uint32_t nq = 0;
+    R m0 = R(0), ux = R(0), uy = R(0);
+    if ((int)threadIdx.x < m) {
+      const uint32_t p = blist[threadIdx.x];
+      const unsigned long long key = (unsigned long long)A.cand_key[p];
+      oq = key >= edge ? key - edge : 0ull;
+      nq = ~A.cand_idx[p];
+      m0 = A.cand_mom[p];
+      ux = A.cand_mom[A.cap + p];
+      uy = A.cand_mom[2 * A.cap + p];
+      t_off[threadIdx.x] = oq;
+      t_ni[threadIdx.x] = nq;
+      t_p[threadIdx.x] = 0;                         // rank counter of entry threadIdx.x
+    }
+    __syncthreads();
+    if (sl < slices && q < m) {
+      const unsigned long long o = t_off[q];
+      const uint32_t ni = t_ni[q];
+      const int per = ((int)m + slices - 1) / slices;
+      const int j0 = sl * per, j1 = j0 + per < (int)m ? j0 + per : (int)m;
+      unsigned int beat = 0;
+#pragma unroll 4
+      for (int j = j0; j < j1; ++j) {
+        const unsigned long long oj = t_off[j];
+        beat += (oj > o || (oj == o && t_ni[j] > ni)) ? 1u : 0u;
+      }
+      if (beat) atomicAdd(&t_p[q], beat);
+    }
+    __syncthreads();
+    // thread q < m (slice 0 when blockDim.x / mq >= 1) holds entry q's moments
+    const bool sel = (int)threadIdx.x < m && (long long)t_p[threadIdx.x] < take;
+    if (sel) write_feq_at<S, Q>(A, ~nq, m0, ux, uy);
+    const unsigned int slot = lds_slot(sel, &s_tot);
+    if (sel && (long long)slot < k) selected[slot] = (int32_t)~nq;
+  } else if (take > 0 && m > 0) {
     // keys of the bucket differ only in their offset from its lower edge:
     // `shift` bits, or all bits in the open-ended top bucket
     const unsigned long long edge = base + ((unsigned long long)boundary << shift);
     const int nb = boundary == kBuckets - 1 ? KeyTraits<R>::bits : (int)shift;
     const int kd = (nb + 7) / 8;
+    // MSD radix select, one byte per pass; up to kTailStage entries are
+    // read from the candidate buffer once into LDS and every pass works
+    // there.
+    const bool staged = m <= kTailStage;
+    if (staged) {
+      for (long long q = threadIdx.x; q < m; q += blockDim.x) {
+        const uint32_t p = blist[q];
+        const unsigned long long key = (unsigned long long)A.cand_key[p];
+        t_off[q] = key >= edge ? key - edge : 0ull;
+        t_ni[q] = ~A.cand_idx[p];
+        t_p[q] = p;
+      }
+    }
+    auto entry = [&](long long q, unsigned long long& off, uint32_t& ni, uint32_t& p) {
+      if (staged) {
+        off = t_off[q];
+        ni = t_ni[q];
+        p = t_p[q];
+      } else {
+        p = blist[q];
+        const unsigned long long key = (unsigned long long)A.cand_key[p];
+        off = key >= edge ? key - edge : 0ull;
+        ni = ~A.cand_idx[p];
+      }
+    };
     unsigned long long need_left = (unsigned long long)take;
     __shared__ unsigned int s_last_cnt;
     if (threadIdx.x == 0) { s_off_pref = 0; s_idx_pref = 0; s_last_cnt = (unsigned int)m; }
@@ -403,10 +488,9 @@ __device__ void fix_tail(const StepArgs<typename StoreT<S>::R>& A, long long k, 
       const unsigned long long op = s_off_pref;
       const uint32_t ip = s_idx_pref;
       for (long long q = threadIdx.x; q < m; q += blockDim.x) {
-        const uint32_t p = blist[q];
-        const unsigned long long key = (unsigned long long)A.cand_key[p];
-        const unsigned long long off = key >= edge ? key - edge : 0ull;
-        const uint32_t ni = ~A.cand_idx[p];
+        unsigned long long off;
+        uint32_t ni, p;
+        entry(q, off, ni, p);
         bool match;
         unsigned int digit;
         const int topb = sb + 8;
@@ -439,17 +523,15 @@ __device__ void fix_tail(const StepArgs<typename StoreT<S>::R>& A, long long k, 
     for (long long q0 = 0; q0 < m; q0 += blockDim.x) {
       const long long q = q0 + threadIdx.x;
       bool sel = false;
-      uint32_t p = 0;
+      uint32_t p = 0, ni = 0;
       if (q < m) {
-        p = blist[q];
-        const unsigned long long key = (unsigned long long)A.cand_key[p];
-        const unsigned long long off = key >= edge ? key - edge : 0ull;
-        const uint32_t ni = ~A.cand_idx[p];
+        unsigned long long off;
+        entry(q, off, ni, p);
         sel = off > to || (off == to && ni >= ti);
       }
       if (sel) write_feq<S, Q>(A, p);
       const unsigned int slot = lds_slot(sel, &s_tot);
-      if (sel && (long long)slot < k) selected[slot] = (int32_t)A.cand_idx[p];
+      if (sel && (long long)slot < k) selected[slot] = (int32_t)~ni;
     }
   }
   __syncthreads();
@@ -461,24 +543,35 @@ __device__ void fix_tail(const StepArgs<typename StoreT<S>::R>& A, long long k, 
   const unsigned long long dk = delta_key<R>(A.ehr_delta);
   unsigned long long fnext = dk;
   if (10 * k < n_sites && k > 0) {
-    const bool keep = st->floor_raised[par] && !st->fallback && nc >= 2 * k && nc <= 6 * k;
+    const bool keep = raised && !fell_back && nc >= 2 * k && nc <= 6 * k;
     if (keep) {
-      fnext = st->floor_key[par];
+      fnext = floor_prev;
     } else {
       int t2;
       unsigned long long a2;
       find_from_top<kBuckets>(h, 3ull * (unsigned long long)k, &t2, &a2);
       if (t2 >= 0 && t2 < kBuckets - 1) fnext = base + ((unsigned long long)t2 << shift);
       else if (t2 < 0) fnext = base > 2 * KeyTraits<R>::quarter ? base - 2 * KeyTraits<R>::quarter : 0ull;
-      else fnext = st->floor_key[par];
+      else fnext = floor_prev;
     }
     if (fnext < dk) fnext = dk;
   }
+  // top nonempty bucket: per-thread maximum, wavefront maximum by
+  // shuffles, one LDS atomic per wavefront
   __shared__ int s_top;
   if (threadIdx.x == 0) s_top = -1;
   __syncthreads();
-  for (int i = threadIdx.x; i < kBuckets; i += blockDim.x)
-    if (h[i]) atomicMax(&s_top, i);
+  {
+    int tmax = -1;
+    for (int i = threadIdx.x; i < kBuckets; i += blockDim.x)
+      if (h[i]) tmax = i;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const int v = __shfl_xor(tmax, o);
+      tmax = v > tmax ? v : tmax;
+    }
+    if (__lane_id() == 0 && tmax >= 0) atomicMax(&s_top, tmax);
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     // upper end of this step's keys: the top nonempty bucket's upper edge,
@@ -493,8 +586,8 @@ __device__ void fix_tail(const StepArgs<typename StoreT<S>::R>& A, long long k, 
     const unsigned int ns = s_tot < (unsigned int)k ? s_tot : (unsigned int)k;
     st->n_sel = (long long)ns;
     if (n_sel_out) *n_sel_out = (long long)ns;
-    if (m_all > bcap) st->overflows += 1;
-    st->cand_total += (unsigned long long)nc;
+    if (m_all > bcap) st->overflows = overflows + 1;
+    st->cand_total = cand_total + (unsigned long long)nc;
     st->fallback = 0;
     st->sel_acc = 0;
     st->bcount = 0;
@@ -503,6 +596,11 @@ __device__ void fix_tail(const StepArgs<typename StoreT<S>::R>& A, long long k, 
   for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) A.hist[i] = 0;
   for (int i = threadIdx.x; i < kCountSlots; i += blockDim.x) A.ccount[i * kCountStride] = 0;
 }
+
+// LDS staging of a k_fix_regions workgroup: selected sites and boundary
+// entries (the rest, up to 256 x 64 entries, go to its global stage).
+constexpr int kRegSel = 1536;
+constexpr int kRegBnd = 512;
 
 // Selection: k_fix_regions sends every candidate above the boundary bucket to
 // equilibrium and lists the boundary bucket; k_fix_tail (one workgroup of
@@ -517,10 +615,14 @@ __global__ __launch_bounds__(256) void k_fix_regions(const StepArgs<typename Sto
   SelState* st = A.sel;
   __shared__ unsigned int s_sel, s_bnd;
   __shared__ unsigned long long s_base_sel, s_base_bnd;
-  const int par = (int)(st->step & 1ull);
-  const unsigned long long base = st->base_key[par];
-  const unsigned int shift = st->shift[par];
+  __shared__ int32_t l_sel[kRegSel], l_bnd[kRegBnd];
+  // both parities' frames are loaded with the step count (one round trip)
+  const unsigned long long step = st->step;
+  const unsigned long long base0 = st->base_key[0], base1 = st->base_key[1];
+  const unsigned int shift0 = st->shift[0], shift1 = st->shift[1];
   const int boundary = st->b_bin;          // -1: take every candidate
+  const unsigned long long base = (step & 1ull) ? base1 : base0;
+  const unsigned int shift = (step & 1ull) ? shift1 : shift0;
   if (threadIdx.x == 0) { s_sel = 0; s_bnd = 0; }
   __syncthreads();
   // 64 regions per wavefront, spread over the whole lattice with a stride of
@@ -543,16 +645,31 @@ __global__ __launch_bounds__(256) void k_fix_regions(const StepArgs<typename Sto
     const long long rj = __shfl(my_r, j);
     const long long p = rj * 64 + lane;
     bool sel = false, bnd = false;
+    uint32_t idx = 0;
+    R m0 = R(0), ux = R(0), uy = R(0);
     if ((uint32_t)lane < c) {
-      const int b = bucket_of<R>((unsigned long long)A.cand_key[p], base, shift);
+      // the whole entry in one round trip
+      const unsigned long long key = (unsigned long long)A.cand_key[p];
+      idx = A.cand_idx[p];
+      m0 = A.cand_mom[p];
+      ux = A.cand_mom[A.cap + p];
+      uy = A.cand_mom[2 * A.cap + p];
+      const int b = bucket_of<R>(key, base, shift);
       sel = boundary < 0 || b > boundary;
       bnd = b == boundary;
     }
-    if (sel) write_feq<S, Q>(A, p);
+    if (sel) write_feq_at<S, Q>(A, idx, m0, ux, uy);
+    // staged in LDS, or past its capacity in the workgroup's global stage
     const unsigned int slot = lds_slot(sel, &s_sel);
-    if (sel) my_stage[slot] = (int32_t)A.cand_idx[p];
+    if (sel) {
+      if (slot < (unsigned int)kRegSel) l_sel[slot] = (int32_t)idx;
+      else my_stage[slot] = (int32_t)idx;
+    }
     const unsigned int q = lds_slot(bnd, &s_bnd);
-    if (bnd) my_stage[256 * 64 - 1 - q] = (int32_t)p;   // boundary entries fill from the end
+    if (bnd) {                                  // boundary entries fill from the end
+      if (q < (unsigned int)kRegBnd) l_bnd[q] = (int32_t)p;
+      else my_stage[256 * 64 - 1 - q] = (int32_t)p;
+    }
   }
   if (cnt) A.wcount[my_r] = 0;
   __syncthreads();
@@ -562,9 +679,11 @@ __global__ __launch_bounds__(256) void k_fix_regions(const StepArgs<typename Sto
   }
   __syncthreads();
   for (unsigned int i = threadIdx.x; i < s_sel; i += blockDim.x)
-    if ((long long)(s_base_sel + i) < k) selected[s_base_sel + i] = my_stage[i];
+    if ((long long)(s_base_sel + i) < k)
+      selected[s_base_sel + i] = i < (unsigned int)kRegSel ? l_sel[i] : my_stage[i];
   for (unsigned int i = threadIdx.x; i < s_bnd; i += blockDim.x)
-    if ((long long)(s_base_bnd + i) < bcap) blist[s_base_bnd + i] = (uint32_t)my_stage[256 * 64 - 1 - i];
+    if ((long long)(s_base_bnd + i) < bcap)
+      blist[s_base_bnd + i] = (uint32_t)(i < (unsigned int)kRegBnd ? l_bnd[i] : my_stage[256 * 64 - 1 - i]);
 }
 
 template <class S, int Q>

@@ -126,28 +126,32 @@ __device__ __forceinline__ void moments_v(const R v[Q], R rho0, R& m0, R& ux, R&
 }
 
 // Nonequilibrium entropy of a site (section 4, eq. DelS), sum_i f_i
-// ln(f_i / f*_i), evaluated as sum_i f*_i h((f_i - f*_i) / f*_i) (same value
-// because f and f* share rho).  With the product form of f*, 1/f*_ab =
-// (S/rho) / ((c_a + dt_a)(c_b + dt_b)), so 1 + 2*3 reciprocals replace nine
-// divisions.  +inf if some f_i < 0 or f*_i <= 0.
+// ln(f_i / f*_i), evaluated as sum_i f*_i h(x_i), x_i = (f_i - f*_i) / f*_i
+// (same value because f and f* share rho).  With the product form of f*,
+// 1/f*_ab = (S/rho) / ((c_a + dt_a)(c_b + dt_b)), so 1 + 2*3 reciprocals
+// replace nine divisions.  +inf if some f_i < 0 or f*_i <= 0.
 //
 // Screening: for x >= -1/2, h(x) <= x^2/2 + max(-x, 0)^3/3 (for x >= 0 since
 // h'' <= 1; for -1/2 <= x < 0 the series terms beyond the cubic one sum to
-// less than the cubic term), so U = sum_i f*_i (that bound at x_i) bounds
-// Delta S from above.  When U < screen (and every x_i >= -1/2) the exact sum
-// is skipped and U is returned: the caller only needs to know that Delta S is
-// below `screen`.  screen = 0 always evaluates the exact sum.
+// less than the cubic term).  With y_i = -x_i = d_i / f*_i the bound on
+// f*_i h(x_i) reads d_i y_i (1/2 + max(y_i, 0)/3), and U, its sum over i,
+// bounds Delta S from above.  When U < screen (and every y_i <= 1/2) the
+// exact sum is skipped and U is returned: the caller only needs to know that
+// Delta S is below `screen`.  screen = 0 always evaluates the exact sum.
 template <class R, int Q, bool SH>
 __device__ __forceinline__ R site_dS(const R v[Q], const R d[Q], R m0, R rho0, R ux, R uy,
                                      int kind, R screen = R(0)) {
   R dx[3], dy[3], fx[3], fy[3], rx[3], ry[3];
   eq_dev6<R>(ux, kind, dx);
   if constexpr (Q == 9) eq_dev6<R>(uy, kind, dy);
-  bool bad = false;
+  const R rho = SH ? rho0 + m0 : m0;
+  constexpr R S = Q == 9 ? R(36) : R(6);
+  const R irs = S * rcp<R>(rho);
+  bool bad = rho <= R(0);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     fx[a] = (R)c1(a - 1) + dx[a];
-    rx[a] = rcp<R>(fx[a]);
+    rx[a] = irs * rcp<R>(fx[a]);       // S / (rho (c_a + dt_a))
     bad |= fx[a] <= R(0);
     if constexpr (Q == 9) {
       fy[a] = (R)c1(a - 1) + dy[a];
@@ -155,33 +159,28 @@ __device__ __forceinline__ R site_dS(const R v[Q], const R d[Q], R m0, R rho0, R
       bad |= fy[a] <= R(0);
     }
   }
-  const R rho = SH ? rho0 + m0 : m0;
-  constexpr R S = Q == 9 ? R(36) : R(6);
-  const R irs = S * rcp<R>(rho);
-  bad |= rho <= R(0);
-  R x[Q], fq[Q];
-  R ub = R(0);
-  bool far = false;
+  R y[Q];
+  R ub = R(0), ymax = R(0);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const int a = vx_of<Q>(i) + 1, b = vy_of<Q>(i) + 1;
     const R sh = SH ? wt<R, Q>(i) * rho0 : R(0);
     bad |= (v[i] + sh) < R(0);
-    R inv;
-    if constexpr (Q == 9) { fq[i] = fx[a] * fy[b]; inv = irs * (rx[a] * ry[b]); }
-    else { fq[i] = fx[a]; inv = irs * rx[a]; }
-    x[i] = -d[i] * inv;
-    far |= x[i] < R(-0.5);
-    const R xn = x[i] < R(0) ? -x[i] : R(0);
-    ub += fq[i] * (x[i] * x[i] * R(0.5) + xn * xn * xn * R(1.0 / 3.0));
+    const R inv = Q == 9 ? rx[a] * ry[b] : rx[a];   // 1 / f*_i
+    y[i] = d[i] * inv;
+    ymax = fmax(ymax, y[i]);
+    ub += (d[i] * y[i]) * (R(0.5) + fmax(y[i], R(0)) * R(1.0 / 3.0));
   }
   if (bad) return r_inf<R>();
-  ub *= rho * (R(1) / S);
   // the margin covers the rounding of the bound itself
-  if (!far && ub * R(1.0001) < screen) return ub;
+  if (!(ymax > R(0.5)) && ub * R(1.0001) < screen) return ub;
   R acc = R(0);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) acc += fq[i] * h_fn<R>(x[i]);
+  for (int i = 0; i < Q; ++i) {
+    const int a = vx_of<Q>(i) + 1, b = vy_of<Q>(i) + 1;
+    const R fq = Q == 9 ? fx[a] * fy[b] : fx[a];
+    acc += fq * h_fn<R>(-y[i]);
+  }
   return acc * (rho * (R(1) / S));
 }
 
