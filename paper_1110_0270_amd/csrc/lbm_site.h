@@ -237,13 +237,29 @@ __device__ __forceinline__ int bucket_of(unsigned long long key, unsigned long l
   return b >= (unsigned long long)kBuckets ? kBuckets - 1 : (int)b;
 }
 
+// Candidate floor and histogram frame of this step's parity.  Both
+// parities' fields and the step count are read unconditionally (the state
+// always exists), so that the loads issue together.
+struct StepFrame {
+  unsigned long long floor, base;
+  unsigned int shift;
+};
+__device__ __forceinline__ StepFrame step_frame(const SelState* sel) {
+  const unsigned long long f0 = sel->floor_key[0], f1 = sel->floor_key[1];
+  const unsigned long long b0 = sel->base_key[0], b1 = sel->base_key[1];
+  const unsigned int s0 = sel->shift[0], s1 = sel->shift[1];
+  const bool odd = (sel->step & 1ull) != 0;
+  return StepFrame{odd ? f1 : f0, odd ? b1 : b0, odd ? s1 : s0};
+}
+
 // Append of Ehrenfest candidates by one wavefront (all its lanes call it):
 // the wavefront owns 64 entries of the candidate buffer (its region), so a
 // ballot gives every candidate its slot without a global counter; the
 // region's count goes to wcount and each key's bucket count to the
 // histogram.
 template <class R>
-__device__ __forceinline__ void append_candidates(const StepArgs<R>& A, long long region, bool is_c,
+__device__ __forceinline__ void append_candidates(const StepArgs<R>& A, const StepFrame& fr,
+                                                  long long region, bool is_c,
                                                   typename KeyOf<R>::T key, uint32_t idx,
                                                   R m0, R ux, R uy) {
   const unsigned long long mask = __ballot(is_c);
@@ -260,8 +276,7 @@ __device__ __forceinline__ void append_candidates(const StepArgs<R>& A, long lon
     A.cand_mom[pos] = m0;
     A.cand_mom[A.cap + pos] = ux;
     A.cand_mom[2 * A.cap + pos] = uy;
-    const int par = (int)(A.sel->step & 1ull);
-    atomicAdd(&A.hist[bucket_of<R>((unsigned long long)key, A.sel->base_key[par], A.sel->shift[par])], 1u);
+    atomicAdd(&A.hist[bucket_of<R>((unsigned long long)key, fr.base, fr.shift)], 1u);
   }
 }
 

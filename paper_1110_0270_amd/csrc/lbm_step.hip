@@ -48,22 +48,23 @@ __device__ __forceinline__ void sort_net9(R a[9]) {
 // (eligible, Delta S > delta, and above the floor), collision, positivity
 // rule, store into the second lattice, and the limiter counters.  Every lane
 // of the wavefront calls it.
-template <class S, int Q, int COLL>
+template <class S, int Q, int COLL, bool EHR = true>
 __device__ __forceinline__ void site_finish(const StepArgs<typename StoreT<S>::R>& A, int x, int y,
                                             bool valid, long long region,
                                             typename StoreT<S>::R v[Q],
                                             typename StoreT<S>::R feq[Q],
                                             typename StoreT<S>::R d[Q], typename StoreT<S>::R m0,
                                             typename StoreT<S>::R ux, typename StoreT<S>::R uy,
-                                            typename StoreT<S>::R dS, int par,
+                                            typename StoreT<S>::R dS,
+                                            const StepFrame& fr,
                                             unsigned long long* cnt) {
   using R = typename StoreT<S>::R;
   // Ehrenfest candidates: eligible (Delta S > delta) and above the floor.
-  if (A.ehrenfest) {
+  if (EHR && A.ehrenfest) {
     using K = typename KeyOf<R>::T;
     const K key = key_of<R>(dS);
-    const bool is_c = valid && (dS > A.ehr_delta) && (key >= (K)A.sel->floor_key[par]);
-    append_candidates<R>(A, region, is_c, key, (uint32_t)(y * A.nx + x), m0, ux, uy);
+    const bool is_c = valid && (dS > A.ehr_delta) && (key >= (K)fr.floor);
+    append_candidates<R>(A, fr, region, is_c, key, (uint32_t)(y * A.nx + x), m0, ux, uy);
   }
 
   R post[Q];
@@ -129,8 +130,8 @@ void k_step(const StepArgs<typename StoreT<S>::R> A) {
   const bool need_dS = MEDIAN || A.ehrenfest;
   // Without the median filter, Delta S only decides Ehrenfest candidacy:
   // sites provably below the floor skip its exact evaluation.
-  const int par = A.ehrenfest ? (int)(A.sel->step & 1ull) : 0;
-  const R screen = (!MEDIAN && A.ehrenfest) ? value_of_key<R>(A.sel->floor_key[par]) : R(0);
+  const StepFrame fr = step_frame(A.sel);
+  const R screen = (!MEDIAN && A.ehrenfest) ? value_of_key<R>(fr.floor) : R(0);
   R v[Q], feq[Q], d[Q], m0 = R(0), ux = R(0), uy = R(0), dS = R(0);
   if (valid) dS = site_prep<S, Q, PER>(A, x, y, v, feq, d, m0, ux, uy, need_dS, screen);
 
@@ -199,7 +200,7 @@ void k_step(const StepArgs<typename StoreT<S>::R> A) {
   }
 
   site_finish<S, Q, COLL>(A, x, y, valid, (long long)t * 4 + threadIdx.x / 64, v, feq, d, m0, ux,
-                          uy, dS, par, cnt);
+                          uy, dS, fr, cnt);
 }
 
 // The step on a periodic lattice without the median filter, in rows of 256
@@ -209,7 +210,7 @@ void k_step(const StepArgs<typename StoreT<S>::R> A) {
 // one-site kernel waits on a full memory latency for every site).  Per-site
 // arithmetic is the one-site kernel's, so the results are bit-identical.
 // Used for the 16-bit storage forms and for ELBM in FP32.
-template <class S, int Q, int COLL, int ROWS>
+template <class S, int Q, int COLL, int ROWS, bool EHR>
 __global__ __launch_bounds__(256) void k_step_rows(const StepArgs<typename StoreT<S>::R> A) {
   using R = typename StoreT<S>::R;
   constexpr bool SH = StoreT<S>::shifted;
@@ -224,8 +225,8 @@ __global__ __launch_bounds__(256) void k_step_rows(const StepArgs<typename Store
   const unsigned c[3] = {(unsigned)(xl == A.nx - 1 ? 0 : xl + 1), (unsigned)xl,
                          (unsigned)(xl == 0 ? A.nx - 1 : xl - 1)};   // source columns, a = -1, 0, +1
   unsigned long long* const cnt = A.counters + (blockIdx.x % kCntSlots) * CNT_N;
-  const int par = A.ehrenfest ? (int)(A.sel->step & 1ull) : 0;
-  const R screen = A.ehrenfest ? value_of_key<R>(A.sel->floor_key[par]) : R(0);
+  const StepFrame fr = step_frame(A.sel);
+  const R screen = (EHR && A.ehrenfest) ? value_of_key<R>(fr.floor) : R(0);
   const S* __restrict__ src = (const S*)A.src;
 
   auto load_row = [&](int y, S raw[Q]) {
@@ -254,11 +255,11 @@ __global__ __launch_bounds__(256) void k_step_rows(const StepArgs<typename Store
     equilibrium_v<R, Q, SH>(m0, A.rho0, ux, uy, A.eq_kind, feq);
 #pragma unroll
     for (int i = 0; i < Q; ++i) d[i] = feq[i] - v[i];
-    const R dS = (A.ehrenfest && valid)
+    const R dS = (EHR && A.ehrenfest && valid)
                      ? site_dS<R, Q, SH>(v, d, m0, A.rho0, ux, uy, A.eq_kind, screen)
                      : R(0);
     const long long region = ((long long)y * A.tiles_x + tile_x) * 4 + threadIdx.x / 64;
-    site_finish<S, Q, COLL>(A, x, y, valid, region, v, feq, d, m0, ux, uy, dS, par, cnt);
+    site_finish<S, Q, COLL, EHR>(A, x, y, valid, region, v, feq, d, m0, ux, uy, dS, fr, cnt);
   }
 }
 
@@ -295,10 +296,14 @@ static hipError_t launch_t(const void* args, hipStream_t s, hipEvent_t e0, hipEv
         if (A.bc == BC_PERIODIC) {
           constexpr int ROWS = 4;
           const dim3 grid(A.tiles_x * ((A.ny + ROWS - 1) / ROWS)), block(256);
+          // without Ehrenfest, a kernel compiled without the candidate code
+          // (fewer registers, one more wavefront per SIMD in 16-bit storage)
+          auto kern = A.ehrenfest ? k_step_rows<S, Q, COLL, ROWS, true>
+                                  : k_step_rows<S, Q, COLL, ROWS, false>;
           if (e0 && e1)
-            hipExtLaunchKernelGGL((k_step_rows<S, Q, COLL, ROWS>), grid, block, 0, s, e0, e1, 0, A);
+            hipExtLaunchKernelGGL(kern, grid, block, 0, s, e0, e1, 0, A);
           else
-            hipLaunchKernelGGL((k_step_rows<S, Q, COLL, ROWS>), grid, block, 0, s, A);
+            hipLaunchKernelGGL(kern, grid, block, 0, s, A);
           rows = true;
         }
       }
