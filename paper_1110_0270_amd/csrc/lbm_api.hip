@@ -96,7 +96,7 @@ Layout make_layout(const lbm_config* c) {
     L.off_cidx = take((size_t)L.cap * 4);
     L.off_cmom = take((size_t)L.cap * 3 * rb);
     L.off_wcount = take((size_t)tiles * 4 * 4);
-    L.off_hist = take(kBuckets * 4);
+    L.off_hist = take((size_t)kHistWords * 4);
     L.off_coarse = take(kCoarse * 4);
     L.off_ccount = take((size_t)kCountSlots * kCountStride * 8);
     // 256 regions x 64 entries per k_fix_regions workgroup
@@ -291,7 +291,7 @@ lbm_status lbm_init(const lbm_config* cfg, void* ws, size_t ws_bytes, void* stre
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.off_cnt, 0, (size_t)kCntSlots * CNT_N * 8, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.off_div, 0xff, sizeof(long long), c->stream);
   if (e == hipSuccess && (cfg->limiters & LBM_LIM_EHRENFEST)) {
-    e = hipMemsetAsync(c->ws + L.off_hist, 0, kBuckets * 4, c->stream);
+    e = hipMemsetAsync(c->ws + L.off_hist, 0, (size_t)kHistWords * 4, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.off_coarse, 0, kCoarse * 4, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.off_wcount, 0, (size_t)(L.cap / 64) * 4, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.off_ccount, 0, (size_t)kCountSlots * kCountStride * 8, c->stream);

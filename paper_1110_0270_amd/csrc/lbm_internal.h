@@ -35,6 +35,13 @@ struct SelState {
 };
 
 constexpr int kBuckets = 4096;        // histogram of candidate keys
+// Bucket b is counted at hist[hist_pos(b)].  The step kernel's atomics crowd
+// into the few buckets just above the floor, and atomics on one cache line
+// queue behind each other: consecutive buckets go to 128 different lines
+// (bucket 128 q + r at word 32 r + q, r < 128).
+constexpr long long kHistWords = kBuckets;
+__host__ __device__ inline int hist_pos(int b) { return (b % 128) * 32 + b / 128; }
+static_assert(kBuckets == 128 * 32, "hist_pos spreads 4096 buckets over 128 lines of 32");
 constexpr int kCoarse = 4096;         // rescan histogram: top 12 bits of the FP32 key
 constexpr int kCountSlots = 64;       // candidate counters, 128 bytes apart
 constexpr int kCountStride = 16;      // in unsigned long long
@@ -93,7 +100,7 @@ struct StepArgs {
   long long cap;         // 256 * number of tiles
   uint32_t* wcount;
   unsigned long long* ccount;  // kCountSlots partial candidate counts (spread atomics)
-  unsigned int* hist;    // kBuckets counts of this step's candidates
+  unsigned int* hist;    // kBuckets counts of this step's candidates (stride kHistStride)
   unsigned long long* counters;  // [kCntSlots][CNT_N]
   // ELBM recompute for the adjoint: alpha and branch of every site ([ny][pitch]),
   // or nullptr

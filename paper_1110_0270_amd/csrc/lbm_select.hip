@@ -202,7 +202,7 @@ __global__ __launch_bounds__(256) void k_fb_scan(const StepArgs<typename StoreT<
   }
   __syncthreads();
   for (int i = threadIdx.x; i < kCoarse; i += blockDim.x) coarse[i] = 0;
-  for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) A.hist[i] = 0;
+  for (int i = threadIdx.x; i < kHistWords; i += blockDim.x) A.hist[i] = 0;
   for (int i = threadIdx.x; i < kCountSlots; i += blockDim.x) A.ccount[i * kCountStride] = 0;
 }
 
@@ -230,7 +230,7 @@ template <class R>
 __device__ void find_boundary(const StepArgs<R>& A, long long k) {
   __shared__ unsigned int h[kBuckets];
   __shared__ unsigned long long s_nc;
-  for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) h[i] = ld_rlx(&A.hist[i]);
+  for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) h[i] = ld_rlx(&A.hist[hist_pos(i)]);
   if (threadIdx.x < 64) {
     const unsigned long long n = candidate_count(A.ccount);
     if (threadIdx.x == 0) s_nc = n;
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(256) void k_fb_append(const StepArgs<typename Store
       A.cand_mom[A.cap + pos] = ux;
       A.cand_mom[2 * A.cap + pos] = uy;
       const int par = (int)(st->step & 1ull);
-      atomicAdd(&A.hist[bucket_of<R>((unsigned long long)key_of<R>(dS), st->base_key[par], st->shift[par])], 1u);
+      atomicAdd(&A.hist[hist_pos(bucket_of<R>((unsigned long long)key_of<R>(dS), st->base_key[par], st->shift[par]))], 1u);
     }
   }
   if (last_block(&st->ticket)) {
@@ -296,7 +296,7 @@ __global__ __launch_bounds__(1024) void k_decide(const StepArgs<typename StoreT<
   // every load is issued before the first barrier: one memory round trip
   __shared__ unsigned int h[kBuckets];
   __shared__ unsigned long long s_nc;
-  for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) h[i] = ld_rlx(&A.hist[i]);
+  for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) h[i] = ld_rlx(&A.hist[hist_pos(i)]);
   if (threadIdx.x < 64) {
     const unsigned long long n = candidate_count(A.ccount);
     if (threadIdx.x == 0) s_nc = n;
@@ -375,7 +375,7 @@ __device__ void fix_tail(const StepArgs<typename StoreT<S>::R>& A, long long k, 
   const unsigned int shift_p[2] = {st->shift[0], st->shift[1]};
   const int raised_p[2] = {st->floor_raised[0], st->floor_raised[1]};
   const unsigned long long floor_p[2] = {st->floor_key[0], st->floor_key[1]};
-  for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) h[i] = ld_rlx(&A.hist[i]);
+  for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) h[i] = ld_rlx(&A.hist[hist_pos(i)]);
   // candidate count, boundary bucket and the count above it, as found by
   // k_decide (or by the rescan's last workgroup)
   const long long nc = (long long)st->b_nc;
@@ -593,7 +593,7 @@ __device__ void fix_tail(const StepArgs<typename StoreT<S>::R>& A, long long k, 
     st->bcount = 0;
     st->step += 1;
   }
-  for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) A.hist[i] = 0;
+  for (int i = threadIdx.x; i < kHistWords; i += blockDim.x) A.hist[i] = 0;
   for (int i = threadIdx.x; i < kCountSlots; i += blockDim.x) A.ccount[i * kCountStride] = 0;
 }
 

@@ -276,7 +276,7 @@ __device__ __forceinline__ void append_candidates(const StepArgs<R>& A, const St
     A.cand_mom[pos] = m0;
     A.cand_mom[A.cap + pos] = ux;
     A.cand_mom[2 * A.cap + pos] = uy;
-    atomicAdd(&A.hist[bucket_of<R>((unsigned long long)key, fr.base, fr.shift)], 1u);
+    atomicAdd(&A.hist[hist_pos(bucket_of<R>((unsigned long long)key, fr.base, fr.shift))], 1u);
   }
 }
 
