@@ -174,12 +174,27 @@ __device__ __forceinline__ R site_dS(const R v[Q], const R d[Q], R m0, R rho0, R
   if (bad) return r_inf<R>();
   // the margin covers the rounding of the bound itself
   if (!(ymax > R(0.5)) && ub * R(1.0001) < screen) return ub;
-  R acc = R(0);
+  // h_fn takes the Taylor series wherever |x| < 0.1; when that holds for
+  // every component of every active lane of the wavefront, the logarithms
+  // are skipped for all of them (same values, the series either way).
+  bool big = false;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const int a = vx_of<Q>(i) + 1, b = vy_of<Q>(i) + 1;
-    const R fq = Q == 9 ? fx[a] * fy[b] : fx[a];
-    acc += fq * h_fn<R>(-y[i]);
+  for (int i = 0; i < Q; ++i) big |= !(fabs(y[i]) < R(0.1));
+  R acc = R(0);
+  if (__ballot(big) == 0ull) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int a = vx_of<Q>(i) + 1, b = vy_of<Q>(i) + 1;
+      const R fq = Q == 9 ? fx[a] * fy[b] : fx[a];
+      acc += fq * h_series<R>(-y[i]);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int a = vx_of<Q>(i) + 1, b = vy_of<Q>(i) + 1;
+      const R fq = Q == 9 ? fx[a] * fy[b] : fx[a];
+      acc += fq * h_fn<R>(-y[i]);
+    }
   }
   return acc * (rho * (R(1) / S));
 }
