@@ -40,7 +40,7 @@ struct Layout {
   size_t off_lat[2] = {0, 0}, off_omega = 0, off_sel = 0, off_cnt = 0, off_partial = 0,
          off_stats = 0, off_div = 0, off_ckey = 0, off_cidx = 0, off_cmom = 0, off_hist = 0,
          off_coarse = 0, off_wcount = 0, off_ccount = 0, off_stage = 0, off_blist = 0,
-         off_selected = 0;
+         off_selected = 0, off_f64list = 0, off_f64cnt = 0;
   AdjointLayout adj;
   size_t total = 0;
 };
@@ -104,6 +104,10 @@ Layout make_layout(const lbm_config* c) {
     L.bcap = std::min<long long>(L.cap, 1ll << 20);
     L.off_blist = take((size_t)L.bcap * 4);
     L.off_selected = take((size_t)std::max<long long>(L.k, 1) * 4);
+  }
+  if (c->collision == LBM_ELBM && !is_f64(c->storage)) {
+    L.off_f64list = take((size_t)L.n_sites * 4);
+    L.off_f64cnt = take(2 * sizeof(unsigned int));
   }
   L.adj = adjoint_layout(c, L.lat_bytes, L.qs, L.k, o);
   o = L.adj.end;
@@ -204,6 +208,8 @@ void fill_args(StepArgs<R>& A, const lbm_config* c, const Layout& L, char* ws) {
   A.ehr_delta = (R)c->ehr_delta;
   A.sel = (SelState*)(ws + L.off_sel);
   A.counters = (unsigned long long*)(ws + L.off_cnt);
+  A.f64_sites = L.off_f64list ? (uint32_t*)(ws + L.off_f64list) : nullptr;
+  A.f64_count = L.off_f64cnt ? (unsigned int*)(ws + L.off_f64cnt) : nullptr;
   if (A.ehrenfest) {
     A.cand_key = (typename KeyOf<R>::T*)(ws + L.off_ckey);
     A.cand_idx = (uint32_t*)(ws + L.off_cidx);
@@ -290,6 +296,8 @@ lbm_status lbm_init(const lbm_config* cfg, void* ws, size_t ws_bytes, void* stre
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.off_cnt, 0, (size_t)kCntSlots * CNT_N * 8, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.off_div, 0xff, sizeof(long long), c->stream);
+  if (e == hipSuccess && L.off_f64cnt)
+    e = hipMemsetAsync(c->ws + L.off_f64cnt, 0, 2 * sizeof(unsigned int), c->stream);
   if (e == hipSuccess && (cfg->limiters & LBM_LIM_EHRENFEST)) {
     e = hipMemsetAsync(c->ws + L.off_hist, 0, (size_t)kHistWords * 4, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.off_coarse, 0, kCoarse * 4, c->stream);

@@ -37,12 +37,15 @@ struct CollInfo {
   int pos_arg = -1; // positivity rule: component set to 0, -1 if inactive
   R phi = R(1);     // positivity rule: homothety coefficient
   int iters = 0;    // ELBM root iterations
+  bool deferred = false;  // FP64 solve left to k_elbm_f64
 };
 
 // Collision (eq. CollisionIntegral; section 5 MRT in moment space; section
 // 3 ELBM), in the storage representation: d = f* - f, om the relaxation rate
 // (LBGK omega, MRT shear rate s_nu, ELBM 2 beta).
-template <class S, int Q, int COLL>
+// DEFER (FP32 ELBM only): a site that needs the FP64 solve is not collided;
+// ci.deferred is set and post[] is left unset.
+template <class S, int Q, int COLL, bool DEFER = false>
 __device__ __forceinline__ void collide_site(const StepArgs<typename StoreT<S>::R>& A,
                                              const typename StoreT<S>::R v[Q],
                                              const typename StoreT<S>::R feq[Q],
@@ -86,6 +89,10 @@ __device__ __forceinline__ void collide_site(const StepArgs<typename StoreT<S>::
     bool f64 = false;
     if constexpr (sizeof(R) == 4) {
       if (amax < A.f64_below) {
+        if constexpr (DEFER) {
+          ci.deferred = true;
+          return;
+        }
         // FP64 solve near the no-root (degenerate) branch.
         ElbmF64Site st;
 #pragma unroll

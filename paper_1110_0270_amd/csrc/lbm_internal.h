@@ -106,6 +106,12 @@ struct StepArgs {
   // or nullptr
   R* alpha_out;
   unsigned char* branch_out;
+  // ELBM with FP32 arithmetic: the step kernels list the sites whose root
+  // solve needs FP64 (site index) and k_elbm_f64 finishes them, so that the
+  // step kernels do not carry the FP64 solve's registers; [0] count,
+  // [1] last-workgroup ticket.  nullptr: no such sites can occur.
+  uint32_t* f64_sites;
+  unsigned int* f64_count;
 };
 
 // Launchers (one per translation unit); return hipSuccess or the error.

@@ -601,6 +601,8 @@ __device__ void fix_tail(const StepArgs<typename StoreT<S>::R>& A, long long k, 
 // entries (the rest, up to 256 x 64 entries, go to its global stage).
 constexpr int kRegSel = 1536;
 constexpr int kRegBnd = 512;
+// Regions with at most this many candidates are walked lane by lane.
+constexpr int kFewCand = 4;
 
 // Selection: k_fix_regions sends every candidate above the boundary bucket to
 // equilibrium and lists the boundary bucket; k_fix_tail (one workgroup of
@@ -637,17 +639,14 @@ __global__ __launch_bounds__(256) void k_fix_regions(const StepArgs<typename Sto
   int32_t* my_stage = stage + (long long)blockIdx.x * 256 * 64;
   uint32_t cnt = 0;
   if (my_r < nreg) cnt = A.wcount[my_r];
-  unsigned long long nz = __ballot(cnt != 0);
-  while (nz) {
-    const int j = __ffsll((long long)nz) - 1;
-    nz &= nz - 1;
-    const uint32_t c = __shfl(cnt, j);
-    const long long rj = __shfl(my_r, j);
-    const long long p = rj * 64 + lane;
+  // One candidate entry p (when `on`): f* at the selected, staging of the
+  // selected and of the boundary entries.  Every lane of the wavefront calls
+  // it (the LDS slots come from ballots).
+  auto visit = [&](bool on, long long p) {
     bool sel = false, bnd = false;
     uint32_t idx = 0;
     R m0 = R(0), ux = R(0), uy = R(0);
-    if ((uint32_t)lane < c) {
+    if (on) {
       // the whole entry in one round trip
       const unsigned long long key = (unsigned long long)A.cand_key[p];
       idx = A.cand_idx[p];
@@ -670,6 +669,26 @@ __global__ __launch_bounds__(256) void k_fix_regions(const StepArgs<typename Sto
       if (q < (unsigned int)kRegBnd) l_bnd[q] = (int32_t)p;
       else my_stage[256 * 64 - 1 - q] = (int32_t)p;
     }
+  };
+  // Sparse regions (at most kFewCand entries, where candidates are scattered
+  // over the lattice) are walked by their own lane, all lanes at once; dense
+  // regions (candidates crowding into the rows of a shear layer) one after
+  // another with one lane per entry.
+  const uint32_t few = cnt <= (uint32_t)kFewCand ? cnt : 0u;
+  uint32_t fmax_c = few;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t v = __shfl_xor(fmax_c, o);
+    fmax_c = v > fmax_c ? v : fmax_c;
+  }
+  for (uint32_t e = 0; e < fmax_c; ++e) visit(e < few, my_r * 64 + e);
+  unsigned long long nz = __ballot(cnt > (uint32_t)kFewCand);
+  while (nz) {
+    const int j = __ffsll((long long)nz) - 1;
+    nz &= nz - 1;
+    const uint32_t c = __shfl(cnt, j);
+    const long long rj = __shfl(my_r, j);
+    visit((uint32_t)lane < c, rj * 64 + lane);
   }
   if (cnt) A.wcount[my_r] = 0;
   __syncthreads();

@@ -48,7 +48,9 @@ __device__ __forceinline__ void sort_net9(R a[9]) {
 // (eligible, Delta S > delta, and above the floor), collision, positivity
 // rule, store into the second lattice, and the limiter counters.  Every lane
 // of the wavefront calls it.
-template <class S, int Q, int COLL, bool EHR = true>
+// DEFER (FP32 ELBM): sites whose root solve needs FP64 are listed for
+// k_elbm_f64 instead of being collided, limited and stored here.
+template <class S, int Q, int COLL, bool EHR = true, bool DEFER = false>
 __device__ __forceinline__ void site_finish(const StepArgs<typename StoreT<S>::R>& A, int x, int y,
                                             bool valid, long long region,
                                             typename StoreT<S>::R v[Q],
@@ -68,13 +70,15 @@ __device__ __forceinline__ void site_finish(const StepArgs<typename StoreT<S>::R
   }
 
   R post[Q];
-  bool pos_event = false;
+  bool pos_event = false, deferred = false;
   if (valid) {
     const R om = A.omega_field ? A.omega_field[(long long)y * A.pitch + x] : A.omega;
     CollInfo<R> ci;
-    collide_site<S, Q, COLL>(A, v, feq, d, om, post, ci);
+    collide_site<S, Q, COLL, DEFER>(A, v, feq, d, om, post, ci);
+    deferred = ci.deferred;
     if constexpr (COLL == COLL_ELBM) {
-      if (A.alpha_out) {
+      // a deferred site counts no event here (its CollInfo is the default)
+      if (A.alpha_out && !deferred) {
         const long long o = (long long)y * A.pitch + x;
         A.alpha_out[o] = ci.alpha;
         A.branch_out[o] = (unsigned char)ci.branch;
@@ -86,14 +90,16 @@ __device__ __forceinline__ void site_finish(const StepArgs<typename StoreT<S>::R
         count_sum(ci.iters, cnt + CNT_ELBM_ITERS);
       }
     }
-    if (A.positivity) {
-      positivity_site<S, Q>(A, feq, post, ci);
-      pos_event = ci.pos_arg >= 0;
-    }
-    S* dst = (S*)A.dst;
-    const unsigned o = (unsigned)(y * A.pitch + x);
+    if (!deferred) {
+      if (A.positivity) {
+        positivity_site<S, Q>(A, feq, post, ci);
+        pos_event = ci.pos_arg >= 0;
+      }
+      S* dst = (S*)A.dst;
+      const unsigned o = (unsigned)(y * A.pitch + x);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) StoreT<S>::st(at(dst + (long long)i * A.qs, o), post[i]);
+      for (int i = 0; i < Q; ++i) StoreT<S>::st(at(dst + (long long)i * A.qs, o), post[i]);
+    }
   } else if constexpr (COLL == COLL_ELBM) {
     if (A.count_events) {
       count_event(false, cnt + CNT_ELBM_NOROOT);
@@ -103,6 +109,48 @@ __device__ __forceinline__ void site_finish(const StepArgs<typename StoreT<S>::R
     }
   }
   if (A.positivity && A.count_events) count_event(pos_event, cnt + CNT_POSITIVITY);
+  if constexpr (DEFER) {
+    // wave-aggregated append to the FP64 list
+    const unsigned long long m = __ballot(deferred);
+    if (m) {
+      const int lane = __lane_id(), leader = __ffsll((long long)m) - 1;
+      unsigned int base = 0;
+      if (lane == leader) base = atomicAdd(A.f64_count, (unsigned int)__popcll(m));
+      base = __shfl(base, leader);
+      if (deferred) A.f64_sites[base + __popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)(y * A.nx + x);
+    }
+  }
+}
+
+// Sites of an FP32 ELBM step that need the FP64 root solve, listed by the
+// step kernel: each is recomputed from the source lattice (pull, moments,
+// f*: the same values the step kernel had), collided with the FP64 solve,
+// limited and stored, with its counters and adjoint records, exactly as the
+// step kernel would have done in place.  The last workgroup clears the list.
+template <class S, int Q>
+__global__ __launch_bounds__(256) void k_elbm_f64(const StepArgs<typename StoreT<S>::R> A) {
+  using R = typename StoreT<S>::R;
+  const unsigned int n = A.f64_count[0];
+  unsigned long long* const cnt = A.counters + (blockIdx.x % kCntSlots) * CNT_N;
+  const StepFrame fr{0ull, 0ull, 0u};
+  for (unsigned int b0 = blockIdx.x * 256u; b0 < n; b0 += gridDim.x * 256u) {
+    const unsigned int i = b0 + threadIdx.x;
+    const bool on = i < n;
+    const uint32_t idx = on ? A.f64_sites[i] : 0u;
+    const int x = (int)(idx % (uint32_t)A.nx), y = (int)(idx / (uint32_t)A.nx);
+    R v[Q], feq[Q], d[Q], m0 = R(0), ux = R(0), uy = R(0);
+    if (on) site_prep<S, Q>(A, x, y, v, feq, d, m0, ux, uy, false);
+    site_finish<S, Q, COLL_ELBM, false, false>(A, x, y, on, 0, v, feq, d, m0, ux, uy, R(0), fr, cnt);
+  }
+  __shared__ bool last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(&A.f64_count[1], 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (last && threadIdx.x == 0) {
+    A.f64_count[0] = 0;
+    A.f64_count[1] = 0;
+  }
 }
 
 // LBGK in FP32/16-bit storage on row tiles fits 64 registers: keep the full
@@ -199,7 +247,8 @@ void k_step(const StepArgs<typename StoreT<S>::R> A) {
     }
   }
 
-  site_finish<S, Q, COLL>(A, x, y, valid, (long long)t * 4 + threadIdx.x / 64, v, feq, d, m0, ux,
+  constexpr bool DEFER = COLL == COLL_ELBM && sizeof(R) == 4 && !MEDIAN;
+  site_finish<S, Q, COLL, true, DEFER>(A, x, y, valid, (long long)t * 4 + threadIdx.x / 64, v, feq, d, m0, ux,
                           uy, dS, fr, cnt);
 }
 
@@ -259,7 +308,8 @@ __global__ __launch_bounds__(256) void k_step_rows(const StepArgs<typename Store
                      ? site_dS<R, Q, SH>(v, d, m0, A.rho0, ux, uy, A.eq_kind, screen)
                      : R(0);
     const long long region = ((long long)y * A.tiles_x + tile_x) * 4 + threadIdx.x / 64;
-    site_finish<S, Q, COLL, EHR>(A, x, y, valid, region, v, feq, d, m0, ux, uy, dS, fr, cnt);
+    site_finish<S, Q, COLL, EHR, COLL == COLL_ELBM && sizeof(R) == 4>(A, x, y, valid, region, v, feq,
+                                                                       d, m0, ux, uy, dS, fr, cnt);
   }
 }
 
@@ -318,6 +368,12 @@ static hipError_t launch_t(const void* args, hipStream_t s, hipEvent_t e0, hipEv
     } else {
       launch_k<S, Q, COLL, MEDIAN, 64, 4>(A, s, e0, e1);
     }
+  }
+  if constexpr (COLL == COLL_ELBM && sizeof(R) == 4 && !MEDIAN) {
+    // the sites the step kernel left for the FP64 root solve (few; the
+    // kernel returns at once when there are none)
+    if (A.f64_sites)
+      hipLaunchKernelGGL((k_elbm_f64<S, Q>), dim3(64), dim3(256), 0, s, A);
   }
   return hipGetLastError();
 }

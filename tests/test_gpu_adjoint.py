@@ -141,7 +141,8 @@ def test_adjoint_fp64_matches_oracle_gradient(name):
 
 
 @pytest.mark.parametrize("name", ["lbgk_periodic", "mrt_m1_field_cavity",
-                                  "lbgk_cavity_ehrenfest_pos", "elbm_periodic"])
+                                  "lbgk_cavity_ehrenfest_pos", "elbm_periodic",
+                                  "elbm_far_positivity"])
 def test_adjoint_fp32_storage(name):
     elbm = CASES[name].get("collision") == "elbm"
     _check_case(name, "f32", 4, 3, None, 1e-3 if elbm else 1e-4)

@@ -256,6 +256,44 @@ def test_low_precision_one_step(storage, name):
     assert float(excess) <= 0, f"error exceeds the stated bound by {float(excess):.3e}"
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16s"])
+@pytest.mark.parametrize("size", ["narrow", "wide", "d1q3"])
+@pytest.mark.parametrize("name", ["elbm_far_positivity", "elbm_far_ehrenfest_rule"])
+def test_elbm_fp64_sites_of_fp32_arithmetic(storage, size, name):
+    """Far from equilibrium some sites have alpha_max < 3 and take the FP64
+    root solve; the FP32-arithmetic step kernels (one-site 64 x 4 tiles and
+    256-site row tiles) list them for a second kernel that finishes them.
+    The step must still agree with the oracle within the storage bound at
+    every site, the FP64 counter must equal the number of such sites, and
+    the no-root / non-positive counters must match the oracle's branches."""
+    if size == "d1q3":
+        p = {"lattice": "D1Q3", "nx": 300, "ny": 1, **CASES[name]}
+        amp = p.pop("_amp")
+    else:
+        p, amp = _params(name, WIDE if size == "wide" else NARROW)
+    f0 = random_state(p, 23, amp=amp, kind=_kind(p))
+    f_in, f_gpu, sim = gpu_run(p, f0, 1, storage)
+    f_ora, infos = oracle_run(p, f_in, 1)
+    cnt = sim.counters()
+    # sites whose alpha_max (FP64, from the stored state) is below 3
+    lat = lattice(p)
+    pre = torch.stack([torch.roll(f_in[i], shifts=(int(lat.vy[i]), int(lat.vx[i])), dims=(0, 1))
+                       for i in range(f_in.shape[0])])
+    r, jx, jy = O.moments(lat, pre)
+    feq = O.equilibrium(lat, r, jx / r, jy / r, "entropic")
+    D = feq - pre
+    ratio = torch.where(D < 0, -pre / D, torch.full_like(D, float("inf")))
+    amax = ratio.min(0).values
+    n_lo, n_hi = int((amax < 3.0 - 1e-5).sum()), int((amax < 3.0 + 1e-5).sum())
+    assert n_lo > 0, "the case must exercise the FP64 solve"
+    assert n_lo <= cnt[3] <= n_hi
+    br = infos[0]["branch"]
+    assert cnt[2] == int((br == O.ELBM_NOROOT).sum())
+    assert cnt[4] == int((br == O.ELBM_NONPOS).sum())
+    excess = ((f_gpu - f_ora).abs() - storage_bound(f_ora, storage, lat)).max()
+    assert float(excess) <= 0, f"error exceeds the stated bound by {float(excess):.3e}"
+
+
 @pytest.mark.parametrize("name,n", [("lbgk", 300), ("mrt", 1000), ("elbm", 100),
                                     ("lbgk_median", 200)])
 def test_cavity_256_from_rest_fp64(name, n):
