@@ -239,12 +239,13 @@ struct lbm_ctx {
   // kGraphSteps steps captured once per starting lattice and replayed by
   // lbm_step (kernels only; every argument is the same at each replay)
   hipStream_t cap_stream = nullptr;
-  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [recording][lattice]
   void* lat(int i) { return ws + L.off_lat[i]; }
   bool f64() const { return cfg.storage == LBM_F64; }
   ~lbm_ctx() {
-    for (auto& g : graph)
-      if (g) hipGraphExecDestroy(g);
+    for (auto& gg : graph)
+      for (auto& g : gg)
+        if (g) hipGraphExecDestroy(g);
     if (cap_stream) hipStreamDestroy(cap_stream);
   }
 };
@@ -313,6 +314,9 @@ static lbm_status reset_rollout(lbm_ctx* c) {
   c->steps = 0;
   c->recorded = false;
   hipError_t e = hipMemsetAsync(c->ws + c->L.off_div, 0xff, sizeof(long long), c->stream);
+  if (e == hipSuccess)
+    e = hipMemsetAsync(c->ws + c->L.off_sel + offsetof(SelState, tape_t), 0, sizeof(long long),
+                       c->stream);
   if (e != hipSuccess) return hip_fail(e, "reset");
   if (c->cfg.limiters & LBM_LIM_EHRENFEST) {
     const void* args;
@@ -407,13 +411,17 @@ static SelectArgs select_args(lbm_ctx* c, const void* args) {
     SelectArgs sa;
     sa.storage = c->cfg.storage; sa.Q = c->L.Q; sa.coll = c->cfg.collision; sa.step_args = args;
     sa.k = c->L.k; sa.n_sites = c->L.n_sites;
-    sa.selected = adjoint_selected_slot(c->L.adj, c->ws, c->steps,
-                                        (int32_t*)(c->ws + c->L.off_selected));
+    sa.selected = (int32_t*)(c->ws + c->L.off_selected);
     sa.segsel = (int32_t*)(c->ws + c->L.off_stage);
     sa.blist = (uint32_t*)(c->ws + c->L.off_blist);
     sa.bcap = c->L.bcap;
     sa.coarse = (unsigned int*)(c->ws + c->L.off_coarse);
-    sa.n_sel_out = adjoint_count_slot(c->L.adj, c->ws, c->steps);
+    sa.n_sel_out = nullptr;
+    // recording: the selection kernels index the tape by the device's step
+    // count since the rollout began
+    sa.tape_sel = adjoint_selected_slot(c->L.adj, c->ws, 0, nullptr);
+    sa.tape_cnt = adjoint_count_slot(c->L.adj, c->ws, 0);
+    sa.tape_len = sa.tape_sel ? c->L.adj.max_steps : 0;
     return sa;
 }
 
@@ -438,32 +446,57 @@ static hipError_t capture_graph(lbm_ctx* c) {
   c->stream = user;
   c->cur = cur0;
   c->steps = steps0;
-  if (e == hipSuccess) e = hipGraphInstantiate(&c->graph[cur0], g, nullptr, nullptr, 0);
+  if (e == hipSuccess)
+    e = hipGraphInstantiate(&c->graph[c->L.adj.on ? 1 : 0][cur0], g, nullptr, nullptr, 0);
   if (g) hipGraphDestroy(g);
   return e;
 }
 
-static lbm_status run_steps(lbm_ctx* c, long long n, hipEvent_t* ev) {
-  // Launch-bound lattices gain most; any plain run of at least kGraphSteps
-  // steps replays the graph (no events, no rollout recording, no periodic
-  // checks, whose arguments change from step to step).
-  if (!ev && !c->recorded && !c->L.adj.on && c->cfg.check_interval <= 0) {
-    while (n >= kGraphSteps) {
-      if (!c->graph[c->cur]) {
-        const hipError_t e = capture_graph(c);
-        if (e != hipSuccess) return hip_fail(e, "graph capture");
-      }
-      const hipError_t e = hipGraphLaunch(c->graph[c->cur], c->stream);
-      if (e != hipSuccess) return hip_fail(e, "graph launch");
-      c->steps += kGraphSteps;
-      n -= kGraphSteps;
-    }
+// Replay kGraphSteps steps from the captured graph (capturing it first).
+static lbm_status replay_graph(lbm_ctx* c) {
+  hipGraphExec_t& g = c->graph[c->L.adj.on ? 1 : 0][c->cur];
+  if (!g) {
+    const hipError_t e = capture_graph(c);
+    if (e != hipSuccess) return hip_fail(e, "graph capture");
   }
-  for (long long s = 0; s < n; ++s) {
+  const hipError_t e = hipGraphLaunch(g, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "graph launch");
+  c->steps += kGraphSteps;
+  return LBM_OK;
+}
+
+static lbm_status run_steps(lbm_ctx* c, long long n, hipEvent_t* ev) {
+  // Launch-bound lattices gain most: whole groups of kGraphSteps steps
+  // replay a captured graph, except with events or periodic checks (whose
+  // arguments change from step to step).  While recording a rollout the
+  // tape is indexed on the device and the checkpoint copies stay outside
+  // the graph: a replay never spans a checkpoint or the end of the tape.
+  const bool rec = c->recorded && c->L.adj.on;
+  const bool graphs = !ev && c->cfg.check_interval <= 0 && (rec || !c->L.adj.on);
+  long long eager = 0;   // eager steps of this call (index into ev)
+  while (n > 0) {
+    bool fits = graphs && n >= kGraphSteps;
+    if (fits && rec) {
+      const long long K = c->L.adj.K;
+      fits = c->steps + kGraphSteps <= c->cfg.max_steps && K - c->steps % K >= kGraphSteps;
+    }
+    if (fits) {
+      const lbm_status st = replay_graph(c);
+      if (st != LBM_OK) return st;
+      n -= kGraphSteps;
+      if (rec) {
+        const hipError_t e = adjoint_after_step(c->L.adj, c->ws, c->steps, c->lat(c->cur),
+                                                c->L.lat_bytes, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "checkpoint");
+      }
+      continue;
+    }
     if (c->recorded && c->steps >= c->cfg.max_steps)
       return fail(LBM_ESTATE, "rollout longer than cfg.max_steps; lbm_backward could not cover it");
-    hipError_t e = ev ? one_step(c, ev[2 * s], ev[2 * s + 1]) : one_step(c);
+    hipError_t e = ev ? one_step(c, ev[2 * eager], ev[2 * eager + 1]) : one_step(c);
     if (e != hipSuccess) return hip_fail(e, "lbm_step");
+    ++eager;
+    --n;
     if (c->recorded) {
       e = adjoint_after_step(c->L.adj, c->ws, c->steps, c->lat(c->cur), c->L.lat_bytes, c->stream);
       if (e != hipSuccess) return hip_fail(e, "checkpoint");

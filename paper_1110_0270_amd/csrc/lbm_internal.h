@@ -31,6 +31,7 @@ struct SelState {
   unsigned long long b_nc;       // this step's candidate count
   unsigned long long b_above;    // candidates in buckets above b_bin
   int rescan;                    // this step's candidates cannot hold the answer
+  long long tape_t;              // steps selected since the rollout began (tape index)
   int pad[3];
 };
 
@@ -151,6 +152,13 @@ struct SelectArgs {
   long long bcap;          // capacity of blist
   unsigned int* coarse;    // kCoarse
   long long* n_sel_out;    // optional: the step's selection count is copied here
+  // Recording a rollout: the selection goes to tape_sel + t k and its count
+  // to tape_cnt[t], t = SelState::tape_t (read on the device, so that the
+  // arguments are the same every step and the steps can be replayed from a
+  // HIP graph); t >= tape_len writes to `selected` / n_sel_out instead.
+  int32_t* tape_sel;
+  long long* tape_cnt;
+  long long tape_len;
 };
 hipError_t launch_select(const SelectArgs& a, hipStream_t s);
 // Place the first candidate floor of a freshly set lattice at the 3k-th

@@ -358,7 +358,8 @@ constexpr int kTailRank = 256;
 template <class S, int Q>
 __device__ void fix_tail(const StepArgs<typename StoreT<S>::R>& A, long long k, long long n_sites,
                          int32_t* selected, uint32_t* blist, long long bcap,
-                         long long* n_sel_out) {
+                         long long* n_sel_out, int32_t* tape_sel, long long* tape_cnt,
+                         long long tape_len) {
   using R = typename StoreT<S>::R;
   SelState* st = A.sel;
   __shared__ unsigned int h[kBuckets];
@@ -384,6 +385,11 @@ __device__ void fix_tail(const StepArgs<typename StoreT<S>::R>& A, long long k, 
   const long long m_all = (long long)st->bcount;
   // state the epilogue updates
   const bool fell_back = st->fallback != 0;
+  const long long tape_t = st->tape_t;
+  if (tape_sel && tape_t < tape_len) {
+    selected = tape_sel + tape_t * k;
+    n_sel_out = tape_cnt + tape_t;
+  }
   const unsigned long long overflows = st->overflows, cand_total = st->cand_total;
   if (threadIdx.x == 0) s_tot = (unsigned int)st->sel_acc;
   __syncthreads();
@@ -592,6 +598,7 @@ __device__ void fix_tail(const StepArgs<typename StoreT<S>::R>& A, long long k, 
     st->sel_acc = 0;
     st->bcount = 0;
     st->step += 1;
+    st->tape_t = tape_t + 1;
   }
   for (int i = threadIdx.x; i < kHistWords; i += blockDim.x) A.hist[i] = 0;
   for (int i = threadIdx.x; i < kCountSlots; i += blockDim.x) A.ccount[i * kCountStride] = 0;
@@ -612,7 +619,8 @@ template <class S, int Q>
 __global__ __launch_bounds__(256) void k_fix_regions(const StepArgs<typename StoreT<S>::R> A,
                                                      long long k, int32_t* selected,
                                                      int32_t* stage, uint32_t* blist,
-                                                     long long bcap) {
+                                                     long long bcap, int32_t* tape_sel,
+                                                     long long tape_len) {
   using R = typename StoreT<S>::R;
   SelState* st = A.sel;
   __shared__ unsigned int s_sel, s_bnd;
@@ -623,6 +631,8 @@ __global__ __launch_bounds__(256) void k_fix_regions(const StepArgs<typename Sto
   const unsigned long long base0 = st->base_key[0], base1 = st->base_key[1];
   const unsigned int shift0 = st->shift[0], shift1 = st->shift[1];
   const int boundary = st->b_bin;          // -1: take every candidate
+  const long long tape_t = st->tape_t;
+  if (tape_sel && tape_t < tape_len) selected = tape_sel + tape_t * k;
   const unsigned long long base = (step & 1ull) ? base1 : base0;
   const unsigned int shift = (step & 1ull) ? shift1 : shift0;
   if (threadIdx.x == 0) { s_sel = 0; s_bnd = 0; }
@@ -709,8 +719,10 @@ template <class S, int Q>
 __global__ __launch_bounds__(1024) void k_fix_tail(const StepArgs<typename StoreT<S>::R> A,
                                                    long long k, long long n_sites,
                                                    int32_t* selected, uint32_t* blist,
-                                                   long long bcap, long long* n_sel_out) {
-  fix_tail<S, Q>(A, k, n_sites, selected, blist, bcap, n_sel_out);
+                                                   long long bcap, long long* n_sel_out,
+                                                   int32_t* tape_sel, long long* tape_cnt,
+                                                   long long tape_len) {
+  fix_tail<S, Q>(A, k, n_sites, selected, blist, bcap, n_sel_out, tape_sel, tape_cnt, tape_len);
 }
 
 template <class S, int Q>
@@ -724,9 +736,10 @@ static hipError_t launch_select_t(const SelectArgs& a, hipStream_t s) {
   const long long nreg = (long long)A.tiles_x * A.tiles_y * 4;
   const int gfix = (int)((nreg + 255) / 256);
   hipLaunchKernelGGL((k_fix_regions<S, Q>), dim3(gfix), dim3(256), 0, s, A, a.k, a.selected,
-                     a.segsel, a.blist, a.bcap);
+                     a.segsel, a.blist, a.bcap, a.tape_sel, a.tape_len);
   hipLaunchKernelGGL((k_fix_tail<S, Q>), dim3(1), dim3(1024), 0, s, A, a.k, a.n_sites,
-                     a.selected, a.blist, a.bcap, a.n_sel_out);
+                     a.selected, a.blist, a.bcap, a.n_sel_out, a.tape_sel, a.tape_cnt,
+                     a.tape_len);
   return hipGetLastError();
 }
 

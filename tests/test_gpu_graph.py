@@ -1,12 +1,14 @@
 """Replays of the captured step graph against eager stepping.
 
-A plain run of at least 16 steps (no rollout recording, no periodic
-checks) replays a HIP graph of 16 captured steps; single steps run eagerly.
+A run of at least 16 steps without periodic checks replays a HIP graph of
+16 captured steps (while a rollout is recorded, only groups that do not
+span a checkpoint); single steps run eagerly.
 Two simulations start from the same state: one takes step(1) calls, the
 other step(n) calls that replay the graph.  After every call, with eager
 work (population and counter reads, torch arithmetic, synchronisation)
 between the replays, the populations, the Ehrenfest set and the limiter
 counters must agree bit for bit."""
+import numpy as np
 import pytest
 import torch
 
@@ -63,3 +65,45 @@ def test_graph_replays_match_eager(name):
     graph.step(32)
     torch.cuda.synchronize()
     assert torch.equal(eager.populations(), graph.populations())
+
+
+REC_CASES = {
+    "cavity_f32_mrt_ehr_pos": (dict(nx=96, ny=80, bc="cavity", u_lid=0.1, collision="mrt", nu=0.002,
+                                    s_e=1.64, s_eps=1.64, s_q=1.9, ehrenfest=True, ehr_k=9,
+                                    ehr_delta=1e-6, positivity=True), "f32"),
+    "periodic_f64_lbgk_ehr": (dict(nx=300, ny=13, bc="periodic", collision="lbgk", nu=1e-4,
+                                   ehrenfest=True, ehr_k=20, ehr_delta=0.0), "f64"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(REC_CASES))
+def test_recorded_rollout_graphs_match_eager(name):
+    """A recorded rollout (checkpoints every 32 steps, 87 steps: graph groups
+    between checkpoints, eager steps across them and at the end) against the
+    same rollout taken one step at a time: final state, last selection and
+    the backward pass's gradients bit for bit."""
+    p0, storage = REC_CASES[name]
+    p = {**p0, "checkpoint_every": 32, "max_steps": 96}
+    f0 = random_state(p, 71, amp=0.04, umax=0.06)
+    w = torch.tensor(np.random.default_rng(72).normal(size=f0.shape), dtype=torch.float64)
+    out = []
+    for mode in ("graph", "eager"):
+        sim = make_sim(p, storage)
+        sim.set_populations(f0.to("cuda"))
+        if mode == "graph":
+            sim.step(40)
+            torch.cuda.synchronize()
+            sim.step(47)
+        else:
+            for _ in range(87):
+                sim.step(1)
+        fT = sim.populations().cpu()
+        sel = sorted(sim.selected())
+        g0 = torch.empty(sim.shape, dtype=torch.float64, device="cuda")
+        sim.backward(w.to("cuda"), g0, None)
+        torch.cuda.synchronize()
+        out.append((fT, sel, g0.cpu()))
+        del sim
+    assert torch.equal(out[0][0], out[1][0])
+    assert out[0][1] == out[1][1]
+    assert torch.equal(out[0][2], out[1][2])
