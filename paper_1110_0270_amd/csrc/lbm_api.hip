@@ -465,14 +465,24 @@ static lbm_status replay_graph(lbm_ctx* c) {
   return LBM_OK;
 }
 
+// The periodic divergence check (FP64 reduction) after a step.
+static hipError_t check_now(lbm_ctx* c) {
+  return launch_stats(c->cfg.storage, c->L.Q, c->lat(c->cur), c->L.qs, c->cfg.nx, c->cfg.ny,
+                      c->L.pitch, c->cfg.rho0, (double*)(c->ws + c->L.off_partial),
+                      (double*)(c->ws + c->L.off_stats), (long long*)(c->ws + c->L.off_div),
+                      c->steps, c->stream);
+}
+
 static lbm_status run_steps(lbm_ctx* c, long long n, hipEvent_t* ev) {
   // Launch-bound lattices gain most: whole groups of kGraphSteps steps
-  // replay a captured graph, except with events or periodic checks (whose
-  // arguments change from step to step).  While recording a rollout the
-  // tape is indexed on the device and the checkpoint copies stay outside
-  // the graph: a replay never spans a checkpoint or the end of the tape.
+  // replay a captured graph (not with events, which time each step).  The
+  // work that falls between steps stays outside the graph, and a replay
+  // never spans it: the checkpoint copies and the end of the tape of a
+  // recorded rollout (the tape itself is indexed on the device), and the
+  // periodic divergence checks.
   const bool rec = c->recorded && c->L.adj.on;
-  const bool graphs = !ev && c->cfg.check_interval <= 0 && (rec || !c->L.adj.on);
+  const bool graphs = !ev && (rec || !c->L.adj.on);
+  const long long ci = c->cfg.check_interval;
   long long eager = 0;   // eager steps of this call (index into ev)
   while (n > 0) {
     bool fits = graphs && n >= kGraphSteps;
@@ -480,6 +490,7 @@ static lbm_status run_steps(lbm_ctx* c, long long n, hipEvent_t* ev) {
       const long long K = c->L.adj.K;
       fits = c->steps + kGraphSteps <= c->cfg.max_steps && K - c->steps % K >= kGraphSteps;
     }
+    if (fits && ci > 0) fits = ci - c->steps % ci >= kGraphSteps;
     if (fits) {
       const lbm_status st = replay_graph(c);
       if (st != LBM_OK) return st;
@@ -488,6 +499,10 @@ static lbm_status run_steps(lbm_ctx* c, long long n, hipEvent_t* ev) {
         const hipError_t e = adjoint_after_step(c->L.adj, c->ws, c->steps, c->lat(c->cur),
                                                 c->L.lat_bytes, c->stream);
         if (e != hipSuccess) return hip_fail(e, "checkpoint");
+      }
+      if (ci > 0 && c->steps % ci == 0) {
+        const hipError_t e = check_now(c);
+        if (e != hipSuccess) return hip_fail(e, "check");
       }
       continue;
     }
@@ -501,11 +516,8 @@ static lbm_status run_steps(lbm_ctx* c, long long n, hipEvent_t* ev) {
       e = adjoint_after_step(c->L.adj, c->ws, c->steps, c->lat(c->cur), c->L.lat_bytes, c->stream);
       if (e != hipSuccess) return hip_fail(e, "checkpoint");
     }
-    if (c->cfg.check_interval > 0 && c->steps % c->cfg.check_interval == 0) {
-      e = launch_stats(c->cfg.storage, c->L.Q, c->lat(c->cur), c->L.qs, c->cfg.nx, c->cfg.ny,
-                       c->L.pitch, c->cfg.rho0, (double*)(c->ws + c->L.off_partial),
-                       (double*)(c->ws + c->L.off_stats), (long long*)(c->ws + c->L.off_div),
-                       c->steps, c->stream);
+    if (ci > 0 && c->steps % ci == 0) {
+      e = check_now(c);
       if (e != hipSuccess) return hip_fail(e, "check");
     }
   }

@@ -107,3 +107,28 @@ def test_recorded_rollout_graphs_match_eager(name):
     assert torch.equal(out[0][0], out[1][0])
     assert out[0][1] == out[1][1]
     assert torch.equal(out[0][2], out[1][2])
+
+
+@pytest.mark.parametrize("ci", [48, 40])
+def test_periodic_checks_with_graphs(ci):
+    """Periodic divergence checks every ci steps between graph groups (40 is
+    not a multiple of 16: the steps around each check run eagerly): state
+    and the checks' statistics equal to eager stepping."""
+    p = dict(nx=96, ny=80, bc="cavity", u_lid=0.1, collision="lbgk", nu=0.002,
+             positivity=True, check_interval=ci)
+    f0 = random_state(p, 81, amp=0.04, umax=0.06)
+    res = []
+    for mode in ("graph", "eager"):
+        sim = make_sim(p, "f32")
+        sim.set_populations(f0.to("cuda"))
+        if mode == "graph":
+            sim.step(150)
+            sim.step(53)
+        else:
+            for _ in range(203):
+                sim.step(1)
+        st = sim.stats()
+        res.append((sim.populations().cpu(), st.mass, st.entropy, int(st.diverged_step)))
+        del sim
+    assert torch.equal(res[0][0], res[1][0])
+    assert res[0][1:] == res[1][1:]
