@@ -24,6 +24,19 @@ template <class R, int Q> __device__ __forceinline__ R wt(int i) {
   return Q == 9 ? w9<R>(i) : w1<R>(i - 1);
 }
 
+// a / b from rb, a reciprocal of b within an ulp, corrected once by the
+// exact residual a - q b: within a small fraction of an ulp of the
+// correctly rounded quotient and, unlike a * rb, without a bias.  A biased
+// velocity or equilibrium scale (a * rcp(rho), rho * fl(1/36)) is a
+// systematic momentum error at every step; at omega near 2 it accumulates
+// (the FP32 shear layer then lost most of its entropy production over 20k
+// steps).
+template <class R>
+__device__ __forceinline__ R qdiv(R a, R b, R rb) {
+  const R q = a * rb;
+  return fma(fma(-q, b, a), rb, q);
+}
+
 // Equilibrium in the storage representation (unshifted f*_i, or the
 // deviation f*_i - w_i rho0) from m0 (rho, or rho - rho0 when shifted):
 // the product of the 1D equilibria (section 8), f*_ab = rho phi_a phi_b,
@@ -34,9 +47,10 @@ __device__ __forceinline__ void equilibrium_v(R m0, R rho0, R ux, R uy, int kind
   eq_dev6<R>(ux, kind, dx);
   if constexpr (Q == 9) eq_dev6<R>(uy, kind, dy);
   const R rho = SH ? rho0 + m0 : m0;
-  constexpr R iS = Q == 9 ? R(1) / R(36) : R(1) / R(6);
-  const R rs = rho * iS;
-  const R ms = m0 * iS;
+  constexpr R S = Q == 9 ? R(36) : R(6);
+  constexpr R iS = R(1) / S;
+  const R rs = qdiv<R>(rho, S, iS);
+  const R ms = qdiv<R>(m0, S, iS);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     if constexpr (Q == 9) {
@@ -121,8 +135,8 @@ __device__ __forceinline__ void moments_v(const R v[Q], R rho0, R& m0, R& ux, R&
   m0 = s;
   const R rho = SH ? rho0 + s : s;
   const R ir = rcp<R>(rho);
-  ux = jx * ir;
-  uy = jy * ir;
+  ux = qdiv<R>(jx, rho, ir);
+  uy = qdiv<R>(jy, rho, ir);
 }
 
 // Nonequilibrium entropy of a site (section 4, eq. DelS), sum_i f_i
