@@ -283,6 +283,12 @@ __device__ R elbm_alpha(const R f[Q], const R feq[Q], const R D[Q], R amax,
   // iteration also serves the final sign check.
   bool probe = amax < r_inf<R>();
   R a = amax > R(2) ? R(2) : R(0.5) * (R(1) + amax);
+  R prev = r_inf<R>();
+  // a Newton step within 64 units in the last place of alpha that no longer
+  // halves is rounding noise: the iteration has converged as far as this
+  // precision allows (otherwise such a site spins to max_iter and holds up
+  // its whole wavefront)
+  constexpr R kNoise = R(64) * (sizeof(R) == 4 ? R(1.1920929e-7) : R(2.220446049250313e-16));
   for (int it = 0;;) {
     R sf, d1, d2;
     sf_parts<R, Q>(f, D, lnr, probe ? amax : a, sf, d1, d2);
@@ -295,12 +301,14 @@ __device__ R elbm_alpha(const R f[Q], const R feq[Q], const R D[Q], R amax,
       continue;
     }
     const R step_est = fabs(sf / d1);
-    if (step_est * nrm < p.eps || step_est < p.atol || it >= p.max_iter) {
+    const bool stalled = it >= 2 && step_est >= R(0.5) * prev && step_est < kNoise * a;
+    if (step_est * nrm < p.eps || step_est < p.atol || it >= p.max_iter || stalled) {
       if (sf < R(0)) a = a - R(2) * sf / d1;
       break;
     }
     ++it;
     ++iters;
+    prev = step_est;
     R disc = d1 * d1 - R(2) * sf * d2;
     R delta = disc >= R(0) ? R(2) * sf / (-d1 + sqrt(disc)) : -sf / d1;
     R an = a + delta;
