@@ -47,11 +47,15 @@ long long* adjoint_count_slot(const AdjointLayout& L, char* ws, long long t);
 // src = the state the step read; lam_in/lam_out/gom use the same precision
 // and the pitched layout of the lattice.
 // alpha/branch: the step's ELBM alpha and branch per site, from the
-// recompute (required for ELBM, ignored otherwise).  e0/e1: optional events
-// recorded right before and after the kernel.
+// recompute (required for ELBM, ignored otherwise).  list/count/k: the
+// step's Ehrenfest sites when k <= kAdjListMax (read into LDS in place of
+// the mask; nullptr otherwise).  e0/e1: optional events recorded right
+// before and after the kernel.
+constexpr long long kAdjListMax = 64;
 hipError_t launch_adjoint(int storage, int Q, int coll, const void* step_args, const void* lam_in,
                           void* lam_out, void* gom, const unsigned char* mask,
-                          const void* alpha, const unsigned char* branch, hipStream_t s,
+                          const void* alpha, const unsigned char* branch, const int32_t* list,
+                          const long long* count, long long k, hipStream_t s,
                           hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // f* written into step_args->dst at the first *count sites of list (<= k).
 hipError_t launch_tape_fix(int storage, int Q, const void* step_args, const int32_t* list,

@@ -71,7 +71,13 @@ struct AdjArgs {
   const unsigned char* mask;// 1 at sites the Ehrenfest limiter sent to f* (or nullptr)
   const R* alpha;           // ELBM: the step's alpha per site [ny][pitch]
   const unsigned char* branch;  // ELBM: the step's branch per site
+  // Short Ehrenfest lists (k <= kAdjListLds) replace the mask: the step's
+  // selected sites and their count, read into LDS by every workgroup.
+  const int32_t* list;
+  const long long* count;
+  long long k;
 };
+constexpr int kAdjListLds = (int)kAdjListMax;
 
 template <class S, int Q, int COLL>
 __global__ __launch_bounds__(256) void k_adjoint(const StepArgs<typename StoreT<S>::R> A,
@@ -79,7 +85,17 @@ __global__ __launch_bounds__(256) void k_adjoint(const StepArgs<typename StoreT<
   using R = typename StoreT<S>::R;
   constexpr bool SH = StoreT<S>::shifted;
   const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ int32_t lsel[kAdjListLds];
+  int nl = 0;
+  if (B.list) {
+    const long long c = *B.count;
+    nl = (int)(c < B.k ? c : B.k);
+    if ((int)threadIdx.x < nl) lsel[threadIdx.x] = B.list[threadIdx.x];
+    __syncthreads();
+  }
   if (s >= (long long)A.nx * A.ny) return;
+  bool ehr = B.mask && B.mask[s];
+  for (int j = 0; j < nl; ++j) ehr |= lsel[j] == (int32_t)s;
   const int y = (int)(s / A.nx), x = (int)(s % A.nx);
   R v[Q], feq[Q], d[Q], m0, ux, uy;
   site_prep<S, Q>(A, x, y, v, feq, d, m0, ux, uy, false);
@@ -92,7 +108,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const StepArgs<typename StoreT<
     lf[i] = R(0);
   }
   R gw = R(0);
-  if (B.mask && B.mask[s]) {
+  if (ehr) {
     // Ehrenfest step: g' = f*(p)
 #pragma unroll
     for (int i = 0; i < Q; ++i) { lf[i] = lam[i]; mu[i] = R(0); }
@@ -347,16 +363,18 @@ static hipError_t launch_adj_s(int Q, int coll, const void* sargs, const void* a
 
 hipError_t launch_adjoint(int storage, int Q, int coll, const void* step_args, const void* lam_in,
                           void* lam_out, void* gom, const unsigned char* mask,
-                          const void* alpha, const unsigned char* branch, hipStream_t s,
-                          hipEvent_t e0, hipEvent_t e1) {
+                          const void* alpha, const unsigned char* branch, const int32_t* list,
+                          const long long* count, long long k, hipStream_t s, hipEvent_t e0,
+                          hipEvent_t e1) {
   if (coll == COLL_ELBM && (!alpha || !branch)) return hipErrorInvalidValue;
+  if (list && (!count || k > kAdjListLds)) return hipErrorInvalidValue;
   if (storage == 0) {
     AdjArgs<double> B{(const double*)lam_in, (double*)lam_out, (double*)gom, mask,
-                      (const double*)alpha, branch};
+                      (const double*)alpha, branch, list, count, k};
     return launch_adj_s<double>(Q, coll, step_args, &B, s, e0, e1);
   }
   AdjArgs<float> B{(const float*)lam_in, (float*)lam_out, (float*)gom, mask,
-                   (const float*)alpha, branch};
+                   (const float*)alpha, branch, list, count, k};
   if (storage == 1) return launch_adj_s<float>(Q, coll, step_args, &B, s, e0, e1);
   if (storage == 2) return launch_adj_s<_Float16>(Q, coll, step_args, &B, s, e0, e1);
   return launch_adj_s<bf16_t>(Q, coll, step_args, &B, s, e0, e1);

@@ -764,14 +764,17 @@ static lbm_status backward_impl(lbm_ctx* c, const void* dL_dfT, void* dL_df0, vo
     for (long long t = t1 - 1; t >= t0 && e == hipSuccess; --t) {
       const int32_t* list = A.k > 0 ? adjoint_selected_slot(A, ws, t, nullptr) : nullptr;
       const long long* cnt = A.k > 0 ? adjoint_count_slot(A, ws, t) : nullptr;
-      if (mask) e = launch_mark(mask, list, cnt, A.k, 1, st);
+      // short lists go to the adjoint kernel itself; long ones through the mask
+      const bool short_list = list && A.k <= kAdjListMax;
+      if (mask && !short_list) e = launch_mark(mask, list, cnt, A.k, 1, st);
       const void* args = args_for(seg(t - t0), nullptr);
       if (e == hipSuccess)
         e = launch_adjoint(c->cfg.storage, Q, c->cfg.collision, args, lam[cur], lam[1 - cur],
-                           dL_domega ? gom : nullptr, mask, alpha_slot(t - t0),
-                           branch_slot(t - t0), st,
+                           dL_domega ? gom : nullptr, short_list ? nullptr : mask,
+                           alpha_slot(t - t0), branch_slot(t - t0),
+                           short_list ? list : nullptr, cnt, A.k, st,
                            ev ? (*ev)[2 * t] : nullptr, ev ? (*ev)[2 * t + 1] : nullptr);
-      if (e == hipSuccess && mask) e = launch_mark(mask, list, cnt, A.k, 0, st);
+      if (e == hipSuccess && mask && !short_list) e = launch_mark(mask, list, cnt, A.k, 0, st);
       cur = 1 - cur;
     }
   }

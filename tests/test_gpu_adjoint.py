@@ -42,6 +42,9 @@ CASES = {
                                     elbm_fallback="ehrenfest", _amp=0.6),
     "elbm_ehrenfest": dict(bc="periodic", nu=1e-4, collision="elbm", ehrenfest=True,
                            ehr_k=12, ehr_delta=0.0, _amp=0.2),
+    # more selected sites than the adjoint kernel reads into LDS: the mask path
+    "lbgk_ehrenfest_k100_pos": dict(bc="periodic", omega=1.98, ehrenfest=True, ehr_k=100,
+                                    ehr_delta=0.0, positivity=True, _amp=0.4),
     "d1q3_shock_ehrenfest": dict(lattice="D1Q3", nx=300, ny=1, bc="bounceback", nu=1e-4,
                                  ehrenfest=True, ehr_k=4, ehr_delta=0.0, _amp=0.2),
     "d1q3_elbm_periodic": dict(lattice="D1Q3", nx=300, ny=1, bc="periodic", nu=1e-4,
