@@ -163,12 +163,15 @@ void k_step(const StepArgs<typename StoreT<S>::R> A) {
   constexpr bool SH = StoreT<S>::shifted;
   static_assert(TX * TY == 256, "tile must hold 256 sites");
 
-  // XCD-aware tile order: consecutive workgroups are dealt round-robin to the
-  // 8 XCDs; give each XCD a contiguous band of tiles so that the rows above
-  // and below a tile sit in the same L2.
+  // Tile order.  Consecutive workgroups are dealt round-robin to the 8
+  // XCDs.  The median filter re-reads its halo, so each XCD gets a
+  // contiguous band of tiles (the rows above and below a tile in the same
+  // L2).  Otherwise every population is read once and the loads bypass the
+  // caches: tiles in launch order, all XCDs streaming the same stretch of
+  // the lattice, measured 5 % (FP32) and 10 % (FP64) faster than the bands.
   const int T = A.tiles_x * A.tiles_y;
   const int b = blockIdx.x;
-  const int t = (T % 8 == 0) ? (b % 8) * (T / 8) + b / 8 : b;
+  const int t = (MEDIAN && T % 8 == 0) ? (b % 8) * (T / 8) + b / 8 : b;
   const int tile_x = t % A.tiles_x, tile_y = t / A.tiles_x;
   const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
   const int x = tile_x * TX + lx, y = tile_y * TY + ly;
