@@ -262,11 +262,11 @@ void k_step(const StepArgs<typename StoreT<S>::R> A) {
 
 // The step on a periodic lattice without the median filter, in rows of 256
 // sites: each workgroup takes ROWS consecutive rows of one 256-column strip,
-// and every thread issues the loads of its next row before it computes the
-// current one, so that each wavefront keeps two rows of loads in flight (the
-// one-site kernel waits on a full memory latency for every site).  Per-site
-// arithmetic is the one-site kernel's, so the results are bit-identical.
-// Used for the 16-bit storage forms and for ELBM in FP32.
+// and with ROWS > 1 every thread issues the loads of its next row before it
+// computes the current one (two rows of loads in flight per wavefront).
+// Per-site arithmetic is the one-site kernel's, so the results are
+// bit-identical.  Used for the 16-bit storage forms and for ELBM in FP32,
+// with a compile-time variant without the Ehrenfest code.
 template <class S, int Q, int COLL, int ROWS, bool EHR>
 __global__ __launch_bounds__(256) void k_step_rows(const StepArgs<typename StoreT<S>::R> A) {
   using R = typename StoreT<S>::R;
@@ -344,15 +344,16 @@ static hipError_t launch_t(const void* args, hipStream_t s, hipEvent_t e0, hipEv
     launch_k<S, Q, COLL, MEDIAN, 64, 4>(A, s, e0, e1);
   } else {
     if (tile_shape(Q, MEDIAN, A.nx).tx == 256) {
-      // 16-bit storage: one site per lane leaves the memory system idle
-      // (measured 2.4 TB/s against 4.2 TB/s for the row-pipelined kernel);
-      // FP32 and FP64 LBGK/MRT already keep enough loads in flight at full
-      // occupancy.  ELBM (two wavefronts per SIMD) gains from the pipelining
-      // in FP32 too.
+      // 16-bit storage and ELBM.  With cached loads the one-site-per-lane
+      // kernel left the memory system idle in 16-bit storage (2.4 TB/s
+      // against 4.2 TB/s with four rows per workgroup and the next row's
+      // loads in flight); with nontemporal loads one row per workgroup is
+      // fastest (FP16 plain 123 -> 109 us, BF16 Ehrenfest 188 -> 154 us,
+      // 4096^2 ELBM 1.11 -> 1.06 ms against four rows).
       bool rows = false;
       if constexpr (sizeof(S) == 2 || (sizeof(S) == 4 && COLL == COLL_ELBM)) {
         if (A.bc == BC_PERIODIC) {
-          constexpr int ROWS = 4;
+          constexpr int ROWS = 1;
           const dim3 grid(A.tiles_x * ((A.ny + ROWS - 1) / ROWS)), block(256);
           // without Ehrenfest, a kernel compiled without the candidate code
           // (fewer registers, one more wavefront per SIMD in 16-bit storage)
