@@ -30,9 +30,8 @@ struct SelState {
   int b_bin;                     // this step's boundary bucket (-1: take every candidate)
   unsigned long long b_nc;       // this step's candidate count
   unsigned long long b_above;    // candidates in buckets above b_bin
-  int rescan;                    // this step's candidates cannot hold the answer
   long long tape_t;              // steps selected since the rollout began (tape index)
-  int pad[3];
+  int pad[4];
 };
 
 constexpr int kBuckets = 4096;        // histogram of candidate keys

@@ -8,13 +8,13 @@
 // is at least a floor carried over from the previous step, and counts them
 // in a 4096-bucket histogram whose frame also comes from the previous step.
 // Selection then touches the short candidate list only:
-//   k_decide    counts the candidates; unless a rescan is needed, finds the
-//               boundary bucket (holding the k-th largest key) from the
-//               histogram;
-//   k_fb_scan   only when the candidates cannot hold the answer (fewer than
-//               k above a raised floor, or more than the buffer holds):
-//               rescans the lattice, histograms the top 12 bits of Delta S
-//               and picks a floor bin that holds at least k sites;
+//   k_fb_scan   counts the candidates in every workgroup; unless a rescan
+//               is needed, its first workgroup finds the boundary bucket
+//               (holding the k-th largest key) from the histogram and the
+//               others return.  Only when the candidates cannot hold the
+//               answer (fewer than k above a raised floor) all of them
+//               rescan the lattice, histogram the top 12 bits of Delta S
+//               and pick a floor bin that holds at least k sites;
 //   k_fb_append same condition: rescans and appends from that bin up;
 //               its last workgroup then finds the boundary bucket;
 //   k_fix_regions writes f* at candidates above the boundary bucket and
@@ -139,15 +139,60 @@ __device__ __forceinline__ unsigned long long candidate_count(const unsigned lon
   return n;
 }
 
-// calibrate = 0: the step's fallback; 1: first floor of a freshly set lattice.
+// The bucket holding the k-th largest candidate key, from the step's
+// histogram (in LDS) and candidate count; stored in the selection state
+// for the region sweep.  Every thread of one workgroup calls it.
+template <class R>
+__device__ void boundary_from(const unsigned int* h, long long nc, long long k, SelState* st) {
+  int boundary = -1;
+  unsigned long long above = 0;
+  if (k <= 0) {
+    boundary = kBuckets;                 // take nothing
+  } else if (nc > k) {
+    find_from_top<kBuckets>(h, (unsigned long long)k, &boundary, &above);
+    if (boundary < 0) boundary = -1;
+  }
+  if (threadIdx.x == 0) {
+    st->b_bin = boundary;
+    st->b_nc = (unsigned long long)nc;
+    st->b_above = above;
+  }
+}
+
+// calibrate = 0: the step's first selection kernel; 1: first floor of a
+// freshly set lattice.
 template <class S, int Q>
 __global__ __launch_bounds__(256) void k_fb_scan(const StepArgs<typename StoreT<S>::R> A,
                                                  long long k, unsigned int* coarse,
                                                  int calibrate) {
   using R = typename StoreT<S>::R;
   SelState* st = A.sel;
+  static_assert(kCoarse == kBuckets, "one LDS histogram serves both uses");
   __shared__ unsigned int h[kCoarse];
-  if (!calibrate && !st->rescan) return;      // decided by k_decide
+  if (!calibrate) {
+    // Every workgroup takes the same decision from the same counters.  The
+    // first one loads the histogram with them (one memory round trip) and,
+    // unless the step rescans, finds the boundary bucket.
+    __shared__ unsigned long long s_nc;
+    if (blockIdx.x == 0)
+      for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) h[i] = ld_rlx(&A.hist[hist_pos(i)]);
+    if (threadIdx.x < 64) {
+      const unsigned long long n = candidate_count(A.ccount);
+      if (threadIdx.x == 0) s_nc = n;
+    }
+    const unsigned long long step = st->step;
+    const int fr0 = st->floor_raised[0], fr1 = st->floor_raised[1];
+    const bool raised = ((step & 1ull) ? fr1 : fr0) != 0;
+    __syncthreads();
+    // a rescan is needed when the floor was raised and fewer than k sites
+    // reached it
+    const long long nc = (long long)s_nc;
+    if (!(nc < k && raised)) {
+      if (blockIdx.x == 0) boundary_from<R>(h, nc, k, st);
+      return;
+    }
+    __syncthreads();
+  }
   for (int i = threadIdx.x; i < kCoarse; i += blockDim.x) h[i] = 0;
   __syncthreads();
   const long long n = (long long)A.nx * A.ny;
@@ -204,26 +249,6 @@ __global__ __launch_bounds__(256) void k_fb_scan(const StepArgs<typename StoreT<
   for (int i = threadIdx.x; i < kCoarse; i += blockDim.x) coarse[i] = 0;
   for (int i = threadIdx.x; i < kHistWords; i += blockDim.x) A.hist[i] = 0;
   for (int i = threadIdx.x; i < kCountSlots; i += blockDim.x) A.ccount[i * kCountStride] = 0;
-}
-
-// The bucket holding the k-th largest candidate key, from the step's
-// histogram (in LDS) and candidate count; stored in the selection state
-// for the region sweep.  Every thread of one workgroup calls it.
-template <class R>
-__device__ void boundary_from(const unsigned int* h, long long nc, long long k, SelState* st) {
-  int boundary = -1;
-  unsigned long long above = 0;
-  if (k <= 0) {
-    boundary = kBuckets;                 // take nothing
-  } else if (nc > k) {
-    find_from_top<kBuckets>(h, (unsigned long long)k, &boundary, &above);
-    if (boundary < 0) boundary = -1;
-  }
-  if (threadIdx.x == 0) {
-    st->b_bin = boundary;
-    st->b_nc = (unsigned long long)nc;
-    st->b_above = above;
-  }
 }
 
 template <class R>
@@ -283,34 +308,6 @@ __global__ __launch_bounds__(256) void k_fb_append(const StepArgs<typename Store
     find_boundary<R>(A, k);
     if (threadIdx.x == 0) st->ticket = 0;
   }
-}
-
-// First selection kernel of a step (one workgroup): the candidate count,
-// and either the rescan flag or, when the candidates hold the answer, the
-// boundary bucket.
-template <class S, int Q>
-__global__ __launch_bounds__(1024) void k_decide(const StepArgs<typename StoreT<S>::R> A,
-                                                long long k) {
-  using R = typename StoreT<S>::R;
-  SelState* st = A.sel;
-  // every load is issued before the first barrier: one memory round trip
-  __shared__ unsigned int h[kBuckets];
-  __shared__ unsigned long long s_nc;
-  for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) h[i] = ld_rlx(&A.hist[hist_pos(i)]);
-  if (threadIdx.x < 64) {
-    const unsigned long long n = candidate_count(A.ccount);
-    if (threadIdx.x == 0) s_nc = n;
-  }
-  const unsigned long long step = st->step;
-  const int fr0 = st->floor_raised[0], fr1 = st->floor_raised[1];
-  const bool raised = ((step & 1ull) ? fr1 : fr0) != 0;
-  __syncthreads();
-  // a rescan is needed when the floor was raised and fewer than k sites
-  // reached it
-  const long long nc = (long long)s_nc;
-  const bool rescan = nc < k && raised;
-  if (threadIdx.x == 0) st->rescan = rescan ? 1 : 0;
-  if (!rescan) boundary_from<R>(h, nc, k, st);
 }
 
 // f* of site idx from the moments recorded with its candidate entry,
@@ -378,7 +375,7 @@ __device__ void fix_tail(const StepArgs<typename StoreT<S>::R>& A, long long k, 
   const unsigned long long floor_p[2] = {st->floor_key[0], st->floor_key[1]};
   for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) h[i] = ld_rlx(&A.hist[hist_pos(i)]);
   // candidate count, boundary bucket and the count above it, as found by
-  // k_decide (or by the rescan's last workgroup)
+  // k_fb_scan (or by the rescan's last workgroup)
   const long long nc = (long long)st->b_nc;
   const int b_bin = st->b_bin;
   const unsigned long long b_above = st->b_above;
@@ -729,8 +726,8 @@ template <class S, int Q>
 static hipError_t launch_select_t(const SelectArgs& a, hipStream_t s) {
   using R = typename StoreT<S>::R;
   const StepArgs<R>& A = *(const StepArgs<R>*)a.step_args;
-  hipLaunchKernelGGL((k_decide<S, Q>), dim3(1), dim3(1024), 0, s, A, a.k);
-  // one workgroup per CU: both return at once unless this step rescans (rare)
+  // one workgroup per CU: all but the first of k_fb_scan, and all of
+  // k_fb_append, return at once unless this step rescans (rare)
   hipLaunchKernelGGL((k_fb_scan<S, Q>), dim3(256), dim3(256), 0, s, A, a.k, a.coarse, 0);
   hipLaunchKernelGGL((k_fb_append<S, Q>), dim3(256), dim3(256), 0, s, A, a.k);
   const long long nreg = (long long)A.tiles_x * A.tiles_y * 4;
