@@ -126,7 +126,10 @@ __device__ __forceinline__ void site_finish(const StepArgs<typename StoreT<S>::R
 // step kernel: each is recomputed from the source lattice (pull, moments,
 // f*: the same values the step kernel had), collided with the FP64 solve,
 // limited and stored, with its counters and adjoint records, exactly as the
-// step kernel would have done in place.  The last workgroup clears the list.
+// step kernel would have done in place.  The last workgroup clears the list:
+// every workgroup has used the list length (its loop bounds) before it takes
+// its ticket, and nothing else that a workgroup wrote is read here, so no
+// device-scope fence is needed (on gfx950 one writes back the XCD's L2).
 template <class S, int Q>
 __global__ __launch_bounds__(256) void k_elbm_f64(const StepArgs<typename StoreT<S>::R> A) {
   using R = typename StoreT<S>::R;
@@ -143,7 +146,6 @@ __global__ __launch_bounds__(256) void k_elbm_f64(const StepArgs<typename StoreT
     site_finish<S, Q, COLL_ELBM, false, false>(A, x, y, on, 0, v, feq, d, m0, ux, uy, R(0), fr, cnt);
   }
   __shared__ bool last;
-  __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) last = atomicAdd(&A.f64_count[1], 1u) == gridDim.x - 1;
   __syncthreads();
