@@ -453,10 +453,19 @@ def main():
         import torch
         x = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         for _ in range(10):
             y.copy_(x)
+        e1.record()
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": args.copy_probe, "launches": 10}))
+        us = e0.elapsed_time(e1) * 1e3 / 10
+        # a copy reads and writes the buffer once: the rate that a streaming
+        # kernel moving the same bytes can reach
+        print(json.dumps({"copy_bytes": args.copy_probe, "launches": 11, "us_per_copy": round(us, 1),
+                          "read_plus_write_gbs": round(2 * args.copy_probe / us / 1e3, 1)}))
         return
 
     import torch

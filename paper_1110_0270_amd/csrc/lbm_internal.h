@@ -16,8 +16,6 @@ struct SelState {
   unsigned long long floor_key[2]; // candidate iff eligible and key >= floor_key[parity]
   unsigned long long base_key[2];  // histogram frame: bucket = (key - base_key) >> shift
   unsigned long long step;         // steps selected so far (parity = step & 1)
-  unsigned long long bcount;     // length of the boundary-bucket list
-  unsigned long long sel_acc;    // sites selected so far in the running step
   unsigned long long fallbacks;  // steps that needed a full rescan (cumulative)
   unsigned long long overflows;  // steps whose boundary list overflowed (cumulative)
   unsigned long long cand_total; // candidates over all steps (cumulative)
@@ -32,6 +30,12 @@ struct SelState {
   unsigned long long b_above;    // candidates in buckets above b_bin
   long long tape_t;              // steps selected since the rollout began (tape index)
   int pad[4];
+  // Sites selected so far in the running step (high 32 bits) and the length
+  // of the boundary-bucket list (low 32 bits): one atomic per region-sweep
+  // workgroup reserves both, on a cache line of its own (every workgroup of
+  // the sweep adds to it).
+  alignas(128) unsigned long long sel_bnd;
+  unsigned long long pad_line[15];
 };
 
 constexpr int kBuckets = 4096;        // histogram of candidate keys

@@ -379,7 +379,8 @@ __device__ void fix_tail(const StepArgs<typename StoreT<S>::R>& A, long long k, 
   const long long nc = (long long)st->b_nc;
   const int b_bin = st->b_bin;
   const unsigned long long b_above = st->b_above;
-  const long long m_all = (long long)st->bcount;
+  const unsigned long long sel_bnd = st->sel_bnd;
+  const long long m_all = (long long)(sel_bnd & 0xffffffffull);
   // state the epilogue updates
   const bool fell_back = st->fallback != 0;
   const long long tape_t = st->tape_t;
@@ -388,7 +389,7 @@ __device__ void fix_tail(const StepArgs<typename StoreT<S>::R>& A, long long k, 
     n_sel_out = tape_cnt + tape_t;
   }
   const unsigned long long overflows = st->overflows, cand_total = st->cand_total;
-  if (threadIdx.x == 0) s_tot = (unsigned int)st->sel_acc;
+  if (threadIdx.x == 0) s_tot = (unsigned int)(sel_bnd >> 32);
   __syncthreads();
   const int par = (int)(step & 1ull);
   const unsigned long long base = par ? base_p[1] : base_p[0];
@@ -592,8 +593,7 @@ __device__ void fix_tail(const StepArgs<typename StoreT<S>::R>& A, long long k, 
     if (m_all > bcap) st->overflows = overflows + 1;
     st->cand_total = cand_total + (unsigned long long)nc;
     st->fallback = 0;
-    st->sel_acc = 0;
-    st->bcount = 0;
+    st->sel_bnd = 0;
     st->step += 1;
     st->tape_t = tape_t + 1;
   }
@@ -700,8 +700,13 @@ __global__ __launch_bounds__(256) void k_fix_regions(const StepArgs<typename Sto
   if (cnt) A.wcount[my_r] = 0;
   __syncthreads();
   if (threadIdx.x == 0) {
-    s_base_sel = s_sel ? atomicAdd(&st->sel_acc, (unsigned long long)s_sel) : 0ull;
-    s_base_bnd = s_bnd ? atomicAdd(&st->bcount, (unsigned long long)s_bnd) : 0ull;
+    // one atomic reserves both lists' slots (same-address atomics from
+    // every workgroup queue behind each other); neither count reaches 2^31,
+    // the limit on the lattice's sites, so no carry crosses the halves
+    const unsigned long long both = ((unsigned long long)s_sel << 32) | s_bnd;
+    const unsigned long long old = both ? atomicAdd(&st->sel_bnd, both) : 0ull;
+    s_base_sel = old >> 32;
+    s_base_bnd = old & 0xffffffffull;
   }
   __syncthreads();
   for (unsigned int i = threadIdx.x; i < s_sel; i += blockDim.x)
