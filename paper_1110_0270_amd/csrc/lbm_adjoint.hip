@@ -84,7 +84,13 @@ __global__ __launch_bounds__(256) void k_adjoint(const StepArgs<typename StoreT<
                                                  const AdjArgs<typename StoreT<S>::R> B) {
   using R = typename StoreT<S>::R;
   constexpr bool SH = StoreT<S>::shifted;
-  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  // Workgroups go round-robin to the 8 XCDs; each XCD takes pairs of
+  // adjacent 256-site segments, which share the lines that the pull and the
+  // push reach across their edge (the last, incomplete group of 16 keeps
+  // launch order).
+  const long long nb = gridDim.x, b = blockIdx.x;
+  const long long tb = (b / 16 * 16 + 16 <= nb) ? (b / 16) * 16 + (b % 8) * 2 + (b / 8) % 2 : b;
+  const long long s = tb * blockDim.x + threadIdx.x;
   __shared__ int32_t lsel[kAdjListLds];
   int nl = 0;
   if (B.list) {
@@ -104,7 +110,9 @@ __global__ __launch_bounds__(256) void k_adjoint(const StepArgs<typename StoreT<
   R lam[Q], mu[Q], lf[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    lam[i] = B.lam_in[(long long)i * A.qs + o];
+    // the adjoint lattices, like the populations, are streamed once per
+    // step: nontemporal loads and stores
+    lam[i] = __builtin_nontemporal_load(&B.lam_in[(long long)i * A.qs + o]);
     lf[i] = R(0);
   }
   R gw = R(0);
@@ -261,10 +269,10 @@ __global__ __launch_bounds__(256) void k_adjoint(const StepArgs<typename StoreT<
     } else {
       out = (sx < 0) | (sx >= A.nx) | (sy < 0) | (sy >= A.ny);
     }
-    if (!out) B.lam_out[(long long)i * A.qs + (long long)sy * A.pitch + sx] = val;
-    else B.lam_out[(long long)(Q - 1 - i) * A.qs + o] = val;
+    if (!out) __builtin_nontemporal_store(val, &B.lam_out[(long long)i * A.qs + (long long)sy * A.pitch + sx]);
+    else __builtin_nontemporal_store(val, &B.lam_out[(long long)(Q - 1 - i) * A.qs + o]);
   }
-  if (B.gom) B.gom[o] += gw;
+  if (B.gom) __builtin_nontemporal_store(__builtin_nontemporal_load(&B.gom[o]) + gw, &B.gom[o]);
 }
 
 // Recompute of an Ehrenfest step from its tape: f* at the listed sites,
