@@ -29,6 +29,103 @@ __device__ __noinline__ ElbmF64Result elbm_alpha_fp64(ElbmF64Site s, double eps,
   return r;
 }
 
+// The same FP64 root solve with one site spread over a group of 16 lanes of
+// the wavefront: lane c of the group holds component c of f and f* (idle
+// lanes, c >= Q or a group without a site, hold f = f* = 1 and add zero to
+// every sum).  The sums over the components are butterfly reductions within
+// the group, which leave the same bits in every lane of it, so every lane
+// takes the same branches and returns the same result.  Each iteration costs
+// one logarithm and two divisions per lane instead of Q of each in one lane.
+__device__ __forceinline__ double group16_sum(double v) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ double group16_min(double v) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ double group16_max(double v) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ bool group16_any(bool b) {
+  int v = b ? 1 : 0;
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) v |= __shfl_xor(v, o);
+  return v != 0;
+}
+
+__device__ ElbmF64Result elbm_alpha_fp64_group(float f_c, float q_c, bool act, double eps,
+                                               double dS_cut, int max_iter, int norm,
+                                               int fallback) {
+  const double f = act ? (double)f_c : 1.0, q = act ? (double)q_c : 1.0, D = q - f;
+  ElbmF64Result r;
+  r.iters = 0;
+  if (group16_any(act && f <= 0.0)) {
+    r.alpha = 1.0f;
+    r.branch = EB_NONPOS;
+    return r;
+  }
+  const double x = -D / q;
+  const double U = group16_sum(q * x * x);
+  const double xmax = group16_max(act ? x : -1.0);
+  if (U < 2.0 * dS_cut * (1.0 + xmax / 3.0)) {
+    const double dS = group16_sum(q * h_fn<double>(x));
+    if (dS < dS_cut) {
+      r.alpha = 2.0f;
+      r.branch = EB_CUTOFF;
+      return r;
+    }
+  }
+  const double lnr = log1p(x);
+  const double nrm = norm == 0 ? sqrt(U) : group16_sum(fabs(D));
+  const double s1 = group16_sum(D * lnr);
+  const double amax = group16_min(D < 0.0 ? f / (-D) : __builtin_huge_val());
+  bool probe = amax < __builtin_huge_val();
+  double a = amax > 2.0 ? 2.0 : 0.5 * (1.0 + amax);
+  double prev = __builtin_huge_val();
+  constexpr double kNoise = 64.0 * 2.220446049250313e-16;
+  for (int it = 0;;) {
+    const double aa = probe ? amax : a;
+    const double xa = aa * D / f;
+    const double l = log1p(xa < -1.0 ? -1.0 : xa);
+    const double s0 = group16_sum(f * h_log<double>(xa, l));
+    const double t1 = group16_sum(D * (l + lnr));
+    const double t2 = group16_sum(D * D / (f + aa * D));
+    const double sf = -s0 - aa * s1, d1 = -t1, d2 = -t2;
+    if (probe) {
+      if (sf >= 0.0) {
+        r.alpha = (float)(fallback == 0 ? amax : 1.0);
+        r.branch = EB_NOROOT;
+        return r;
+      }
+      probe = false;
+      continue;
+    }
+    const double step_est = fabs(sf / d1);
+    const bool stalled = it >= 2 && step_est >= 0.5 * prev && step_est < kNoise * a;
+    if (step_est * nrm < eps || it >= max_iter || stalled) {
+      if (sf < 0.0) a = a - 2.0 * sf / d1;
+      break;
+    }
+    ++it;
+    ++r.iters;
+    prev = step_est;
+    const double disc = d1 * d1 - 2.0 * sf * d2;
+    const double delta = disc >= 0.0 ? 2.0 * sf / (-d1 + sqrt(disc)) : -sf / d1;
+    double an = a + delta;
+    if (an >= amax) an = 0.5 * (a + amax);
+    if (an <= 1.0) an = 0.5 * (a + 1.0);
+    a = an;
+  }
+  r.alpha = (float)a;
+  r.branch = EB_ROOT;
+  return r;
+}
+
 template <class R>
 struct CollInfo {
   R alpha = R(2);   // ELBM alpha (2 elsewhere)
@@ -44,7 +141,8 @@ struct CollInfo {
 // 3 ELBM), in the storage representation: d = f* - f, om the relaxation rate
 // (LBGK omega, MRT shear rate s_nu, ELBM 2 beta).
 // DEFER (FP32 ELBM only): a site that needs the FP64 solve is not collided;
-// ci.deferred is set and post[] is left unset.
+// ci.deferred is set and post[] is left unset.  preset: the FP64 solve's
+// result for such a site, already found by its lane group.
 template <class S, int Q, int COLL, bool DEFER = false>
 __device__ __forceinline__ void collide_site(const StepArgs<typename StoreT<S>::R>& A,
                                              const typename StoreT<S>::R v[Q],
@@ -52,7 +150,8 @@ __device__ __forceinline__ void collide_site(const StepArgs<typename StoreT<S>::
                                              const typename StoreT<S>::R d[Q],
                                              typename StoreT<S>::R om,
                                              typename StoreT<S>::R post[Q],
-                                             CollInfo<typename StoreT<S>::R>& ci) {
+                                             CollInfo<typename StoreT<S>::R>& ci,
+                                             const ElbmF64Result* preset = nullptr) {
   using R = typename StoreT<S>::R;
   constexpr bool SH = StoreT<S>::shifted;
   if constexpr (COLL == COLL_LBGK) {
@@ -101,7 +200,8 @@ __device__ __forceinline__ void collide_site(const StepArgs<typename StoreT<S>::
           st.q[i] = qa[i];
         }
         const ElbmF64Result r =
-            elbm_alpha_fp64<Q>(st, A.eps64, A.dS_cut64, A.max_iter, A.norm, A.fallback);
+            preset ? *preset
+                   : elbm_alpha_fp64<Q>(st, A.eps64, A.dS_cut64, A.max_iter, A.norm, A.fallback);
         alpha = r.alpha;
         br = r.branch;
         ci.iters = r.iters;

@@ -59,7 +59,8 @@ __device__ __forceinline__ void site_finish(const StepArgs<typename StoreT<S>::R
                                             typename StoreT<S>::R ux, typename StoreT<S>::R uy,
                                             typename StoreT<S>::R dS,
                                             const StepFrame& fr,
-                                            unsigned long long* cnt) {
+                                            unsigned long long* cnt,
+                                            const ElbmF64Result* preset = nullptr) {
   using R = typename StoreT<S>::R;
   // Ehrenfest candidates: eligible (Delta S > delta) and above the floor.
   if (EHR && A.ehrenfest) {
@@ -74,7 +75,7 @@ __device__ __forceinline__ void site_finish(const StepArgs<typename StoreT<S>::R
   if (valid) {
     const R om = A.omega_field ? A.omega_field[(long long)y * A.pitch + x] : A.omega;
     CollInfo<R> ci;
-    collide_site<S, Q, COLL, DEFER>(A, v, feq, d, om, post, ci);
+    collide_site<S, Q, COLL, DEFER>(A, v, feq, d, om, post, ci, preset);
     deferred = ci.deferred;
     if constexpr (COLL == COLL_ELBM) {
       // a deferred site counts no event here (its CollInfo is the default)
@@ -133,17 +134,39 @@ __device__ __forceinline__ void site_finish(const StepArgs<typename StoreT<S>::R
 template <class S, int Q>
 __global__ __launch_bounds__(256) void k_elbm_f64(const StepArgs<typename StoreT<S>::R> A) {
   using R = typename StoreT<S>::R;
+  constexpr bool SH = StoreT<S>::shifted;
   const unsigned int n = A.f64_count[0];
   unsigned long long* const cnt = A.counters + (blockIdx.x % kCntSlots) * CNT_N;
   const StepFrame fr{0ull, 0ull, 0u};
-  for (unsigned int b0 = blockIdx.x * 256u; b0 < n; b0 += gridDim.x * 256u) {
-    const unsigned int i = b0 + threadIdx.x;
+  // 16 sites per workgroup, one per group of 16 lanes: every lane of the
+  // group recomputes the site, lane c takes component c into the group's
+  // root solve, and lane 0 collides, limits and stores it.
+  const unsigned int grp = threadIdx.x / 16, c = threadIdx.x % 16;
+  for (unsigned int b0 = blockIdx.x * 16u; b0 < n; b0 += gridDim.x * 16u) {
+    const unsigned int i = b0 + grp;
     const bool on = i < n;
     const uint32_t idx = on ? A.f64_sites[i] : 0u;
     const int x = (int)(idx % (uint32_t)A.nx), y = (int)(idx / (uint32_t)A.nx);
     R v[Q], feq[Q], d[Q], m0 = R(0), ux = R(0), uy = R(0);
-    if (on) site_prep<S, Q>(A, x, y, v, feq, d, m0, ux, uy, false);
-    site_finish<S, Q, COLL_ELBM, false, false>(A, x, y, on, 0, v, feq, d, m0, ux, uy, R(0), fr, cnt);
+    ElbmF64Result r{2.0f, EB_CUTOFF, 0};
+    if (on) {
+      site_prep<S, Q>(A, x, y, v, feq, d, m0, ux, uy, false);
+      // component c of f and f* in the unshifted representation, as the
+      // per-site solve receives them
+      float f_c = 1.0f, q_c = 1.0f;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        const R sh = SH ? wt<R, Q>(k) * A.rho0 : R(0);
+        if ((int)c == k) {
+          f_c = v[k] + sh;
+          q_c = feq[k] + sh;
+        }
+      }
+      r = elbm_alpha_fp64_group(f_c, q_c, (int)c < Q, A.eps64, A.dS_cut64, A.max_iter, A.norm,
+                                A.fallback);
+    }
+    site_finish<S, Q, COLL_ELBM, false, false>(A, x, y, on && c == 0, 0, v, feq, d, m0, ux, uy,
+                                                R(0), fr, cnt, &r);
   }
   __shared__ bool last;
   __syncthreads();
@@ -384,7 +407,7 @@ static hipError_t launch_t(const void* args, hipStream_t s, hipEvent_t e0, hipEv
     // the sites the step kernel left for the FP64 root solve (few; the
     // kernel returns at once when there are none)
     if (A.f64_sites)
-      hipLaunchKernelGGL((k_elbm_f64<S, Q>), dim3(64), dim3(256), 0, s, A);
+      hipLaunchKernelGGL((k_elbm_f64<S, Q>), dim3(256), dim3(256), 0, s, A);
   }
   return hipGetLastError();
 }
