@@ -299,7 +299,12 @@ __global__ __launch_bounds__(256) void k_step_rows(const StepArgs<typename Store
   const int nyc = (A.ny + ROWS - 1) / ROWS;
   const int T = A.tiles_x * nyc;
   const int b = blockIdx.x;
-  const int t = (T % 8 == 0) ? (b % 8) * (T / 8) + b / 8 : b;   // XCD-aware order
+  // Workgroups go round-robin to the 8 XCDs; each XCD takes pairs of
+  // adjacent row segments, which share the line the pull reaches across
+  // their edge (the last, incomplete group of 16 keeps launch order).  With
+  // nontemporal loads this beats one contiguous band of rows per XCD:
+  // FP16 108.4 -> 103.2 us, BF16 111.4 -> 107.3 us without limiters.
+  const int t = (b / 16 * 16 + 16 <= T) ? (b / 16) * 16 + (b % 8) * 2 + (b / 8) % 2 : b;
   const int tile_x = t % A.tiles_x, y0 = (t / A.tiles_x) * ROWS;
   const int x = tile_x * 256 + (int)threadIdx.x;
   const bool valid = x < A.nx;
