@@ -356,7 +356,7 @@ template <class S, int Q>
 __device__ void fix_tail(const StepArgs<typename StoreT<S>::R>& A, long long k, long long n_sites,
                          int32_t* selected, uint32_t* blist, long long bcap,
                          long long* n_sel_out, int32_t* tape_sel, long long* tape_cnt,
-                         long long tape_len) {
+                         long long tape_len, uint32_t* scratch, long long scratch_len) {
   using R = typename StoreT<S>::R;
   SelState* st = A.sel;
   __shared__ unsigned int h[kBuckets];
@@ -454,22 +454,51 @@ __device__ void fix_tail(const StepArgs<typename StoreT<S>::R>& A, long long k, 
     const int kd = (nb + 7) / 8;
     // MSD radix select, one byte per pass; up to kTailStage entries are
     // read from the candidate buffer once into LDS and every pass works
-    // there.
+    // there.  Longer lists (large groups of exactly tied keys, frequent
+    // with 16-bit storage) are written once as 16-byte records (offset,
+    // ~index, position) to a global scratch array, the region sweep's
+    // stage (unused once the sweep has finished), so that every pass reads
+    // one record per entry instead of two dependent loads; without room
+    // there the passes read the candidate buffer.
     const bool staged = m <= kTailStage;
-    if (staged) {
-      for (long long q = threadIdx.x; q < m; q += blockDim.x) {
-        const uint32_t p = blist[q];
-        const unsigned long long key = (unsigned long long)A.cand_key[p];
-        t_off[q] = key >= edge ? key - edge : 0ull;
-        t_ni[q] = ~A.cand_idx[p];
-        t_p[q] = p;
+    const bool recs = !staged && scratch && 4 * m <= scratch_len;
+    if (staged || recs) {
+      for (long long q0 = threadIdx.x; q0 < m; q0 += 4 * (long long)blockDim.x) {
+        uint32_t pu[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const long long q = q0 + u * (long long)blockDim.x;
+          pu[u] = q < m ? blist[q] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const long long q = q0 + u * (long long)blockDim.x;
+          if (q >= m) continue;
+          const unsigned long long key = (unsigned long long)A.cand_key[pu[u]];
+          const unsigned long long off = key >= edge ? key - edge : 0ull;
+          const uint32_t ni = ~A.cand_idx[pu[u]];
+          if (staged) {
+            t_off[q] = off;
+            t_ni[q] = ni;
+            t_p[q] = pu[u];
+          } else {
+            *reinterpret_cast<uint4*>(scratch + 4 * q) =
+                make_uint4((uint32_t)off, (uint32_t)(off >> 32), ni, pu[u]);
+          }
+        }
       }
+      __syncthreads();
     }
     auto entry = [&](long long q, unsigned long long& off, uint32_t& ni, uint32_t& p) {
       if (staged) {
         off = t_off[q];
         ni = t_ni[q];
         p = t_p[q];
+      } else if (recs) {
+        const uint4 r = *reinterpret_cast<const uint4*>(scratch + 4 * q);
+        off = (unsigned long long)r.x | ((unsigned long long)r.y << 32);
+        ni = r.z;
+        p = r.w;
       } else {
         p = blist[q];
         const unsigned long long key = (unsigned long long)A.cand_key[p];
@@ -491,23 +520,35 @@ __device__ void fix_tail(const StepArgs<typename StoreT<S>::R>& A, long long k, 
       const int sb = on_key ? 8 * (kd - 1 - dgt) : 8 * (3 - (dgt - kd));
       const unsigned long long op = s_off_pref;
       const uint32_t ip = s_idx_pref;
-      for (long long q = threadIdx.x; q < m; q += blockDim.x) {
-        unsigned long long off;
-        uint32_t ni, p;
-        entry(q, off, ni, p);
-        bool match;
-        unsigned int digit;
-        const int topb = sb + 8;
-        if (on_key) {
-          const unsigned long long hm = topb >= 64 ? 0ull : (~0ull << topb);
-          match = (off & hm) == (op & hm);
-          digit = (unsigned int)((off >> sb) & 0xffu);
-        } else {
-          const uint32_t hm = topb >= 32 ? 0u : (~0u << topb);
-          match = off == op && (ni & hm) == (ip & hm);
-          digit = (ni >> sb) & 0xffu;
+      // four entries per thread in flight
+      for (long long q0 = threadIdx.x; q0 < m; q0 += 4 * (long long)blockDim.x) {
+        unsigned long long offs[4];
+        uint32_t nis[4], ps[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const long long q = q0 + u * (long long)blockDim.x;
+          if (q < m) entry(q, offs[u], nis[u], ps[u]);
         }
-        if (match) atomicAdd(&dh[digit], 1u);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const long long q = q0 + u * (long long)blockDim.x;
+          if (q >= m) continue;
+          const unsigned long long off = offs[u];
+          const uint32_t ni = nis[u];
+          bool match;
+          unsigned int digit;
+          const int topb = sb + 8;
+          if (on_key) {
+            const unsigned long long hm = topb >= 64 ? 0ull : (~0ull << topb);
+            match = (off & hm) == (op & hm);
+            digit = (unsigned int)((off >> sb) & 0xffu);
+          } else {
+            const uint32_t hm = topb >= 32 ? 0u : (~0u << topb);
+            match = off == op && (ni & hm) == (ip & hm);
+            digit = (ni >> sb) & 0xffu;
+          }
+          if (match) atomicAdd(&dh[digit], 1u);
+        }
       }
       __syncthreads();
       int dsel;
@@ -723,8 +764,10 @@ __global__ __launch_bounds__(1024) void k_fix_tail(const StepArgs<typename Store
                                                    int32_t* selected, uint32_t* blist,
                                                    long long bcap, long long* n_sel_out,
                                                    int32_t* tape_sel, long long* tape_cnt,
-                                                   long long tape_len) {
-  fix_tail<S, Q>(A, k, n_sites, selected, blist, bcap, n_sel_out, tape_sel, tape_cnt, tape_len);
+                                                   long long tape_len, uint32_t* scratch,
+                                                   long long scratch_len) {
+  fix_tail<S, Q>(A, k, n_sites, selected, blist, bcap, n_sel_out, tape_sel, tape_cnt, tape_len,
+                 scratch, scratch_len);
 }
 
 template <class S, int Q>
@@ -741,9 +784,10 @@ static hipError_t launch_select_t(const SelectArgs& a, hipStream_t s) {
   const int gfix = (int)((nreg + 255) / 256);
   hipLaunchKernelGGL((k_fix_regions<S, Q>), dim3(gfix), dim3(256), 0, s, A, a.k, a.selected,
                      a.segsel, a.blist, a.bcap, a.tape_sel, a.tape_len);
+  // the region sweep's stage: gfix workgroups x 256 regions x 64 entries
   hipLaunchKernelGGL((k_fix_tail<S, Q>), dim3(1), dim3(1024), 0, s, A, a.k, a.n_sites,
                      a.selected, a.blist, a.bcap, a.n_sel_out, a.tape_sel, a.tape_cnt,
-                     a.tape_len);
+                     a.tape_len, (uint32_t*)a.segsel, (long long)gfix * 256 * 64);
   return hipGetLastError();
 }
 
