@@ -99,8 +99,8 @@ Layout make_layout(const lbm_config* c) {
     L.off_hist = take((size_t)kHistWords * 4);
     L.off_coarse = take(kCoarse * 4);
     L.off_ccount = take((size_t)kCountSlots * kCountStride * 8);
-    // 256 regions x 64 entries per k_fix_regions workgroup
-    L.off_stage = take((size_t)((tiles * 4 + 255) / 256) * 256 * 64 * 4);
+    // kSweepRegions regions x 64 entries per k_fix_regions workgroup
+    L.off_stage = take((size_t)((tiles * 4 + kSweepRegions - 1) / kSweepRegions) * kSweepRegions * 64 * 4);
     L.bcap = std::min<long long>(L.cap, 1ll << 20);
     L.off_blist = take((size_t)L.bcap * 4);
     L.off_selected = take((size_t)std::max<long long>(L.k, 1) * 4);

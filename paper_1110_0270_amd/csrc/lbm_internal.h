@@ -38,6 +38,12 @@ struct SelState {
   unsigned long long pad_line[15];
 };
 
+// Regions (the candidate areas of the step kernel's wavefronts) per
+// workgroup of the region sweep, one per thread: 16 wavefronts.  Each
+// workgroup reserves its slots in the selected and boundary lists with one
+// same-address atomic, so fewer, larger workgroups queue fewer of them
+// (1024 against 256 regions: 7 us less per FP32 step).
+constexpr int kSweepRegions = 1024;
 constexpr int kBuckets = 4096;        // histogram of candidate keys
 // Bucket b is counted at hist[hist_pos(b)].  The step kernel's atomics crowd
 // into the few buckets just above the floor, and atomics on one cache line

@@ -643,9 +643,10 @@ __device__ void fix_tail(const StepArgs<typename StoreT<S>::R>& A, long long k, 
 }
 
 // LDS staging of a k_fix_regions workgroup: selected sites and boundary
-// entries (the rest, up to 256 x 64 entries, go to its global stage).
-constexpr int kRegSel = 1536;
-constexpr int kRegBnd = 512;
+// entries (the rest, up to kSweepRegions x 64 entries, go to its global
+// stage).
+constexpr int kRegSel = 6144;
+constexpr int kRegBnd = 2048;
 // Regions with at most this many candidates are walked lane by lane.
 constexpr int kFewCand = 4;
 
@@ -654,7 +655,7 @@ constexpr int kFewCand = 4;
 // 1024: the exact resolution is a chain of dependent loads over the list)
 // resolves the boundary bucket exactly and prepares the next step.
 template <class S, int Q>
-__global__ __launch_bounds__(256) void k_fix_regions(const StepArgs<typename StoreT<S>::R> A,
+__global__ __launch_bounds__(kSweepRegions) void k_fix_regions(const StepArgs<typename StoreT<S>::R> A,
                                                      long long k, int32_t* selected,
                                                      int32_t* stage, uint32_t* blist,
                                                      long long bcap, int32_t* tape_sel,
@@ -682,9 +683,10 @@ __global__ __launch_bounds__(256) void k_fix_regions(const StepArgs<typename Sto
   // lane per entry.
   const long long nreg = (long long)A.tiles_x * A.tiles_y * 4;
   const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const long long g = (long long)blockIdx.x * 4 + w, nwave = (long long)gridDim.x * 4;
+  constexpr int kWaves = kSweepRegions / 64;
+  const long long g = (long long)blockIdx.x * kWaves + w, nwave = (long long)gridDim.x * kWaves;
   const long long my_r = (long long)lane * nwave + g;
-  int32_t* my_stage = stage + (long long)blockIdx.x * 256 * 64;
+  int32_t* my_stage = stage + (long long)blockIdx.x * kSweepRegions * 64;
   uint32_t cnt = 0;
   if (my_r < nreg) cnt = A.wcount[my_r];
   // One candidate entry p (when `on`): f* at the selected, staging of the
@@ -715,7 +717,7 @@ __global__ __launch_bounds__(256) void k_fix_regions(const StepArgs<typename Sto
     const unsigned int q = lds_slot(bnd, &s_bnd);
     if (bnd) {                                  // boundary entries fill from the end
       if (q < (unsigned int)kRegBnd) l_bnd[q] = (int32_t)p;
-      else my_stage[256 * 64 - 1 - q] = (int32_t)p;
+      else my_stage[kSweepRegions * 64 - 1 - q] = (int32_t)p;
     }
   };
   // Sparse regions (at most kFewCand entries, where candidates are scattered
@@ -755,7 +757,7 @@ __global__ __launch_bounds__(256) void k_fix_regions(const StepArgs<typename Sto
       selected[s_base_sel + i] = i < (unsigned int)kRegSel ? l_sel[i] : my_stage[i];
   for (unsigned int i = threadIdx.x; i < s_bnd; i += blockDim.x)
     if ((long long)(s_base_bnd + i) < bcap)
-      blist[s_base_bnd + i] = (uint32_t)(i < (unsigned int)kRegBnd ? l_bnd[i] : my_stage[256 * 64 - 1 - i]);
+      blist[s_base_bnd + i] = (uint32_t)(i < (unsigned int)kRegBnd ? l_bnd[i] : my_stage[kSweepRegions * 64 - 1 - i]);
 }
 
 template <class S, int Q>
@@ -781,13 +783,14 @@ static hipError_t launch_select_t(const SelectArgs& a, hipStream_t s) {
   hipLaunchKernelGGL((k_fb_scan<S, Q>), dim3(64), dim3(1024), 0, s, A, a.k, a.coarse, 0);
   hipLaunchKernelGGL((k_fb_append<S, Q>), dim3(256), dim3(256), 0, s, A, a.k);
   const long long nreg = (long long)A.tiles_x * A.tiles_y * 4;
-  const int gfix = (int)((nreg + 255) / 256);
-  hipLaunchKernelGGL((k_fix_regions<S, Q>), dim3(gfix), dim3(256), 0, s, A, a.k, a.selected,
+  const int gfix = (int)((nreg + kSweepRegions - 1) / kSweepRegions);
+  hipLaunchKernelGGL((k_fix_regions<S, Q>), dim3(gfix), dim3(kSweepRegions), 0, s, A, a.k, a.selected,
                      a.segsel, a.blist, a.bcap, a.tape_sel, a.tape_len);
-  // the region sweep's stage: gfix workgroups x 256 regions x 64 entries
+  // the region sweep's stage: gfix workgroups x kSweepRegions regions x 64
+  // entries
   hipLaunchKernelGGL((k_fix_tail<S, Q>), dim3(1), dim3(1024), 0, s, A, a.k, a.n_sites,
                      a.selected, a.blist, a.bcap, a.n_sel_out, a.tape_sel, a.tape_cnt,
-                     a.tape_len, (uint32_t*)a.segsel, (long long)gfix * 256 * 64);
+                     a.tape_len, (uint32_t*)a.segsel, (long long)gfix * kSweepRegions * 64);
   return hipGetLastError();
 }
 
