@@ -389,6 +389,9 @@ __device__ void fix_tail(const StepArgs<typename StoreT<S>::R>& A, long long k, 
     n_sel_out = tape_cnt + tape_t;
   }
   const unsigned long long overflows = st->overflows, cand_total = st->cand_total;
+  // this thread's boundary-list entry, loaded with the state (the short-list
+  // path below needs it; past the list's length it is not used)
+  const uint32_t p_mine = (long long)threadIdx.x < bcap ? blist[threadIdx.x] : 0u;
   if (threadIdx.x == 0) s_tot = (unsigned int)(sel_bnd >> 32);
   __syncthreads();
   const int par = (int)(step & 1ull);
@@ -415,7 +418,7 @@ __device__ void fix_tail(const StepArgs<typename StoreT<S>::R>& A, long long k, 
     uint32_t nq = 0;
     R m0 = R(0), ux = R(0), uy = R(0);
     if ((int)threadIdx.x < m) {
-      const uint32_t p = blist[threadIdx.x];
+      const uint32_t p = p_mine;
       const unsigned long long key = (unsigned long long)A.cand_key[p];
       oq = key >= edge ? key - edge : 0ull;
       nq = ~A.cand_idx[p];
