@@ -58,9 +58,9 @@ __device__ __forceinline__ bool group16_any(bool b) {
   return v != 0;
 }
 
-__device__ ElbmF64Result elbm_alpha_fp64_group(float f_c, float q_c, bool act, double eps,
-                                               double dS_cut, int max_iter, int norm,
-                                               int fallback) {
+static __device__ ElbmF64Result elbm_alpha_fp64_group(float f_c, float q_c, bool act,
+                                                      double eps, double dS_cut, int max_iter,
+                                                      int norm, int fallback) {
   const double f = act ? (double)f_c : 1.0, q = act ? (double)q_c : 1.0, D = q - f;
   ElbmF64Result r;
   r.iters = 0;
