@@ -281,10 +281,14 @@ template <class S, int Q>
 __global__ void k_tape_fix(const StepArgs<typename StoreT<S>::R> A, const int32_t* list,
                            const long long* count, long long k) {
   using R = typename StoreT<S>::R;
-  const long long n = *count < k ? *count : k;
-  for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+  // the list's slots (k of them) are loaded with its count: one round trip
+  // fewer than loading them after it
+  const long long c = *count;
+  const long long n = c < k ? c : k;
+  for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < k;
        j += (long long)gridDim.x * blockDim.x) {
     const int idx = list[j];
+    if (j >= n) continue;
     const int y = idx / A.nx, x = idx % A.nx;
     R v[Q], feq[Q], d[Q], m0, ux, uy;
     site_prep<S, Q>(A, x, y, v, feq, d, m0, ux, uy, false);
