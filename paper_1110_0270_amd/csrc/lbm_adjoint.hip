@@ -94,9 +94,12 @@ __global__ __launch_bounds__(256) void k_adjoint(const StepArgs<typename StoreT<
   __shared__ int32_t lsel[kAdjListLds];
   int nl = 0;
   if (B.list) {
+    // the list's k slots (k <= kAdjListLds) are loaded with its count: one
+    // round trip
     const long long c = *B.count;
+    const int32_t v = (long long)threadIdx.x < B.k ? B.list[threadIdx.x] : 0;
     nl = (int)(c < B.k ? c : B.k);
-    if ((int)threadIdx.x < nl) lsel[threadIdx.x] = B.list[threadIdx.x];
+    if ((int)threadIdx.x < nl) lsel[threadIdx.x] = v;
     __syncthreads();
   }
   if (s >= (long long)A.nx * A.ny) return;
