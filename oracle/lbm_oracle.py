@@ -472,13 +472,19 @@ def median_filter(lat: Lattice, cfg: Config, f, feq, dS):
         valid.append(ok)
     stack = torch.stack(vals)
     n = torch.stack(valid).sum(0)
-    srt = stack.sort(0).values
+    # stable: among equal values the neighbour listed first holds the median
+    # (decides only which neighbour a gradient flows to)
+    srt = stack.sort(dim=0, stable=True).values
     rank = (n + 1) // 2 - 1                                   # ceil(n/2) - 1
     med = srt.gather(0, rank.unsqueeze(0)).squeeze(0)
     accept = (dS > cfg.med_delta) & (med < dS) & torch.isfinite(dS)
     ratio = torch.where(accept, med / torch.where(accept, dS, torch.ones_like(dS)),
                         torch.ones_like(dS))
-    coef = torch.where(accept, torch.sqrt(ratio.clamp(min=0.0)), torch.ones_like(dS))
+    # Reading (gradients only): a zero median maps the site onto f*; the
+    # derivative of sqrt at 0 is infinite, so none is taken through it.
+    pos = ratio > 0
+    root = torch.sqrt(torch.where(pos, ratio, torch.ones_like(ratio)))
+    coef = torch.where(accept, torch.where(pos, root, torch.zeros_like(root)), torch.ones_like(dS))
     return feq + coef.unsqueeze(0) * (f - feq), accept
 
 

@@ -424,6 +424,97 @@ def test_elbm_root_matches_bisection_and_is_a_lower_estimate():
     assert checked >= 10
 
 
+def _dec_sf_d1(f, a):
+    """S_f(a) = S(f + a D) - S(f) and its derivative in a, evaluated from the
+    definition in 50-digit decimal with the exact entropic equilibrium of f
+    (D = f* - f).  Returns (S_f, S_f', D, f*)."""
+    W = [Decimal(1) / 36, Decimal(1) / 9, Decimal(1) / 36, Decimal(1) / 9, Decimal(4) / 9,
+         Decimal(1) / 9, Decimal(1) / 36, Decimal(1) / 9, Decimal(1) / 36]
+    fd = [Decimal(float(x)) for x in f]
+    qd = _dec_entropic_eq(fd)
+    Dd = [b - x for x, b in zip(fd, qd)]
+    a = Decimal(a)
+    g = [x + a * d for x, d in zip(fd, Dd)]
+    sf = _dec_S(g, W) - _dec_S(fd, W)
+    # dS(f + a D)/da = -sum D_i (ln(g_i / W_i) + 1), and sum D_i = 0
+    d1 = -sum(d * (gi / wi).ln() for d, gi, wi in zip(Dd, g, W))
+    return sf, d1, Dd, qd
+
+
+def test_elbm_l1_norm_stopping_rule():
+    """The stopping test of the root iteration, |S_f / S_f'| ||Delta|| < eps
+    (section 3, "Numerical method"), with either norm of Delta: the L1 norm
+    sum |Delta_i| or the entropic norm sqrt(sum Delta_i^2 / f*_i).
+
+    (i) eps = 1e-14, L1 norm: alpha is a lower estimate of the root within
+    2 eps / ||Delta||_1 (50-digit bisection), as for the entropic norm.
+    (ii) The test at the start alpha_0 = 2: with eps set to the geometric mean
+    of |S_f/S_f'|(2) ||Delta||_1 and |S_f/S_f'|(2) ||Delta||_ent (both from the
+    definition, in decimal), exactly one of the two norms stops at alpha_0,
+    and its result is alpha_0 followed by the sign check (alpha_0 when
+    S_f(2) >= 0, else the double-length Newton step 2 - 2 S_f / S_f'); the
+    other norm iterates on to the root.  A wrong norm (a missing absolute
+    value, a missing square root, a swapped option) changes which one stops."""
+    rng = np.random.default_rng(23)
+    checked = both = 0
+    for amp in (0.02, 0.1, 0.3):
+        f0 = rand_state(L2, 1, 6, 40 + int(amp * 100), amp=0.0, kind="entropic")
+        Mom = torch.stack([torch.ones(9, dtype=DT), L2.vx, L2.vy])
+        null = torch.linalg.svd(Mom).Vh[3:]
+        d = (null.T @ torch.tensor(rng.normal(size=(6, 6)))).reshape(9, 1, 6) * amp * 0.05
+        f = (f0 + d).reshape(9, -1)
+        assert bool((f > 0).all())
+        r, vx, vy = O.velocity(L2, f.view(9, 1, 6))
+        q = O.equilibrium(L2, r, vx, vy, "entropic").reshape(9, -1)
+        alpha, branch = O.elbm_alpha(f, q, norm="l1")
+        for s in range(6):
+            if int(branch[s]) != O.ELBM_ROOT:
+                continue
+            sf, d1, Dd, qd = _dec_sf_d1(f[:, s], 2)
+            n1 = sum(abs(x) for x in Dd)
+            ne = sum(x * x / y for x, y in zip(Dd, qd)).sqrt()
+            hi = min([float(f[i, s] / (q[i, s] - f[i, s])) * -1 for i in range(9)
+                      if q[i, s] < f[i, s]] or [10.0])
+            root, _ = _dec_root(f[:, s], 1.0 + 1e-12, hi)
+            a = float(alpha[s])
+            assert a <= root + 2e-15
+            assert root - a <= 2 * 1e-14 / float(n1) + 1e-13
+            checked += 1
+            # (ii): eps between the two norms' values of the test at alpha = 2
+            r0 = abs(sf / d1)
+            lo_n, hi_n = min(n1, ne), max(n1, ne)
+            if hi_n / lo_n < Decimal("1.02"):
+                continue
+            eps = float(r0 * (n1 * ne).sqrt())
+            stop_val = 2.0 if sf >= 0 else float(2 - 2 * sf / d1)
+            a1, _ = O.elbm_alpha(f[:, s:s + 1], q[:, s:s + 1], norm="l1", eps=eps)
+            ae, _ = O.elbm_alpha(f[:, s:s + 1], q[:, s:s + 1], norm="entropic", eps=eps)
+            stopped, iterated = (a1, ae) if n1 < ne else (ae, a1)
+            assert abs(float(stopped[0]) - stop_val) <= 1e-14
+            assert abs(float(iterated[0]) - root) < abs(stop_val - root)
+            both += 1
+    assert checked >= 10 and both >= 5
+
+
+def test_elbm_nonpositive_population_reading():
+    """Reading: a site with a population <= 0 has no entropy (ln of a
+    non-positive number), so no entropic root exists; it takes alpha = 1, the
+    Ehrenfest-rule value (section 3, rule 1), and the ELBM collision is then
+    f + beta (f* - f).  The branch is reported as non-positive."""
+    f = rand_state(L2, 1, 3, 90, amp=0.05, kind="entropic").reshape(9, -1).clone()
+    f[2, 0] = 0.0
+    f[5, 1] = -1e-3
+    r, vx, vy = O.velocity(L2, f.view(9, 1, 3))
+    q = O.equilibrium(L2, r, vx, vy, "entropic").reshape(9, -1)
+    a, b = O.elbm_alpha(f, q)
+    assert b.tolist()[:2] == [O.ELBM_NONPOS, O.ELBM_NONPOS] and int(b[2]) != O.ELBM_NONPOS
+    assert float(a[0]) == 1.0 and float(a[1]) == 1.0
+    om = 1.7
+    post, alpha, branch = O.elbm(f.view(9, 1, 3), q.view(9, 1, 3), om)
+    exp = f[:, :2] + (om / 2) * (q[:, :2] - f[:, :2])
+    assert torch.equal(post.reshape(9, -1)[:, :2], exp)
+
+
 def test_elbm_alpha_tends_to_two_and_cutoff():
     f0 = rand_state(L2, 1, 3, 40, amp=0.0, kind="entropic").reshape(9, -1)
     r, vx, vy = O.velocity(L2, f0.view(9, 1, 3))
@@ -565,6 +656,39 @@ def test_median_filter_brute_force(lat, ny, nx, bc):
     assert bool((dS2 <= dS + 1e-18).all())                # dissipative only
     for a, b in zip(O.moments(lat, out), O.moments(lat, f)):
         assert torch.allclose(a, b, atol=1e-15, rtol=0)
+
+
+def test_median_filter_zero_median_gradient():
+    """A lone non-equilibrium site among sites at exact equilibrium has a zero
+    median: the filter maps it onto f* (section 4, median entropy filter).
+    Reading for gradients: none flows through the zero median (its one-sided
+    derivative is infinite), so the filtered site's gradient is exactly that
+    of f*(p), the transposed Jacobian of the equilibrium."""
+    n = 5
+    rho, ux, uy = np.ones((n, n)), np.full((n, n), 0.03), np.full((n, n), -0.02)
+    f = O.init_equilibrium(L2, rho, ux, uy).clone()
+    for _ in range(8):          # a floating-point fixed point of f -> f*(m(f))
+        f = O.equilibrium(L2, *O.velocity(L2, f))
+    f[:, 2, 2] *= 1 + torch.tensor(np.random.default_rng(71).uniform(-0.2, 0.2, 9))
+    cfg = O.Config(nx=n, ny=n, bc="periodic", med_delta=1e-6)
+    g = f.clone().requires_grad_(True)
+    r, vx, vy = O.velocity(L2, g)
+    q = O.equilibrium(L2, r, vx, vy)
+    dS = O.kullback_dS(g, q)
+    assert int((dS == 0).sum()) == n * n - 1
+    out, acc = O.median_filter(L2, cfg, g, q, dS)
+    assert bool(acc[2, 2]) and int(acc.sum()) == 1
+    assert torch.allclose(out[:, 2, 2], q[:, 2, 2], atol=1e-16, rtol=0)
+    w = torch.tensor(np.random.default_rng(72).normal(size=9))
+    (out[:, 2, 2] * w).sum().backward()
+    p = f[:, 2, 2].clone().requires_grad_(True)
+    r1, vx1, vy1 = O.velocity(L2, p.view(9, 1, 1))
+    (O.equilibrium(L2, r1, vx1, vy1).view(9) * w).sum().backward()
+    assert bool(torch.isfinite(g.grad).all())
+    assert torch.allclose(g.grad[:, 2, 2], p.grad, atol=1e-14, rtol=0)
+    others = g.grad.clone()
+    others[:, 2, 2] = 0
+    assert float(others.abs().max()) == 0.0
 
 
 # ---------------------------------------------------------------- gradient
