@@ -287,6 +287,12 @@ class Simulation:
         off = (-self.workspace.data_ptr()) % 256
         self._ws = self.workspace[off:off + nbytes]
         self.ctx = lbm_init(cfg, self._ws)
+        # Identity of the rollout the context records: the generation changes
+        # with every call that resets the lattice or the relaxation field,
+        # and the step count grows with every step.  LBMRollout checks both
+        # before it runs the adjoint.
+        self.generation = 0
+        self.steps_taken = 0
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
@@ -296,9 +302,13 @@ class Simulation:
 
     def set_equilibrium(self, rho, ux, uy=None):
         lbm_set_equilibrium(self.ctx, rho, ux, uy)
+        self.generation += 1
+        self.steps_taken = 0
 
     def set_populations(self, f):
         lbm_set_populations(self.ctx, f)
+        self.generation += 1
+        self.steps_taken = 0
 
     def populations(self, dtype=torch.float64):
         f = torch.empty(self.shape, dtype=dtype, device=self.workspace.device)
@@ -307,9 +317,11 @@ class Simulation:
 
     def set_omega(self, omega):
         lbm_set_omega(self.ctx, omega)
+        self.generation += 1
 
     def step(self, n: int = 1):
         lbm_step(self.ctx, n)
+        self.steps_taken += int(n)
 
     def moments(self, dtype=torch.float64):
         dev = self.workspace.device
@@ -331,7 +343,9 @@ class Simulation:
         return lbm_counters(self.ctx)
 
     def profile_step(self, n: int):
-        return lbm_profile_step(self.ctx, n)
+        out = lbm_profile_step(self.ctx, n)
+        self.steps_taken += int(n)
+        return out
 
     def backward(self, dL_dfT, dL_df0, dL_domega=None):
         lbm_backward(self.ctx, dL_dfT, dL_df0, dL_domega)
@@ -351,6 +365,7 @@ class LBMRollout(torch.autograd.Function):
             sim.set_omega(omega.contiguous())
         sim.step(n)
         ctx.sim = sim
+        ctx.rollout = (sim.generation, sim.steps_taken)
         ctx.has_omega = omega is not None
         ctx.dtype = f0.dtype
         return sim.populations(f0.dtype)
@@ -358,6 +373,10 @@ class LBMRollout(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_fT):
         sim = ctx.sim
+        if (sim.generation, sim.steps_taken) != ctx.rollout:
+            raise RuntimeError("LBMRollout.backward: the Simulation was reset, given a new "
+                               "relaxation field or stepped after this rollout's forward "
+                               "pass, so the rollout it recorded is gone")
         g0 = torch.empty(sim.shape, dtype=ctx.dtype, device=grad_fT.device)
         gw = (torch.zeros((sim.cfg.ny, sim.cfg.nx), dtype=ctx.dtype, device=grad_fT.device)
               if ctx.has_omega else None)

@@ -49,6 +49,19 @@ CASES = {
                                  ehrenfest=True, ehr_k=4, ehr_delta=0.0, _amp=0.2),
     "d1q3_elbm_periodic": dict(lattice="D1Q3", nx=300, ny=1, bc="periodic", nu=1e-4,
                                collision="elbm", _amp=0.2),
+    # median entropy filter: the homothety's derivative through the site's
+    # own Delta S and its median neighbour's
+    "lbgk_median_periodic": dict(bc="periodic", nu=1e-3, median=True, med_delta=1e-5),
+    "lbgk_median_cavity": dict(bc="cavity", u_lid=0.1, nu=1e-3, median=True, med_delta=1e-5),
+    "mrt_median_field_cavity": dict(bc="cavity", u_lid=0.1, collision="mrt", s_e=1.64,
+                                    s_eps=1.54, s_q=1.9, median=True, med_delta=1e-5,
+                                    _field=True),
+    "elbm_median": dict(bc="periodic", nu=1e-3, collision="elbm", median=True, med_delta=1e-5),
+    "lbgk_median_ehrenfest_pos": dict(bc="periodic", omega=1.98, median=True, med_delta=1e-5,
+                                      ehrenfest=True, ehr_k=9, ehr_delta=0.0, positivity=True,
+                                      _amp=0.4),
+    "d1q3_median_bb": dict(lattice="D1Q3", nx=300, ny=1, bc="bounceback", nu=1e-3,
+                           median=True, med_delta=1e-5, _amp=0.1),
 }
 
 
@@ -139,13 +152,16 @@ def test_adjoint_fp64_matches_oracle_gradient(name):
         assert sum(int(i["positivity_mask"].sum()) for i in infos) > 0
     if name.startswith("elbm_far"):
         assert any(bool((i["branch"] == O.ELBM_NOROOT).any()) for i in infos)
+    if CASES[name].get("median"):
+        assert sum(int(i["median_mask"].sum()) for i in infos) > 0
     # the backward pass leaves the final state in place
     assert torch.equal(sim.populations().cpu(), fT)
 
 
 @pytest.mark.parametrize("name", ["lbgk_periodic", "mrt_m1_field_cavity",
                                   "lbgk_cavity_ehrenfest_pos", "elbm_periodic",
-                                  "elbm_far_positivity"])
+                                  "elbm_far_positivity", "lbgk_median_cavity",
+                                  "elbm_median"])
 def test_adjoint_fp32_storage(name):
     elbm = CASES[name].get("collision") == "elbm"
     _check_case(name, "f32", 4, 3, None, 1e-3 if elbm else 1e-4)
@@ -203,13 +219,6 @@ def test_adjoint_errors():
     with pytest.raises(B.LBMError) as e:
         sim.step(4)                               # longer than max_steps
     assert e.value.status == B.LBM_ESTATE
-    pm = {**p, "median": True, "checkpoint_every": 2, "max_steps": 3}
-    sim = make_sim(pm, "f64")
-    sim.set_populations(f0)
-    sim.step(1)
-    with pytest.raises(B.LBMError) as e:
-        sim.backward(f0, g)
-    assert e.value.status == B.LBM_EUNSUPPORTED
 
 
 def test_rollout_autograd_function():
@@ -228,6 +237,29 @@ def test_rollout_autograd_function():
     _, g0_o, gw_o, _ = _oracle_grad(p, f0, 4, field, w)
     assert _rel(f0d.grad.cpu(), g0_o) <= 1e-11
     assert _rel(omd.grad.cpu(), gw_o) <= 1e-11
+
+
+def test_rollout_backward_refuses_a_replaced_rollout():
+    """The Simulation records one rollout: once a second LBMRollout.apply (or
+    a further step) has replaced it, the first graph's backward raises
+    instead of returning gradients of another rollout."""
+    from paper_1110_0270_amd import lbm as B
+    p, amp, _ = _params("lbgk_periodic")
+    f0 = random_state(p, 3, amp=amp).to("cuda")
+    sim = make_sim({**p, "checkpoint_every": 2, "max_steps": 6}, "f64")
+    a = f0.clone().requires_grad_(True)
+    fa = B.LBMRollout.apply(a, None, sim, 3)
+    b = (1.01 * f0).requires_grad_(True)
+    fb = B.LBMRollout.apply(b, None, sim, 2)
+    with pytest.raises(RuntimeError, match="rollout"):
+        fa.sum().backward()
+    fb.sum().backward()                      # the current rollout still works
+    assert b.grad is not None and bool(torch.isfinite(b.grad).all())
+    c = f0.clone().requires_grad_(True)
+    fc = B.LBMRollout.apply(c, None, sim, 2)
+    sim.step(1)
+    with pytest.raises(RuntimeError, match="rollout"):
+        fc.sum().backward()
 
 
 def test_adjoint_full_size_directional_derivative():

@@ -244,14 +244,22 @@ def test_low_precision_one_step(storage, name):
     f_ora, infos = oracle_run(p, f_in, 1)
     lat = lattice(p)
     bound = storage_bound(f_ora, storage, lat)
-    excess = ((f_gpu - f_ora).abs() - bound).max()
+    mask = torch.ones(1, p["ny"], p["nx"], dtype=torch.bool)
     if p.get("ehrenfest"):
         sel_gpu = sim.selected()
         sel_ora = infos[0]["selected"].tolist()
+        eligible = int((infos[0]["dS"] > p["ehr_delta"]).sum())
+        assert len(sel_gpu) == len(sel_ora) == min(p["ehr_k"], eligible)
         assert near_tie_ok(sel_gpu, sel_ora, infos[0]["dS"], p["ehr_k"], 1e-5)
-        if sel_gpu != sel_ora:
-            return
-    worst = float(((f_gpu - f_ora).abs() / bound).max())
+        # a near-tie may move a site in or out of the set: compare every
+        # other site
+        moved = sorted(set(sel_gpu) ^ set(sel_ora))
+        if moved:
+            mask.view(-1)[torch.tensor(moved)] = False
+        assert int(mask.sum()) >= p["ny"] * p["nx"] - 4
+    err = (f_gpu - f_ora).abs() * mask
+    excess = (err - bound).max()
+    worst = float((err / bound).max())
     print(f"{name} {storage}: max error / bound = {worst:.3f}")
     assert float(excess) <= 0, f"error exceeds the stated bound by {float(excess):.3e}"
 
