@@ -177,15 +177,18 @@ lbm_status lbm_moments(lbm_ctx* ctx, void* rho, void* ux, void* uy, int dtype);
  * omega, its sum over sites is dL/d omega).  Gradients pass through the
  * limiters along the branch the forward pass took (a site the Ehrenfest
  * limiter sent to equilibrium through the Jacobian of f*; the positivity rule through
- * its coefficient and the component that set it), through the ELBM root by
+ * its coefficient and the component that set it; the median entropy filter
+ * (section 4) through its homothety coefficient sqrt(med / Delta S), i.e.
+ * through the site's own Delta S and that of the neighbour holding the
+ * median, with equal values ranked by neighbour order and no derivative
+ * through a zero median), through the ELBM root by
  * implicit differentiation of the entropy condition (section 3), and
  * through storage rounding as the identity.  The rollout is recomputed
  * from the checkpoints taken every cfg.checkpoint_every steps, with the
  * recorded Ehrenfest selections, so the recompute takes the forward pass's
  * branches bit for bit.  Work runs in the compute precision (FP64 for
  * LBM_F64 storage, FP32 otherwise).  The lattice is left in its final
- * state.  Errors: LBM_ESTATE without a recorded rollout; LBM_EUNSUPPORTED
- * for the median filter (its adjoint is not provided). */
+ * state.  Errors: LBM_ESTATE without a recorded rollout. */
 lbm_status lbm_backward(lbm_ctx* ctx, const void* dL_dfT, void* dL_df0,
                         void* dL_domega, int dtype);
 

@@ -29,7 +29,19 @@ struct AdjointLayout {
   bool store_alpha = false;  // ELBM: the recompute keeps alpha and branch per site
   size_t off_alpha = 0;      // K x [ny][pitch] alpha (compute precision)
   size_t off_branch = 0;     // K x [ny][pitch] branch bytes
+  bool median = false;       // median filter: per-site records of its adjoint
+  size_t off_med_gs = 0;     // [ny][pitch] dL/d Delta S through the site's own homothety
+  size_t off_med_h = 0;      // [ny][pitch] dL/d Delta S of the site's median neighbour
+  size_t off_med_am = 0;     // [ny][pitch] bytes: that neighbour's offset code (255: none)
   size_t end = 0;
+};
+
+// Per-site records of the median filter's adjoint (all nullptr when the
+// filter is off): see k_adjoint_med.
+struct MedianAdjoint {
+  void* gs = nullptr;
+  void* h = nullptr;
+  unsigned char* am = nullptr;
 };
 
 AdjointLayout adjoint_layout(const lbm_config* c, size_t lat_bytes, long long qs, long long k,
@@ -49,14 +61,15 @@ long long* adjoint_count_slot(const AdjointLayout& L, char* ws, long long t);
 // alpha/branch: the step's ELBM alpha and branch per site, from the
 // recompute (required for ELBM, ignored otherwise).  list/count/k: the
 // step's Ehrenfest sites when k <= kAdjListMax (read into LDS in place of
-// the mask; nullptr otherwise).  e0/e1: optional events recorded right
-// before and after the kernel.
+// the mask; nullptr otherwise).  med: the median filter's records (the
+// step then runs as two kernels).  e0/e1: optional events recorded right
+// before and after the kernel(s).
 constexpr long long kAdjListMax = 64;
 hipError_t launch_adjoint(int storage, int Q, int coll, const void* step_args, const void* lam_in,
                           void* lam_out, void* gom, const unsigned char* mask,
                           const void* alpha, const unsigned char* branch, const int32_t* list,
-                          const long long* count, long long k, hipStream_t s,
-                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+                          const long long* count, long long k, const MedianAdjoint& med,
+                          hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // f* written into step_args->dst at the first *count sites of list (<= k).
 hipError_t launch_tape_fix(int storage, int Q, const void* step_args, const int32_t* list,
                            const long long* count, long long k, hipStream_t s);

@@ -76,49 +76,37 @@ struct AdjArgs {
   const int32_t* list;
   const long long* count;
   long long k;
+  // Median filter ([ny][pitch] each, or nullptr): per site, the derivative
+  // of the loss with respect to its own Delta S through its homothety
+  // (med_gs), the derivative with respect to its median neighbour's Delta S
+  // (med_h), and which neighbour that is (med_am: offset code, 255 = none).
+  R* med_gs;
+  R* med_h;
+  unsigned char* med_am;
 };
 constexpr int kAdjListLds = (int)kAdjListMax;
 
+// The step's adjoint at one site: a = dL/dv for the state v that entered
+// the collision (the pulled state, after the median filter when it is on),
+// given lam = dL/d(the site's post-collision state), along the branch the
+// forward step took; gw receives dL/d omega(x).  d = f* - v.
 template <class S, int Q, int COLL>
-__global__ __launch_bounds__(256) void k_adjoint(const StepArgs<typename StoreT<S>::R> A,
-                                                 const AdjArgs<typename StoreT<S>::R> B) {
+__device__ __forceinline__ void adjoint_site(const StepArgs<typename StoreT<S>::R>& A,
+                                             const AdjArgs<typename StoreT<S>::R>& B, long long o,
+                                             bool ehr, const typename StoreT<S>::R v[Q],
+                                             const typename StoreT<S>::R feq[Q],
+                                             const typename StoreT<S>::R d[Q],
+                                             typename StoreT<S>::R ux, typename StoreT<S>::R uy,
+                                             typename StoreT<S>::R om,
+                                             const typename StoreT<S>::R lam[Q],
+                                             typename StoreT<S>::R a[Q],
+                                             typename StoreT<S>::R& gw) {
   using R = typename StoreT<S>::R;
   constexpr bool SH = StoreT<S>::shifted;
-  // Workgroups go round-robin to the 8 XCDs; each XCD takes pairs of
-  // adjacent 256-site segments, which share the lines that the pull and the
-  // push reach across their edge (the last, incomplete group of 16 keeps
-  // launch order).
-  const long long nb = gridDim.x, b = blockIdx.x;
-  const long long tb = (b / 16 * 16 + 16 <= nb) ? (b / 16) * 16 + (b % 8) * 2 + (b / 8) % 2 : b;
-  const long long s = tb * blockDim.x + threadIdx.x;
-  __shared__ int32_t lsel[kAdjListLds];
-  int nl = 0;
-  if (B.list) {
-    // the list's k slots (k <= kAdjListLds) are loaded with its count: one
-    // round trip
-    const long long c = *B.count;
-    const int32_t v = (long long)threadIdx.x < B.k ? B.list[threadIdx.x] : 0;
-    nl = (int)(c < B.k ? c : B.k);
-    if ((int)threadIdx.x < nl) lsel[threadIdx.x] = v;
-    __syncthreads();
-  }
-  if (s >= (long long)A.nx * A.ny) return;
-  bool ehr = B.mask && B.mask[s];
-  for (int j = 0; j < nl; ++j) ehr |= lsel[j] == (int32_t)s;
-  const int y = (int)(s / A.nx), x = (int)(s % A.nx);
-  R v[Q], feq[Q], d[Q], m0, ux, uy;
-  site_prep<S, Q>(A, x, y, v, feq, d, m0, ux, uy, false);
-  const long long o = (long long)y * A.pitch + x;
-  const R om = A.omega_field ? A.omega_field[o] : A.omega;
-  R lam[Q], mu[Q], lf[Q];
+  R mu[Q], lf[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    // the adjoint lattices, like the populations, are streamed once per
-    // step: nontemporal loads and stores
-    lam[i] = __builtin_nontemporal_load(&B.lam_in[(long long)i * A.qs + o]);
-    lf[i] = R(0);
-  }
-  R gw = R(0);
+  for (int i = 0; i < Q; ++i) lf[i] = R(0);
+  gw = R(0);
   if (ehr) {
     // Ehrenfest step: g' = f*(p)
 #pragma unroll
@@ -256,10 +244,20 @@ __global__ __launch_bounds__(256) void k_adjoint(const StepArgs<typename StoreT<
   }
   R tf[Q];
   feq_vjp<R, Q>(lf, ux, uy, A.eq_kind, tf);
-  // transpose of the pull: push mu_i to the population it was pulled from
+#pragma unroll
+  for (int i = 0; i < Q; ++i) a[i] = mu[i] + tf[i];
+}
+
+// Transpose of the pull: val_i, the derivative with respect to the
+// population that site (x, y) pulled in direction i, goes to that
+// population's slot of the adjoint lattice (add = true adds it to what is
+// there).  Every slot is reached from exactly one site.
+template <class R, int Q, bool ADD = false>
+__device__ __forceinline__ void push_adjoint(const StepArgs<R>& A, R* lam_out, int x, int y,
+                                             const R val[Q]) {
+  const long long o = (long long)y * A.pitch + x;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const R val = mu[i] + tf[i];
     int sx = x - vx_of<Q>(i), sy = y - vy_of<Q>(i);
     bool out;
     if (A.bc == BC_PERIODIC) {
@@ -272,10 +270,216 @@ __global__ __launch_bounds__(256) void k_adjoint(const StepArgs<typename StoreT<
     } else {
       out = (sx < 0) | (sx >= A.nx) | (sy < 0) | (sy >= A.ny);
     }
-    if (!out) __builtin_nontemporal_store(val, &B.lam_out[(long long)i * A.qs + (long long)sy * A.pitch + sx]);
-    else __builtin_nontemporal_store(val, &B.lam_out[(long long)(Q - 1 - i) * A.qs + o]);
+    R* dst = !out ? &lam_out[(long long)i * A.qs + (long long)sy * A.pitch + sx]
+                  : &lam_out[(long long)(Q - 1 - i) * A.qs + o];
+    if constexpr (ADD) *dst += val[i];
+    else __builtin_nontemporal_store(val[i], dst);
   }
+}
+
+// Reads a short Ehrenfest list into LDS (every thread of the workgroup
+// calls it) and returns its length; 0 without a list.
+template <class R>
+__device__ __forceinline__ int load_short_list(const AdjArgs<R>& B, int32_t* lsel) {
+  if (!B.list) return 0;
+  // the list's k slots (k <= kAdjListLds) are loaded with its count: one
+  // round trip
+  const long long c = *B.count;
+  const int32_t v = (long long)threadIdx.x < B.k ? B.list[threadIdx.x] : 0;
+  const int nl = (int)(c < B.k ? c : B.k);
+  if ((int)threadIdx.x < nl) lsel[threadIdx.x] = v;
+  __syncthreads();
+  return nl;
+}
+
+template <class S, int Q, int COLL>
+__global__ __launch_bounds__(256) void k_adjoint(const StepArgs<typename StoreT<S>::R> A,
+                                                 const AdjArgs<typename StoreT<S>::R> B) {
+  using R = typename StoreT<S>::R;
+  // Workgroups go round-robin to the 8 XCDs; each XCD takes pairs of
+  // adjacent 256-site segments, which share the lines that the pull and the
+  // push reach across their edge (the last, incomplete group of 16 keeps
+  // launch order).
+  const long long nb = gridDim.x, b = blockIdx.x;
+  const long long tb = (b / 16 * 16 + 16 <= nb) ? (b / 16) * 16 + (b % 8) * 2 + (b / 8) % 2 : b;
+  const long long s = tb * blockDim.x + threadIdx.x;
+  __shared__ int32_t lsel[kAdjListLds];
+  const int nl = load_short_list<R>(B, lsel);
+  if (s >= (long long)A.nx * A.ny) return;
+  bool ehr = B.mask && B.mask[s];
+  for (int j = 0; j < nl; ++j) ehr |= lsel[j] == (int32_t)s;
+  const int y = (int)(s / A.nx), x = (int)(s % A.nx);
+  R v[Q], feq[Q], d[Q], m0, ux, uy;
+  site_prep<S, Q>(A, x, y, v, feq, d, m0, ux, uy, false);
+  const long long o = (long long)y * A.pitch + x;
+  const R om = A.omega_field ? A.omega_field[o] : A.omega;
+  R lam[Q], a[Q], gw;
+#pragma unroll
+  for (int i = 0; i < Q; ++i)
+    // the adjoint lattices, like the populations, are streamed once per
+    // step: nontemporal loads and stores
+    lam[i] = __builtin_nontemporal_load(&B.lam_in[(long long)i * A.qs + o]);
+  adjoint_site<S, Q, COLL>(A, B, o, ehr, v, feq, d, ux, uy, om, lam, a, gw);
+  push_adjoint<R, Q>(A, B.lam_out, x, y, a);
   if (B.gom) __builtin_nontemporal_store(__builtin_nontemporal_load(&B.gom[o]) + gw, &B.gom[o]);
+}
+
+// Adjoint of a step with the median entropy filter (section 4), first part.
+// The forward step replaced the pulled state p of a site by
+//   p~ = f* + c (p - f*),  c = sqrt(med / Delta S)
+// where the site was accepted (Delta S > delta and med < Delta S; med the
+// median Delta S of its neighbourhood), and collided p~; f* is the same for
+// p and p~ (same moments).  With a = dL/dp~ from the collision's adjoint:
+//   dL/dp = c a + (df*/dp)^T ((1 - c) a)          (through p and f*)
+//         + dL/dc dc/d Delta S(x) grad Delta S(x)  (through the site's own Delta S)
+// and dL/dc dc/dmed flows to the median neighbour y's Delta S.  Each
+// workgroup recomputes Delta S of its tile and a one-site halo in LDS (as
+// the forward kernel does), finds the median and which neighbour holds it
+// (stable ranks: among equal values the lowest offset code, -1..1 in y then
+// x), pushes the first line into the adjoint lattice and records, per site,
+// the two Delta S derivatives and the median neighbour's code for
+// k_median_gather.  dL/dc = sum_i a_i (p_i - f*_i); dc/dDelta S = -c /
+// (2 Delta S); dc/dmed = c / (2 med), taken as 0 where med = 0 (the site
+// was mapped onto f*; the one-sided derivative is infinite).
+template <class S, int Q, int COLL, int TX, int TY>
+__global__ __launch_bounds__(256) void k_adjoint_med(const StepArgs<typename StoreT<S>::R> A,
+                                                     const AdjArgs<typename StoreT<S>::R> B) {
+  using R = typename StoreT<S>::R;
+  static_assert(TX * TY == 256, "tile must hold 256 sites");
+  const int t = blockIdx.x;
+  const int tile_x = t % A.tiles_x, tile_y = t / A.tiles_x;
+  const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+  const int x = tile_x * TX + lx, y = tile_y * TY + ly;
+  const bool valid = x < A.nx && y < A.ny;
+  __shared__ int32_t lsel[kAdjListLds];
+  const int nl = load_short_list<R>(B, lsel);
+  R v[Q], feq[Q], d[Q], m0 = R(0), ux = R(0), uy = R(0), dS = R(0);
+  if (valid) dS = site_prep<S, Q>(A, x, y, v, feq, d, m0, ux, uy, true);
+  constexpr int HY = (Q == 9) ? 1 : 0;
+  constexpr int SW = TX + 2, SH_ = TY + 2 * HY;
+  __shared__ R sdS[SH_ * SW];
+  sdS[(ly + HY) * SW + lx + 1] = valid ? dS : slot_dS<S, Q>(A, x, y);
+  constexpr int NHALO = SH_ * SW - TX * TY;
+  for (int s = threadIdx.x; s < NHALO; s += 256) {
+    int hx, hy;
+    if constexpr (HY == 1) {
+      if (s < SW) { hx = s; hy = 0; }
+      else if (s < 2 * SW) { hx = s - SW; hy = SH_ - 1; }
+      else { const int r = s - 2 * SW; hy = 1 + r / 2; hx = (r & 1) ? SW - 1 : 0; }
+    } else {
+      hy = 0;
+      hx = (s == 0) ? 0 : SW - 1;
+    }
+    sdS[hy * SW + hx] = slot_dS<S, Q>(A, tile_x * TX + hx - 1, tile_y * TY + hy - HY);
+  }
+  __syncthreads();
+  if (!valid) return;
+  constexpr int NN = (Q == 9) ? 9 : 3;
+  R nb[NN];
+  int n = 0;
+#pragma unroll
+  for (int k = 0; k < NN; ++k) {
+    const int dy = (Q == 9) ? k / 3 - 1 : 0, dx = (Q == 9) ? k % 3 - 1 : k - 1;
+    const R val = sdS[(ly + HY + dy) * SW + lx + 1 + dx];
+    const bool in = !(val != val);
+    n += in ? 1 : 0;
+    nb[k] = in ? val : r_inf<R>();
+  }
+  // the median (the ceil(n/2)-th smallest) and the neighbour that holds it
+  const int rank = (n + 1) / 2 - 1;
+  int am = -1;
+  R med = r_inf<R>();
+#pragma unroll
+  for (int k = 0; k < NN; ++k) {
+    int r = 0;
+#pragma unroll
+    for (int j = 0; j < NN; ++j) r += (nb[j] < nb[k] || (j < k && nb[j] == nb[k])) ? 1 : 0;
+    if (r == rank) { am = k; med = nb[k]; }
+  }
+  const bool acc = (dS > A.med_delta) & (med < dS) & (dS < r_inf<R>());
+  const R c = acc ? sqrt(med / dS) : R(1);
+  // the filtered state, as the forward step formed it
+  R vt[Q], dt[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    vt[i] = acc ? feq[i] + c * (v[i] - feq[i]) : v[i];
+    dt[i] = feq[i] - vt[i];
+  }
+  const long long s = (long long)y * A.nx + x;
+  bool ehr = B.mask && B.mask[s];
+  for (int j = 0; j < nl; ++j) ehr |= lsel[j] == (int32_t)s;
+  const long long o = (long long)y * A.pitch + x;
+  const R om = A.omega_field ? A.omega_field[o] : A.omega;
+  R lam[Q], a[Q], gw;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) lam[i] = B.lam_in[(long long)i * A.qs + o];
+  adjoint_site<S, Q, COLL>(A, B, o, ehr, vt, feq, dt, ux, uy, om, lam, a, gw);
+  R gs = R(0), h = R(0);
+  if (acc) {
+    R sc = R(0), ra[Q], tf[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      sc -= a[i] * d[i];                  // dL/dc = sum a_i (p_i - f*_i)
+      ra[i] = (R(1) - c) * a[i];
+    }
+    feq_vjp<R, Q>(ra, ux, uy, A.eq_kind, tf);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) a[i] = c * a[i] + tf[i];
+    gs = -sc * c / (R(2) * dS);
+    h = med > R(0) ? sc * c / (R(2) * med) : R(0);
+  }
+  push_adjoint<R, Q>(A, B.lam_out, x, y, a);
+  B.med_gs[o] = gs;
+  B.med_h[o] = h;
+  B.med_am[o] = (acc && h != R(0)) ? (unsigned char)am : (unsigned char)255;
+  if (B.gom) B.gom[o] += gw;
+}
+
+// Second part: site y collects G = dL/dDelta S(y), its own term plus the
+// terms of the neighbours whose median it held, and adds G grad_p Delta S(y)
+// to the adjoint slots that its pulled populations came from.  With
+// Delta S = sum_i p_i ln(p_i / f*_i) and f* a function of the moments of p:
+//   grad_p Delta S = ln(p / f*) + (df*/dp)^T ((f* - p) / f*)
+// (the 1 from differentiating p ln p cancels against sum_j df*_j/dp =
+// d rho / dp = 1).  For the entropic equilibrium the second term vanishes:
+// ln f* is affine in the velocity and f*, p share their moments.
+template <class S, int Q>
+__global__ __launch_bounds__(256) void k_median_gather(const StepArgs<typename StoreT<S>::R> A,
+                                                       const AdjArgs<typename StoreT<S>::R> B) {
+  using R = typename StoreT<S>::R;
+  constexpr bool SH = StoreT<S>::shifted;
+  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= (long long)A.nx * A.ny) return;
+  const int y = (int)(s / A.nx), x = (int)(s % A.nx);
+  const long long o = (long long)y * A.pitch + x;
+  R G = B.med_gs[o];
+  constexpr int NN = (Q == 9) ? 9 : 3;
+  const bool wrap_x = A.bc == BC_PERIODIC || A.bc == BC_COUETTE;
+  const bool wrap_y = A.bc == BC_PERIODIC;
+#pragma unroll
+  for (int k = 0; k < NN; ++k) {
+    const int dy = (Q == 9) ? k / 3 - 1 : 0, dx = (Q == 9) ? k % 3 - 1 : k - 1;
+    int gx = x + dx, gy = y + dy;
+    if (wrap_x) gx = gx < 0 ? gx + A.nx : (gx >= A.nx ? gx - A.nx : gx);
+    if (wrap_y) gy = gy < 0 ? gy + A.ny : (gy >= A.ny ? gy - A.ny : gy);
+    if (gx < 0 || gx >= A.nx || gy < 0 || gy >= A.ny) continue;
+    const long long on = (long long)gy * A.pitch + gx;
+    // neighbour (gx, gy) = (x, y) + e had its median at offset -e
+    if (B.med_am[on] == (unsigned char)(NN - 1 - k)) G += B.med_h[on];
+  }
+  if (G == R(0)) return;
+  R v[Q], feq[Q], d[Q], m0, ux, uy;
+  site_prep<S, Q>(A, x, y, v, feq, d, m0, ux, uy, false);
+  R r[Q], tf[Q], g[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const R sh = SH ? wt<R, Q>(i) * A.rho0 : R(0);
+    r[i] = d[i] / (feq[i] + sh);           // (f* - p) / f*
+  }
+  feq_vjp<R, Q>(r, ux, uy, A.eq_kind, tf);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) g[i] = G * (lg1p<R>(-r[i]) + tf[i]);
+  push_adjoint<R, Q, true>(A, B.lam_out, x, y, g);
 }
 
 // Recompute of an Ehrenfest step from its tape: f* at the listed sites,
@@ -349,6 +553,21 @@ template <class S, int Q, int COLL>
 static void launch_adj_k(const StepArgs<typename StoreT<S>::R>& A,
                          const AdjArgs<typename StoreT<S>::R>& B, int g, hipStream_t s,
                          hipEvent_t e0, hipEvent_t e1) {
+  if (B.med_am) {
+    // median filter: the 64 x 4 (D1Q3: 256 x 1) tiles of the forward median
+    // kernel, then the gather; the events bracket both
+    constexpr int TX = Q == 9 ? 64 : 256, TY = 256 / TX;
+    const dim3 gt(A.tiles_x * A.tiles_y);
+    const int gs = (int)(((long long)A.nx * A.ny + 255) / 256);
+    if (e0 || e1) {
+      hipExtLaunchKernelGGL((k_adjoint_med<S, Q, COLL, TX, TY>), gt, dim3(256), 0, s, e0, nullptr, 0, A, B);
+      hipExtLaunchKernelGGL((k_median_gather<S, Q>), dim3(gs), dim3(256), 0, s, nullptr, e1, 0, A, B);
+    } else {
+      hipLaunchKernelGGL((k_adjoint_med<S, Q, COLL, TX, TY>), gt, dim3(256), 0, s, A, B);
+      hipLaunchKernelGGL((k_median_gather<S, Q>), dim3(gs), dim3(256), 0, s, A, B);
+    }
+    return;
+  }
   if (e0 || e1)
     hipExtLaunchKernelGGL((k_adjoint<S, Q, COLL>), dim3(g), dim3(256), 0, s, e0, e1, 0, A, B);
   else
@@ -379,17 +598,20 @@ static hipError_t launch_adj_s(int Q, int coll, const void* sargs, const void* a
 hipError_t launch_adjoint(int storage, int Q, int coll, const void* step_args, const void* lam_in,
                           void* lam_out, void* gom, const unsigned char* mask,
                           const void* alpha, const unsigned char* branch, const int32_t* list,
-                          const long long* count, long long k, hipStream_t s, hipEvent_t e0,
-                          hipEvent_t e1) {
+                          const long long* count, long long k, const MedianAdjoint& med,
+                          hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (coll == COLL_ELBM && (!alpha || !branch)) return hipErrorInvalidValue;
   if (list && (!count || k > kAdjListLds)) return hipErrorInvalidValue;
+  if (med.am && (!med.gs || !med.h)) return hipErrorInvalidValue;
   if (storage == 0) {
     AdjArgs<double> B{(const double*)lam_in, (double*)lam_out, (double*)gom, mask,
-                      (const double*)alpha, branch, list, count, k};
+                      (const double*)alpha, branch, list, count, k,
+                      (double*)med.gs, (double*)med.h, med.am};
     return launch_adj_s<double>(Q, coll, step_args, &B, s, e0, e1);
   }
   AdjArgs<float> B{(const float*)lam_in, (float*)lam_out, (float*)gom, mask,
-                   (const float*)alpha, branch, list, count, k};
+                   (const float*)alpha, branch, list, count, k,
+                   (float*)med.gs, (float*)med.h, med.am};
   if (storage == 1) return launch_adj_s<float>(Q, coll, step_args, &B, s, e0, e1);
   if (storage == 2) return launch_adj_s<_Float16>(Q, coll, step_args, &B, s, e0, e1);
   return launch_adj_s<bf16_t>(Q, coll, step_args, &B, s, e0, e1);

@@ -31,6 +31,12 @@ AdjointLayout adjoint_layout(const lbm_config* c, size_t lat_bytes, long long qs
     L.off_alpha = take((size_t)L.K * a256((size_t)qs * rb));
     L.off_branch = take((size_t)L.K * a256((size_t)qs));
   }
+  L.median = (c->limiters & LBM_LIM_MEDIAN) != 0;
+  if (L.median) {
+    L.off_med_gs = take((size_t)qs * rb);
+    L.off_med_h = take((size_t)qs * rb);
+    L.off_med_am = take((size_t)qs);
+  }
   L.off_lam[0] = take(L.lam_bytes);
   L.off_lam[1] = take(L.lam_bytes);
   L.off_gom = take((size_t)qs * rb);

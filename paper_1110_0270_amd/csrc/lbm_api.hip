@@ -704,19 +704,24 @@ static lbm_status backward_impl(lbm_ctx* c, const void* dL_dfT, void* dL_df0, vo
   if (dtype != LBM_F64 && dtype != LBM_F32) return fail(LBM_EINVAL, "dtype must be LBM_F64 or LBM_F32");
   if (c->cfg.checkpoint_every <= 0 || !c->recorded)
     return fail(LBM_ESTATE, "no recorded rollout (set checkpoint_every > 0 and call lbm_set_* first)");
-  if (c->cfg.limiters & LBM_LIM_MEDIAN)
-    return fail(LBM_EUNSUPPORTED, "the adjoint of the median filter is not implemented");
   const AdjointLayout& A = c->L.adj;
   const long long T = c->steps;
   const int Q = c->L.Q, nx = c->cfg.nx, ny = c->cfg.ny, pitch = c->L.pitch;
   const long long qs = c->L.qs;
   const bool r64 = c->f64();
+  const bool med = (c->cfg.limiters & LBM_LIM_MEDIAN) != 0;
   const int din = dtype == LBM_F64;
   hipStream_t st = c->stream;
   char* ws = c->ws;
   void* lam[2] = {ws + A.off_lam[0], ws + A.off_lam[1]};
   void* gom = ws + A.off_gom;
   unsigned char* mask = A.k > 0 ? (unsigned char*)(ws + A.off_mask) : nullptr;
+  MedianAdjoint mad;
+  if (A.median) {
+    mad.gs = ws + A.off_med_gs;
+    mad.h = ws + A.off_med_h;
+    mad.am = (unsigned char*)(ws + A.off_med_am);
+  }
   auto seg = [&](long long j) { return (void*)(ws + A.off_seg + (size_t)j * align256(c->L.lat_bytes)); };
   auto ckpt = [&](long long s) { return (const void*)(ws + A.off_ckpt + (size_t)s * align256(c->L.lat_bytes)); };
   // Step arguments of the recompute: no selection, no counters.
@@ -755,7 +760,7 @@ static lbm_status backward_impl(lbm_ctx* c, const void* dL_dfT, void* dL_df0, vo
       const bool last = t + 1 == t1;
       const void* args = args_for(seg(t - t0), last ? seg(A.K) : seg(t + 1 - t0),
                                   alpha_slot(t - t0), branch_slot(t - t0));
-      e = launch_step(c->cfg.storage, Q, c->cfg.collision, false, args, st);
+      e = launch_step(c->cfg.storage, Q, c->cfg.collision, med, args, st);
       if (e == hipSuccess && A.k > 0 && !last)
         e = launch_tape_fix(c->cfg.storage, Q, args, adjoint_selected_slot(A, ws, t, nullptr),
                             adjoint_count_slot(A, ws, t), A.k, st);
@@ -772,7 +777,7 @@ static lbm_status backward_impl(lbm_ctx* c, const void* dL_dfT, void* dL_df0, vo
         e = launch_adjoint(c->cfg.storage, Q, c->cfg.collision, args, lam[cur], lam[1 - cur],
                            dL_domega ? gom : nullptr, short_list ? nullptr : mask,
                            alpha_slot(t - t0), branch_slot(t - t0),
-                           short_list ? list : nullptr, cnt, A.k, st,
+                           short_list ? list : nullptr, cnt, A.k, mad, st,
                            ev ? (*ev)[2 * t] : nullptr, ev ? (*ev)[2 * t + 1] : nullptr);
       if (e == hipSuccess && mask && !short_list) e = launch_mark(mask, list, cnt, A.k, 0, st);
       cur = 1 - cur;
