@@ -212,7 +212,8 @@ _H_SERIES = [((-1.0) ** n) / (n * (n - 1)) for n in range(2, 17)]
 
 
 def h_fn(x: torch.Tensor) -> torch.Tensor:
-    """h(x) = (1 + x) ln(1 + x) - x for x >= -1, with h(-1) = 1 (0 ln 0 = 0).
+    """h(x) = (1 + x) ln(1 + x) - x for x >= -1, with h(-1) = 1 (0 ln 0 = 0;
+    autograd takes h constant there, i.e. no derivative at a zero population).
 
     For |x| < 0.1 the Taylor series sum_{n>=2} (-1)^n x^n / (n (n-1)) is
     summed to n = 16 (truncation below 1e-16 relative), avoiding the

@@ -442,7 +442,9 @@ __global__ __launch_bounds__(256) void k_adjoint_med(const StepArgs<typename Sto
 //   grad_p Delta S = ln(p / f*) + (df*/dp)^T ((f* - p) / f*)
 // (the 1 from differentiating p ln p cancels against sum_j df*_j/dp =
 // d rho / dp = 1).  For the entropic equilibrium the second term vanishes:
-// ln f* is affine in the velocity and f*, p share their moments.
+// ln f* is affine in the velocity and f*, p share their moments.  A
+// population at 0 (left there by the positivity rule) contributes 0 ln 0 =
+// 0 to Delta S with no derivative (the one-sided one is infinite).
 template <class S, int Q>
 __global__ __launch_bounds__(256) void k_median_gather(const StepArgs<typename StoreT<S>::R> A,
                                                        const AdjArgs<typename StoreT<S>::R> B) {
@@ -478,7 +480,7 @@ __global__ __launch_bounds__(256) void k_median_gather(const StepArgs<typename S
   }
   feq_vjp<R, Q>(r, ux, uy, A.eq_kind, tf);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) g[i] = G * (lg1p<R>(-r[i]) + tf[i]);
+  for (int i = 0; i < Q; ++i) g[i] = G * ((r[i] < R(1) ? lg1p<R>(-r[i]) : R(0)) + tf[i]);
   push_adjoint<R, Q, true>(A, B.lam_out, x, y, g);
 }
 
