@@ -36,7 +36,7 @@ DT = torch.float64
 __all__ = [
     "Lattice", "Config", "relaxation_rate", "phi_poly", "phi_entropic",
     "equilibrium", "moments", "velocity", "stream", "entropy", "h_fn",
-    "kullback_dS", "lbgk", "mrt_basis", "mrt_rates", "mrt", "elbm_alpha",
+    "kullback_dS", "lbgk", "mrt_basis", "mrt_rates", "mrt_preset_rates", "mrt", "elbm_alpha",
     "elbm", "positivity", "median_filter", "ehrenfest_select", "step", "run",
     "stats", "init_equilibrium", "ELBM_ROOT", "ELBM_CUTOFF", "ELBM_NOROOT",
     "ELBM_NONPOS",
@@ -90,7 +90,14 @@ class Config:
     s_e: float = 1.64
     s_eps: float = 1.54
     s_q: float = 1.9
+    # M1 rate presets of sections 5, 7 and 8: given (s_e, s_eps, s_q as set) |
+    # trt | mrt_trtq | mrt1 | shear
+    mrt_preset: str = "given"
     ehrenfest: bool = False
+    # what the selected sites receive: "equilibrium" (Ehrenfests' step) or
+    # "mrt" (the MRT collision with mrt_basis and its rates: the MRT limiter
+    # of section 5, on an LBGK lattice)
+    sel_action: str = "equilibrium"
     ehr_k: int = 0
     ehr_delta: float = 0.0
     median: bool = False
@@ -290,6 +297,32 @@ def mrt_rates(kind: str, s_e: float, s_eps: float, s_q: float, s_nu):
     else:
         c = [one, one, one, one, s_nu, s_nu, one, one, one]
     return torch.stack(c)
+
+
+def mrt_preset_rates(preset: str, s_nu, s_e: float = 1.64, s_eps: float = 1.54,
+                     s_q: float = 1.9):
+    """(s_e, s_eps, s_q) of the M1 (C1) rate presets, as functions of the
+    shear rate s_nu (a number or a per-site tensor):
+      trt      s_e = s_eps = s_nu, s_q = 8 (2 - s_nu) / (8 - s_nu)  (section 5,
+               TRT; Reading: the printed "8(2=s_nu)" is 8(2 - s_nu))
+      mrt_trtq s_e = 1.64, s_eps = 1.54, s_q as for trt (section 8, the
+               cavity study's MRT with the TRT third-order rate)
+      mrt1     s_e = 1.64, s_eps = 1.54, s_q = 1.9 (section 8, MRT1)
+      shear    s_e = 1.64, s_eps = 1.54, s_q = 3 (2 - s_nu) / (3 - s_nu)
+               (section 7, the shear-wave MRT)
+      given    the rates as configured."""
+    s_nu = torch.as_tensor(s_nu, dtype=DT)
+    if preset == "given":
+        return s_e, s_eps, s_q
+    if preset == "trt":
+        return s_nu, s_nu, 8.0 * (2.0 - s_nu) / (8.0 - s_nu)
+    if preset == "mrt_trtq":
+        return 1.64, 1.54, 8.0 * (2.0 - s_nu) / (8.0 - s_nu)
+    if preset == "mrt1":
+        return 1.64, 1.54, 1.9
+    if preset == "shear":
+        return 1.64, 1.54, 3.0 * (2.0 - s_nu) / (3.0 - s_nu)
+    raise ValueError(preset)
 
 
 def mrt(f, feq, M, rates):
@@ -526,11 +559,15 @@ def step(lat: Lattice, cfg: Config, g: torch.Tensor,
     if cfg.ehrenfest:
         sel = ehrenfest_select(dS.detach().flatten(), cfg.ehr_k, cfg.ehr_delta)
         info["selected"] = sel
+    def mrt_collision():
+        se, seps, sq = mrt_preset_rates(cfg.mrt_preset, omega, cfg.s_e, cfg.s_eps, cfg.s_q)
+        rates = mrt_rates(cfg.mrt_basis, se, seps, sq, omega)
+        return mrt(pre, feq, mrt_basis(cfg.mrt_basis), rates)
+
     if cfg.collision == "lbgk":
         post = lbgk(pre, feq, omega)
     elif cfg.collision == "mrt":
-        M = mrt_basis(cfg.mrt_basis)
-        post = mrt(pre, feq, M, mrt_rates(cfg.mrt_basis, cfg.s_e, cfg.s_eps, cfg.s_q, omega))
+        post = mrt_collision()
     elif cfg.collision == "elbm":
         post, alpha, branch = elbm(pre, feq, omega, eps=cfg.elbm_eps,
                                    max_iter=cfg.elbm_max_iter, dS_cut=cfg.elbm_dS_cut,
@@ -547,10 +584,17 @@ def step(lat: Lattice, cfg: Config, g: torch.Tensor,
     if sel is not None and sel.numel() > 0:
         selmask[sel] = True
         selmask_q = selmask.view(1, *rho.shape)
-        post = torch.where(selmask_q, feq, post)
+        if cfg.sel_action == "mrt":
+            # the MRT limiter: the MRT collision replaces LBGK's at the
+            # selected sites (section 5)
+            post = torch.where(selmask_q, mrt_collision(), post)
+        else:
+            post = torch.where(selmask_q, feq, post)
     if cfg.positivity:
         lim, act = positivity(post, feq)
-        act = act & ~selmask.view(rho.shape)
+        if cfg.sel_action != "mrt":
+            # f* needs no positivity rule
+            act = act & ~selmask.view(rho.shape)
         post = torch.where(act.unsqueeze(0), lim, post)
         info["positivity_mask"] = act
     return post, info

@@ -224,18 +224,80 @@ def shear_decay_rate(cfg, n=64):
     return -math.log(amp(g) / a1) / (T - T // 4)
 
 
-@pytest.mark.parametrize("collision,basis", [("lbgk", "M1"), ("mrt", "M1"), ("mrt", "M2")])
-def test_shear_wave_viscosity(collision, basis):
+@pytest.mark.parametrize("collision,basis,preset", [("lbgk", "M1", "given"), ("mrt", "M1", "given"),
+                                                    ("mrt", "M2", "given"), ("mrt", "M1", "trt"),
+                                                    ("mrt", "M1", "shear")])
+def test_shear_wave_viscosity(collision, basis, preset):
     """Section 7: the shear wave decays as exp(-nu k^2 t) with
     nu = c_s^2 (1/omega - 1/2), k = 2 pi / n; MRT produces the same shear
-    viscosity as BGK.  The lattice error is O(k^2): 0.3 % at n = 32,
+    viscosity as BGK, whatever its other rates (the TRT and shear-wave
+    presets included).  The lattice error is O(k^2): 0.3 % at n = 32,
     0.08 % at n = 64."""
     n, nu = 64, 0.02
     cfg = O.Config(nx=n, ny=n, bc="periodic", nu=nu, collision=collision,
-                   mrt_basis=basis, s_e=1.64, s_eps=1.54, s_q=1.9)
+                   mrt_basis=basis, s_e=1.64, s_eps=1.54, s_q=1.9, mrt_preset=preset)
     rate = shear_decay_rate(cfg, n)
     k = 2 * math.pi / n
     assert abs(rate / (nu * k * k) - 1) < 2e-3
+
+
+def test_mrt_presets():
+    """The M1 rate presets.  TRT (section 5) sets s_e = s_eps = s_nu and its
+    third-order rate so that the product of the two relaxation parameters
+    Lambda = (1/s_nu - 1/2)(1/s_q - 1/2) is the constant 3/16 for every
+    s_nu; the shear-wave MRT of section 7 has Lambda = 1/12; the cavity
+    study's MRT takes the TRT third-order rate with s_e = 1.64,
+    s_eps = 1.54; MRT1 (section 8) is s_q = 1.9, s_e = 1.64, s_eps = 1.54.
+    Per-site shear rates give per-site presets."""
+    s_nu = torch.tensor([0.5, 1.0, 1.5, 1.9, 1.99], dtype=DT)
+    lam = lambda sq: (1 / s_nu - 0.5) * (1 / sq - 0.5)  # noqa: E731
+    se, seps, sq = O.mrt_preset_rates("trt", s_nu)
+    assert torch.equal(se, s_nu) and torch.equal(seps, s_nu)
+    assert torch.allclose(lam(sq), torch.full_like(s_nu, 3 / 16), rtol=1e-12, atol=0)
+    se, seps, sq = O.mrt_preset_rates("shear", s_nu)
+    assert (se, seps) == (1.64, 1.54)
+    assert torch.allclose(lam(sq), torch.full_like(s_nu, 1 / 12), rtol=1e-12, atol=0)
+    se, seps, sq2 = O.mrt_preset_rates("mrt_trtq", s_nu)
+    assert (se, seps) == (1.64, 1.54) and torch.equal(sq2, O.mrt_preset_rates("trt", s_nu)[2])
+    assert O.mrt_preset_rates("mrt1", s_nu) == (1.64, 1.54, 1.9)
+    assert O.mrt_preset_rates("given", s_nu, 1.1, 1.2, 1.3) == (1.1, 1.2, 1.3)
+    # a TRT step relaxes e and epsilon at the shear rate: the energy-like
+    # nonequilibrium moments decay exactly like the shear ones
+    f = rand_state(L2, 2, 3, 95, amp=0.1)
+    r, vx, vy = O.velocity(L2, f)
+    q = O.equilibrium(L2, r, vx, vy)
+    M = O.mrt_basis("M1")
+    cfg = O.Config(nx=3, ny=2, bc="periodic", omega=1.3, collision="mrt", mrt_preset="trt")
+    post = O.mrt(f, q, M, O.mrt_rates("M1", *O.mrt_preset_rates("trt", 1.3), 1.3))
+    dm_in = (M @ (f - q).reshape(9, -1))
+    dm_out = (M @ (post - q).reshape(9, -1))
+    for row in (1, 2, 7, 8):
+        assert torch.allclose(dm_out[row], (1 - 1.3) * dm_in[row], atol=1e-15, rtol=0)
+    a, _ = O.step(L2, cfg, f)
+    assert a.shape == f.shape
+
+
+def test_mrt_limiter():
+    """The MRT limiter of section 5 on an LBGK lattice: the k sites of
+    largest Delta S > delta receive the MRT collision (M2/C2: every mode but
+    shear sent to equilibrium) instead of LBGK's; all other sites are LBGK.
+    With k >= N and delta = 0 the step is the MRT step at every site; with a
+    small k exactly the brute-force top-k sites differ from LBGK; moments
+    are conserved."""
+    g = rand_state(L2, 5, 6, 96, amp=0.1)
+    base = dict(nx=6, ny=5, bc="periodic", nu=1e-3, ehrenfest=True, ehr_delta=0.0,
+                sel_action="mrt", mrt_basis="M2")
+    a, _ = O.step(L2, O.Config(**base, ehr_k=30), g)
+    b, _ = O.step(L2, O.Config(**{**base, "ehrenfest": False}, collision="mrt"), g)
+    assert torch.allclose(a, b, atol=1e-16, rtol=0)
+    c, info = O.step(L2, O.Config(**base, ehr_k=4), g)
+    d, _ = O.step(L2, O.Config(**{**base, "ehrenfest": False}), g)
+    diff = ((c - d).abs().amax(0) > 0).flatten().nonzero().flatten().tolist()
+    dS = info["dS"].flatten()
+    top = sorted(range(30), key=lambda i: (-float(dS[i]), i))[:4]
+    assert diff == sorted(top) == info["selected"].tolist()
+    for m_c, m_g in zip(O.moments(L2, c), O.moments(L2, O.stream(L2, g, "periodic"))):
+        assert torch.allclose(m_c, m_g, atol=1e-15, rtol=0)
 
 
 # ---------------------------------------------------------------- MRT
