@@ -69,6 +69,24 @@ enum { LBM_BC_PERIODIC = 0, LBM_BC_BOUNCEBACK = 1, LBM_BC_CAVITY = 2, LBM_BC_COU
 enum { LBM_LBGK = 0, LBM_MRT = 1, LBM_ELBM = 2 };
 enum { LBM_EQ_POLY = 0, LBM_EQ_ENTROPIC = 1 };
 enum { LBM_MRT_M1 = 0, LBM_MRT_M2 = 1 };
+/* Rate presets of the M1 basis (section 5 TRT; section 7 shear-wave MRT;
+ * section 8 cavity study), functions of the shear rate s_nu = omega (per
+ * site with an omega field):
+ *   GIVEN    s_e, s_eps, s_q as configured;
+ *   TRT      s_e = s_eps = s_nu, s_q = 8 (2 - s_nu) / (8 - s_nu) (the printed
+ *            "8(2=s_nu)" read as 8(2 - s_nu));
+ *   MRT_TRTQ s_e = 1.64, s_eps = 1.54, s_q as for TRT;
+ *   MRT1     s_e = 1.64, s_eps = 1.54, s_q = 1.9;
+ *   SHEAR    s_e = 1.64, s_eps = 1.54, s_q = 3 (2 - s_nu) / (3 - s_nu). */
+enum { LBM_RATES_GIVEN = 0, LBM_RATES_TRT = 1, LBM_RATES_MRT_TRTQ = 2, LBM_RATES_MRT1 = 3,
+       LBM_RATES_SHEAR = 4 };
+/* What the Ehrenfest selection (the k sites of largest Delta S > delta)
+ * does to its sites: EQUILIBRIUM sends them to f* (Ehrenfests' step); MRT
+ * gives them the MRT collision of mrt_basis and its rates (with s_nu the
+ * site's omega) in place of LBGK's: the MRT limiter of section 5 (LBGK
+ * lattices, D2Q9 only).  The positivity rule, when on, then also acts on
+ * them. */
+enum { LBM_SEL_EQUILIBRIUM = 0, LBM_SEL_MRT = 1 };
 enum { LBM_LIM_EHRENFEST = 1, LBM_LIM_POSITIVITY = 2, LBM_LIM_MEDIAN = 4 };
 enum { LBM_NORM_ENTROPIC = 0, LBM_NORM_L1 = 1 };
 enum { LBM_FB_POSITIVITY = 0, LBM_FB_EHRENFEST = 1 };
@@ -105,6 +123,8 @@ typedef struct lbm_config {
   int checkpoint_every;   /* K > 0: record a rollout for lbm_backward           */
   long long max_steps;    /* longest rollout lbm_backward must cover            */
   int check_interval;     /* steps between divergence checks (0: only on lbm_stats) */
+  int mrt_preset;         /* LBM_RATES_* (M1 basis; GIVEN uses s_e, s_eps, s_q)   */
+  int sel_action;         /* LBM_SEL_EQUILIBRIUM | LBM_SEL_MRT                   */
 } lbm_config;
 
 typedef struct lbm_stats {

@@ -107,7 +107,9 @@ __device__ __forceinline__ void adjoint_site(const StepArgs<typename StoreT<S>::
 #pragma unroll
   for (int i = 0; i < Q; ++i) lf[i] = R(0);
   gw = R(0);
-  if (ehr) {
+  // on an MRT-limited lattice a selected site took the MRT collision
+  const bool mrt_here = COLL == COLL_MRT || (Q == 9 && ehr && A.sel_mrt);
+  if (ehr && !A.sel_mrt) {
     // Ehrenfest step: g' = f*(p)
 #pragma unroll
     for (int i = 0; i < Q; ++i) { lf[i] = lam[i]; mu[i] = R(0); }
@@ -122,6 +124,9 @@ __device__ __forceinline__ void adjoint_site(const StepArgs<typename StoreT<S>::
       const R ab = ci.alpha * (om * R(0.5));
 #pragma unroll
       for (int i = 0; i < Q; ++i) q[i] = v[i] + ab * d[i];
+    } else if constexpr (Q == 9) {
+      if (mrt_here) collide_site<S, Q, COLL_MRT>(A, v, feq, d, om, q, ci);
+      else collide_site<S, Q, COLL>(A, v, feq, d, om, q, ci);
     } else {
       collide_site<S, Q, COLL>(A, v, feq, d, om, q, ci);
     }
@@ -152,16 +157,9 @@ __device__ __forceinline__ void adjoint_site(const StepArgs<typename StoreT<S>::
         lf[a] -= se * phi * phi * qa / (fa * fa);
       }
     }
-    if constexpr (COLL == COLL_LBGK) {
-      // q = p + omega (f* - p)
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        mu[i] = (R(1) - om) * lq[i];
-        lf[i] += om * lq[i];
-        gw += lq[i] * d[i];
-      }
-    } else if constexpr (COLL == COLL_MRT) {
-      // q = p + B (f* - p), B = Minv diag(rates) M
+    if (COLL == COLL_MRT || mrt_here) {
+      // q = p + B (f* - p), B = Minv diag(rates(omega)) M; the rates of the
+      // presets depend on the shear rate too
       R z[Q], m[Q];
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
@@ -173,10 +171,10 @@ __device__ __forceinline__ void adjoint_site(const StepArgs<typename StoreT<S>::
         }
         z[k] = sz;
         m[k] = sm;
-        if ((A.nu_rows >> k) & 1u) gw += sz * sm;
+        gw += mrt_drate<R>(A, k, om) * sz * sm;
       }
 #pragma unroll
-      for (int k = 0; k < Q; ++k) z[k] *= ((A.nu_rows >> k) & 1u) ? om : A.rates[k];
+      for (int k = 0; k < Q; ++k) z[k] *= mrt_rate<R>(A, k, om);
 #pragma unroll
       for (int j = 0; j < Q; ++j) {
         R w = R(0);
@@ -184,6 +182,14 @@ __device__ __forceinline__ void adjoint_site(const StepArgs<typename StoreT<S>::
         for (int k = 0; k < Q; ++k) w += A.M[k * Q + j] * z[k];
         mu[j] = lq[j] - w;
         lf[j] += w;
+      }
+    } else if constexpr (COLL == COLL_LBGK) {
+      // q = p + omega (f* - p)
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        mu[i] = (R(1) - om) * lq[i];
+        lf[i] += om * lq[i];
+        gw += lq[i] * d[i];
       }
     } else {
       // q = p + alpha beta (f* - p), beta = omega / 2
@@ -484,8 +490,9 @@ __global__ __launch_bounds__(256) void k_median_gather(const StepArgs<typename S
   push_adjoint<R, Q, true>(A, B.lam_out, x, y, g);
 }
 
-// Recompute of an Ehrenfest step from its tape: f* at the listed sites,
-// from the pulled state exactly as the step kernel computed it.
+// Recompute of an Ehrenfest step from its tape: the selected state (f*, or
+// the MRT limiter's collision) at the listed sites, from the pulled state
+// exactly as the selection kernels computed it.
 template <class S, int Q>
 __global__ void k_tape_fix(const StepArgs<typename StoreT<S>::R> A, const int32_t* list,
                            const long long* count, long long k) {
@@ -501,6 +508,7 @@ __global__ void k_tape_fix(const StepArgs<typename StoreT<S>::R> A, const int32_
     const int y = idx / A.nx, x = idx % A.nx;
     R v[Q], feq[Q], d[Q], m0, ux, uy;
     site_prep<S, Q>(A, x, y, v, feq, d, m0, ux, uy, false);
+    if (A.sel_mrt) selected_state<S, Q>(A, x, y, m0, ux, uy, feq);
     S* dst = (S*)A.dst;
 #pragma unroll
     for (int i = 0; i < Q; ++i)

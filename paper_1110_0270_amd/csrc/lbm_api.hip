@@ -63,23 +63,37 @@ bool validate(const lbm_config* c, std::string& why) {
     why = "ehr_k and ehr_delta must be >= 0"; return false;
   }
   if (c->collision == LBM_ELBM && c->elbm_max_iter < 1) { why = "elbm_max_iter must be >= 1"; return false; }
+  if (c->mrt_preset < LBM_RATES_GIVEN || c->mrt_preset > LBM_RATES_SHEAR) { why = "unknown mrt_preset"; return false; }
+  if (c->mrt_preset != LBM_RATES_GIVEN && c->mrt_basis != LBM_MRT_M1) {
+    why = "the rate presets are rates of the M1 basis"; return false;
+  }
+  if (c->sel_action != LBM_SEL_EQUILIBRIUM && c->sel_action != LBM_SEL_MRT) { why = "unknown sel_action"; return false; }
+  if (c->sel_action == LBM_SEL_MRT &&
+      (!(c->limiters & LBM_LIM_EHRENFEST) || c->collision != LBM_LBGK || c->lattice != LBM_D2Q9)) {
+    why = "the MRT limiter (sel_action = LBM_SEL_MRT) needs the Ehrenfest selection, LBGK and D2Q9";
+    return false;
+  }
   if (c->checkpoint_every < 0 || c->max_steps < 0) { why = "checkpoint_every/max_steps must be >= 0"; return false; }
   if (c->checkpoint_every > 0 && c->max_steps < 1) { why = "checkpoint_every > 0 needs max_steps >= 1"; return false; }
   return true;
 }
 
-Layout make_layout(const lbm_config* c) {
+// lattices = false: the two lattices are the caller's (not in the
+// workspace), densely packed (row pitch nx), and no adjoint is recorded.
+Layout make_layout(const lbm_config* c, bool lattices = true) {
   Layout L;
   L.Q = c->lattice == LBM_D2Q9 ? 9 : 3;
-  L.pitch = (c->nx + 63) / 64 * 64;
+  L.pitch = lattices ? (c->nx + 63) / 64 * 64 : c->nx;
   L.qs = (long long)c->ny * L.pitch;
   L.n_sites = (long long)c->nx * c->ny;
   L.lat_bytes = (size_t)L.Q * L.qs * elem_bytes(c->storage);
   const size_t rb = is_f64(c->storage) ? 8 : 4;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
-  L.off_lat[0] = take(L.lat_bytes);
-  L.off_lat[1] = take(L.lat_bytes);
+  if (lattices) {
+    L.off_lat[0] = take(L.lat_bytes);
+    L.off_lat[1] = take(L.lat_bytes);
+  }
   L.off_omega = c->omega_field ? take((size_t)L.qs * rb) : 0;
   L.off_sel = take(sizeof(SelState));
   L.off_cnt = take((size_t)kCntSlots * CNT_N * sizeof(unsigned long long));
@@ -109,8 +123,10 @@ Layout make_layout(const lbm_config* c) {
     L.off_f64list = take((size_t)L.n_sites * 4);
     L.off_f64cnt = take(2 * sizeof(unsigned int));
   }
-  L.adj = adjoint_layout(c, L.lat_bytes, L.qs, L.k, o);
-  o = L.adj.end;
+  if (lattices) {
+    L.adj = adjoint_layout(c, L.lat_bytes, L.qs, L.k, o);
+    o = L.adj.end;
+  }
   L.total = o;
   return L;
 }
@@ -179,15 +195,44 @@ void fill_args(StepArgs<R>& A, const lbm_config* c, const Layout& L, char* ws) {
       A.lid[i] = (R)(6.0 * w * c->rho_wall * a * c->u_lid);
     }
   }
-  if (c->collision == LBM_MRT) {
+  // MRT: the collision itself, or the MRT limiter at the selected sites of
+  // an LBGK lattice (section 5)
+  A.sel_mrt = c->sel_action == LBM_SEL_MRT ? 1 : 0;
+  if (c->collision == LBM_MRT || A.sel_mrt) {
     double M[81], Mi[81];
     mrt_matrices(c->mrt_basis, M, Mi);
     for (int i = 0; i < 81; ++i) { A.M[i] = (R)M[i]; A.Minv[i] = (R)Mi[i]; }
     double rates[9];
     if (c->mrt_basis == LBM_MRT_M1) {
-      const double r1[9] = {1, c->s_e, c->s_eps, 1, c->s_q, 1, c->s_q, om, om};
-      std::memcpy(rates, r1, sizeof(rates));
+      // rows rho, e, epsilon, j_x, q_x, j_y, q_y, p_xx, p_xy
+      double se = c->s_e, seps = c->s_eps, sq = c->s_q;
       A.nu_rows = (1u << 7) | (1u << 8);
+      A.q_rows = 0;
+      A.q_mode = 0;
+      switch (c->mrt_preset) {
+        case LBM_RATES_TRT:        // s_e = s_eps = s_nu, s_q = 8 (2 - s_nu) / (8 - s_nu)
+          A.nu_rows |= (1u << 1) | (1u << 2);
+          A.q_rows = (1u << 4) | (1u << 6);
+          A.q_mode = 1;
+          break;
+        case LBM_RATES_MRT_TRTQ:   // s_e = 1.64, s_eps = 1.54, TRT third-order rate
+          se = 1.64; seps = 1.54;
+          A.q_rows = (1u << 4) | (1u << 6);
+          A.q_mode = 1;
+          break;
+        case LBM_RATES_MRT1:
+          se = 1.64; seps = 1.54; sq = 1.9;
+          break;
+        case LBM_RATES_SHEAR:      // s_q = 3 (2 - s_nu) / (3 - s_nu)
+          se = 1.64; seps = 1.54;
+          A.q_rows = (1u << 4) | (1u << 6);
+          A.q_mode = 2;
+          break;
+        default:
+          break;
+      }
+      const double r1[9] = {1, se, seps, 1, sq, 1, sq, om, om};
+      std::memcpy(rates, r1, sizeof(rates));
     } else {
       const double r2[9] = {1, 1, 1, 1, om, om, 1, 1, 1};
       std::memcpy(rates, r2, sizeof(rates));
@@ -251,6 +296,7 @@ struct lbm_ctx {
 };
 
 static SelectArgs select_args(lbm_ctx* c, const void* args);
+static hipError_t capture_graph(lbm_ctx* c);
 
 extern "C" {
 
@@ -305,6 +351,13 @@ lbm_status lbm_init(const lbm_config* cfg, void* ws, size_t ws_bytes, void* stre
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.off_wcount, 0, (size_t)(L.cap / 64) * 4, c->stream);
     if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.off_ccount, 0, (size_t)kCountSlots * kCountStride * 8, c->stream);
   }
+  // Capture the graphs that lbm_step replays (kGraphSteps steps from either
+  // lattice) now, so that no later lbm_step call pays for a capture.
+  for (int l = 0; l < 2 && e == hipSuccess; ++l) {
+    c->cur = l;
+    e = capture_graph(c);
+  }
+  c->cur = 0;
   if (e != hipSuccess) { delete c; return hip_fail(e, "lbm_init"); }
   *out = c;
   return LBM_OK;

@@ -10,8 +10,10 @@ namespace lbm {
 struct ElbmF64Site { float f[9], q[9]; };
 struct ElbmF64Result { float alpha; int branch; int iters; };
 
-// The FP64 root solve for a site of an FP32 lattice, out of line: the FP32
-// kernels carry its code once, away from their hot path (few sites take it).
+// The FP64 root solve for a site of an FP32 lattice from its FP32 state, out
+// of line (the kernels carry its code once, away from their hot path): used
+// by the median filter's kernel, which has no deferred list; the other FP32
+// ELBM kernels defer such sites to k_elbm_f64, which rebuilds them in FP64.
 template <int Q>
 __device__ __noinline__ ElbmF64Result elbm_alpha_fp64(ElbmF64Site s, double eps, double dS_cut,
                                                       int max_iter, int norm, int fallback) {
@@ -58,14 +60,16 @@ __device__ __forceinline__ bool group16_any(bool b) {
   return v != 0;
 }
 
-static __device__ ElbmF64Result elbm_alpha_fp64_group(float f_c, float q_c, bool act,
-                                                      double eps, double dS_cut, int max_iter,
-                                                      int norm, int fallback) {
-  const double f = act ? (double)f_c : 1.0, q = act ? (double)q_c : 1.0, D = q - f;
-  ElbmF64Result r;
+struct ElbmGroupResult { double alpha; int branch; int iters; };
+
+static __device__ ElbmGroupResult elbm_alpha_fp64_group(double f_c, double q_c, bool act,
+                                                        double eps, double dS_cut, int max_iter,
+                                                        int norm, int fallback) {
+  const double f = act ? f_c : 1.0, q = act ? q_c : 1.0, D = q - f;
+  ElbmGroupResult r;
   r.iters = 0;
   if (group16_any(act && f <= 0.0)) {
-    r.alpha = 1.0f;
+    r.alpha = 1.0;
     r.branch = EB_NONPOS;
     return r;
   }
@@ -75,7 +79,7 @@ static __device__ ElbmF64Result elbm_alpha_fp64_group(float f_c, float q_c, bool
   if (U < 2.0 * dS_cut * (1.0 + xmax / 3.0)) {
     const double dS = group16_sum(q * h_fn<double>(x));
     if (dS < dS_cut) {
-      r.alpha = 2.0f;
+      r.alpha = 2.0;
       r.branch = EB_CUTOFF;
       return r;
     }
@@ -98,7 +102,7 @@ static __device__ ElbmF64Result elbm_alpha_fp64_group(float f_c, float q_c, bool
     const double sf = -s0 - aa * s1, d1 = -t1, d2 = -t2;
     if (probe) {
       if (sf >= 0.0) {
-        r.alpha = (float)(fallback == 0 ? amax : 1.0);
+        r.alpha = fallback == 0 ? amax : 1.0;
         r.branch = EB_NOROOT;
         return r;
       }
@@ -121,9 +125,28 @@ static __device__ ElbmF64Result elbm_alpha_fp64_group(float f_c, float q_c, bool
     if (an <= 1.0) an = 0.5 * (a + 1.0);
     a = an;
   }
-  r.alpha = (float)a;
+  r.alpha = a;
   r.branch = EB_ROOT;
   return r;
+}
+
+// Relaxation rate of MRT row k at shear rate om (section 5, with the rate
+// presets of sections 5, 7 and 8), and its derivative in om.
+template <class R>
+__device__ __forceinline__ R mrt_rate(const StepArgs<R>& A, int k, R om) {
+  if ((A.nu_rows >> k) & 1u) return om;
+  if ((A.q_rows >> k) & 1u)
+    return A.q_mode == 1 ? R(8) * (R(2) - om) / (R(8) - om) : R(3) * (R(2) - om) / (R(3) - om);
+  return A.rates[k];
+}
+template <class R>
+__device__ __forceinline__ R mrt_drate(const StepArgs<R>& A, int k, R om) {
+  if ((A.nu_rows >> k) & 1u) return R(1);
+  if ((A.q_rows >> k) & 1u) {
+    const R c = A.q_mode == 1 ? R(8) : R(3), t = c - om;
+    return -c * (c - R(2)) / (t * t);
+  }
+  return R(0);
 }
 
 template <class R>
@@ -141,8 +164,7 @@ struct CollInfo {
 // 3 ELBM), in the storage representation: d = f* - f, om the relaxation rate
 // (LBGK omega, MRT shear rate s_nu, ELBM 2 beta).
 // DEFER (FP32 ELBM only): a site that needs the FP64 solve is not collided;
-// ci.deferred is set and post[] is left unset.  preset: the FP64 solve's
-// result for such a site, already found by its lane group.
+// ci.deferred is set and post[] is left unset (k_elbm_f64 rebuilds it).
 template <class S, int Q, int COLL, bool DEFER = false>
 __device__ __forceinline__ void collide_site(const StepArgs<typename StoreT<S>::R>& A,
                                              const typename StoreT<S>::R v[Q],
@@ -150,8 +172,7 @@ __device__ __forceinline__ void collide_site(const StepArgs<typename StoreT<S>::
                                              const typename StoreT<S>::R d[Q],
                                              typename StoreT<S>::R om,
                                              typename StoreT<S>::R post[Q],
-                                             CollInfo<typename StoreT<S>::R>& ci,
-                                             const ElbmF64Result* preset = nullptr) {
+                                             CollInfo<typename StoreT<S>::R>& ci) {
   using R = typename StoreT<S>::R;
   constexpr bool SH = StoreT<S>::shifted;
   if constexpr (COLL == COLL_LBGK) {
@@ -164,7 +185,7 @@ __device__ __forceinline__ void collide_site(const StepArgs<typename StoreT<S>::
       R s = R(0);
 #pragma unroll
       for (int j = 0; j < Q; ++j) s += A.M[k * Q + j] * d[j];
-      m[k] = s * (((A.nu_rows >> k) & 1u) ? om : A.rates[k]);
+      m[k] = s * mrt_rate<R>(A, k, om);
     }
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -200,8 +221,7 @@ __device__ __forceinline__ void collide_site(const StepArgs<typename StoreT<S>::
           st.q[i] = qa[i];
         }
         const ElbmF64Result r =
-            preset ? *preset
-                   : elbm_alpha_fp64<Q>(st, A.eps64, A.dS_cut64, A.max_iter, A.norm, A.fallback);
+            elbm_alpha_fp64<Q>(st, A.eps64, A.dS_cut64, A.max_iter, A.norm, A.fallback);
         alpha = r.alpha;
         br = r.branch;
         ci.iters = r.iters;
@@ -250,6 +270,33 @@ __device__ __forceinline__ void positivity_site(const StepArgs<typename StoreT<S
     ci.pos_arg = arg;
     ci.phi = phi;
   }
+}
+
+// The state the Ehrenfest selection gives a selected site (section 4, and
+// the MRT limiter of section 5): f* from the moments the step recorded for
+// it, or, on an MRT-limited lattice, the MRT collision of its pulled state
+// (the step's source lattice, intact while the selection runs) followed by
+// the positivity rule when that is on.
+template <class S, int Q>
+__device__ __forceinline__ void selected_state(const StepArgs<typename StoreT<S>::R>& A, int x,
+                                               int y, typename StoreT<S>::R m0,
+                                               typename StoreT<S>::R ux,
+                                               typename StoreT<S>::R uy,
+                                               typename StoreT<S>::R out[Q]) {
+  using R = typename StoreT<S>::R;
+  constexpr bool SH = StoreT<S>::shifted;
+  if constexpr (Q == 9) {
+    if (A.sel_mrt) {
+      R v[Q], feq[Q], d[Q], mm, vx, vy;
+      site_prep<S, Q>(A, x, y, v, feq, d, mm, vx, vy, false);
+      const R om = A.omega_field ? A.omega_field[(long long)y * A.pitch + x] : A.omega;
+      CollInfo<R> ci;
+      collide_site<S, Q, COLL_MRT>(A, v, feq, d, om, out, ci);
+      if (A.positivity) positivity_site<S, Q>(A, feq, out, ci);
+      return;
+    }
+  }
+  equilibrium_v<R, Q, SH>(m0, A.rho0, ux, uy, A.eq_kind, out);
 }
 
 }  // namespace lbm

@@ -92,6 +92,9 @@ struct StepArgs {
   R Minv[81];
   R rates[9];
   unsigned nu_rows;      // bit mask of rows whose rate is the shear rate
+  unsigned q_rows;       // rows whose rate is a function q_mode of the shear rate
+  int q_mode;            // 1: 8 (2 - s) / (8 - s); 2: 3 (2 - s) / (3 - s)
+  int sel_mrt;           // selected sites get the MRT collision instead of f*
   // ELBM
   R eps, atol, dS_cut;
   int max_iter, norm, fallback;

@@ -21,8 +21,10 @@
 //               lists those inside it;
 //   k_fix_tail  resolves the boundary bucket exactly by an MSD radix select
 //               on (key descending, site index ascending), sets the next
-//               step's floor and frame, and resets the counters.
-#include "lbm_site.h"
+//               step's floor and frame, and resets the counters;
+//   k_sel_mrt   (MRT limiter only) replaces f* at the selected sites by the
+//               MRT collision.
+#include "lbm_collide.h"
 
 namespace lbm {
 
@@ -775,6 +777,33 @@ __global__ __launch_bounds__(1024) void k_fix_tail(const StepArgs<typename Store
                  scratch, scratch_len);
 }
 
+// The MRT limiter (section 5) on an LBGK lattice: the step's selected sites,
+// which the sweep has just sent to f*, receive the MRT collision of their
+// pulled state instead (the source lattice is intact until the next step),
+// then the positivity rule when it is on.  The list is where k_fix_tail
+// wrote it: the tape slot of the step when recording, else `selected`.
+template <class S, int Q>
+__global__ __launch_bounds__(256) void k_sel_mrt(const StepArgs<typename StoreT<S>::R> A,
+                                                 long long k, const int32_t* selected,
+                                                 const int32_t* tape_sel, long long tape_len) {
+  using R = typename StoreT<S>::R;
+  const SelState* st = A.sel;
+  const long long n = st->n_sel;
+  const long long t = st->tape_t - 1;
+  const int32_t* list = (tape_sel && t >= 0 && t < tape_len) ? tape_sel + t * k : selected;
+  for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+       j += (long long)gridDim.x * blockDim.x) {
+    const int idx = list[j];
+    const int y = idx / A.nx, x = idx % A.nx;
+    R out[Q];
+    selected_state<S, Q>(A, x, y, R(0), R(0), R(0), out);
+    S* dst = (S*)A.dst;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      StoreT<S>::st(dst + (long long)i * A.qs + (long long)y * A.pitch + x, out[i]);
+  }
+}
+
 template <class S, int Q>
 static hipError_t launch_select_t(const SelectArgs& a, hipStream_t s) {
   using R = typename StoreT<S>::R;
@@ -794,6 +823,11 @@ static hipError_t launch_select_t(const SelectArgs& a, hipStream_t s) {
   hipLaunchKernelGGL((k_fix_tail<S, Q>), dim3(1), dim3(1024), 0, s, A, a.k, a.n_sites,
                      a.selected, a.blist, a.bcap, a.n_sel_out, a.tape_sel, a.tape_cnt,
                      a.tape_len, (uint32_t*)a.segsel, (long long)gfix * kSweepRegions * 64);
+  if (A.sel_mrt) {
+    const long long g = (a.k + 255) / 256;
+    hipLaunchKernelGGL((k_sel_mrt<S, Q>), dim3((unsigned)(g < 1 ? 1 : (g > 1024 ? 1024 : g))),
+                       dim3(256), 0, s, A, a.k, a.selected, a.tape_sel, a.tape_len);
+  }
   return hipGetLastError();
 }
 

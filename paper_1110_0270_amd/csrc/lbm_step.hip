@@ -59,8 +59,7 @@ __device__ __forceinline__ void site_finish(const StepArgs<typename StoreT<S>::R
                                             typename StoreT<S>::R ux, typename StoreT<S>::R uy,
                                             typename StoreT<S>::R dS,
                                             const StepFrame& fr,
-                                            unsigned long long* cnt,
-                                            const ElbmF64Result* preset = nullptr) {
+                                            unsigned long long* cnt) {
   using R = typename StoreT<S>::R;
   // Ehrenfest candidates: eligible (Delta S > delta) and above the floor.
   if (EHR && A.ehrenfest) {
@@ -75,7 +74,7 @@ __device__ __forceinline__ void site_finish(const StepArgs<typename StoreT<S>::R
   if (valid) {
     const R om = A.omega_field ? A.omega_field[(long long)y * A.pitch + x] : A.omega;
     CollInfo<R> ci;
-    collide_site<S, Q, COLL, DEFER>(A, v, feq, d, om, post, ci, preset);
+    collide_site<S, Q, COLL, DEFER>(A, v, feq, d, om, post, ci);
     deferred = ci.deferred;
     if constexpr (COLL == COLL_ELBM) {
       // a deferred site counts no event here (its CollInfo is the default)
@@ -124,49 +123,93 @@ __device__ __forceinline__ void site_finish(const StepArgs<typename StoreT<S>::R
 }
 
 // Sites of an FP32 ELBM step that need the FP64 root solve, listed by the
-// step kernel: each is recomputed from the source lattice (pull, moments,
-// f*: the same values the step kernel had), collided with the FP64 solve,
-// limited and stored, with its counters and adjoint records, exactly as the
-// step kernel would have done in place.  The last workgroup clears the list:
-// every workgroup has used the list length (its loop bounds) before it takes
-// its ticket, and nothing else that a workgroup wrote is read here, so no
-// device-scope fence is needed (on gfx950 one writes back the XCD's L2).
+// step kernel (alpha_max < f64_below: near the no-root branch, where
+// alpha = alpha_max = f_a / (f_a - f*_a) hangs on a small population and the
+// FP32 forms' absolute rounding of the shifted representation, about
+// ulp(w_a rho0), would move it by a relative 1e-4).  Each is rebuilt from the
+// source lattice in FP64: the stored values (exact in FP64) plus w_i rho0,
+// moments, entropic f*, the root solve, the collision and the positivity
+// rule, rounded only when stored; its counters and adjoint records are
+// taken as the step kernel would have.  The last workgroup clears the list:
+// every workgroup has used the list length (its loop bounds) before it
+// takes its ticket, and nothing else that a workgroup wrote is read here,
+// so no device-scope fence is needed (on gfx950 one writes back the XCD's
+// L2).
 template <class S, int Q>
 __global__ __launch_bounds__(256) void k_elbm_f64(const StepArgs<typename StoreT<S>::R> A) {
   using R = typename StoreT<S>::R;
   constexpr bool SH = StoreT<S>::shifted;
   const unsigned int n = A.f64_count[0];
   unsigned long long* const cnt = A.counters + (blockIdx.x % kCntSlots) * CNT_N;
-  const StepFrame fr{0ull, 0ull, 0u};
   // 16 sites per workgroup, one per group of 16 lanes: every lane of the
-  // group recomputes the site, lane c takes component c into the group's
+  // group rebuilds the site, lane c takes component c into the group's
   // root solve, and lane 0 collides, limits and stores it.
   const unsigned int grp = threadIdx.x / 16, c = threadIdx.x % 16;
+  const double rho0 = (double)A.rho0;
   for (unsigned int b0 = blockIdx.x * 16u; b0 < n; b0 += gridDim.x * 16u) {
     const unsigned int i = b0 + grp;
     const bool on = i < n;
     const uint32_t idx = on ? A.f64_sites[i] : 0u;
     const int x = (int)(idx % (uint32_t)A.nx), y = (int)(idx / (uint32_t)A.nx);
-    R v[Q], feq[Q], d[Q], m0 = R(0), ux = R(0), uy = R(0);
-    ElbmF64Result r{2.0f, EB_CUTOFF, 0};
+    double f[Q], q[Q];
+    ElbmGroupResult r{2.0, EB_CUTOFF, 0};
     if (on) {
-      site_prep<S, Q>(A, x, y, v, feq, d, m0, ux, uy, false);
-      // component c of f and f* in the unshifted representation, as the
-      // per-site solve receives them
-      float f_c = 1.0f, q_c = 1.0f;
+      R v[Q];
+      pull<S, Q>((const S*)A.src, A.qs, A.pitch, A.nx, A.ny, A.bc, x, y, A.lid, v);
 #pragma unroll
-      for (int k = 0; k < Q; ++k) {
-        const R sh = SH ? wt<R, Q>(k) * A.rho0 : R(0);
-        if ((int)c == k) {
-          f_c = v[k] + sh;
-          q_c = feq[k] + sh;
-        }
-      }
+      for (int k = 0; k < Q; ++k) f[k] = (double)v[k] + (SH ? wt<double, Q>(k) * rho0 : 0.0);
+      double m0, ux, uy;
+      moments_v<double, Q, false>(f, rho0, m0, ux, uy);
+      equilibrium_v<double, Q, false>(m0, rho0, ux, uy, EQ_ENTROPIC, q);
+      double f_c = 1.0, q_c = 1.0;
+#pragma unroll
+      for (int k = 0; k < Q; ++k)
+        if ((int)c == k) { f_c = f[k]; q_c = q[k]; }
       r = elbm_alpha_fp64_group(f_c, q_c, (int)c < Q, A.eps64, A.dS_cut64, A.max_iter, A.norm,
                                 A.fallback);
     }
-    site_finish<S, Q, COLL_ELBM, false, false>(A, x, y, on && c == 0, 0, v, feq, d, m0, ux, uy,
-                                                R(0), fr, cnt, &r);
+    const bool mine = on && c == 0;
+    bool pos_event = false;
+    if (mine) {
+      const long long o = (long long)y * A.pitch + x;
+      const double om = A.omega_field ? (double)A.omega_field[o] : (double)A.omega;
+      const double ab = r.alpha * (om * 0.5);
+      double post[Q];
+#pragma unroll
+      for (int k = 0; k < Q; ++k) post[k] = f[k] + ab * (q[k] - f[k]);
+      if (A.positivity) {
+        // positivity rule (section 4) in FP64
+        double phi = __builtin_huge_val();
+        int arg = -1;
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+          if (post[k] < 0.0 && q[k] > 0.0) {
+            const double t = q[k] / (q[k] - post[k]);
+            if (t < phi) { phi = t; arg = k; }
+          }
+        if (arg >= 0) {
+#pragma unroll
+          for (int k = 0; k < Q; ++k) post[k] = (k == arg) ? 0.0 : q[k] + phi * (post[k] - q[k]);
+          pos_event = true;
+        }
+      }
+      S* dst = (S*)A.dst;
+#pragma unroll
+      for (int k = 0; k < Q; ++k)
+        StoreT<S>::st(at(dst + (long long)k * A.qs, (unsigned)o),
+                      (R)(post[k] - (SH ? wt<double, Q>(k) * rho0 : 0.0)));
+      if (A.alpha_out) {
+        A.alpha_out[o] = (R)r.alpha;
+        A.branch_out[o] = (unsigned char)r.branch;
+      }
+    }
+    if (A.count_events) {
+      count_event(mine && r.branch == EB_NOROOT, cnt + CNT_ELBM_NOROOT);
+      count_event(mine, cnt + CNT_ELBM_F64);
+      count_event(mine && r.branch == EB_NONPOS, cnt + CNT_ELBM_NONPOS);
+      count_sum(mine ? r.iters : 0, cnt + CNT_ELBM_ITERS);
+      if (A.positivity) count_event(pos_event, cnt + CNT_POSITIVITY);
+    }
   }
   __shared__ bool last;
   __syncthreads();

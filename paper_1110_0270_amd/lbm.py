@@ -28,6 +28,8 @@ LBM_LIM_EHRENFEST, LBM_LIM_POSITIVITY, LBM_LIM_MEDIAN = 1, 2, 4
 LBM_NORM_ENTROPIC, LBM_NORM_L1 = 0, 1
 LBM_FB_POSITIVITY, LBM_FB_EHRENFEST = 0, 1
 LBM_F64, LBM_F32, LBM_F16S, LBM_BF16S = 0, 1, 2, 3
+LBM_RATES_GIVEN, LBM_RATES_TRT, LBM_RATES_MRT_TRTQ, LBM_RATES_MRT1, LBM_RATES_SHEAR = 0, 1, 2, 3, 4
+LBM_SEL_EQUILIBRIUM, LBM_SEL_MRT = 0, 1
 
 EXPORTED = [
     "lbm_config_default", "lbm_workspace_bytes", "lbm_init", "lbm_set_equilibrium",
@@ -52,6 +54,7 @@ class lbm_config(ctypes.Structure):
         ("storage", ctypes.c_int), ("rho0", ctypes.c_double),
         ("omega_field", ctypes.c_int), ("checkpoint_every", ctypes.c_int),
         ("max_steps", ctypes.c_longlong), ("check_interval", ctypes.c_int),
+        ("mrt_preset", ctypes.c_int), ("sel_action", ctypes.c_int),
     ]
 
 
@@ -237,6 +240,9 @@ _BC = {"periodic": LBM_BC_PERIODIC, "bounceback": LBM_BC_BOUNCEBACK, "cavity": L
        "couette": LBM_BC_COUETTE}
 _COLL = {"lbgk": LBM_LBGK, "mrt": LBM_MRT, "elbm": LBM_ELBM}
 _STORE = {"f64": LBM_F64, "f32": LBM_F32, "f16s": LBM_F16S, "bf16s": LBM_BF16S}
+_PRESET = {"given": LBM_RATES_GIVEN, "trt": LBM_RATES_TRT, "mrt_trtq": LBM_RATES_MRT_TRTQ,
+           "mrt1": LBM_RATES_MRT1, "shear": LBM_RATES_SHEAR}
+_SEL = {"equilibrium": LBM_SEL_EQUILIBRIUM, "mrt": LBM_SEL_MRT}
 
 
 def make_config(*, lattice="D2Q9", nx=64, ny=64, bc="periodic", u_lid=0.0, rho_wall=1.0,
@@ -246,7 +252,7 @@ def make_config(*, lattice="D2Q9", nx=64, ny=64, bc="periodic", u_lid=0.0, rho_w
                 elbm_fallback="positivity", elbm_eps=1e-14, elbm_max_iter=32,
                 elbm_dS_cut=1e-15, elbm_f64_below=3.0, storage="f32", rho0=1.0,
                 omega_field=False, checkpoint_every=0, max_steps=0, check_interval=0,
-                **_ignored) -> lbm_config:
+                mrt_preset="given", sel_action="equilibrium", **_ignored) -> lbm_config:
     c = lbm_config_default()
     c.lattice = LBM_D2Q9 if lattice == "D2Q9" else LBM_D1Q3
     c.nx, c.ny = int(nx), int(ny)
@@ -272,6 +278,8 @@ def make_config(*, lattice="D2Q9", nx=64, ny=64, bc="periodic", u_lid=0.0, rho_w
     c.omega_field = 1 if omega_field else 0
     c.checkpoint_every, c.max_steps = int(checkpoint_every), int(max_steps)
     c.check_interval = int(check_interval)
+    c.mrt_preset = _PRESET[mrt_preset]
+    c.sel_action = _SEL[sel_action]
     return c
 
 

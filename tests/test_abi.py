@@ -74,3 +74,4 @@ def test_init_rejects_small_or_missing_workspace_without_touching_the_device():
     assert st == B.LBM_EINVAL
     assert lib.lbm_step(None, 1) == B.LBM_EINVAL
     lib.lbm_destroy(None)
+

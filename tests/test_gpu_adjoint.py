@@ -62,6 +62,19 @@ CASES = {
                                       _amp=0.4),
     "d1q3_median_bb": dict(lattice="D1Q3", nx=300, ny=1, bc="bounceback", nu=1e-3,
                            median=True, med_delta=1e-5, _amp=0.1),
+    # the MRT limiter (selected sites take the M2/C2 collision) and per-site
+    # preset rates (dL/d omega through the TRT and shear-wave third-order
+    # rates)
+    "lbgk_mrt_limiter_pos": dict(bc="periodic", omega=1.98, ehrenfest=True, ehr_k=9,
+                                 ehr_delta=0.0, sel_action="mrt", mrt_basis="M2",
+                                 positivity=True, _amp=0.4),
+    "lbgk_mrt_limiter_field_cavity": dict(bc="cavity", u_lid=0.1, ehrenfest=True, ehr_k=100,
+                                          ehr_delta=0.0, sel_action="mrt", mrt_basis="M1",
+                                          mrt_preset="trt", _field=True, _amp=0.2),
+    "trt_field_cavity": dict(bc="cavity", u_lid=0.1, collision="mrt", mrt_preset="trt",
+                             _field=True),
+    "shear_field_periodic": dict(bc="periodic", collision="mrt", mrt_preset="shear",
+                                 _field=True),
 }
 
 

@@ -45,6 +45,18 @@ CASES = {
     "mrt_ehrenfest_pos": dict(bc="cavity", u_lid=0.1, nu=1e-3, collision="mrt", s_e=1.64,
                               s_eps=1.64, s_q=1.9, ehrenfest=True, ehr_k=9, ehr_delta=1e-4,
                               positivity=True, _amp=0.3),
+    # the MRT limiter of section 5 (M2/C2 at the selected sites of an LBGK
+    # lattice) and the M1 rate presets
+    "lbgk_mrt_limiter": dict(bc="cavity", u_lid=0.1, nu=1e-4, ehrenfest=True, ehr_k=20,
+                             ehr_delta=0.0, sel_action="mrt", mrt_basis="M2"),
+    "lbgk_mrt_limiter_m1_pos": dict(bc="periodic", omega=1.98, ehrenfest=True, ehr_k=40,
+                                    ehr_delta=0.0, sel_action="mrt", mrt_basis="M1",
+                                    mrt_preset="mrt1", positivity=True, _amp=0.5),
+    "trt_cavity": dict(bc="cavity", u_lid=0.1, nu=1e-3, collision="mrt", mrt_preset="trt"),
+    "mrt_trtq_cavity": dict(bc="cavity", u_lid=0.1, nu=1e-3, collision="mrt",
+                            mrt_preset="mrt_trtq"),
+    "mrt1_periodic": dict(bc="periodic", nu=1e-3, collision="mrt", mrt_preset="mrt1"),
+    "shear_preset_periodic": dict(bc="periodic", nu=2e-2, collision="mrt", mrt_preset="shear"),
 }
 
 
@@ -95,7 +107,7 @@ def test_one_step_fp64_narrow(name):
 WIDE_CASES = ["lbgk_periodic", "lbgk_cavity", "lbgk_couette", "lbgk_bounceback",
               "mrt_m1_cavity", "mrt_m2_periodic", "elbm_periodic", "lbgk_median_cavity",
               "lbgk_ehrenfest_k20", "lbgk_ehrenfest_delta", "lbgk_positivity",
-              "mrt_ehrenfest_pos"]
+              "mrt_ehrenfest_pos", "lbgk_mrt_limiter", "lbgk_mrt_limiter_m1_pos", "trt_cavity"]
 
 
 @pytest.mark.parametrize("name", WIDE_CASES)
@@ -105,7 +117,7 @@ def test_one_step_fp64_wide(name):
 
 
 @pytest.mark.parametrize("name", ["lbgk_cavity", "lbgk_couette", "lbgk_ehrenfest_k20",
-                                  "mrt_ehrenfest_pos"])
+                                  "mrt_ehrenfest_pos", "lbgk_mrt_limiter", "trt_cavity"])
 def test_twenty_steps_fp64_wide(name):
     p, amp = _params(name, WIDE)
     _compare(p, amp, 20, 17, 1e-10)
@@ -127,10 +139,17 @@ def test_twenty_steps_fp64(name):
     _compare(p, amp, 20, 13, 1e-10)
 
 
-@pytest.mark.parametrize("coll", ["lbgk", "mrt", "elbm"])
+@pytest.mark.parametrize("coll", ["lbgk", "mrt", "elbm", "mrt:trt", "mrt:shear", "lbgk:limiter"])
 def test_omega_field_fp64(coll):
+    """Per-site relaxation rates, including the presets' per-site rates and
+    the MRT limiter at the selected sites."""
+    coll, _, extra = coll.partition(":")
     p = {"lattice": "D2Q9", **NARROW, "bc": "cavity", "u_lid": 0.1, "nu": 0.01,
          "collision": coll, "omega_field": True, "s_e": 1.64, "s_eps": 1.64, "s_q": 1.9}
+    if extra in ("trt", "shear"):
+        p["mrt_preset"] = extra
+    if extra == "limiter":
+        p.update(ehrenfest=True, ehr_k=15, ehr_delta=0.0, sel_action="mrt", mrt_basis="M2")
     om = torch.tensor(G.smooth_omega_field(p["nx"], p["ny"], seed=41))
     _compare(p, 0.05, 3, 14, 1e-12, omega_field=om)
 
@@ -234,7 +253,7 @@ def storage_bound(ora: torch.Tensor, storage: str, lat: O.Lattice) -> torch.Tens
 @pytest.mark.parametrize("name", ["lbgk_cavity", "mrt_m1_cavity", "elbm_periodic",
                                   "lbgk_median_cavity", "lbgk_ehrenfest_k20",
                                   "wide:lbgk_couette", "wide:mrt_m1_cavity",
-                                  "wide:lbgk_ehrenfest_k20"])
+                                  "wide:lbgk_ehrenfest_k20", "lbgk_mrt_limiter", "trt_cavity"])
 def test_low_precision_one_step(storage, name):
     size = WIDE if name.startswith("wide:") else NARROW
     name = name.split(":")[-1]
