@@ -244,6 +244,34 @@ lbm_status lbm_profile_step(lbm_ctx* ctx, long long n, double out[2]);
 lbm_status lbm_profile_backward(lbm_ctx* ctx, const void* dL_dfT, void* dL_df0,
                                 void* dL_domega, int dtype, double out[2]);
 
+/* Size of the static device array behind lbm_step_noalloc (per device). */
+#define LBM_NOALLOC_SCRATCH_BYTES (64ll << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): one time
+ * step exactly as lbm_step takes it (same kernels), from the lattice f_src
+ * into the lattice f_dst, allocating nothing.  Every other buffer of the
+ * step (selection state, Ehrenfest candidates and lists, histograms, limiter
+ * counters, the FP64-solve list) lives in a static device array of
+ * LBM_NOALLOC_SCRATCH_BYTES that each device holds until the process ends.
+ *   cfg:   as for lbm_init, with checkpoint_every = 0 and omega_field = 0
+ *          (check_interval is ignored).
+ *   f_src, f_dst: distinct device buffers, caller-owned, in the storage form
+ *          of cfg->storage, [Q][ny][nx] densely packed: LBM_F64 holds f_i;
+ *          LBM_F32, LBM_F16S (_Float16) and LBM_BF16S (bfloat16) hold the
+ *          shifted deviation f_i - w_i rho0 rounded to nearest even.
+ *   stream: a hipStream_t (NULL = default stream); the call only enqueues.
+ * Each call starts the Ehrenfest selection from its threshold (no candidate
+ * floor is carried between calls), so it examines every eligible site.
+ * The limiter counters are cleared at every call and not reported.
+ * Errors: LBM_EINVAL (configuration, NULL or equal buffers), LBM_EWORKSPACE
+ * when the configuration needs more scratch than the array holds (large
+ * lattices with the Ehrenfest limiter or FP32 ELBM: use lbm_init with a
+ * workspace), LBM_EHIP.  Every call on a device shares that device's
+ * array: calls that overlap on one device (other streams, other threads)
+ * race and must be serialised by the caller. */
+lbm_status lbm_step_noalloc(const lbm_config* cfg, const void* f_src, void* f_dst, void* stream);
+
 /* Free the context (not the caller's buffers). NULL is allowed. */
 void lbm_destroy(lbm_ctx* ctx);
 

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -840,6 +841,146 @@ static lbm_status backward_impl(lbm_ctx* c, const void* dL_dfT, void* dL_df0, vo
   if (e == hipSuccess && dL_domega)
     e = launch_from_pitch(gom, r64, dL_domega, din, 1, nx, ny, pitch, qs, st);
   if (e != hipSuccess) return hip_fail(e, "lbm_backward");
+  return LBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// One step without any allocation (lbm_step_noalloc).  Every buffer besides
+// the caller's two lattices lives in `scratch`, a static device array that
+// each device holds from the library's load until the process ends.  In
+// host code `scratch` names a host-side stand-in, not device memory: its
+// device address comes from hipGetSymbolAddress, looked up once per device
+// (with that device current) and kept in g_scratch_ptr; only that address
+// is ever passed to kernels.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[LBM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_address(int dev, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// Everything a step reads before writing it, cleared in the scratch array
+// with a kernel (no memset nodes when the caller captures the call): the
+// selection state (its floor back at the threshold), the histograms, the
+// candidate counters and region counts, the limiter counters and the FP64
+// site list's count.
+struct ScratchReset {
+  SelState sel;
+  SelState* sel_dst;
+  unsigned long long* counters;   // kCntSlots * CNT_N
+  unsigned int* hist;             // kHistWords
+  unsigned int* coarse;           // kCoarse
+  unsigned long long* ccount;     // kCountSlots * kCountStride
+  uint32_t* wcount;               // n_wcount
+  long long n_wcount;
+  unsigned int* f64_count;        // 2
+};
+
+__global__ void k_scratch_reset(const ScratchReset r) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  if (t == 0) *r.sel_dst = r.sel;
+  for (long long i = t; i < (long long)kCntSlots * CNT_N; i += stride) r.counters[i] = 0;
+  if (r.hist) {
+    for (long long i = t; i < kHistWords; i += stride) r.hist[i] = 0;
+    for (long long i = t; i < kCoarse; i += stride) r.coarse[i] = 0;
+    for (long long i = t; i < (long long)kCountSlots * kCountStride; i += stride) r.ccount[i] = 0;
+    for (long long i = t; i < r.n_wcount; i += stride) r.wcount[i] = 0;
+  }
+  if (r.f64_count && t < 2) r.f64_count[t] = 0;
+}
+
+}  // namespace
+
+extern "C" lbm_status lbm_step_noalloc(const lbm_config* cfg, const void* f_src, void* f_dst,
+                                       void* stream) {
+  g_err.clear();
+  std::string why;
+  if (!validate(cfg, why)) return fail(LBM_EINVAL, why);
+  if (!f_src || !f_dst || f_src == f_dst)
+    return fail(LBM_EINVAL, "f_src and f_dst must be distinct device buffers");
+  if (cfg->checkpoint_every != 0 || cfg->omega_field != 0)
+    return fail(LBM_EINVAL, "lbm_step_noalloc needs checkpoint_every = 0 and omega_field = 0");
+  const Layout L = make_layout(cfg, false);
+  if (L.total > (size_t)LBM_NOALLOC_SCRATCH_BYTES)
+    return fail(LBM_EWORKSPACE, "lbm_step_noalloc: this configuration needs " +
+                                    std::to_string(L.total) + " bytes of scratch, above the " +
+                                    std::to_string((long long)LBM_NOALLOC_SCRATCH_BYTES) +
+                                    "-byte static array (use lbm_init with a workspace)");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "lbm_step_noalloc");
+  if (dev < 0 || dev >= kMaxDevices) return fail(LBM_EINVAL, "device ordinal out of range");
+  void* base = nullptr;
+  e = scratch_address(dev, &base);
+  if (e != hipSuccess) return hip_fail(e, "lbm_step_noalloc: scratch address");
+  char* ws = (char*)base;
+  const hipStream_t st = (hipStream_t)stream;
+  const bool f64 = cfg->storage == LBM_F64;
+  StepArgs<double> a64;
+  StepArgs<float> a32;
+  const void* args;
+  if (f64) {
+    fill_args<double>(a64, cfg, L, ws);
+    a64.src = f_src;
+    a64.dst = f_dst;
+    args = &a64;
+  } else {
+    fill_args<float>(a32, cfg, L, ws);
+    a32.src = f_src;
+    a32.dst = f_dst;
+    args = &a32;
+  }
+  const bool ehr = (cfg->limiters & LBM_LIM_EHRENFEST) != 0;
+  ScratchReset r;
+  std::memset((void*)&r, 0, sizeof(r));
+  init_select_state(&r.sel, f64);
+  r.sel_dst = (SelState*)(ws + L.off_sel);
+  r.counters = (unsigned long long*)(ws + L.off_cnt);
+  if (ehr) {
+    r.hist = (unsigned int*)(ws + L.off_hist);
+    r.coarse = (unsigned int*)(ws + L.off_coarse);
+    r.ccount = (unsigned long long*)(ws + L.off_ccount);
+    r.wcount = (uint32_t*)(ws + L.off_wcount);
+    r.n_wcount = L.cap / 64;
+  }
+  r.f64_count = L.off_f64cnt ? (unsigned int*)(ws + L.off_f64cnt) : nullptr;
+  hipLaunchKernelGGL(k_scratch_reset, dim3(64), dim3(256), 0, st, r);
+  e = hipGetLastError();
+  if (e == hipSuccess)
+    e = launch_step(cfg->storage, L.Q, cfg->collision, (cfg->limiters & LBM_LIM_MEDIAN) != 0,
+                    args, st);
+  if (e == hipSuccess && ehr) {
+    SelectArgs sa;
+    sa.storage = cfg->storage; sa.Q = L.Q; sa.coll = cfg->collision; sa.step_args = args;
+    sa.k = L.k; sa.n_sites = L.n_sites;
+    sa.selected = (int32_t*)(ws + L.off_selected);
+    sa.segsel = (int32_t*)(ws + L.off_stage);
+    sa.blist = (uint32_t*)(ws + L.off_blist);
+    sa.bcap = L.bcap;
+    sa.coarse = (unsigned int*)(ws + L.off_coarse);
+    sa.n_sel_out = nullptr;
+    sa.tape_sel = nullptr;
+    sa.tape_cnt = nullptr;
+    sa.tape_len = 0;
+    e = launch_select(sa, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "lbm_step_noalloc");
   return LBM_OK;
 }
 

@@ -35,8 +35,11 @@ EXPORTED = [
     "lbm_config_default", "lbm_workspace_bytes", "lbm_init", "lbm_set_equilibrium",
     "lbm_set_populations", "lbm_get_populations", "lbm_set_omega", "lbm_step",
     "lbm_moments", "lbm_backward", "lbm_stats_get", "lbm_selected", "lbm_counters",
-    "lbm_profile_step", "lbm_profile_backward", "lbm_destroy", "lbm_last_error",
+    "lbm_profile_step", "lbm_profile_backward", "lbm_step_noalloc", "lbm_destroy",
+    "lbm_last_error",
 ]
+# size of the static device array behind lbm_step_noalloc (LBM_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class lbm_config(ctypes.Structure):
@@ -98,6 +101,7 @@ def library() -> ctypes.CDLL:
         "lbm_counters": (I, [P, ctypes.POINTER(ctypes.c_ulonglong), I]),
         "lbm_profile_step": (I, [P, LL, ctypes.POINTER(ctypes.c_double)]),
         "lbm_profile_backward": (I, [P, P, P, P, I, ctypes.POINTER(ctypes.c_double)]),
+        "lbm_step_noalloc": (I, [cfgp, P, P, P]),
         "lbm_destroy": (None, [P]),
         "lbm_last_error": (ctypes.c_char_p, []),
     }
@@ -226,6 +230,13 @@ def lbm_profile_backward(ctx, dL_dfT, dL_df0, dL_domega=None):
     _check(library().lbm_profile_backward(ctx, _ptr(dL_dfT), _ptr(dL_df0), _ptr(dL_domega),
                                           _dtype_code(dL_dfT), out), "lbm_profile_backward")
     return out[0], out[1]
+
+
+def lbm_step_noalloc(cfg: lbm_config, f_src, f_dst):
+    """One step from f_src into f_dst (device tensors in the storage form of
+    cfg.storage, [Q][ny][nx]) without any allocation, on the current stream."""
+    _check(library().lbm_step_noalloc(ctypes.byref(cfg), _ptr(f_src), _ptr(f_dst),
+                                      _stream_handle()), "lbm_step_noalloc")
 
 
 def lbm_destroy(ctx):

@@ -75,3 +75,20 @@ def test_init_rejects_small_or_missing_workspace_without_touching_the_device():
     assert lib.lbm_step(None, 1) == B.LBM_EINVAL
     lib.lbm_destroy(None)
 
+
+def test_noalloc_host_checks_without_a_gpu():
+    """lbm_step_noalloc rejects bad arguments and configurations whose
+    scratch exceeds its static array before it touches a device."""
+    lib = B.library()
+    fake_a, fake_b = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000)
+    c = B.make_config(nx=64, ny=64, storage="f32", nu=0.01)
+    assert lib.lbm_step_noalloc(ctypes.byref(c), None, fake_b, None) == B.LBM_EINVAL
+    assert lib.lbm_step_noalloc(ctypes.byref(c), fake_a, fake_a, None) == B.LBM_EINVAL
+    ca = B.make_config(nx=64, ny=64, nu=0.01, checkpoint_every=4, max_steps=8)
+    assert lib.lbm_step_noalloc(ctypes.byref(ca), fake_a, fake_b, None) == B.LBM_EINVAL
+    cw = B.make_config(nx=64, ny=64, nu=0.01, omega_field=True)
+    assert lib.lbm_step_noalloc(ctypes.byref(cw), fake_a, fake_b, None) == B.LBM_EINVAL
+    big = B.make_config(nx=4096, ny=4096, storage="f32", nu=1e-5, ehrenfest=True,
+                        ehr_k=16778)
+    assert lib.lbm_step_noalloc(ctypes.byref(big), fake_a, fake_b, None) == B.LBM_EWORKSPACE
+    assert b"scratch" in lib.lbm_last_error()
