@@ -90,7 +90,10 @@ constexpr int kAdjListLds = (int)kAdjListMax;
 // the collision (the pulled state, after the median filter when it is on),
 // given lam = dL/d(the site's post-collision state), along the branch the
 // forward step took; gw receives dL/d omega(x).  d = f* - v.
-template <class S, int Q, int COLL>
+// SELMRT: an LBGK lattice whose selected sites took the MRT collision (the
+// MRT limiter); a compile-time variant, so that the other kernels do not
+// carry the MRT code.
+template <class S, int Q, int COLL, bool SELMRT = false>
 __device__ __forceinline__ void adjoint_site(const StepArgs<typename StoreT<S>::R>& A,
                                              const AdjArgs<typename StoreT<S>::R>& B, long long o,
                                              bool ehr, const typename StoreT<S>::R v[Q],
@@ -108,8 +111,8 @@ __device__ __forceinline__ void adjoint_site(const StepArgs<typename StoreT<S>::
   for (int i = 0; i < Q; ++i) lf[i] = R(0);
   gw = R(0);
   // on an MRT-limited lattice a selected site took the MRT collision
-  const bool mrt_here = COLL == COLL_MRT || (Q == 9 && ehr && A.sel_mrt);
-  if (ehr && !A.sel_mrt) {
+  const bool mrt_here = COLL == COLL_MRT || (Q == 9 && SELMRT && ehr);
+  if (ehr && !SELMRT) {
     // Ehrenfest step: g' = f*(p)
 #pragma unroll
     for (int i = 0; i < Q; ++i) { lf[i] = lam[i]; mu[i] = R(0); }
@@ -298,9 +301,12 @@ __device__ __forceinline__ int load_short_list(const AdjArgs<R>& B, int32_t* lse
   return nl;
 }
 
-template <class S, int Q, int COLL>
-__global__ __launch_bounds__(256) void k_adjoint(const StepArgs<typename StoreT<S>::R> A,
-                                                 const AdjArgs<typename StoreT<S>::R> B) {
+// LBGK in FP32 arithmetic keeps six wavefronts per SIMD (at most 80
+// registers, no spills): with five the 4096^2 FP32 adjoint step took 553
+// against 363 us.
+template <class S, int Q, int COLL, bool SELMRT = false>
+__global__ __launch_bounds__(256, (COLL == COLL_LBGK && !SELMRT && sizeof(S) <= 4) ? 6 : 1)
+void k_adjoint(const StepArgs<typename StoreT<S>::R> A, const AdjArgs<typename StoreT<S>::R> B) {
   using R = typename StoreT<S>::R;
   // Workgroups go round-robin to the 8 XCDs; each XCD takes pairs of
   // adjacent 256-site segments, which share the lines that the pull and the
@@ -325,7 +331,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const StepArgs<typename StoreT<
     // the adjoint lattices, like the populations, are streamed once per
     // step: nontemporal loads and stores
     lam[i] = __builtin_nontemporal_load(&B.lam_in[(long long)i * A.qs + o]);
-  adjoint_site<S, Q, COLL>(A, B, o, ehr, v, feq, d, ux, uy, om, lam, a, gw);
+  adjoint_site<S, Q, COLL, SELMRT>(A, B, o, ehr, v, feq, d, ux, uy, om, lam, a, gw);
   push_adjoint<R, Q>(A, B.lam_out, x, y, a);
   if (B.gom) __builtin_nontemporal_store(__builtin_nontemporal_load(&B.gom[o]) + gw, &B.gom[o]);
 }
@@ -347,7 +353,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const StepArgs<typename StoreT<
 // k_median_gather.  dL/dc = sum_i a_i (p_i - f*_i); dc/dDelta S = -c /
 // (2 Delta S); dc/dmed = c / (2 med), taken as 0 where med = 0 (the site
 // was mapped onto f*; the one-sided derivative is infinite).
-template <class S, int Q, int COLL, int TX, int TY>
+template <class S, int Q, int COLL, int TX, int TY, bool SELMRT = false>
 __global__ __launch_bounds__(256) void k_adjoint_med(const StepArgs<typename StoreT<S>::R> A,
                                                      const AdjArgs<typename StoreT<S>::R> B) {
   using R = typename StoreT<S>::R;
@@ -419,7 +425,7 @@ __global__ __launch_bounds__(256) void k_adjoint_med(const StepArgs<typename Sto
   R lam[Q], a[Q], gw;
 #pragma unroll
   for (int i = 0; i < Q; ++i) lam[i] = B.lam_in[(long long)i * A.qs + o];
-  adjoint_site<S, Q, COLL>(A, B, o, ehr, vt, feq, dt, ux, uy, om, lam, a, gw);
+  adjoint_site<S, Q, COLL, SELMRT>(A, B, o, ehr, vt, feq, dt, ux, uy, om, lam, a, gw);
   R gs = R(0), h = R(0);
   if (acc) {
     R sc = R(0), ra[Q], tf[Q];
@@ -559,7 +565,7 @@ static int grid_of(long long n) {
   return (int)(g < 1 ? 1 : (g > 65535 * 16 ? 65535 * 16 : g));
 }
 
-template <class S, int Q, int COLL>
+template <class S, int Q, int COLL, bool SELMRT>
 static void launch_adj_k(const StepArgs<typename StoreT<S>::R>& A,
                          const AdjArgs<typename StoreT<S>::R>& B, int g, hipStream_t s,
                          hipEvent_t e0, hipEvent_t e1) {
@@ -570,18 +576,18 @@ static void launch_adj_k(const StepArgs<typename StoreT<S>::R>& A,
     const dim3 gt(A.tiles_x * A.tiles_y);
     const int gs = (int)(((long long)A.nx * A.ny + 255) / 256);
     if (e0 || e1) {
-      hipExtLaunchKernelGGL((k_adjoint_med<S, Q, COLL, TX, TY>), gt, dim3(256), 0, s, e0, nullptr, 0, A, B);
+      hipExtLaunchKernelGGL((k_adjoint_med<S, Q, COLL, TX, TY, SELMRT>), gt, dim3(256), 0, s, e0, nullptr, 0, A, B);
       hipExtLaunchKernelGGL((k_median_gather<S, Q>), dim3(gs), dim3(256), 0, s, nullptr, e1, 0, A, B);
     } else {
-      hipLaunchKernelGGL((k_adjoint_med<S, Q, COLL, TX, TY>), gt, dim3(256), 0, s, A, B);
+      hipLaunchKernelGGL((k_adjoint_med<S, Q, COLL, TX, TY, SELMRT>), gt, dim3(256), 0, s, A, B);
       hipLaunchKernelGGL((k_median_gather<S, Q>), dim3(gs), dim3(256), 0, s, A, B);
     }
     return;
   }
   if (e0 || e1)
-    hipExtLaunchKernelGGL((k_adjoint<S, Q, COLL>), dim3(g), dim3(256), 0, s, e0, e1, 0, A, B);
+    hipExtLaunchKernelGGL((k_adjoint<S, Q, COLL, SELMRT>), dim3(g), dim3(256), 0, s, e0, e1, 0, A, B);
   else
-    hipLaunchKernelGGL((k_adjoint<S, Q, COLL>), dim3(g), dim3(256), 0, s, A, B);
+    hipLaunchKernelGGL((k_adjoint<S, Q, COLL, SELMRT>), dim3(g), dim3(256), 0, s, A, B);
 }
 
 template <class S, int Q>
@@ -591,10 +597,21 @@ static hipError_t launch_adj_q(int coll, const void* sargs, const void* aargs, h
   const StepArgs<R>& A = *(const StepArgs<R>*)sargs;
   const AdjArgs<R>& B = *(const AdjArgs<R>*)aargs;
   const int g = (int)(((long long)A.nx * A.ny + 255) / 256);
-  if (coll == COLL_LBGK) launch_adj_k<S, Q, COLL_LBGK>(A, B, g, s, e0, e1);
-  else if (coll == COLL_ELBM) launch_adj_k<S, Q, COLL_ELBM>(A, B, g, s, e0, e1);
-  else if constexpr (Q == 9) launch_adj_k<S, Q, COLL_MRT>(A, B, g, s, e0, e1);
-  else return hipErrorInvalidValue;
+  if (coll == COLL_LBGK) {
+    if constexpr (Q == 9) {
+      if (A.sel_mrt) {
+        launch_adj_k<S, Q, COLL_LBGK, true>(A, B, g, s, e0, e1);
+        return hipGetLastError();
+      }
+    }
+    launch_adj_k<S, Q, COLL_LBGK, false>(A, B, g, s, e0, e1);
+  } else if (coll == COLL_ELBM) {
+    launch_adj_k<S, Q, COLL_ELBM, false>(A, B, g, s, e0, e1);
+  } else if constexpr (Q == 9) {
+    launch_adj_k<S, Q, COLL_MRT, false>(A, B, g, s, e0, e1);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
