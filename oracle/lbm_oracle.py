@@ -37,7 +37,8 @@ __all__ = [
     "Lattice", "Config", "relaxation_rate", "phi_poly", "phi_entropic",
     "equilibrium", "moments", "velocity", "stream", "entropy", "h_fn",
     "kullback_dS", "lbgk", "mrt_basis", "mrt_rates", "mrt_preset_rates", "mrt", "elbm_alpha",
-    "elbm", "positivity", "median_filter", "ehrenfest_select", "step", "run",
+    "elbm", "positivity", "median_filter", "ehrenfest_select", "ens_threshold",
+    "ens_phi", "ensemble_limiter", "step", "run",
     "stats", "init_equilibrium", "ELBM_ROOT", "ELBM_CUTOFF", "ELBM_NOROOT",
     "ELBM_NONPOS",
 ]
@@ -100,6 +101,15 @@ class Config:
     sel_action: str = "equilibrium"
     ehr_k: int = 0
     ehr_delta: float = 0.0
+    # ensemble-dependent and smooth limiters of section 4 (acting on the
+    # pre-collision state): none | threshold (eqs. EntThresh, entrHom) |
+    # smooth (eq. phiExamp) | double_monotone (eq. DoublMonSpec) | pointwise
+    # (phi = 1 / (1 + alpha Delta S^k))
+    ens_limiter: str = "none"
+    ens_delta0: float = 0.1      # dissipation budget delta_0 of eq. LimEntLim
+    ens_delta: float = 0.0       # lower bound delta of the threshold
+    ens_alpha: float = 1.0
+    ens_k: float = 1.0
     median: bool = False
     med_delta: float = 1e-3
     positivity: bool = False
@@ -522,6 +532,84 @@ def median_filter(lat: Lattice, cfg: Config, f, feq, dS):
     return feq + coef.unsqueeze(0) * (f - feq), accept
 
 
+def ens_threshold(dS: torch.Tensor, production: float, delta0: float) -> float:
+    """Delta S_0 of eq. EntThresh over the lattice's own values (the
+    histogram's density taken as the empirical distribution of Delta S):
+    sum over sites with Delta S > Delta S_0 of (Delta S - Delta S_0) equals
+    delta_0 times the LBGK entropy production `production`.  The left side
+    falls continuously and piecewise linearly from sum Delta S (at 0) to 0
+    (at the largest value); between consecutive values taken in descending
+    order, with the j largest above the threshold, it is S_j - j s.
+    Reading: sites with Delta S = +inf are left out."""
+    v = torch.sort(dS[torch.isfinite(dS)].flatten(), descending=True).values
+    rhs = delta0 * production
+    if v.numel() == 0 or rhs <= 0:
+        return float(v[0]) if v.numel() else 0.0
+    cums = torch.cumsum(v, 0)
+    if rhs >= float(cums[-1]):
+        return 0.0
+    nxt = torch.cat([v[1:], torch.zeros(1, dtype=v.dtype)])
+    j = torch.arange(1, v.numel() + 1, dtype=v.dtype)
+    lhs_at_next = cums - j * nxt         # the left side at the next value down
+    i = int(torch.nonzero(lhs_at_next >= rhs)[0])
+    return float((cums[i] - rhs) / (i + 1))
+
+
+def ens_phi(cfg: "Config", dS: torch.Tensor, mean_dS: float, dS_t: float) -> torch.Tensor:
+    """The coefficient phi of the limiter f* + phi (f - f*) at every site:
+      threshold        sqrt(Delta S_t / Delta S) where Delta S >= Delta S_t
+                       (eq. entrHom), else 1;
+      smooth           (1 + r^(k - 1/2)) / (1 + r^k), r = Delta S /
+                       (alpha E(Delta S))  (eq. phiExamp);
+      double_monotone  (1 + (Delta S / Delta S_t)^k)^(-1/(2k))  (eq. DoublMonSpec);
+      pointwise        1 / (1 + alpha Delta S^k)  (section 4, smooth limiters).
+    Reading: a site with Delta S = +inf (a non-positive population) gets the
+    common limit phi = 0, i.e. f*."""
+    fin = torch.isfinite(dS)
+    x = torch.where(fin, dS, torch.zeros_like(dS))
+    if cfg.ens_limiter == "threshold":
+        phi = torch.where(x >= dS_t, torch.sqrt(dS_t / torch.where(x > 0, x, torch.ones_like(x))),
+                          torch.ones_like(x))
+        phi = torch.where(x >= dS_t, phi, torch.ones_like(x))
+    elif cfg.ens_limiter == "smooth":
+        r = x / (cfg.ens_alpha * mean_dS)
+        phi = (1 + r ** (cfg.ens_k - 0.5)) / (1 + r ** cfg.ens_k)
+    elif cfg.ens_limiter == "double_monotone":
+        phi = (1 + (x / dS_t) ** cfg.ens_k) ** (-1.0 / (2 * cfg.ens_k))
+    elif cfg.ens_limiter == "pointwise":
+        phi = 1.0 / (1.0 + cfg.ens_alpha * x ** cfg.ens_k)
+    else:
+        raise ValueError(cfg.ens_limiter)
+    return torch.where(fin, phi, torch.zeros_like(phi))
+
+
+def ensemble_limiter(cfg: "Config", f, feq, dS, omega):
+    """Section 4, "Monitoring total dissipation": the LBGK entropy production
+    of the step in quadratic approximation, [1 - (2 beta - 1)^2] sum Delta S
+    with beta = omega / 2 (per site under an omega field), the threshold
+    Delta S_t = max(Delta S_0, delta) from eq. EntThresh, the mean E(Delta S),
+    and the limiter f* + phi (f - f*).  Returns (f_new, info) with the
+    limiter's own production in the same approximation,
+    sum (1 - phi^2) Delta S.  Reading: E(Delta S) and both sums are over the
+    sites with finite Delta S.  delta_0 <= 0 fixes Delta S_t = delta (a
+    pointwise threshold)."""
+    om = torch.as_tensor(omega, dtype=DT)
+    fin = torch.isfinite(dS)
+    x = torch.where(fin, dS, torch.zeros_like(dS))
+    c = 1.0 - (om - 1.0) ** 2
+    production = float((c * x).sum())
+    mean_dS = float(x.sum() / fin.sum().clamp(min=1))
+    if cfg.ens_delta0 > 0:
+        dS_t = max(ens_threshold(dS.detach(), production, cfg.ens_delta0), cfg.ens_delta)
+    else:
+        dS_t = cfg.ens_delta
+    phi = ens_phi(cfg, dS, mean_dS, dS_t)
+    out = feq + phi.unsqueeze(0) * (f - feq)
+    lim_production = float(((1.0 - phi.detach() ** 2) * x.detach()).sum())
+    return out, {"lbgk_production": production, "limiter_production": lim_production,
+                 "threshold": dS_t, "mean_dS": mean_dS, "phi": phi.detach()}
+
+
 def ehrenfest_select(dS_flat: torch.Tensor, k: int, delta: float) -> torch.Tensor:
     """Ehrenfests' regularisation with a budget (section 4): the k sites with
     the highest Delta S > delta, ties broken by the lower linear index
@@ -549,12 +637,14 @@ def step(lat: Lattice, cfg: Config, g: torch.Tensor,
     omega = omega_field if omega_field is not None else relaxation_rate(cfg)
     info = {}
     dS = None
-    if cfg.ehrenfest or cfg.median:
+    if cfg.ehrenfest or cfg.median or cfg.ens_limiter != "none":
         dS = kullback_dS(pre, feq)
         info["dS"] = dS.detach()
     if cfg.median:
         pre, acc = median_filter(lat, cfg, pre, feq, dS)
         info["median_mask"] = acc
+    if cfg.ens_limiter != "none":
+        pre, info["ensemble"] = ensemble_limiter(cfg, pre, feq, dS, omega)
     sel = None
     if cfg.ehrenfest:
         sel = ehrenfest_select(dS.detach().flatten(), cfg.ehr_k, cfg.ehr_delta)

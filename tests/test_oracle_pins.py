@@ -677,6 +677,101 @@ def test_ehrenfest_all_sites_is_omega_one():
     assert torch.allclose(a, b, atol=1e-16, rtol=0)
 
 
+# ---------------------------------------------------------------- ensemble limiters
+def test_ens_threshold_solves_entthresh_by_brute_force():
+    """Eq. EntThresh over an empirical distribution: the returned Delta S_0
+    satisfies sum_{Delta S > Delta S_0} (Delta S - Delta S_0) = delta_0 P by
+    direct summation, for distinct values, ties and zeros, and the left side
+    is strictly larger just below it (unique root); delta_0 P at or above
+    sum Delta S gives 0; +inf values are ignored."""
+    rng = np.random.default_rng(101)
+    cases = [rng.exponential(1e-3, 40), np.array([5e-3] * 7 + [1e-3] * 5 + [0.0] * 4),
+             rng.lognormal(-8, 2, 300)]
+    for vals in cases:
+        dS = torch.tensor(vals)
+        P = float(dS.sum())
+        for d0 in (1e-3, 0.05, 0.3, 0.9):
+            s0 = O.ens_threshold(dS, P, d0)
+            lhs = float(torch.clamp(dS - s0, min=0).sum())
+            assert abs(lhs - d0 * P) <= 1e-12 * P
+            assert float(torch.clamp(dS - s0 * (1 - 1e-9), min=0).sum()) > d0 * P
+        assert 0.0 <= O.ens_threshold(dS, P, 1.0) <= 1e-14 * float(dS.max())
+    dS = torch.tensor([1e-3, 2e-3, math.inf, 4e-3], dtype=DT)
+    s0 = O.ens_threshold(dS, 7e-3, 0.1)
+    assert abs(float(torch.clamp(dS[torch.isfinite(dS)] - s0, min=0).sum()) - 7e-4) < 1e-15
+
+
+def test_ensemble_phi_closed_forms():
+    """The phi of section 4.  phiExamp: 1 at Delta S = alpha E, -> 1 for
+    small Delta S, -> sqrt(alpha E / Delta S) for large.  DoublMonSpec: the
+    solution exp(-1/2 int_0^x eta(chi)/chi dchi) of eq. DoublMonGen with
+    eta = x^k / (Delta S_t^k + x^k) (numerical quadrature), double monotone
+    (phi + 2 x phi' >= 0, phi' <= 0), 1 - x^k / (2k Delta S_t^k) for small
+    x and sqrt(Delta S_t / x) for large.  Pointwise 1/(1 + alpha x^k) is
+    dissipative.  Threshold: entrHom above Delta S_t, 1 below.  phi = 0 at
+    Delta S = +inf."""
+    cfg = O.Config(ens_alpha=2.0, ens_k=1.5)
+    x = torch.tensor([1e-9, 1e-6, 1e-4, 1e-3, 2e-3, 1e-1, 10.0, math.inf], dtype=DT)
+    E, t = 1e-3, 2e-3
+    sm = O.ens_phi(cfg.with_(ens_limiter="smooth"), x, E, t)
+    assert abs(float(sm[4]) - 1.0) < 1e-15 and abs(float(sm[0]) - 1) < 1e-5
+    assert abs(float(sm[6]) / math.sqrt(2 * E / 10.0) - 1) < 2e-2 and float(sm[7]) == 0.0
+    for k in (0.5, 1.0, 2.0):
+        c = cfg.with_(ens_limiter="double_monotone", ens_k=k)
+        xs = torch.tensor(np.geomspace(1e-7, 1e2, 400))
+        ph = O.ens_phi(c, xs, E, t)
+        # eq. DoublMonGen by quadrature in log chi
+        lx = np.log(xs.numpy())
+        eta = xs.numpy() ** k / (t ** k + xs.numpy() ** k)
+        integ = np.concatenate([[eta[0] / k], eta[0] / k + np.cumsum(0.5 * (eta[1:] + eta[:-1]) * np.diff(lx))])
+        ref = np.exp(-0.5 * integ)
+        assert np.allclose(ph.numpy(), ref, rtol=2e-4)
+        d = np.gradient(ph.numpy(), xs.numpy())
+        # finite differences on the geometric grid: error about 2e-4 where
+        # phi + 2 x phi' tends to 0
+        assert (d <= 1e-12).all() and (ph.numpy() + 2 * xs.numpy() * d >= -1e-3).all()
+        u = (float(xs[0]) / t) ** k            # second-order remainder O(u^2)
+        assert abs(float(ph[0]) - (1 - u / (2 * k))) < u * u + 4e-16
+        assert abs(float(ph[-1]) / math.sqrt(t / float(xs[-1])) - 1) < 1e-2
+    pw = O.ens_phi(cfg.with_(ens_limiter="pointwise"), x, E, t)
+    assert bool(((pw >= 0) & (pw <= 1)).all())
+    th = O.ens_phi(cfg.with_(ens_limiter="threshold"), x, E, t)
+    assert torch.equal(th[:4], torch.ones(4, dtype=DT)) and float(th[4]) == 1.0
+    assert abs(float(th[5]) - math.sqrt(t / 0.1)) < 1e-15 and float(th[7]) == 0.0
+
+
+def test_threshold_limiter_dissipation_budget():
+    """Section 4, "Monitoring total dissipation": with Delta S_t = Delta S_0 of
+    eq. EntThresh (above delta), the threshold limiter's entropy production in
+    quadratic approximation, sum (1 - phi^2) Delta S, is exactly delta_0
+    times the LBGK production [1 - (2 beta - 1)^2] sum Delta S; the limited
+    sites' Delta S becomes Delta S_t in that approximation and the moments
+    are kept.  A whole step with the limiter on agrees with the limiter
+    applied by hand before the LBGK collision."""
+    g = rand_state(L2, 12, 12, 102, amp=0.2)
+    cfg = O.Config(nx=12, ny=12, bc="periodic", nu=1e-3, ens_limiter="threshold",
+                   ens_delta0=0.05, ens_delta=0.0)
+    pre = O.stream(L2, g, "periodic")
+    r, vx, vy = O.velocity(L2, pre)
+    q = O.equilibrium(L2, r, vx, vy)
+    dS = O.kullback_dS(pre, q)
+    om = O.relaxation_rate(cfg)
+    out, info = O.ensemble_limiter(cfg, pre, q, dS, om)
+    P = (1 - (om - 1) ** 2) * float(dS.sum())
+    assert abs(info["lbgk_production"] - P) <= 1e-12 * P
+    assert abs(info["limiter_production"] - 0.05 * P) <= 1e-11 * P
+    acc = dS >= info["threshold"]
+    assert 0 < int(acc.sum()) < 144
+    approx = (info["phi"] ** 2 * dS)[acc]
+    assert torch.allclose(approx, torch.full_like(approx, info["threshold"]), rtol=1e-12)
+    for a, b in zip(O.moments(L2, out), O.moments(L2, pre)):
+        assert torch.allclose(a, b, atol=1e-15, rtol=0)
+    full, inf2 = O.step(L2, cfg, g)
+    by_hand = O.lbgk(out, q, om)
+    assert torch.allclose(full, by_hand, atol=1e-16, rtol=0)
+    assert inf2["ensemble"]["threshold"] == info["threshold"]
+
+
 # ---------------------------------------------------------------- median
 def _median_brute(dS, periodic):
     ny, nx = dS.shape
