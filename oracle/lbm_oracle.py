@@ -599,7 +599,9 @@ def ensemble_limiter(cfg: "Config", f, feq, dS, omega):
     c = 1.0 - (om - 1.0) ** 2
     production = float((c * x).sum())
     mean_dS = float(x.sum() / fin.sum().clamp(min=1))
-    if cfg.ens_delta0 > 0:
+    if cfg.ens_limiter not in ("threshold", "double_monotone"):
+        dS_t = math.inf                  # the limiter has no threshold
+    elif cfg.ens_delta0 > 0:
         dS_t = max(ens_threshold(dS.detach(), production, cfg.ens_delta0), cfg.ens_delta)
     else:
         dS_t = cfg.ens_delta
