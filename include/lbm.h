@@ -87,6 +87,25 @@ enum { LBM_RATES_GIVEN = 0, LBM_RATES_TRT = 1, LBM_RATES_MRT_TRTQ = 2, LBM_RATES
  * lattices, D2Q9 only).  The positivity rule, when on, then also acts on
  * them. */
 enum { LBM_SEL_EQUILIBRIUM = 0, LBM_SEL_MRT = 1 };
+/* Ensemble-dependent and smooth limiters of section 4, applied to every
+ * site's pre-collision state as f* + phi (f - f*) (not with the median
+ * filter; no adjoint):
+ *   THRESHOLD        phi = sqrt(Delta S_t / Delta S) where Delta S >= Delta S_t,
+ *                    else 1 (eq. entrHom);
+ *   SMOOTH           phi = (1 + r^(k-1/2)) / (1 + r^k), r = Delta S / (alpha
+ *                    E(Delta S)), E the mean over the lattice (eq. phiExamp);
+ *   DOUBLE_MONOTONE  phi = (1 + (Delta S / Delta S_t)^k)^(-1/(2k)) (eq. DoublMonSpec);
+ *   POINTWISE        phi = 1 / (1 + alpha Delta S^k).
+ * Delta S_t = max(Delta S_0, ens_delta), with Delta S_0 the exact solution
+ * over the lattice's Delta S values of eq. EntThresh:
+ *   sum over sites of max(Delta S - Delta S_0, 0) = ens_delta0 * P,
+ *   P = sum over sites of [1 - (omega - 1)^2] Delta S (the LBGK entropy
+ *   production in quadratic approximation, section 4 "Monitoring total
+ *   dissipation"); ens_delta0 <= 0 fixes Delta S_t = ens_delta.
+ * Sites with Delta S = +inf (a non-positive population) take phi = 0 and are
+ * left out of E and of the sums. */
+enum { LBM_ENS_NONE = 0, LBM_ENS_THRESHOLD = 1, LBM_ENS_SMOOTH = 2,
+       LBM_ENS_DOUBLE_MONOTONE = 3, LBM_ENS_POINTWISE = 4 };
 enum { LBM_LIM_EHRENFEST = 1, LBM_LIM_POSITIVITY = 2, LBM_LIM_MEDIAN = 4 };
 enum { LBM_NORM_ENTROPIC = 0, LBM_NORM_L1 = 1 };
 enum { LBM_FB_POSITIVITY = 0, LBM_FB_EHRENFEST = 1 };
@@ -125,6 +144,11 @@ typedef struct lbm_config {
   int check_interval;     /* steps between divergence checks (0: only on lbm_stats) */
   int mrt_preset;         /* LBM_RATES_* (M1 basis; GIVEN uses s_e, s_eps, s_q)   */
   int sel_action;         /* LBM_SEL_EQUILIBRIUM | LBM_SEL_MRT                   */
+  int ens_limiter;        /* LBM_ENS_*                                          */
+  double ens_delta0;      /* dissipation budget delta_0 of eq. EntThresh        */
+  double ens_delta;       /* lower bound delta of the threshold                 */
+  double ens_alpha;       /* alpha of SMOOTH and POINTWISE                      */
+  double ens_k;           /* exponent k of SMOOTH, DOUBLE_MONOTONE, POINTWISE   */
 } lbm_config;
 
 typedef struct lbm_stats {
@@ -139,6 +163,15 @@ typedef struct lbm_stats {
   long long select_overflow;  /* steps whose boundary list overflowed          */
   long long select_candidates;/* Ehrenfest candidates examined, all steps      */
   int nonfinite;          /* 1 if the last check found NaN or Inf               */
+  /* ensemble limiters, last step: Delta S_t (THRESHOLD, DOUBLE_MONOTONE;
+   * +inf for the others), E(Delta S), the LBGK entropy production
+   * [1 - (omega - 1)^2] sum Delta S and the limiter's own,
+   * sum (1 - phi^2) Delta S (both in quadratic approximation); all 0
+   * without an ensemble limiter */
+  double ens_threshold;
+  double ens_mean;
+  double lbgk_production;
+  double limiter_production;
 } lbm_stats;
 
 typedef struct lbm_ctx lbm_ctx;

@@ -41,7 +41,8 @@ struct Layout {
   size_t off_lat[2] = {0, 0}, off_omega = 0, off_sel = 0, off_cnt = 0, off_partial = 0,
          off_stats = 0, off_div = 0, off_ckey = 0, off_cidx = 0, off_cmom = 0, off_hist = 0,
          off_coarse = 0, off_wcount = 0, off_ccount = 0, off_stage = 0, off_blist = 0,
-         off_selected = 0, off_f64list = 0, off_f64cnt = 0;
+         off_selected = 0, off_f64list = 0, off_f64cnt = 0, off_ens = 0, off_ens_dsb = 0,
+         off_ens_cnt = 0, off_ens_sum = 0;
   AdjointLayout adj;
   size_t total = 0;
 };
@@ -73,6 +74,18 @@ bool validate(const lbm_config* c, std::string& why) {
       (!(c->limiters & LBM_LIM_EHRENFEST) || c->collision != LBM_LBGK || c->lattice != LBM_D2Q9)) {
     why = "the MRT limiter (sel_action = LBM_SEL_MRT) needs the Ehrenfest selection, LBGK and D2Q9";
     return false;
+  }
+  if (c->ens_limiter < LBM_ENS_NONE || c->ens_limiter > LBM_ENS_POINTWISE) { why = "unknown ens_limiter"; return false; }
+  if (c->ens_limiter != LBM_ENS_NONE) {
+    if (c->limiters & LBM_LIM_MEDIAN) { why = "the ensemble limiters and the median filter exclude each other"; return false; }
+    if (c->checkpoint_every > 0) { why = "the adjoint does not cover the ensemble limiters (checkpoint_every must be 0)"; return false; }
+    if (!(c->ens_k > 0) || !(c->ens_alpha > 0) || !(c->ens_delta >= 0)) {
+      why = "ens_k and ens_alpha must be > 0 and ens_delta >= 0"; return false;
+    }
+    if ((c->ens_limiter == LBM_ENS_THRESHOLD || c->ens_limiter == LBM_ENS_DOUBLE_MONOTONE) &&
+        !(c->ens_delta0 > 0) && !(c->ens_delta > 0)) {
+      why = "a threshold needs ens_delta0 > 0 (eq. EntThresh) or ens_delta > 0"; return false;
+    }
   }
   if (c->checkpoint_every < 0 || c->max_steps < 0) { why = "checkpoint_every/max_steps must be >= 0"; return false; }
   if (c->checkpoint_every > 0 && c->max_steps < 1) { why = "checkpoint_every > 0 needs max_steps >= 1"; return false; }
@@ -123,6 +136,12 @@ Layout make_layout(const lbm_config* c, bool lattices = true) {
   if (c->collision == LBM_ELBM && !is_f64(c->storage)) {
     L.off_f64list = take((size_t)L.n_sites * 4);
     L.off_f64cnt = take(2 * sizeof(unsigned int));
+  }
+  if (c->ens_limiter != LBM_ENS_NONE) {
+    L.off_ens = take(sizeof(EnsState));
+    L.off_ens_dsb = take((size_t)L.qs * rb);
+    L.off_ens_cnt = take((size_t)kEnsBins * 4);
+    L.off_ens_sum = take((size_t)kEnsBins * 8);
   }
   if (lattices) {
     L.adj = adjoint_layout(c, L.lat_bytes, L.qs, L.k, o);
@@ -254,6 +273,16 @@ void fill_args(StepArgs<R>& A, const lbm_config* c, const Layout& L, char* ws) {
   A.ehr_delta = (R)c->ehr_delta;
   A.sel = (SelState*)(ws + L.off_sel);
   A.counters = (unsigned long long*)(ws + L.off_cnt);
+  A.ens_mode = c->ens_limiter;
+  A.ens_alpha = (R)c->ens_alpha;
+  A.ens_k = (R)c->ens_k;
+  A.ens_delta = (R)c->ens_delta;
+  if (c->ens_limiter != LBM_ENS_NONE) {
+    A.ens = (EnsState*)(ws + L.off_ens);
+    A.ens_dsb = (R*)(ws + L.off_ens_dsb);
+    A.ens_cnt = (unsigned int*)(ws + L.off_ens_cnt);
+    A.ens_sum = (double*)(ws + L.off_ens_sum);
+  }
   A.f64_sites = L.off_f64list ? (uint32_t*)(ws + L.off_f64list) : nullptr;
   A.f64_count = L.off_f64cnt ? (unsigned int*)(ws + L.off_f64cnt) : nullptr;
   if (A.ehrenfest) {
@@ -343,6 +372,7 @@ lbm_status lbm_init(const lbm_config* cfg, void* ws, size_t ws_bytes, void* stre
   hipError_t e = hipMemcpyAsync(c->ws + L.off_sel, &s0, sizeof(SelState), hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.off_cnt, 0, (size_t)kCntSlots * CNT_N * 8, c->stream);
+  if (e == hipSuccess && L.off_ens) e = hipMemsetAsync(c->ws + L.off_ens, 0, sizeof(EnsState), c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.off_div, 0xff, sizeof(long long), c->stream);
   if (e == hipSuccess && L.off_f64cnt)
     e = hipMemsetAsync(c->ws + L.off_f64cnt, 0, 2 * sizeof(unsigned int), c->stream);
@@ -448,8 +478,12 @@ static hipError_t one_step(lbm_ctx* c, hipEvent_t ev0 = nullptr, hipEvent_t ev1 
   const void* args;
   if (c->f64()) { c->a64.src = c->lat(src); c->a64.dst = c->lat(dst); args = &c->a64; }
   else { c->a32.src = c->lat(src); c->a32.dst = c->lat(dst); args = &c->a32; }
-  hipError_t e = launch_step(c->cfg.storage, c->L.Q, c->cfg.collision, med, args, c->stream,
-                             ev0, ev1);
+  hipError_t e = hipSuccess;
+  if (c->cfg.ens_limiter != LBM_ENS_NONE)
+    e = launch_ensemble(c->cfg.storage, c->L.Q, args, c->cfg.ens_delta0, c->cfg.ens_delta,
+                        c->stream);
+  if (e == hipSuccess)
+    e = launch_step(c->cfg.storage, c->L.Q, c->cfg.collision, med, args, c->stream, ev0, ev1);
   if (e != hipSuccess) return e;
   if (c->cfg.limiters & LBM_LIM_EHRENFEST) {
     SelectArgs sa = select_args(c, args);
@@ -661,6 +695,22 @@ lbm_status lbm_stats_get(lbm_ctx* c, lbm_stats* out) {
   out->select_fallbacks = (long long)sel.fallbacks;
   out->select_overflow = (long long)sel.overflows;
   out->select_candidates = (long long)sel.cand_total;
+  if (c->cfg.ens_limiter != LBM_ENS_NONE) {
+    EnsState es;
+    e = hipMemcpy(&es, c->ws + c->L.off_ens, sizeof(es), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "lbm_stats");
+    const bool thr = c->cfg.ens_limiter == LBM_ENS_THRESHOLD ||
+                     c->cfg.ens_limiter == LBM_ENS_DOUBLE_MONOTONE;
+    out->ens_threshold = thr ? es.threshold : __builtin_huge_val();
+    double sdS = 0.0, n = 0.0;
+    for (int k = 0; k < kEnsSlots; ++k) {
+      out->lbgk_production += es.step_acc[k][0];
+      out->limiter_production += es.step_acc[k][1];
+      sdS += es.step_acc[k][2];
+      n += es.step_acc[k][3];
+    }
+    out->ens_mean = n > 0.0 ? sdS / n : 0.0;
+  }
   if (div >= 0) return fail(LBM_EDIVERGED, "non-finite value or rho <= 0 found at step " + std::to_string(div));
   if (sel.overflows) return fail(LBM_ESELECT, "Ehrenfest boundary list overflowed: more than 2^20 sites tie within one histogram bucket");
   return LBM_OK;

@@ -66,6 +66,33 @@ enum Counter : int {
 // one step's atomics do not queue on a single address.
 constexpr int kCntSlots = 64;
 
+// Device state of the ensemble limiters (section 4): the step's threshold
+// and mean, the radix descent that solves eq. EntThresh over the lattice's
+// Delta S values, and the monitor's sums.
+enum EnsMode : int { ENS_NONE = 0, ENS_THRESHOLD = 1, ENS_SMOOTH = 2, ENS_DOUBLE_MONOTONE = 3,
+                     ENS_POINTWISE = 4 };
+constexpr int kEnsBins = 4096;        // radix of the descent: 12 bits per level
+struct EnsState {
+  double sum_dS;        // sum of the finite Delta S (pre-pass)
+  double production;    // sum of [1 - (omega - 1)^2] Delta S (pre-pass)
+  double n_finite;      // sites with finite Delta S (pre-pass)
+  double threshold;     // Delta S_t of the step (+inf: the limiter rests)
+  double mean;          // E(Delta S)
+  double rhs;           // delta_0 * production
+  double above_n;       // descent: values whose key lies above the resolved range
+  double above_s;       //          and their sum
+  unsigned long long prefix;  // descent: key bits resolved so far
+  int prefix_bits;
+  int active;           // descent still running
+  int pad[5];
+  // the step kernel's monitor sums of the step, spread over kEnsSlots copies
+  // (a workgroup adds to copy blockIdx mod kEnsSlots): [slot][0] the LBGK
+  // production, [slot][1] sum (1 - phi^2) Delta S, [slot][2] sum Delta S,
+  // [slot][3] sites with finite Delta S; cleared before each step
+  double step_acc[64][4];
+};
+constexpr int kEnsSlots = 64;
+
 template <class R> struct KeyOf;
 template <> struct KeyOf<float> { using T = uint32_t; };
 template <> struct KeyOf<double> { using T = unsigned long long; };
@@ -119,6 +146,14 @@ struct StepArgs {
   // or nullptr
   R* alpha_out;
   unsigned char* branch_out;
+  // ensemble limiters: mode, parameters, device state; dsb (pre-pass Delta S
+  // per site, [ny][pitch]) and the descent histogram
+  int ens_mode;
+  R ens_alpha, ens_k, ens_delta;
+  EnsState* ens;
+  R* ens_dsb;
+  unsigned int* ens_cnt;      // kEnsBins
+  double* ens_sum;            // kEnsBins
   // ELBM with FP32 arithmetic: the step kernels list the sites whose root
   // solve needs FP64 (site index) and k_elbm_f64 finishes them, so that the
   // step kernels do not carry the FP64 solve's registers; [0] count,
@@ -151,6 +186,13 @@ hipError_t launch_stats(int storage, int Q, const void* lat, long long qs, int n
                         int pitch, double rho0, double* partial, double* out,
                         long long* diverged_step, long long step, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+// Ensemble limiters: before the step kernel, the pre-pass (Delta S of every
+// site, E(Delta S), the LBGK production) and, with a dissipation budget, the
+// descent that solves eq. EntThresh; leaves the step's threshold and mean in
+// the EnsState.  delta0 <= 0: fixed threshold delta.
+hipError_t launch_ensemble(int storage, int Q, const void* step_args, double delta0,
+                           double delta, hipStream_t s);
+
 
 // Ehrenfest selection after a step (selection kernels).
 struct SelectArgs {

@@ -224,8 +224,11 @@ __global__ __launch_bounds__(256) void k_elbm_f64(const StepArgs<typename StoreT
 // LBGK in FP32/16-bit storage on row tiles fits 64 registers: keep the full
 // occupancy of 8 wavefronts per SIMD (the compiler would otherwise take a few
 // more).
-template <class S, int Q, int COLL, bool MEDIAN, int TX, int TY, bool PER>
-__global__ __launch_bounds__(256, ((COLL == COLL_LBGK && sizeof(S) <= 4 && !MEDIAN && TX == 256) ? 8 : 1))
+// ENS: the ensemble or smooth limiter of section 4 acts on the pulled state
+// (f* + phi (f - f*), phi from the site's Delta S and the step's threshold
+// and mean), and the workgroup adds the dissipation monitor's sums.
+template <class S, int Q, int COLL, bool MEDIAN, int TX, int TY, bool PER, bool ENS = false>
+__global__ __launch_bounds__(256, ((COLL == COLL_LBGK && sizeof(S) <= 4 && !MEDIAN && !ENS && TX == 256) ? 8 : 1))
 void k_step(const StepArgs<typename StoreT<S>::R> A) {
   using R = typename StoreT<S>::R;
   constexpr bool SH = StoreT<S>::shifted;
@@ -251,13 +254,60 @@ void k_step(const StepArgs<typename StoreT<S>::R> A) {
   const bool valid = x < A.nx && y < A.ny;
 
   unsigned long long* const cnt = A.counters + (blockIdx.x % kCntSlots) * CNT_N;
-  const bool need_dS = MEDIAN || A.ehrenfest;
+  const bool need_dS = MEDIAN || ENS || A.ehrenfest;
   // Without the median filter, Delta S only decides Ehrenfest candidacy:
   // sites provably below the floor skip its exact evaluation.
   const StepFrame fr = step_frame(A.sel);
-  const R screen = (!MEDIAN && A.ehrenfest) ? value_of_key<R>(fr.floor) : R(0);
+  const R screen = (!MEDIAN && !ENS && A.ehrenfest) ? value_of_key<R>(fr.floor) : R(0);
   R v[Q], feq[Q], d[Q], m0 = R(0), ux = R(0), uy = R(0), dS = R(0);
   if (valid) dS = site_prep<S, Q, PER>(A, x, y, v, feq, d, m0, ux, uy, need_dS, screen);
+
+  if constexpr (ENS) {
+    double prod = 0.0, lim = 0.0, sdS = 0.0, nfin = 0.0;
+    if (valid) {
+      const EnsState* E = A.ens;
+      const R t = (R)E->threshold;
+      R phi;
+      if (!(dS < r_inf<R>())) {
+        phi = R(0);                               // a non-positive population: f*
+      } else if (A.ens_mode == ENS_THRESHOLD) {   // eq. entrHom
+        phi = dS >= t ? sqrt(t / (dS > R(0) ? dS : R(1))) : R(1);
+      } else if (A.ens_mode == ENS_SMOOTH) {      // eq. phiExamp
+        const R r = dS / (A.ens_alpha * (R)E->mean);
+        phi = (R(1) + pow(r, A.ens_k - R(0.5))) / (R(1) + pow(r, A.ens_k));
+      } else if (A.ens_mode == ENS_DOUBLE_MONOTONE) {  // eq. DoublMonSpec
+        phi = pow(R(1) + pow(dS / t, A.ens_k), R(-0.5) / A.ens_k);
+      } else {                                    // pointwise 1 / (1 + alpha Delta S^k)
+        phi = R(1) / (R(1) + A.ens_alpha * pow(dS, A.ens_k));
+      }
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        v[i] = feq[i] + phi * (v[i] - feq[i]);
+        d[i] = feq[i] - v[i];
+      }
+      if (dS < r_inf<R>()) {
+        const R om = A.omega_field ? A.omega_field[(long long)y * A.pitch + x] : A.omega;
+        prod = (1.0 - ((double)om - 1.0) * ((double)om - 1.0)) * (double)dS;
+        lim = (1.0 - (double)phi * (double)phi) * (double)dS;
+        sdS = (double)dS;
+        nfin = 1.0;
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      prod += __shfl_xor(prod, o);
+      lim += __shfl_xor(lim, o);
+      sdS += __shfl_xor(sdS, o);
+      nfin += __shfl_xor(nfin, o);
+    }
+    if (__lane_id() == 0) {
+      double* acc = A.ens->step_acc[blockIdx.x % kEnsSlots];
+      atomicAdd(&acc[0], prod);
+      atomicAdd(&acc[1], lim);
+      atomicAdd(&acc[2], sdS);
+      atomicAdd(&acc[3], nfin);
+    }
+  }
 
   if constexpr (MEDIAN) {
     // Median entropy filter: Delta S of the tile plus a one-site halo in LDS.
@@ -323,7 +373,7 @@ void k_step(const StepArgs<typename StoreT<S>::R> A) {
     }
   }
 
-  constexpr bool DEFER = COLL == COLL_ELBM && sizeof(R) == 4 && !MEDIAN;
+  constexpr bool DEFER = COLL == COLL_ELBM && sizeof(R) == 4 && !MEDIAN && !ENS;
   site_finish<S, Q, COLL, true, DEFER>(A, x, y, valid, (long long)t * 4 + threadIdx.x / 64, v, feq, d, m0, ux,
                           uy, dS, fr, cnt);
 }
@@ -397,20 +447,31 @@ __global__ __launch_bounds__(256) void k_step_rows(const StepArgs<typename Store
 // ---------------------------------------------------------------------------
 // Launch dispatch.
 // ---------------------------------------------------------------------------
-template <class S, int Q, int COLL, bool MEDIAN, int TX, int TY, bool PER = false>
+template <class S, int Q, int COLL, bool MEDIAN, int TX, int TY, bool PER = false, bool ENS = false>
 static void launch_k(const StepArgs<typename StoreT<S>::R>& A, hipStream_t s, hipEvent_t e0,
                      hipEvent_t e1) {
   const dim3 grid(A.tiles_x * A.tiles_y), block(256);
   if (e0 && e1)  // events taken at the kernel's own start and end
-    hipExtLaunchKernelGGL((k_step<S, Q, COLL, MEDIAN, TX, TY, PER>), grid, block, 0, s, e0, e1, 0, A);
+    hipExtLaunchKernelGGL((k_step<S, Q, COLL, MEDIAN, TX, TY, PER, ENS>), grid, block, 0, s, e0, e1, 0, A);
   else
-    hipLaunchKernelGGL((k_step<S, Q, COLL, MEDIAN, TX, TY, PER>), grid, block, 0, s, A);
+    hipLaunchKernelGGL((k_step<S, Q, COLL, MEDIAN, TX, TY, PER, ENS>), grid, block, 0, s, A);
 }
 
 template <class S, int Q, int COLL, bool MEDIAN>
 static hipError_t launch_t(const void* args, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   using R = typename StoreT<S>::R;
   const StepArgs<R>& A = *(const StepArgs<R>*)args;
+  if constexpr (!MEDIAN) {
+    if (A.ens_mode != ENS_NONE) {
+      // the ensemble limiters run on the one-site kernel (no row pipeline,
+      // no deferred FP64 list: the limiter changed the state the list would
+      // rebuild)
+      if constexpr (Q == 3) launch_k<S, Q, COLL, false, 256, 1, false, true>(A, s, e0, e1);
+      else if (tile_shape(Q, false, A.nx).tx == 256) launch_k<S, Q, COLL, false, 256, 1, false, true>(A, s, e0, e1);
+      else launch_k<S, Q, COLL, false, 64, 4, false, true>(A, s, e0, e1);
+      return hipGetLastError();
+    }
+  }
   if constexpr (Q == 3) {
     launch_k<S, Q, COLL, MEDIAN, 256, 1>(A, s, e0, e1);
   } else if constexpr (MEDIAN) {

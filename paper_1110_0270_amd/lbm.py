@@ -30,6 +30,7 @@ LBM_FB_POSITIVITY, LBM_FB_EHRENFEST = 0, 1
 LBM_F64, LBM_F32, LBM_F16S, LBM_BF16S = 0, 1, 2, 3
 LBM_RATES_GIVEN, LBM_RATES_TRT, LBM_RATES_MRT_TRTQ, LBM_RATES_MRT1, LBM_RATES_SHEAR = 0, 1, 2, 3, 4
 LBM_SEL_EQUILIBRIUM, LBM_SEL_MRT = 0, 1
+LBM_ENS_NONE, LBM_ENS_THRESHOLD, LBM_ENS_SMOOTH, LBM_ENS_DOUBLE_MONOTONE, LBM_ENS_POINTWISE = 0, 1, 2, 3, 4
 
 EXPORTED = [
     "lbm_config_default", "lbm_workspace_bytes", "lbm_init", "lbm_set_equilibrium",
@@ -58,6 +59,9 @@ class lbm_config(ctypes.Structure):
         ("omega_field", ctypes.c_int), ("checkpoint_every", ctypes.c_int),
         ("max_steps", ctypes.c_longlong), ("check_interval", ctypes.c_int),
         ("mrt_preset", ctypes.c_int), ("sel_action", ctypes.c_int),
+        ("ens_limiter", ctypes.c_int), ("ens_delta0", ctypes.c_double),
+        ("ens_delta", ctypes.c_double), ("ens_alpha", ctypes.c_double),
+        ("ens_k", ctypes.c_double),
     ]
 
 
@@ -68,7 +72,9 @@ class lbm_stats(ctypes.Structure):
         ("steps", ctypes.c_longlong), ("diverged_step", ctypes.c_longlong),
         ("n_selected", ctypes.c_longlong), ("select_fallbacks", ctypes.c_longlong),
         ("select_overflow", ctypes.c_longlong), ("select_candidates", ctypes.c_longlong),
-        ("nonfinite", ctypes.c_int),
+        ("nonfinite", ctypes.c_int), ("ens_threshold", ctypes.c_double),
+        ("ens_mean", ctypes.c_double), ("lbgk_production", ctypes.c_double),
+        ("limiter_production", ctypes.c_double),
     ]
 
 
@@ -254,6 +260,8 @@ _STORE = {"f64": LBM_F64, "f32": LBM_F32, "f16s": LBM_F16S, "bf16s": LBM_BF16S}
 _PRESET = {"given": LBM_RATES_GIVEN, "trt": LBM_RATES_TRT, "mrt_trtq": LBM_RATES_MRT_TRTQ,
            "mrt1": LBM_RATES_MRT1, "shear": LBM_RATES_SHEAR}
 _SEL = {"equilibrium": LBM_SEL_EQUILIBRIUM, "mrt": LBM_SEL_MRT}
+_ENS = {"none": LBM_ENS_NONE, "threshold": LBM_ENS_THRESHOLD, "smooth": LBM_ENS_SMOOTH,
+        "double_monotone": LBM_ENS_DOUBLE_MONOTONE, "pointwise": LBM_ENS_POINTWISE}
 
 
 def make_config(*, lattice="D2Q9", nx=64, ny=64, bc="periodic", u_lid=0.0, rho_wall=1.0,
@@ -263,7 +271,9 @@ def make_config(*, lattice="D2Q9", nx=64, ny=64, bc="periodic", u_lid=0.0, rho_w
                 elbm_fallback="positivity", elbm_eps=1e-14, elbm_max_iter=32,
                 elbm_dS_cut=1e-15, elbm_f64_below=3.0, storage="f32", rho0=1.0,
                 omega_field=False, checkpoint_every=0, max_steps=0, check_interval=0,
-                mrt_preset="given", sel_action="equilibrium", **_ignored) -> lbm_config:
+                mrt_preset="given", sel_action="equilibrium", ens_limiter="none",
+                ens_delta0=0.1, ens_delta=0.0, ens_alpha=1.0, ens_k=1.0,
+                **_ignored) -> lbm_config:
     c = lbm_config_default()
     c.lattice = LBM_D2Q9 if lattice == "D2Q9" else LBM_D1Q3
     c.nx, c.ny = int(nx), int(ny)
@@ -291,6 +301,9 @@ def make_config(*, lattice="D2Q9", nx=64, ny=64, bc="periodic", u_lid=0.0, rho_w
     c.check_interval = int(check_interval)
     c.mrt_preset = _PRESET[mrt_preset]
     c.sel_action = _SEL[sel_action]
+    c.ens_limiter = _ENS[ens_limiter]
+    c.ens_delta0, c.ens_delta = float(ens_delta0), float(ens_delta)
+    c.ens_alpha, c.ens_k = float(ens_alpha), float(ens_k)
     return c
 
 

@@ -92,3 +92,17 @@ def test_noalloc_host_checks_without_a_gpu():
                         ehr_k=16778)
     assert lib.lbm_step_noalloc(ctypes.byref(big), fake_a, fake_b, None) == B.LBM_EWORKSPACE
     assert b"scratch" in lib.lbm_last_error()
+
+
+def test_ensemble_limiter_validation():
+    """Host-side checks of the ensemble limiters' configuration."""
+    ok = B.make_config(nx=64, ny=64, nu=0.01, ens_limiter="threshold", ens_delta0=0.05)
+    assert B.lbm_workspace_bytes(ok) > B.lbm_workspace_bytes(B.make_config(nx=64, ny=64, nu=0.01))
+    bad = [dict(ens_limiter="threshold", ens_delta0=0.05, median=True),
+           dict(ens_limiter="smooth", checkpoint_every=4, max_steps=8),
+           dict(ens_limiter="smooth", ens_alpha=0.0),
+           dict(ens_limiter="double_monotone", ens_delta0=0.0, ens_delta=0.0)]
+    for kw in bad:
+        c = B.make_config(nx=64, ny=64, nu=0.01, **kw)
+        with pytest.raises(B.LBMError):
+            B.lbm_workspace_bytes(c)
