@@ -94,32 +94,27 @@ __device__ __forceinline__ void pull_periodic(const S* __restrict__ src, long lo
 
 // Pull f_i(x) = f_i(x - v_i) with the boundary rules: periodic wrap, or
 // halfway bounce-back f_i(x) = f_opp(i)(x) plus the moving-wall term when
-// the source lies above the top row.
+// the source lies above the top row.  Branch-free: the plane and offset are
+// selected and every population is one unconditional load (both candidate
+// addresses lie inside the lattice), so that the nine loads issue together
+// instead of each waiting at the join of an if/else.
 template <class S, int Q>
 __device__ __forceinline__ void pull(const S* __restrict__ src, long long qs, int pitch, int nx,
                                      int ny, int bc, int x, int y,
                                      const typename StoreT<S>::R* lid,
                                      typename StoreT<S>::R v[Q]) {
+  using R = typename StoreT<S>::R;
+  const bool wrap_x = bc == BC_PERIODIC || bc == BC_COUETTE, wrap_y = bc == BC_PERIODIC;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     int sx = x - vx_of<Q>(i), sy = y - vy_of<Q>(i);
-    bool out;
-    if (bc == BC_PERIODIC) {
-      sx = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
-      sy = sy < 0 ? sy + ny : (sy >= ny ? sy - ny : sy);
-      out = false;
-    } else if (bc == BC_COUETTE) {
-      sx = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
-      out = (sy < 0) | (sy >= ny);
-    } else {
-      out = (sx < 0) | (sx >= nx) | (sy < 0) | (sy >= ny);
-    }
-    if (!out) {
-      v[i] = StoreT<S>::ld(at(src + (long long)i * qs, (unsigned)(sy * pitch + sx)));
-    } else {
-      v[i] = StoreT<S>::ld(at(src + (long long)(Q - 1 - i) * qs, (unsigned)(y * pitch + x)));
-      if (sy >= ny) v[i] += lid[i];
-    }
+    if (wrap_x) sx = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
+    if (wrap_y) sy = sy < 0 ? sy + ny : (sy >= ny ? sy - ny : sy);
+    const bool out = (sx < 0) | (sx >= nx) | (sy < 0) | (sy >= ny);
+    const int plane = out ? Q - 1 - i : i;
+    const unsigned off = out ? (unsigned)(y * pitch + x) : (unsigned)(sy * pitch + sx);
+    const R val = StoreT<S>::ld(at(src + (long long)plane * qs, off));
+    v[i] = sy >= ny ? val + lid[i] : val;
   }
 }
 
