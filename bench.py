@@ -277,6 +277,7 @@ def run_elbm_8192(steps: int, warmup: int, adj_steps: int, adj_K: int) -> dict:
         "elbm_noroot_per_update": (c1[2] - c0[2]) / upd,
         "elbm_fp64_solve_per_update": (c1[3] - c0[3]) / upd,
         "elbm_nonpositive_per_update": (c1[4] - c0[4]) / upd,
+        "elbm_newton_iters_per_update": (c1[5] - c0[5]) / upd,
         "n_selected": int(st.n_selected), "diverged_step": int(st.diverged_step),
         "mass_per_site": st.mass / n,
     }

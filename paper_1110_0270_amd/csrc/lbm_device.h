@@ -137,14 +137,12 @@ __device__ __forceinline__ double h_series<double>(double x) {
 }
 template <>
 __device__ __forceinline__ float h_series<float>(float x) {
-  // terms up to x^8: truncation below 4e-8 of the leading term
-  float acc = 0.0f;
+  // terms up to x^8 (truncation below 4e-8 of the leading term), Horner's
+  // rule in fused multiply-adds: x^2 sum_{n=2..8} (-1)^n x^(n-2) / (n (n-1))
+  float p = 1.0f / 56.0f;
 #pragma unroll
-  for (int n = 8; n >= 3; --n) {
-    float c = ((n & 1) ? -1.0f : 1.0f) / (float)(n * (n - 1));
-    acc = (acc + c) * x;
-  }
-  return (acc + 0.5f) * x * x;
+  for (int n = 7; n >= 2; --n) p = fmaf(p, x, ((n & 1) ? -1.0f : 1.0f) / (float)(n * (n - 1)));
+  return p * x * x;
 }
 // Branch-free selects: both forms are evaluated and one is kept, so that the
 // nine components of a site interleave instead of running as nine divergent
@@ -164,11 +162,19 @@ __device__ __forceinline__ R h_log(R x, R l) {
 // library routine.
 template <class R> __device__ __forceinline__ R lg1p(R x);
 template <> __device__ __forceinline__ double lg1p<double>(double x) { return log1p(x); }
-template <> __device__ __forceinline__ float lg1p<float>(float x) {
-  float acc = 0.0f;
+// The series part of lg1p<float> (|x| < 0.1).
+template <class R> __device__ __forceinline__ R lg1p_series(R x);
+template <> __device__ __forceinline__ float lg1p_series<float>(float x) {
+  // x sum_{n=1..8} (-1)^(n+1) x^(n-1) / n by Horner's rule in fused
+  // multiply-adds
+  float p = -1.0f / 8.0f;
 #pragma unroll
-  for (int n = 8; n >= 2; --n) acc = (acc + ((n & 1) ? 1.0f : -1.0f) / (float)n) * x;
-  const float ser = (acc + 1.0f) * x;
+  for (int n = 7; n >= 1; --n) p = fmaf(p, x, ((n & 1) ? 1.0f : -1.0f) / (float)n);
+  return p * x;
+}
+template <> __device__ __forceinline__ double lg1p_series<double>(double x) { return log1p(x); }
+template <> __device__ __forceinline__ float lg1p<float>(float x) {
+  const float ser = lg1p_series<float>(x);
   const float u = 1.0f + x;
   const float lgv = __logf(u) * (x * __builtin_amdgcn_rcpf(u - 1.0f));
   return fabsf(x) < 0.1f ? ser : lgv;
@@ -207,19 +213,48 @@ template <> __device__ __forceinline__ float r_inf<float>() { return __builtin_h
 //   S_f'  = -sum D_i ln((f_i + alpha D_i) / f*_i)
 //   S_f'' = -sum D_i^2 / (f_i + alpha D_i)
 // ---------------------------------------------------------------------------
+// x = num / f: in FP32 num times rf = rcp(f), the value fdiv gives, with the
+// reciprocal taken once per site instead of once per evaluation; in FP64 the
+// correctly rounded quotient.
+template <class R>
+__device__ __forceinline__ R over_f(R num, R f, R rf) {
+  if constexpr (sizeof(R) == 4) return num * rf;
+  else return num / f;
+}
+
+// True when b holds on every active lane of the wavefront.
+__device__ __forceinline__ bool wave_all(bool b) { return __all(b) != 0; }
+
+// m = max_i |D_i| / f_i (FP32; from rf): a m < 0.0999999 guarantees every
+// computed |x_i| = |fl(fl(a D_i) rf_i)| < 0.1 (the margin of 1e-6 covers
+// the two roundings), so that the wavefront can take the series alone.
 template <class R, int Q>
-__device__ __forceinline__ void sf_parts(const R f[Q], const R D[Q], const R lnr[Q], R a,
-                                         R& sf, R& d1, R& d2) {
+__device__ __forceinline__ void sf_parts(const R f[Q], const R rf[Q], const R D[Q],
+                                         const R lnr[Q], R m, R a, R& sf, R& d1, R& d2) {
   R s0 = R(0), s1 = R(0), t1 = R(0), t2 = R(0);
+  if (sizeof(R) == 4 && wave_all(a * m < R(0.0999999))) {
+    // every |x_i| < 0.1 on the wavefront: ln(1 + x) and h(x) are their
+    // series, the values the selects below would keep
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    R x = fdiv<R>(a * D[i], f[i]);
-    R xl = x < R(-1) ? R(-1) : x;
-    const R l = lg1p<R>(xl);
-    s0 += f[i] * h_log<R>(x, l);
-    s1 += D[i] * lnr[i];
-    t1 += D[i] * (l + lnr[i]);
-    t2 += fdiv<R>(D[i] * D[i], f[i] + a * D[i]);
+    for (int i = 0; i < Q; ++i) {
+      const R x = over_f<R>(a * D[i], f[i], rf[i]);
+      const R l = lg1p_series<R>(x);
+      s0 += f[i] * h_series<R>(x);
+      s1 += D[i] * lnr[i];
+      t1 += D[i] * (l + lnr[i]);
+      t2 += fdiv<R>(D[i] * D[i], f[i] + a * D[i]);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const R x = over_f<R>(a * D[i], f[i], rf[i]);
+      const R xl = x < R(-1) ? R(-1) : x;
+      const R l = lg1p<R>(xl);
+      s0 += f[i] * h_log<R>(x, l);
+      s1 += D[i] * lnr[i];
+      t1 += D[i] * (l + lnr[i]);
+      t2 += fdiv<R>(D[i] * D[i], f[i] + a * D[i]);
+    }
   }
   sf = -s0 - a * s1;
   d1 = -t1;
@@ -255,11 +290,13 @@ __device__ R elbm_alpha(const R f[Q], const R feq[Q], const R D[Q], R amax,
   for (int i = 0; i < Q; ++i) nonpos |= (f[i] <= R(0));
   if (nonpos) { branch = EB_NONPOS; return R(1); }
   R x[Q], U = R(0), xmax = R(-1);
+  bool xsmall = true;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     x[i] = fdiv<R>(-D[i], feq[i]);
     U += feq[i] * x[i] * x[i];
     xmax = fmax(xmax, x[i]);
+    xsmall &= fabs(x[i]) < R(0.1);
   }
   if (U < R(2) * p.dS_cut * (R(1) + xmax / R(3))) {
     R dS = R(0);
@@ -268,8 +305,13 @@ __device__ R elbm_alpha(const R f[Q], const R feq[Q], const R D[Q], R amax,
     if (dS < p.dS_cut) { branch = EB_CUTOFF; return R(2); }
   }
   R lnr[Q];
+  if (sizeof(R) == 4 && wave_all(xsmall)) {
 #pragma unroll
-  for (int i = 0; i < Q; ++i) lnr[i] = lg1p<R>(x[i]);
+    for (int i = 0; i < Q; ++i) lnr[i] = lg1p_series<R>(x[i]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) lnr[i] = lg1p<R>(x[i]);
+  }
   R nrm = R(0);
   if (p.norm == 0) {
     nrm = sqrt(U);
@@ -277,12 +319,26 @@ __device__ R elbm_alpha(const R f[Q], const R feq[Q], const R D[Q], R amax,
 #pragma unroll
     for (int i = 0; i < Q; ++i) nrm += fabs(D[i]);
   }
+  R rf[Q], m = R(0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    rf[i] = sizeof(R) == 4 ? rcp<R>(f[i]) : R(0);
+    m = fmax(m, fabs(D[i]) * rf[i]);
+  }
   // One evaluation site for S_f and its derivatives (the kernel's code size
-  // decides its speed): first the existence test S_f(alpha_max) < 0 when
-  // alpha_max is finite, then the iteration; the evaluation that stops the
+  // decides its speed).  A root exists iff S_f(alpha_max) < 0 (alpha_max
+  // finite).  S_f is concave (S is concave, f + alpha D affine) with
+  // S_f(0) = 0, so the first iterate's evaluation at a settles that in most
+  // sites: the tangent there bounds S_f from above, and if it reaches 0
+  // within the first half of [a, alpha_max], S_f(alpha_max) <= d1
+  // (alpha_max - a) / 2 < 0, a margin far above rounding.  Otherwise the
+  // next evaluation is the probe at alpha_max, after which the iteration
+  // resumes from the saved first one.  The evaluation that stops the
   // iteration also serves the final sign check.
-  bool probe = amax < r_inf<R>();
+  bool need_probe = amax < r_inf<R>();
+  bool saved = false;
   R a = amax > R(2) ? R(2) : R(0.5) * (R(1) + amax);
+  R sf0 = R(0), d10 = R(0), d20 = R(0);
   R prev = r_inf<R>();
   // a Newton step within 64 units in the last place of alpha that no longer
   // halves is rounding noise: the iteration has converged as far as this
@@ -291,26 +347,40 @@ __device__ R elbm_alpha(const R f[Q], const R feq[Q], const R D[Q], R amax,
   constexpr R kNoise = R(64) * (sizeof(R) == 4 ? R(1.1920929e-7) : R(2.220446049250313e-16));
   for (int it = 0;;) {
     R sf, d1, d2;
-    sf_parts<R, Q>(f, D, lnr, probe ? amax : a, sf, d1, d2);
-    if (probe) {
+    const bool probing = need_probe && saved;
+    sf_parts<R, Q>(f, rf, D, lnr, m, probing ? amax : a, sf, d1, d2);
+    if (probing) {
       if (sf >= R(0)) {
         branch = EB_NOROOT;
         return p.fallback == 0 ? amax : R(1);
       }
-      probe = false;
-      continue;
+      need_probe = false;
+      sf = sf0;
+      d1 = d10;
+      d2 = d20;
+    } else if (need_probe) {
+      const R gap = amax - a;
+      if (d1 < R(0) && gap >= R(0.25) * a && sf + R(0.5) * d1 * gap < R(0)) {
+        need_probe = false;   // the tangent proves the root
+      } else {
+        saved = true;
+        sf0 = sf;
+        d10 = d1;
+        d20 = d2;
+        continue;
+      }
     }
-    const R step_est = fabs(sf / d1);
+    const R step_est = fabs(fdiv<R>(sf, d1));
     const bool stalled = it >= 2 && step_est >= R(0.5) * prev && step_est < kNoise * a;
     if (step_est * nrm < p.eps || step_est < p.atol || it >= p.max_iter || stalled) {
-      if (sf < R(0)) a = a - R(2) * sf / d1;
+      if (sf < R(0)) a = a - fdiv<R>(R(2) * sf, d1);
       break;
     }
     ++it;
     ++iters;
     prev = step_est;
     R disc = d1 * d1 - R(2) * sf * d2;
-    R delta = disc >= R(0) ? R(2) * sf / (-d1 + sqrt(disc)) : -sf / d1;
+    R delta = disc >= R(0) ? fdiv<R>(R(2) * sf, -d1 + sqrt(disc)) : fdiv<R>(-sf, d1);
     R an = a + delta;
     if (an >= amax) an = R(0.5) * (a + amax);
     if (an <= R(1)) an = R(0.5) * (a + R(1));
@@ -326,7 +396,7 @@ __device__ __forceinline__ R alpha_max(const R f[Q], const R D[Q]) {
   R amax = r_inf<R>();
 #pragma unroll
   for (int i = 0; i < Q; ++i)
-    if (D[i] < R(0)) amax = fmin(amax, f[i] / (-D[i]));
+    if (D[i] < R(0)) amax = fmin(amax, fdiv<R>(f[i], -D[i]));
   return amax;
 }
 
