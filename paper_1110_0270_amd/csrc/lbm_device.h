@@ -225,24 +225,36 @@ __device__ __forceinline__ R over_f(R num, R f, R rf) {
 // True when b holds on every active lane of the wavefront.
 __device__ __forceinline__ bool wave_all(bool b) { return __all(b) != 0; }
 
+// S_f and its derivatives at alpha = a.  s1 = sum_i D_i ln(f_i / f*_i), the
+// same for every alpha.  With r_i = D_i / (f_i + a D_i) the higher
+// derivatives are S_f^(2) = -sum D r, S_f^(3) = sum D r^2 and
+// S_f^(4) = -2 sum D r^3 (d2, d3, d4); rmax = max |r_i| bounds the ratio of
+// consecutive terms of the Taylor series of S_f in alpha around a.
 // m = max_i |D_i| / f_i (FP32; from rf): a m < 0.0999999 guarantees every
 // computed |x_i| = |fl(fl(a D_i) rf_i)| < 0.1 (the margin of 1e-6 covers
 // the two roundings), so that the wavefront can take the series alone.
 template <class R, int Q>
-__device__ __forceinline__ void sf_parts(const R f[Q], const R rf[Q], const R D[Q],
-                                         const R lnr[Q], R m, R a, R& sf, R& d1, R& d2) {
-  R s0 = R(0), s1 = R(0), t1 = R(0), t2 = R(0);
+__device__ __forceinline__ void sf_parts(const R f[Q], const R rf[Q], const R D[Q], R s1, R m,
+                                         R a, R& sf, R& d1, R& d2, R& d3, R& d4, R& rmax) {
+  R s0 = R(0), t1 = R(0), t2 = R(0), t3 = R(0), t4 = R(0);
+  rmax = R(0);
+  auto higher = [&](int i) {
+    const R r = D[i] * rcp<R>(f[i] + a * D[i]);
+    const R u = D[i] * r, u2 = u * r;
+    t2 += u;
+    t3 += u2;
+    t4 += u2 * r;
+    rmax = fmax(rmax, fabs(r));
+  };
   if (sizeof(R) == 4 && wave_all(a * m < R(0.0999999))) {
     // every |x_i| < 0.1 on the wavefront: ln(1 + x) and h(x) are their
     // series, the values the selects below would keep
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const R x = over_f<R>(a * D[i], f[i], rf[i]);
-      const R l = lg1p_series<R>(x);
       s0 += f[i] * h_series<R>(x);
-      s1 += D[i] * lnr[i];
-      t1 += D[i] * (l + lnr[i]);
-      t2 += fdiv<R>(D[i] * D[i], f[i] + a * D[i]);
+      t1 += D[i] * lg1p_series<R>(x);
+      higher(i);
     }
   } else {
 #pragma unroll
@@ -251,14 +263,19 @@ __device__ __forceinline__ void sf_parts(const R f[Q], const R rf[Q], const R D[
       const R xl = x < R(-1) ? R(-1) : x;
       const R l = lg1p<R>(xl);
       s0 += f[i] * h_log<R>(x, l);
-      s1 += D[i] * lnr[i];
-      t1 += D[i] * (l + lnr[i]);
-      t2 += fdiv<R>(D[i] * D[i], f[i] + a * D[i]);
+      t1 += D[i] * l;
+      if constexpr (sizeof(R) == 4) {
+        higher(i);
+      } else {
+        t2 += fdiv<R>(D[i] * D[i], f[i] + a * D[i]);
+      }
     }
   }
   sf = -s0 - a * s1;
-  d1 = -t1;
+  d1 = -(t1 + s1);
   d2 = -t2;
+  d3 = t3;
+  d4 = R(-2) * t4;
 }
 
 template <class R>
@@ -304,13 +321,14 @@ __device__ R elbm_alpha(const R f[Q], const R feq[Q], const R D[Q], R amax,
     for (int i = 0; i < Q; ++i) dS += feq[i] * h_fn<R>(x[i]);
     if (dS < p.dS_cut) { branch = EB_CUTOFF; return R(2); }
   }
-  R lnr[Q];
+  // s1 = sum_i D_i ln(f_i / f*_i), ln(f_i / f*_i) = ln(1 + x_i)
+  R s1 = R(0);
   if (sizeof(R) == 4 && wave_all(xsmall)) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) lnr[i] = lg1p_series<R>(x[i]);
+    for (int i = 0; i < Q; ++i) s1 += D[i] * lg1p_series<R>(x[i]);
   } else {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) lnr[i] = lg1p<R>(x[i]);
+    for (int i = 0; i < Q; ++i) s1 += D[i] * lg1p<R>(x[i]);
   }
   R nrm = R(0);
   if (p.norm == 0) {
@@ -335,10 +353,15 @@ __device__ R elbm_alpha(const R f[Q], const R feq[Q], const R D[Q], R amax,
   // next evaluation is the probe at alpha_max, after which the iteration
   // resumes from the saved first one.  The evaluation that stops the
   // iteration also serves the final sign check.
+  // FP32: after a full evaluation at c, S_f and its first two derivatives at
+  // c + dl come from the Taylor series in alpha to the fourth derivative
+  // while |dl| rmax <= 2^-10 (the first omitted term is below 1e-9 of the
+  // second-order one, under FP32 rounding); further away, a full evaluation.
+  constexpr bool TAYLOR = sizeof(R) == 4;
   bool need_probe = amax < r_inf<R>();
-  bool saved = false;
+  bool saved = false, full = true;
   R a = amax > R(2) ? R(2) : R(0.5) * (R(1) + amax);
-  R sf0 = R(0), d10 = R(0), d20 = R(0);
+  R c = a, F0 = R(0), F1 = R(0), F2 = R(0), F3 = R(0), F4 = R(0), rmax = r_inf<R>();
   R prev = r_inf<R>();
   // a Newton step within 64 units in the last place of alpha that no longer
   // halves is rounding noise: the iteration has converged as far as this
@@ -348,27 +371,40 @@ __device__ R elbm_alpha(const R f[Q], const R feq[Q], const R D[Q], R amax,
   for (int it = 0;;) {
     R sf, d1, d2;
     const bool probing = need_probe && saved;
-    sf_parts<R, Q>(f, rf, D, lnr, m, probing ? amax : a, sf, d1, d2);
-    if (probing) {
-      if (sf >= R(0)) {
-        branch = EB_NOROOT;
-        return p.fallback == 0 ? amax : R(1);
-      }
-      need_probe = false;
-      sf = sf0;
-      d1 = d10;
-      d2 = d20;
-    } else if (need_probe) {
-      const R gap = amax - a;
-      if (d1 < R(0) && gap >= R(0.25) * a && sf + R(0.5) * d1 * gap < R(0)) {
-        need_probe = false;   // the tangent proves the root
+    if (full || probing) {
+      R e0, e1, e2, e3, e4, em;
+      sf_parts<R, Q>(f, rf, D, s1, m, probing ? amax : a, e0, e1, e2, e3, e4, em);
+      if (probing) {
+        if (e0 >= R(0)) {
+          branch = EB_NOROOT;
+          return p.fallback == 0 ? amax : R(1);
+        }
+        need_probe = false;   // resume at a = c
+        sf = F0;
+        d1 = F1;
+        d2 = F2;
       } else {
-        saved = true;
-        sf0 = sf;
-        d10 = d1;
-        d20 = d2;
-        continue;
+        c = a;
+        F0 = e0; F1 = e1; F2 = e2; F3 = e3; F4 = e4;
+        rmax = em;
+        sf = e0;
+        d1 = e1;
+        d2 = e2;
+        if (need_probe) {
+          const R gap = amax - a;
+          if (d1 < R(0) && gap >= R(0.25) * a && sf + R(0.5) * d1 * gap < R(0)) {
+            need_probe = false;   // the tangent proves the root
+          } else {
+            saved = true;
+            continue;
+          }
+        }
       }
+    } else {
+      const R dl = a - c;
+      sf = F0 + dl * (F1 + dl * (R(0.5) * F2 + dl * (F3 * R(1.0 / 6.0) + dl * (F4 * R(1.0 / 24.0)))));
+      d1 = F1 + dl * (F2 + dl * (R(0.5) * F3 + dl * (F4 * R(1.0 / 6.0))));
+      d2 = F2 + dl * (F3 + dl * (R(0.5) * F4));
     }
     const R step_est = fabs(fdiv<R>(sf, d1));
     const bool stalled = it >= 2 && step_est >= R(0.5) * prev && step_est < kNoise * a;
@@ -385,6 +421,7 @@ __device__ R elbm_alpha(const R f[Q], const R feq[Q], const R D[Q], R amax,
     if (an >= amax) an = R(0.5) * (a + amax);
     if (an <= R(1)) an = R(0.5) * (a + R(1));
     a = an;
+    full = !TAYLOR || !(fabs(a - c) * rmax <= R(0x1p-10));
   }
   branch = EB_ROOT;
   return a;
