@@ -449,6 +449,136 @@ def precision_study(w: dict, checkpoints: list) -> dict:
     return out
 
 
+def c5_study(steps: int, K: int, checkpoints: list) -> dict:
+    """The 8192^2 ELBM workload at its stated length: FP16 shifted storage,
+    `steps` steps forward with checkpoints every K, then the adjoint of the
+    velocity misfit to the seeded Fourier target with recompute.  Next to
+    it, the same forward run in FP64 (the reference), in FP32, and in FP64
+    from the FP16-rounded initial state (the control: what the flow's own
+    amplification makes of one FP16 rounding of the initial state), with the
+    velocity error against FP64 at the checkpoints and the limiter
+    statistics of each run."""
+    import torch
+
+    from lbm_inputs import generators as G
+    from lbm_inputs.workloads import workload
+    from paper_1110_0270_amd import lbm as B
+
+    w = workload("elbm_8192")
+    n = w["nx"] * w["ny"]
+    r0, ux, uy = G.spectral_velocity(w["nx"], seed=w["seed"])
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")  # noqa: E731
+    rho, uxd, uyd = t(r0), t(ux), t(uy)
+    del r0, ux, uy
+    cps = [c for c in checkpoints if c <= steps]
+    if not cps or cps[-1] != steps:
+        cps.append(steps)
+    # the FP16-stored initial state, in FP64
+    sim = B.Simulation(B.make_config(**{**w, "storage": "f16s", "checkpoint_every": 0}))
+    sim.set_equilibrium(rho, uxd, uyd)
+    rounded = sim.populations()
+    del sim
+    torch.cuda.empty_cache()
+
+    def forward(form: str, sim, t_start: float) -> dict:
+        snaps, done = {}, 0
+        c0 = sim.counters()
+        for c in cps:
+            while done < c:
+                m = min(500, c - done)
+                sim.step(m)
+                done += m
+                torch.cuda.synchronize()
+                log(f"[c5] {form}: step {done}, {time.perf_counter() - t_start:.1f} s")
+            mom = sim.moments(dtype=torch.float32)
+            st = sim.stats(allow_status=(B.LBM_OK, B.LBM_EDIVERGED, B.LBM_ESELECT))
+            snaps[c] = {"u": torch.stack(mom[1:]), "sel": set(sim.selected()),
+                        "mass": st.mass, "entropy": st.entropy,
+                        "diverged_step": int(st.diverged_step)}
+            del mom
+        c1 = sim.counters()
+        upd = n * steps
+        return {"snaps": snaps, "limiters": {
+            "positivity_per_update": (c1[0] - c0[0]) / upd,
+            "elbm_noroot_per_update": (c1[2] - c0[2]) / upd,
+            "elbm_fp64_solve_per_update": (c1[3] - c0[3]) / upd,
+            "elbm_nonpositive_per_update": (c1[4] - c0[4]) / upd,
+            "elbm_newton_iters_per_update": (c1[5] - c0[5]) / upd}}
+
+    runs, out = {}, {"workload": "elbm_8192", "nx": w["nx"], "ny": w["ny"], "steps": steps,
+                     "checkpoint_every": K, "checkpoints": cps, "reference": "f64", "forms": {}}
+    for form in ("f64", "f64_from_f16_init", "f32"):
+        storage = "f64" if form.startswith("f64") else form
+        sim = B.Simulation(B.make_config(**{**w, "storage": storage, "checkpoint_every": 0}))
+        if form == "f64_from_f16_init":
+            sim.set_populations(rounded)
+        else:
+            sim.set_equilibrium(rho, uxd, uyd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        runs[form] = forward(form, sim, t0)
+        runs[form]["mlups"] = n * steps / (time.perf_counter() - t0) / 1e6
+        del sim
+        torch.cuda.empty_cache()
+    del rounded
+
+    # FP16 with recording, then the adjoint
+    cfg = B.make_config(**{**w, "storage": "f16s", "checkpoint_every": K, "max_steps": steps})
+    sim = B.Simulation(cfg)
+    sim.set_equilibrium(rho, uxd, uyd)
+    del rho, uxd, uyd
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs["f16s"] = forward("f16s", sim, t0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tx, ty = G.fourier_target(w["nx"], w["ny"], seed=w["target_seed"])
+    loss, g = velocity_loss_grad(sim.populations(), t(tx), t(ty))
+    del tx, ty
+    g0 = torch.empty_like(g)
+    gw = torch.empty((w["ny"], w["nx"]), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    log(f"[c5] f16s: loss {loss:.6g}, backward over {steps} steps ...")
+    t2 = time.perf_counter()
+    adj_kern, _ = sim.profile_backward(g, g0, gw)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    log(f"[c5] f16s: backward {t3 - t2:.1f} s")
+    adjoint = {
+        "loss": loss, "fwd_s": t1 - t0, "bwd_s": t3 - t2,
+        "fwd_mlups": n * steps / (t1 - t0) / 1e6,
+        "bwd_mlups": n * steps / (t3 - t2) / 1e6,
+        "fwd_adjoint_mlups": n * steps / (t3 - t2 + t1 - t0) / 1e6,
+        "adjoint_kernel_us": adj_kern / steps * 1e3,
+        "grad_finite": bool(torch.isfinite(g0).all()) and bool(torch.isfinite(gw).all()),
+        "grad_f0_l2": float(g0.norm()), "grad_omega_l2": float(gw.norm()),
+        "workspace_gb": sim.workspace.numel() / 1e9,
+        "device_peak_gb": torch.cuda.max_memory_allocated() / 1e9,
+    }
+    del sim, g, g0, gw
+    torch.cuda.empty_cache()
+
+    ref = runs["f64"]["snaps"]
+    for form, r in runs.items():
+        rows = []
+        for c in cps:
+            a, b = r["snaps"][c], ref[c]
+            rows.append({
+                "step": c,
+                "rel_l2_u": rel_l2(a["u"].double(), b["u"].double()),
+                "max_abs_u": float((a["u"] - b["u"]).abs().max()),
+                "selection_jaccard": len(a["sel"] & b["sel"]) / max(1, len(a["sel"] | b["sel"])),
+                "mass_drift": a["mass"] / n - 1.0,
+                "entropy": a["entropy"],
+                "diverged_step": a["diverged_step"],
+            })
+        out["forms"][form] = {"error_vs_f64": rows, "limiters": r["limiters"]}
+        if "mlups" in r:
+            out["forms"][form]["forward_mlups"] = r["mlups"]
+    out["forms"]["f16s"]["adjoint"] = adjoint
+    return out
+
+
 def _round(x):
     if isinstance(x, dict):
         return {k: _round(v) for k, v in x.items()}
@@ -466,9 +596,13 @@ def main():
     ap.add_argument("--forms", default="f64,f16s,bf16s")
     ap.add_argument("--study", default="", help="'precision': error of the storage forms "
                     "against FP64 over a long shear-layer run; 'cavity': the four 256^2 "
-                    "cavity runs in FP64 and FP32 (one JSON document each)")
+                    "cavity runs in FP64 and FP32; 'c5': the 8192^2 ELBM workload, "
+                    "FP16 forward plus adjoint over --study-steps steps, with FP64, "
+                    "FP32 and FP64-control forward runs (one JSON document each)")
     ap.add_argument("--study-checkpoints", default="100,1000,5000,10000,20000")
     ap.add_argument("--study-steps", type=int, default=50000)
+    ap.add_argument("--study-k", type=int, default=71,
+                    help="checkpoint interval of --study c5 (about sqrt of its 5000 steps)")
     ap.add_argument("--adjoint-steps", type=int, default=8192)
     ap.add_argument("--scale-adjoint-steps", type=int, default=128)
     ap.add_argument("--elbm-steps", type=int, default=50)
@@ -481,6 +615,10 @@ def main():
     if args.study == "cavity":
         cps = [1000, 5000, 10000, 20000, 50000]
         print(json.dumps(_round(cavity_study(args.study_steps, cps))), flush=True)
+        return
+    if args.study == "c5":
+        cps = [int(x) for x in args.study_checkpoints.split(",")]
+        print(json.dumps(_round(c5_study(args.study_steps, args.study_k, cps))), flush=True)
         return
     if args.study == "precision":
         from lbm_inputs.workloads import workload
