@@ -609,6 +609,8 @@ def main():
     ap.add_argument("--elbm-adjoint-steps", type=int, default=32)
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--median", action="store_true",
+                    help="the headline workload with the median entropy filter on (delta 1e-3)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run 10 device copies of this many bytes (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -654,7 +656,10 @@ def main():
     from lbm_inputs.workloads import workload
 
     w = workload("shear_layer_4096")
-    log(f"[bench] {w['nx']}x{w['ny']} D2Q9 LBGK + Ehrenfest k={w['ehr_k']}, storage {args.storage}")
+    if args.median:
+        w.update(median=True, med_delta=1e-3)
+    log(f"[bench] {w['nx']}x{w['ny']} D2Q9 LBGK + Ehrenfest k={w['ehr_k']}"
+        f"{' + median' if args.median else ''}, storage {args.storage}")
     main_res, main_mom = run_form(w, args.storage, args.steps, args.warmup)
     log(f"[bench] {args.storage}: {main_res['mlups']:.0f} MLUPS, kernel {main_res['kernel_ms']*1e3:.1f} us "
         f"= {main_res['kernel_gbs']:.0f} GB/s")
@@ -729,13 +734,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": "shear_layer_4096", "lattice": "D2Q9", "nx": w["nx"],
                    "ny": w["ny"], "bc": "periodic", "collision": "lbgk", "nu": w["nu"],
-                   "limiters": f"ehrenfest k={w['ehr_k']} delta={w['ehr_delta']}",
+                   "limiters": f"ehrenfest k={w['ehr_k']} delta={w['ehr_delta']}"
+                               + (f", median delta={w['med_delta']}" if args.median else ""),
                    "storage": args.storage},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": (HBM_TRAFFIC_F32 if args.storage == "f32" else None),
+                     "traffic": (HBM_TRAFFIC_F32 if args.storage == "f32" and not args.median
+                                 else None),
                      "traffic_unit": "bytes per launch",
-                     "kernel": "k_step (fused collide-stream)",
+                     "kernel": "k_step (fused collide-stream"
+                               + (", median filter in LDS)" if args.median else ")"),
                      "kernel_us": round(main_res["kernel_ms"] * 1e3, 2),
                      "alg_bytes_per_launch": main_res["alg_bytes_per_launch"],
                      # the whole step (step kernel, Ehrenfest selection and

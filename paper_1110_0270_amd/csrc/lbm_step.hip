@@ -227,12 +227,19 @@ __global__ __launch_bounds__(256) void k_elbm_f64(const StepArgs<typename StoreT
 // ENS: the ensemble or smooth limiter of section 4 acts on the pulled state
 // (f* + phi (f - f*), phi from the site's Delta S and the step's threshold
 // and mean), and the workgroup adds the dissipation monitor's sums.
-template <class S, int Q, int COLL, bool MEDIAN, int TX, int TY, bool PER, bool ENS = false>
-__global__ __launch_bounds__(256, ((COLL == COLL_LBGK && sizeof(S) <= 4 && !MEDIAN && !ENS && TX == 256) ? 8 : 1))
+// NB (median filter only): the workgroup takes NB tiles stacked vertically
+// (TX x NB TY sites, 256 NB threads) and shares one LDS tile of Delta S
+// with a one-site halo: 156 halo sites per 768 with NB = 3 against 140 per
+// 256, whose populations are pulled a second time.  Each wavefront keeps
+// the candidate region of its own 256-site tile.
+template <class S, int Q, int COLL, bool MEDIAN, int TX, int TY, bool PER, bool ENS = false,
+          int NB = 1>
+__global__ __launch_bounds__(256 * NB, ((COLL == COLL_LBGK && sizeof(S) <= 4 && !MEDIAN && !ENS && TX == 256) ? 8 : 1))
 void k_step(const StepArgs<typename StoreT<S>::R> A) {
   using R = typename StoreT<S>::R;
   constexpr bool SH = StoreT<S>::shifted;
   static_assert(TX * TY == 256, "tile must hold 256 sites");
+  static_assert(NB == 1 || MEDIAN, "stacked tiles serve the median filter's halo");
 
   // Tile order.  Consecutive workgroups are dealt round-robin to the 8
   // XCDs.  The median filter re-reads its halo, so each XCD gets a
@@ -243,13 +250,15 @@ void k_step(const StepArgs<typename StoreT<S>::R> A) {
   // than the bands).  With 4-byte storage each XCD takes pairs of
   // horizontally adjacent tiles, which share the line the pull reaches
   // across their edge (2 % faster again; FP64 gains nothing from pairs).
-  const int T = A.tiles_x * A.tiles_y;
+  const int T = A.tiles_x * ((A.tiles_y + NB - 1) / NB);   // workgroups
   const int b = blockIdx.x;
   constexpr int G = sizeof(S) == 4 ? 2 : 1;
-  const int t = (MEDIAN && T % 8 == 0) ? (b % 8) * (T / 8) + b / 8
-              : ((T % (8 * G) == 0) ? (b / (8 * G)) * (8 * G) + (b % 8) * G + (b / 8) % G : b);
-  const int tile_x = t % A.tiles_x, tile_y = t / A.tiles_x;
-  const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+  const int tb = (MEDIAN && T % 8 == 0) ? (b % 8) * (T / 8) + b / 8
+               : ((T % (8 * G) == 0) ? (b / (8 * G)) * (8 * G) + (b % 8) * G + (b / 8) % G : b);
+  const int sub = (int)threadIdx.x / 256, tid = (int)threadIdx.x % 256;
+  const int tile_x = tb % A.tiles_x, tile_y = (tb / A.tiles_x) * NB + sub;
+  const int t = tile_y * A.tiles_x + tile_x;   // this thread's 256-site tile
+  const int lx = tid % TX, ly = tid / TX;
   const int x = tile_x * TX + lx, y = tile_y * TY + ly;
   const bool valid = x < A.nx && y < A.ny;
 
@@ -312,11 +321,13 @@ void k_step(const StepArgs<typename StoreT<S>::R> A) {
   if constexpr (MEDIAN) {
     // Median entropy filter: Delta S of the tile plus a one-site halo in LDS.
     constexpr int HY = (Q == 9) ? 1 : 0;
-    constexpr int SW = TX + 2, SH_ = TY + 2 * HY;
+    constexpr int SW = TX + 2, SH_ = TY * NB + 2 * HY;
     __shared__ R sdS[SH_ * SW];
-    sdS[(ly + HY) * SW + lx + 1] = valid ? dS : slot_dS<S, Q>(A, x, y);
-    constexpr int NHALO = SH_ * SW - TX * TY;
-    for (int s = threadIdx.x; s < NHALO; s += 256) {
+    const int by = sub * TY + ly;                         // row within the workgroup
+    const int x0 = tile_x * TX, y0 = (tb / A.tiles_x) * NB * TY;
+    sdS[(by + HY) * SW + lx + 1] = valid ? dS : slot_dS<S, Q>(A, x, y);
+    constexpr int NHALO = SH_ * SW - TX * TY * NB;
+    for (int s = threadIdx.x; s < NHALO; s += 256 * NB) {
       // halo slot s -> LDS coordinates: top row, bottom row, then the left
       // and right columns (2D); the two end slots of the single row (1D)
       int hx, hy;
@@ -328,7 +339,7 @@ void k_step(const StepArgs<typename StoreT<S>::R> A) {
         hy = 0;
         hx = (s == 0) ? 0 : SW - 1;
       }
-      sdS[hy * SW + hx] = slot_dS<S, Q>(A, tile_x * TX + hx - 1, tile_y * TY + hy - HY);
+      sdS[hy * SW + hx] = slot_dS<S, Q>(A, x0 + hx - 1, y0 + hy - HY);
     }
     __syncthreads();
     if (valid) {
@@ -338,7 +349,7 @@ void k_step(const StepArgs<typename StoreT<S>::R> A) {
 #pragma unroll
       for (int k = 0; k < NN; ++k) {
         const int dy = (Q == 9) ? k / 3 - 1 : 0, dx = (Q == 9) ? k % 3 - 1 : k - 1;
-        const R val = sdS[(ly + HY + dy) * SW + lx + 1 + dx];
+        const R val = sdS[(by + HY + dy) * SW + lx + 1 + dx];
         const bool in = !(val != val);
         n += in ? 1 : 0;
         nb[k] = in ? val : r_inf<R>();
@@ -374,7 +385,7 @@ void k_step(const StepArgs<typename StoreT<S>::R> A) {
   }
 
   constexpr bool DEFER = COLL == COLL_ELBM && sizeof(R) == 4 && !MEDIAN && !ENS;
-  site_finish<S, Q, COLL, true, DEFER>(A, x, y, valid, (long long)t * 4 + threadIdx.x / 64, v, feq, d, m0, ux,
+  site_finish<S, Q, COLL, true, DEFER>(A, x, y, valid, (long long)t * 4 + tid / 64, v, feq, d, m0, ux,
                           uy, dS, fr, cnt);
 }
 
@@ -447,14 +458,15 @@ __global__ __launch_bounds__(256) void k_step_rows(const StepArgs<typename Store
 // ---------------------------------------------------------------------------
 // Launch dispatch.
 // ---------------------------------------------------------------------------
-template <class S, int Q, int COLL, bool MEDIAN, int TX, int TY, bool PER = false, bool ENS = false>
+template <class S, int Q, int COLL, bool MEDIAN, int TX, int TY, bool PER = false, bool ENS = false,
+          int NB = 1>
 static void launch_k(const StepArgs<typename StoreT<S>::R>& A, hipStream_t s, hipEvent_t e0,
                      hipEvent_t e1) {
-  const dim3 grid(A.tiles_x * A.tiles_y), block(256);
+  const dim3 grid(A.tiles_x * ((A.tiles_y + NB - 1) / NB)), block(256 * NB);
   if (e0 && e1)  // events taken at the kernel's own start and end
-    hipExtLaunchKernelGGL((k_step<S, Q, COLL, MEDIAN, TX, TY, PER, ENS>), grid, block, 0, s, e0, e1, 0, A);
+    hipExtLaunchKernelGGL((k_step<S, Q, COLL, MEDIAN, TX, TY, PER, ENS, NB>), grid, block, 0, s, e0, e1, 0, A);
   else
-    hipLaunchKernelGGL((k_step<S, Q, COLL, MEDIAN, TX, TY, PER, ENS>), grid, block, 0, s, A);
+    hipLaunchKernelGGL((k_step<S, Q, COLL, MEDIAN, TX, TY, PER, ENS, NB>), grid, block, 0, s, A);
 }
 
 template <class S, int Q, int COLL, bool MEDIAN>
@@ -475,7 +487,12 @@ static hipError_t launch_t(const void* args, hipStream_t s, hipEvent_t e0, hipEv
   if constexpr (Q == 3) {
     launch_k<S, Q, COLL, MEDIAN, 256, 1>(A, s, e0, e1);
   } else if constexpr (MEDIAN) {
-    launch_k<S, Q, COLL, MEDIAN, 64, 4>(A, s, e0, e1);
+    // Three stacked tiles with FP32 arithmetic (LBGK, MRT): 12 wavefronts,
+    // two workgroups per CU at 74 registers.  4096^2 FP32 on one box: one
+    // tile 412 us, two 379, three 353; four 457 on another (one workgroup
+    // per CU).  FP64 and ELBM (over 128 registers) keep one tile.
+    constexpr int NB = (COLL != COLL_ELBM && sizeof(typename StoreT<S>::R) == 4) ? 3 : 1;
+    launch_k<S, Q, COLL, MEDIAN, 64, 4, false, false, NB>(A, s, e0, e1);
   } else {
     if (tile_shape(Q, MEDIAN, A.nx).tx == 256) {
       // 16-bit storage and ELBM.  With cached loads the one-site-per-lane
