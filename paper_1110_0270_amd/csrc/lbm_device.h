@@ -121,29 +121,32 @@ __device__ __forceinline__ void eq_dev6(R u, int kind, R dt[3]) {
 __device__ __forceinline__ int c1(int a) { return a == 0 ? 4 : 1; }  // 6 w_a
 
 // h(x) = (1 + x) ln(1 + x) - x, h(-1) = 1; Taylor series for |x| < 0.1.
-// h_series is the series part; h_log(x, l) takes l = ln(1 + x) from the
-// caller (so that a sum that also needs ln(1 + x) evaluates it once).
+// h_series is the series part, x^2 h_poly(x); h_log(x, l) takes
+// l = ln(1 + x) from the caller (so that a sum that also needs ln(1 + x)
+// evaluates it once).
 template <class R>
-__device__ __forceinline__ R h_series(R x);
+__device__ __forceinline__ R h_poly(R x);
 template <>
-__device__ __forceinline__ double h_series<double>(double x) {
+__device__ __forceinline__ double h_poly<double>(double x) {
   double acc = 0.0;
 #pragma unroll
   for (int n = 16; n >= 3; --n) {
     double c = ((n & 1) ? -1.0 : 1.0) / (double)(n * (n - 1));
     acc = (acc + c) * x;
   }
-  return (acc + 0.5) * x * x;
+  return acc + 0.5;
 }
 template <>
-__device__ __forceinline__ float h_series<float>(float x) {
+__device__ __forceinline__ float h_poly<float>(float x) {
   // terms up to x^8 (truncation below 4e-8 of the leading term), Horner's
-  // rule in fused multiply-adds: x^2 sum_{n=2..8} (-1)^n x^(n-2) / (n (n-1))
+  // rule in fused multiply-adds: sum_{n=2..8} (-1)^n x^(n-2) / (n (n-1))
   float p = 1.0f / 56.0f;
 #pragma unroll
   for (int n = 7; n >= 2; --n) p = fmaf(p, x, ((n & 1) ? -1.0f : 1.0f) / (float)(n * (n - 1)));
-  return p * x * x;
+  return p;
 }
+template <class R>
+__device__ __forceinline__ R h_series(R x) { return h_poly<R>(x) * x * x; }
 // Branch-free selects: both forms are evaluated and one is kept, so that the
 // nine components of a site interleave instead of running as nine divergent
 // branches one after another.

@@ -143,10 +143,12 @@ __device__ __forceinline__ void moments_v(const R v[Q], R rho0, R& m0, R& ux, R&
 // Screening: for x >= -1/2, h(x) <= x^2/2 + max(-x, 0)^3/3 (for x >= 0 since
 // h'' <= 1; for -1/2 <= x < 0 the series terms beyond the cubic one sum to
 // less than the cubic term).  With y_i = -x_i = d_i / f*_i the bound on
-// f*_i h(x_i) reads d_i y_i (1/2 + max(y_i, 0)/3), and U, its sum over i,
-// bounds Delta S from above.  When U < screen (and every y_i <= 1/2) the
-// exact sum is skipped and U is returned: the caller only needs to know that
-// Delta S is below `screen`.  screen = 0 always evaluates the exact sum.
+// f*_i h(x_i) reads d_i y_i (1/2 + max(y_i, 0)/3) <= d_i y_i (1/2 +
+// max(ymax, 0)/3) (d_i y_i = f*_i y_i^2 >= 0), so U = (sum_i d_i y_i)
+// (1/2 + max(ymax, 0)/3) bounds Delta S from above.  When U < screen (and
+// every y_i <= 1/2) the exact sum is skipped and U is returned: the caller
+// only needs to know that Delta S is below `screen`.  screen = 0 always
+// evaluates the exact sum.
 template <class R, int Q, bool SH>
 __device__ __forceinline__ R site_dS(const R v[Q], const R d[Q], R m0, R rho0, R ux, R uy,
                                      int kind, R screen = R(0)) {
@@ -169,7 +171,7 @@ __device__ __forceinline__ R site_dS(const R v[Q], const R d[Q], R m0, R rho0, R
     }
   }
   R y[Q];
-  R ub = R(0), ymax = R(0);
+  R sdy = R(0), ymax = R(0);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const int a = vx_of<Q>(i) + 1, b = vy_of<Q>(i) + 1;
@@ -178,9 +180,10 @@ __device__ __forceinline__ R site_dS(const R v[Q], const R d[Q], R m0, R rho0, R
     const R inv = Q == 9 ? rx[a] * ry[b] : rx[a];   // 1 / f*_i
     y[i] = d[i] * inv;
     ymax = fmax(ymax, y[i]);
-    ub += (d[i] * y[i]) * (R(0.5) + fmax(y[i], R(0)) * R(1.0 / 3.0));
+    sdy += d[i] * y[i];
   }
   if (bad) return r_inf<R>();
+  const R ub = sdy * (R(0.5) + ymax * R(1.0 / 3.0));   // ymax >= 0 (it starts at 0)
   // the margin covers the rounding of the bound itself
   if (!(ymax > R(0.5)) && ub * R(1.0001) < screen) return ub;
   // h_fn takes the Taylor series wherever |x| < 0.1; when that holds for
@@ -191,12 +194,10 @@ __device__ __forceinline__ R site_dS(const R v[Q], const R d[Q], R m0, R rho0, R
   for (int i = 0; i < Q; ++i) big |= !(fabs(y[i]) < R(0.1));
   R acc = R(0);
   if (__ballot(big) == 0ull) {
+    // f*_i h(x_i) = f*_i y_i^2 h_poly(-y_i) = (d_i y_i) h_poly(-y_i)
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const int a = vx_of<Q>(i) + 1, b = vy_of<Q>(i) + 1;
-      const R fq = Q == 9 ? fx[a] * fy[b] : fx[a];
-      acc += fq * h_series<R>(-y[i]);
-    }
+    for (int i = 0; i < Q; ++i) acc += (d[i] * y[i]) * h_poly<R>(-y[i]);
+    return acc;
   } else {
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
