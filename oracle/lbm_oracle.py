@@ -40,7 +40,7 @@ __all__ = [
     "elbm", "positivity", "median_filter", "ehrenfest_select", "ens_threshold",
     "ens_phi", "ensemble_limiter", "step", "run",
     "stats", "init_equilibrium", "ELBM_ROOT", "ELBM_CUTOFF", "ELBM_NOROOT",
-    "ELBM_NONPOS",
+    "ELBM_NONPOS", "wall_nodes", "diffusive_wall", "enstrophy", "hopf_energy",
 ]
 
 
@@ -80,7 +80,7 @@ class Config:
     lattice: str = "D2Q9"
     nx: int = 16
     ny: int = 16
-    bc: str = "periodic"          # periodic | bounceback | cavity | couette
+    bc: str = "periodic"          # periodic | bounceback | cavity | couette | diffusive
     u_lid: float = 0.0
     rho_wall: float = 1.0
     collision: str = "lbgk"       # lbgk | mrt | elbm
@@ -206,6 +206,10 @@ def stream(lat: Lattice, g: torch.Tensor, bc: str, u_lid: float = 0.0,
             outside = outside | (sx < 0) | (sx >= nx)
         outside = outside.expand(ny, nx)
         refl = g[lat.opp[i]]
+        if bc == "diffusive":
+            # the wall rule (diffusive_wall) replaces every such population
+            out.append(torch.where(outside, refl, shifted))
+            continue
         if bc in ("cavity", "couette"):
             from_lid = (sy >= ny).expand(ny, nx)
             lid = torch.tensor(6.0 * float(lat.w[i]) * rho_wall * a * u_lid, dtype=DT)
@@ -214,6 +218,93 @@ def stream(lat: Lattice, g: torch.Tensor, bc: str, u_lid: float = 0.0,
             raise ValueError(bc)
         out.append(torch.where(outside, refl, shifted))
     return torch.stack(out)
+
+
+# ---------------------------------------------------------------------------
+# Diffusive Maxwell wall (section 8, "First Hopf bifurcation"): after the
+# advection, at a wall site the populations pointing into the fluid become
+# gamma f*_i(u_wall), gamma = (sum of the populations that reached the wall)
+# / (sum of f*_i(u_wall) over the incoming directions), f* at unit density
+# (density is a linear factor); wall sites do not collide.
+# Reading: the lattice is nx x ny nodes; its outer ring of nodes is the wall
+# (the lid is the top row y = ny - 1, moving with (u_lid, 0); the other
+# walls rest).  At an edge site the incoming directions are those with
+# v . n > 0 (n the inward normal: on the lid S, SW, SE, as printed); at a
+# corner only the diagonal along n, which makes the rule bounce-back there
+# (as the paper states).  Every population whose source lies outside the
+# lattice takes gamma f*_i(u_wall) with the site's gamma: at an edge these
+# are exactly the incoming ones; at a corner the others run along a wall or
+# out of the lattice and never reach the fluid.  Corners rest (u_wall = 0;
+# the diagonal's value does not depend on it).  f* is the step's
+# equilibrium kind.
+# ---------------------------------------------------------------------------
+def wall_nodes(ny: int, nx: int) -> torch.Tensor:
+    """Boolean (ny, nx) mask of the wall ring of a diffusive-wall lattice."""
+    m = torch.zeros((ny, nx), dtype=torch.bool)
+    m[0, :] = True
+    m[-1, :] = True
+    m[:, 0] = True
+    m[:, -1] = True
+    return m
+
+
+def diffusive_wall(lat: Lattice, pre: torch.Tensor, u_lid: float, kind: str) -> torch.Tensor:
+    """The wall rule on the streamed state `pre` (Q, ny, nx); interior sites
+    are returned unchanged."""
+    Q, ny, nx = pre.shape
+    one = torch.ones((1, 1), dtype=DT)
+    zero = torch.zeros((1, 1), dtype=DT)
+    feq_lid = equilibrium(lat, one, one * u_lid, zero, kind)[:, 0, 0]
+    feq_rest = equilibrium(lat, one, zero, zero, kind)[:, 0, 0]
+    out = pre.clone()
+    X, Y = nx - 1, ny - 1
+    # (ys, xs, inward normal, f*(u_wall)) for the four edges and four corners
+    parts = [
+        (torch.full((nx - 2,), Y), torch.arange(1, X), (0, -1), feq_lid),    # lid
+        (torch.full((nx - 2,), 0), torch.arange(1, X), (0, 1), feq_rest),    # floor
+        (torch.arange(1, Y), torch.full((ny - 2,), 0), (1, 0), feq_rest),    # left
+        (torch.arange(1, Y), torch.full((ny - 2,), X), (-1, 0), feq_rest),   # right
+        (torch.tensor([0]), torch.tensor([0]), (1, 1), feq_rest),
+        (torch.tensor([0]), torch.tensor([X]), (-1, 1), feq_rest),
+        (torch.tensor([Y]), torch.tensor([0]), (1, -1), feq_rest),
+        (torch.tensor([Y]), torch.tensor([X]), (-1, -1), feq_rest),
+    ]
+    for ys, xs, (n_x, n_y), feq_w in parts:
+        corner = n_x != 0 and n_y != 0
+        incoming = [i for i, (a, b) in enumerate(lat.vel)
+                    if ((a, b) == (n_x, n_y) if corner else a * n_x + b * n_y > 0)]
+        unknown = [i for i, (a, b) in enumerate(lat.vel) if a * n_x > 0 or b * n_y > 0]
+        reached = sum(pre[lat.opp[i], ys, xs] for i in incoming)
+        gamma = reached / sum(float(feq_w[i]) for i in incoming)
+        for i in unknown:
+            out[i, ys, xs] = gamma * feq_w[i]
+    return out
+
+
+def enstrophy(lat: Lattice, g: torch.Tensor, bc: str = "periodic") -> float:
+    """Enstrophy (section 8, cavity study): the sum of the squared vorticity
+    over the lattice divided by the number of sites.  Reading: vorticity
+    du_y/dx - du_x/dy by central differences of the velocity at the sites
+    with four neighbours inside the lattice (all sites of a periodic
+    lattice, with wrap-around), and the sum is divided by the number of
+    those sites."""
+    rho, jx, jy = moments(lat, g)
+    ux, uy = jx / rho, jy / rho
+    # roll(a, -1, dims=1)[y, x] = a[y, x + 1]
+    duy_dx = (torch.roll(uy, -1, dims=1) - torch.roll(uy, 1, dims=1)) / 2.0
+    dux_dy = (torch.roll(ux, -1, dims=0) - torch.roll(ux, 1, dims=0)) / 2.0
+    w = duy_dx - dux_dy
+    if bc != "periodic":
+        w = w[1:-1, 1:-1]
+    return float((w * w).sum() / w.numel())
+
+
+def hopf_energy(signal, L: float, u0: float) -> float:
+    """E_u of eq. energy: the l2 norm of sqrt(L / (u0 n)) (s - mean(s)) over
+    the n samples of the probe signal s."""
+    s = torch.as_tensor(signal, dtype=DT)
+    n = s.numel()
+    return float(math.sqrt(L / (u0 * n)) * torch.linalg.vector_norm(s - s.mean()))
 
 
 # ---------------------------------------------------------------------------
@@ -489,7 +580,7 @@ def positivity(post, feq):
     return torch.where(act.unsqueeze(0), out, post), act
 
 
-def median_filter(lat: Lattice, cfg: Config, f, feq, dS):
+def median_filter(lat: Lattice, cfg: Config, f, feq, dS, wall=None):
     """Median entropy filter (section 4): dS_med is the middle value of the
     neighbourhood of each site (itself included; 3 sites in 1D, 3x3 in 2D);
     where dS_med < dS the homothety f* + sqrt(dS_med / dS) (f - f*) is
@@ -498,7 +589,9 @@ def median_filter(lat: Lattice, cfg: Config, f, feq, dS):
     with n of them the median is the ceil(n/2)-th smallest (2nd of 3, 5th of
     9 as printed; 3rd of 6 and 2nd of 4 at walls).  Reading: the paper's
     delta (1e-3 in the Hopf study) is an acceptance threshold: only sites
-    with dS > delta are filtered.  Returns (f_new, mask)."""
+    with dS > delta are filtered.  With diffusive walls (`wall`, the wall
+    sites) only fluid sites filter and count as neighbours.
+    Returns (f_new, mask)."""
     ny, nx = dS.shape
     offs = [(0, -1), (0, 0), (0, 1)] if lat.name == "D1Q3" else \
         [(dy, dx) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
@@ -512,6 +605,8 @@ def median_filter(lat: Lattice, cfg: Config, f, feq, dS):
         else:
             sy, sx = ys + dy, xs + dx
             ok = (sy >= 0) & (sy < ny) & (sx >= 0) & (sx < nx)
+            if wall is not None:
+                ok = ok & ~torch.roll(wall, shifts=(-dy, -dx), dims=(0, 1))
         vals.append(torch.where(ok, v, torch.full_like(v, math.inf)))
         valid.append(ok)
     stack = torch.stack(vals)
@@ -522,6 +617,8 @@ def median_filter(lat: Lattice, cfg: Config, f, feq, dS):
     rank = (n + 1) // 2 - 1                                   # ceil(n/2) - 1
     med = srt.gather(0, rank.unsqueeze(0)).squeeze(0)
     accept = (dS > cfg.med_delta) & (med < dS) & torch.isfinite(dS)
+    if wall is not None:
+        accept = accept & ~wall
     ratio = torch.where(accept, med / torch.where(accept, dS, torch.ones_like(dS)),
                         torch.ones_like(dS))
     # Reading (gradients only): a zero median maps the site onto f*; the
@@ -631,10 +728,19 @@ def step(lat: Lattice, cfg: Config, g: torch.Tensor,
     """One time step from the stored post-collision lattice g (Q, ny, nx).
     Returns (g_next, info).  Reading: the Ehrenfest step replaces the
     collision at the selected sites (f' = f*), and selection ranks the
-    unfiltered Delta S; the median filter acts on the pre-collision state."""
+    unfiltered Delta S; the median filter acts on the pre-collision state.
+    Diffusive walls: the wall sites keep their streamed state after the wall
+    rule (no collision, no limiter); they are neither selected nor counted
+    as median neighbours."""
     pre = stream(lat, g, cfg.bc, cfg.u_lid, cfg.rho_wall)
-    rho, jx, jy = moments(lat, pre)
     kind = "entropic" if cfg.collision == "elbm" else cfg.equilibrium
+    wall = None
+    if cfg.bc == "diffusive":
+        if lat.name != "D2Q9" or cfg.ens_limiter != "none":
+            raise ValueError("diffusive walls: D2Q9 without the ensemble limiters")
+        pre = diffusive_wall(lat, pre, cfg.u_lid, kind)
+        wall = wall_nodes(*pre.shape[1:])
+    rho, jx, jy = moments(lat, pre)
     feq = equilibrium(lat, rho, jx / rho, jy / rho, kind)
     omega = omega_field if omega_field is not None else relaxation_rate(cfg)
     info = {}
@@ -642,14 +748,16 @@ def step(lat: Lattice, cfg: Config, g: torch.Tensor,
     if cfg.ehrenfest or cfg.median or cfg.ens_limiter != "none":
         dS = kullback_dS(pre, feq)
         info["dS"] = dS.detach()
+    walls_pre = pre
     if cfg.median:
-        pre, acc = median_filter(lat, cfg, pre, feq, dS)
+        pre, acc = median_filter(lat, cfg, pre, feq, dS, wall)
         info["median_mask"] = acc
     if cfg.ens_limiter != "none":
         pre, info["ensemble"] = ensemble_limiter(cfg, pre, feq, dS, omega)
     sel = None
     if cfg.ehrenfest:
-        sel = ehrenfest_select(dS.detach().flatten(), cfg.ehr_k, cfg.ehr_delta)
+        dS_sel = dS.detach() if wall is None else torch.where(wall, torch.zeros_like(dS), dS.detach())
+        sel = ehrenfest_select(dS_sel.flatten(), cfg.ehr_k, cfg.ehr_delta)
         info["selected"] = sel
     def mrt_collision():
         se, seps, sq = mrt_preset_rates(cfg.mrt_preset, omega, cfg.s_e, cfg.s_eps, cfg.s_q)
@@ -666,12 +774,16 @@ def step(lat: Lattice, cfg: Config, g: torch.Tensor,
                                    norm=cfg.elbm_norm, fallback=cfg.elbm_fallback)
         info["alpha"] = alpha.detach().reshape(rho.shape)
         info["branch"] = branch.reshape(rho.shape)
+        if wall is not None:
+            info["branch"] = torch.where(wall, torch.full_like(info["branch"], -1), info["branch"])
     else:
         raise ValueError(cfg.collision)
     if cfg.positivity:
         # diagnostic only: where the collided state (before any Ehrenfest
         # step) has a negative population the rule acts
         info["positivity_collided"] = ((post < 0) & (feq > 0)).any(0)
+        if wall is not None:
+            info["positivity_collided"] = info["positivity_collided"] & ~wall
     selmask = torch.zeros(rho.numel(), dtype=torch.bool)
     if sel is not None and sel.numel() > 0:
         selmask[sel] = True
@@ -687,8 +799,12 @@ def step(lat: Lattice, cfg: Config, g: torch.Tensor,
         if cfg.sel_action != "mrt":
             # f* needs no positivity rule
             act = act & ~selmask.view(rho.shape)
+        if wall is not None:
+            act = act & ~wall
         post = torch.where(act.unsqueeze(0), lim, post)
         info["positivity_mask"] = act
+    if wall is not None:
+        post = torch.where(wall.unsqueeze(0), walls_pre, post)
     return post, info
 
 

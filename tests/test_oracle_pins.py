@@ -911,3 +911,141 @@ def test_shock_tube_runs_and_conserves_mass():
     assert max(len(i["selected"]) for i in infos) == 4
     r, u, _ = O.velocity(L1, g)
     assert float(r.min()) > 0.4 and float(r.max()) < 1.1
+
+
+# --------------------------------------------------- diffusive Maxwell wall
+# Section 8, "First Hopf bifurcation": the wall re-emits, proportional to its
+# equilibrium, what reached it (mass balance), and coincides with bounce-back
+# in the corners.
+def _edge_sites(ny, nx):
+    """(ys, xs, inward normal) of the four edges without their corners."""
+    X, Y = nx - 1, ny - 1
+    return [(torch.full((nx - 2,), Y), torch.arange(1, X), (0, -1)),
+            (torch.full((nx - 2,), 0), torch.arange(1, X), (0, 1)),
+            (torch.arange(1, Y), torch.full((ny - 2,), 0), (1, 0)),
+            (torch.arange(1, Y), torch.full((ny - 2,), X), (-1, 0))]
+
+
+@pytest.mark.parametrize("kind", ["poly", "entropic"])
+def test_diffusive_wall_no_normal_mass_flux(kind):
+    """After the rule, no mass crosses any straight wall: the normal mass
+    flux sum_i f_i (v_i . n) vanishes at every edge site, whatever reached
+    the wall and whatever the lid speed."""
+    ny, nx = 7, 9
+    pre = rand_state(L2, ny, nx, 81, amp=0.3)
+    out = O.diffusive_wall(L2, pre, 0.1, kind)
+    vx, vy = L2.vx.view(9, 1), L2.vy.view(9, 1)
+    for ys, xs, (n_x, n_y) in _edge_sites(ny, nx):
+        f = out[:, ys, xs]
+        flux = (f * (vx * n_x + vy * n_y)).sum(0)
+        assert float(flux.abs().max()) < 1e-15
+        # and the interior of the lattice is untouched
+    assert torch.equal(out[:, 1:-1, 1:-1], pre[:, 1:-1, 1:-1])
+
+
+@pytest.mark.parametrize("kind", ["poly", "entropic"])
+def test_diffusive_wall_reemits_its_maxwellian(kind):
+    """If what reaches a wall is the wall's own equilibrium at some density
+    rho' (moving with the wall), the wall sends back exactly that
+    equilibrium: on the lid the tangential lid velocity is carried by the
+    emitted S, SW, SE populations."""
+    ny, nx, u_lid = 6, 8, 0.1
+    rng = np.random.default_rng(5)
+    pre = rand_state(L2, ny, nx, 82, amp=0.3)
+    dens = torch.tensor(0.7 + 0.6 * rng.uniform(size=(ny, nx)), dtype=DT)
+    for ys, xs, (n_x, n_y) in _edge_sites(ny, nx):
+        u = u_lid if (n_x, n_y) == (0, -1) else 0.0
+        feq = O.equilibrium(L2, dens[ys, xs], torch.full_like(dens[ys, xs], u),
+                            torch.zeros_like(dens[ys, xs]), kind)
+        for i, (a, b) in enumerate(L2.vel):
+            if a * n_x + b * n_y < 0:          # reaches the wall
+                pre[i, ys, xs] = feq[i]
+    out = O.diffusive_wall(L2, pre, u_lid, kind)
+    for ys, xs, (n_x, n_y) in _edge_sites(ny, nx):
+        u = u_lid if (n_x, n_y) == (0, -1) else 0.0
+        feq = O.equilibrium(L2, dens[ys, xs], torch.full_like(dens[ys, xs], u),
+                            torch.zeros_like(dens[ys, xs]), kind)
+        for i, (a, b) in enumerate(L2.vel):
+            if a * n_x + b * n_y > 0:          # emitted into the fluid
+                assert torch.allclose(out[i, ys, xs], feq[i], rtol=1e-14, atol=0)
+
+
+def test_diffusive_wall_is_bounce_back_in_the_corners():
+    ny, nx = 5, 6
+    pre = rand_state(L2, ny, nx, 83, amp=0.4)
+    out = O.diffusive_wall(L2, pre, 0.1, "entropic")
+    idx = {v: i for i, v in enumerate(L2.vel)}
+    for (y, x, n) in [(0, 0, (1, 1)), (0, nx - 1, (-1, 1)), (ny - 1, 0, (1, -1)),
+                      (ny - 1, nx - 1, (-1, -1))]:
+        i_in, i_out = idx[n], idx[(-n[0], -n[1])]
+        assert float(out[i_in, y, x]) == float(pre[i_out, y, x])
+
+
+@pytest.mark.parametrize("collision,kind", [("lbgk", "poly"), ("lbgk", "entropic"),
+                                            ("elbm", "entropic"), ("mrt", "poly")])
+def test_diffusive_cavity_at_rest_is_a_fixed_point(collision, kind):
+    """A uniform equilibrium at rest inside resting diffusive walls is a
+    fixed point of the whole step (streaming, wall rule, collision)."""
+    ny, nx = 6, 7
+    cfg = O.Config(nx=nx, ny=ny, bc="diffusive", u_lid=0.0, collision=collision,
+                   equilibrium=kind, nu=0.01, median=True, med_delta=1e-12)
+    rho = torch.full((ny, nx), 1.3, dtype=DT)
+    z = torch.zeros((ny, nx), dtype=DT)
+    f = O.equilibrium(L2, rho, z, z, "entropic" if collision == "elbm" else kind)
+    g, info = O.step(L2, cfg, f)
+    assert torch.allclose(g, f, rtol=2e-15, atol=0)
+    assert not bool(info["median_mask"].any())
+
+
+def test_diffusive_wall_sites_do_not_collide():
+    """Wall sites keep the streamed state after the rule, and the fluid
+    sites take a plain LBGK collision of the same streamed state."""
+    ny, nx = 6, 8
+    cfg = O.Config(nx=nx, ny=ny, bc="diffusive", u_lid=0.1, collision="lbgk", nu=0.02)
+    f = rand_state(L2, ny, nx, 84, amp=0.2)
+    g, _ = O.step(L2, cfg, f)
+    pre = O.diffusive_wall(L2, O.stream(L2, f, "diffusive"), 0.1, "poly")
+    wall = O.wall_nodes(ny, nx)
+    assert torch.equal(g[:, wall], pre[:, wall])
+    r, jx, jy = O.moments(L2, pre)
+    feq = O.equilibrium(L2, r, jx / r, jy / r)
+    post = O.lbgk(pre, feq, O.relaxation_rate(cfg))
+    assert torch.allclose(g[:, ~wall], post[:, ~wall], rtol=1e-15, atol=1e-17)
+
+
+def test_median_filter_excludes_diffusive_walls():
+    ny, nx = 6, 7
+    f = rand_state(L2, ny, nx, 85, amp=0.1)
+    rho, ux, uy = O.velocity(L2, f)
+    q = O.equilibrium(L2, rho, ux, uy)
+    dS = O.kullback_dS(f, q)
+    wall = O.wall_nodes(ny, nx)
+    cfg = O.Config(nx=nx, ny=ny, bc="diffusive", med_delta=1e-5)
+    out, acc = O.median_filter(L2, cfg, f, q, dS, wall)
+    d = dS.numpy()
+    for y in range(1, ny - 1):
+        for x in range(1, nx - 1):
+            vals = sorted(d[yy, xx] for yy in (y - 1, y, y + 1) for xx in (x - 1, x, x + 1)
+                          if 0 < yy < ny - 1 and 0 < xx < nx - 1)
+            med = vals[(len(vals) + 1) // 2 - 1]
+            assert bool(acc[y, x]) == bool(d[y, x] > 1e-5 and med < d[y, x])
+    assert not bool(acc[wall].any())
+
+
+def test_hopf_energy_of_a_sine():
+    """E_u (eq. energy) of whole periods of A sin: the mean is 0 and the
+    squares average A^2/2, so E_u = A sqrt(L / (2 u0))."""
+    n, A, L, u0 = 4000, 0.013, 100.0, 0.1
+    s = 0.2 + A * np.sin(2 * np.pi * 7 * np.arange(n) / n)
+    assert abs(O.hopf_energy(s, L, u0) - A * math.sqrt(L / (2 * u0))) < 1e-13
+
+
+def test_enstrophy_of_rigid_rotation():
+    """Rigid rotation u = Omega (-(y - yc), x - xc) has vorticity 2 Omega,
+    which central differences reproduce exactly: enstrophy 4 Omega^2."""
+    ny, nx, om = 9, 11, 3e-3
+    ys, xs = np.mgrid[0:ny, 0:nx].astype(float)
+    ux = -om * (ys - 4.0)
+    uy = om * (xs - 5.0)
+    f = O.init_equilibrium(L2, np.ones((ny, nx)), ux, uy)
+    assert abs(O.enstrophy(L2, f, "diffusive") - 4 * om * om) < 1e-18
