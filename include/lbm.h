@@ -64,8 +64,18 @@ typedef enum {
 enum { LBM_D1Q3 = 1, LBM_D2Q9 = 2 };
 /* Boundaries: periodic in x and y; bounce-back walls on all sides; cavity =
  * bounce-back walls with the top wall moving at (u_lid, 0); couette =
- * periodic in x, resting bottom wall, moving top wall. */
-enum { LBM_BC_PERIODIC = 0, LBM_BC_BOUNCEBACK = 1, LBM_BC_CAVITY = 2, LBM_BC_COUETTE = 3 };
+ * periodic in x, resting bottom wall, moving top wall; diffusive = the
+ * diffusive Maxwell wall of section 8 (First Hopf bifurcation) on the outer
+ * ring of nodes, the top row moving at (u_lid, 0): after streaming, a wall
+ * node sets the populations pointing into the fluid to gamma f*_i(u_wall)
+ * (f* of the configured equilibrium at unit density, gamma = the sum of the
+ * populations that reached the wall over the sum of those f*_i; at a corner
+ * only the inward diagonal, which is bounce-back), every other population
+ * whose source lies outside likewise, and does not collide; wall nodes are
+ * neither Ehrenfest candidates nor median neighbours.  D2Q9, nx, ny >= 3;
+ * no adjoint (checkpoint_every = 0) and no ensemble limiter. */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_BOUNCEBACK = 1, LBM_BC_CAVITY = 2, LBM_BC_COUETTE = 3,
+       LBM_BC_DIFFUSIVE = 4 };
 enum { LBM_LBGK = 0, LBM_MRT = 1, LBM_ELBM = 2 };
 enum { LBM_EQ_POLY = 0, LBM_EQ_ENTROPIC = 1 };
 enum { LBM_MRT_M1 = 0, LBM_MRT_M2 = 1 };
@@ -172,6 +182,11 @@ typedef struct lbm_stats {
   double ens_mean;
   double lbgk_production;
   double limiter_production;
+  /* enstrophy (section 8, cavity study): the sum of the squared vorticity
+   * du_y/dx - du_x/dy (central differences of u, FP64) over the sites with
+   * four neighbours in the lattice (every site when periodic), divided by
+   * their number; 0 for D1Q3 */
+  double enstrophy;
 } lbm_stats;
 
 typedef struct lbm_ctx lbm_ctx;

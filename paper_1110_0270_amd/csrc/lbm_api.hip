@@ -56,7 +56,16 @@ bool validate(const lbm_config* c, std::string& why) {
   if (c->lattice == LBM_D1Q3 && c->bc != LBM_BC_PERIODIC && c->bc != LBM_BC_BOUNCEBACK) {
     why = "D1Q3 supports periodic and bounce-back ends only"; return false;
   }
-  if (c->bc < 0 || c->bc > 3) { why = "unknown boundary"; return false; }
+  if (c->bc < 0 || c->bc > 4) { why = "unknown boundary"; return false; }
+  if (c->bc == LBM_BC_DIFFUSIVE) {
+    if (c->lattice != LBM_D2Q9 || c->nx < 3 || c->ny < 3) {
+      why = "the diffusive wall needs D2Q9 with nx, ny >= 3"; return false;
+    }
+    if (c->ens_limiter != LBM_ENS_NONE) { why = "the diffusive wall excludes the ensemble limiters"; return false; }
+    if (c->checkpoint_every > 0) {
+      why = "the adjoint does not cover the diffusive wall (checkpoint_every must be 0)"; return false;
+    }
+  }
   if (c->collision < 0 || c->collision > 2) { why = "unknown collision"; return false; }
   if (c->collision == LBM_MRT && c->lattice != LBM_D2Q9) { why = "MRT is defined for D2Q9"; return false; }
   if (c->storage < 0 || c->storage > 3) { why = "unknown storage"; return false; }
@@ -206,6 +215,7 @@ void fill_args(StepArgs<R>& A, const lbm_config* c, const Layout& L, char* ws) {
   A.omega = (R)om;
   A.omega_field = c->omega_field ? (const R*)(ws + L.off_omega) : nullptr;
   for (int i = 0; i < 9; ++i) A.lid[i] = 0;
+  A.lid_u = c->bc == LBM_BC_DIFFUSIVE ? (R)c->u_lid : R(0);
   if (c->bc == LBM_BC_CAVITY || c->bc == LBM_BC_COUETTE) {
     for (int i = 0; i < L.Q; ++i) {
       const int a = L.Q == 9 ? (i % 3) - 1 : i - 1;
@@ -556,7 +566,8 @@ static lbm_status replay_graph(lbm_ctx* c) {
 // The periodic divergence check (FP64 reduction) after a step.
 static hipError_t check_now(lbm_ctx* c) {
   return launch_stats(c->cfg.storage, c->L.Q, c->lat(c->cur), c->L.qs, c->cfg.nx, c->cfg.ny,
-                      c->L.pitch, c->cfg.rho0, (double*)(c->ws + c->L.off_partial),
+                      c->L.pitch, c->cfg.bc == LBM_BC_PERIODIC, c->cfg.rho0,
+                      (double*)(c->ws + c->L.off_partial),
                       (double*)(c->ws + c->L.off_stats), (long long*)(c->ws + c->L.off_div),
                       c->steps, c->stream);
 }
@@ -672,7 +683,7 @@ lbm_status lbm_stats_get(lbm_ctx* c, lbm_stats* out) {
   g_err.clear();
   if (!c || !out) return fail(LBM_EINVAL, "NULL argument");
   hipError_t e = launch_stats(c->cfg.storage, c->L.Q, c->lat(c->cur), c->L.qs, c->cfg.nx,
-                              c->cfg.ny, c->L.pitch, c->cfg.rho0,
+                              c->cfg.ny, c->L.pitch, c->cfg.bc == LBM_BC_PERIODIC, c->cfg.rho0,
                               (double*)(c->ws + c->L.off_partial),
                               (double*)(c->ws + c->L.off_stats),
                               (long long*)(c->ws + c->L.off_div), c->steps, c->stream);
@@ -681,7 +692,7 @@ lbm_status lbm_stats_get(lbm_ctx* c, lbm_stats* out) {
   long long div = -1;
   SelState sel;
   std::memset(&sel, 0, sizeof(sel));
-  e = hipMemcpyAsync(st, c->ws + c->L.off_stats, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  e = hipMemcpyAsync(st, c->ws + c->L.off_stats, 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(&div, c->ws + c->L.off_div, sizeof(div), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(&sel, c->ws + c->L.off_sel, sizeof(sel), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -689,6 +700,7 @@ lbm_status lbm_stats_get(lbm_ctx* c, lbm_stats* out) {
   std::memset(out, 0, sizeof(*out));
   out->mass = st[0]; out->mom_x = st[1]; out->mom_y = st[2]; out->entropy = st[3];
   out->min_rho = st[4]; out->nonfinite = st[5] != 0.0;
+  out->enstrophy = st[7] > 0.0 ? st[6] / st[7] : 0.0;
   out->steps = c->steps;
   out->diverged_step = div;
   out->n_selected = sel.n_sel;

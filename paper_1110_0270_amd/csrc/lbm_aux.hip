@@ -107,13 +107,24 @@ __global__ void k_moments(const S* lat, long long qs, int nx, int ny, int pitch,
 constexpr int kStatsBlocks = 1024;
 constexpr int kStatsThreads = 256;
 
+// u at site (x, y) in FP64 (for the vorticity)
+template <class S, int Q>
+__device__ __forceinline__ void site_u64(const S* lat, long long qs, int pitch, int x, int y,
+                                         double rho0, double& ux, double& uy) {
+  double f[Q], r, jx, jy;
+  site_moments64<S, Q>(lat, qs, pitch, x, y, rho0, f, r, jx, jy);
+  ux = jx / r;
+  uy = jy / r;
+}
+
 template <class S, int Q>
 __global__ __launch_bounds__(kStatsThreads) void k_stats(const S* lat, long long qs, int nx,
-                                                         int ny, int pitch, double rho0,
-                                                         double* partial) {
-  __shared__ double sm[6][kStatsThreads];
+                                                         int ny, int pitch, int periodic,
+                                                         double rho0, double* partial) {
+  __shared__ double sm[8][kStatsThreads];
   const long long n = (long long)nx * ny;
   double a_m = 0, a_x = 0, a_y = 0, a_s = 0, a_min = __builtin_huge_val(), a_bad = 0;
+  double a_w = 0, a_n = 0;
   for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n;
        s += (long long)gridDim.x * blockDim.x) {
     const int y = (int)(s / nx), x = (int)(s % nx);
@@ -127,45 +138,65 @@ __global__ __launch_bounds__(kStatsThreads) void k_stats(const S* lat, long long
     }
     a_m += r; a_x += jx; a_y += jy; a_s += ent;
     a_min = fmin(a_min, r);
+    // vorticity du_y/dx - du_x/dy by central differences (D2Q9)
+    if (Q == 9 && (periodic || (x > 0 && y > 0 && x < nx - 1 && y < ny - 1))) {
+      const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+      const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+      double ux_a, uy_a, ux_b, uy_b, ux_c, uy_c, ux_d, uy_d;
+      site_u64<S, Q>(lat, qs, pitch, xp, y, rho0, ux_a, uy_a);
+      site_u64<S, Q>(lat, qs, pitch, xm, y, rho0, ux_b, uy_b);
+      site_u64<S, Q>(lat, qs, pitch, x, yp, rho0, ux_c, uy_c);
+      site_u64<S, Q>(lat, qs, pitch, x, ym, rho0, ux_d, uy_d);
+      const double w = (uy_a - uy_b) / 2.0 - (ux_c - ux_d) / 2.0;
+      a_w += w * w;
+      a_n += 1.0;
+    }
   }
   const int t = threadIdx.x;
   sm[0][t] = a_m; sm[1][t] = a_x; sm[2][t] = a_y; sm[3][t] = a_s; sm[4][t] = a_min; sm[5][t] = a_bad;
+  sm[6][t] = a_w; sm[7][t] = a_n;
   __syncthreads();
   for (int off = kStatsThreads / 2; off > 0; off >>= 1) {
     if (t < off) {
       for (int k = 0; k < 4; ++k) sm[k][t] += sm[k][t + off];
       sm[4][t] = fmin(sm[4][t], sm[4][t + off]);
       sm[5][t] = fmax(sm[5][t], sm[5][t + off]);
+      sm[6][t] += sm[6][t + off];
+      sm[7][t] += sm[7][t + off];
     }
     __syncthreads();
   }
-  if (t < 6) partial[(long long)blockIdx.x * 6 + t] = sm[t][0];
+  if (t < 8) partial[(long long)blockIdx.x * 8 + t] = sm[t][0];
 }
 
 __global__ __launch_bounds__(kStatsThreads) void k_stats_final(const double* partial, int nb,
                                                                double* out,
                                                                long long* diverged_step,
                                                                long long step) {
-  __shared__ double sm[6][kStatsThreads];
+  __shared__ double sm[8][kStatsThreads];
   const int t = threadIdx.x;
-  double a[6] = {0, 0, 0, 0, __builtin_huge_val(), 0};
+  double a[8] = {0, 0, 0, 0, __builtin_huge_val(), 0, 0, 0};
   for (int b = t; b < nb; b += kStatsThreads) {
-    for (int k = 0; k < 4; ++k) a[k] += partial[(long long)b * 6 + k];
-    a[4] = fmin(a[4], partial[(long long)b * 6 + 4]);
-    a[5] = fmax(a[5], partial[(long long)b * 6 + 5]);
+    for (int k = 0; k < 4; ++k) a[k] += partial[(long long)b * 8 + k];
+    a[4] = fmin(a[4], partial[(long long)b * 8 + 4]);
+    a[5] = fmax(a[5], partial[(long long)b * 8 + 5]);
+    a[6] += partial[(long long)b * 8 + 6];
+    a[7] += partial[(long long)b * 8 + 7];
   }
-  for (int k = 0; k < 6; ++k) sm[k][t] = a[k];
+  for (int k = 0; k < 8; ++k) sm[k][t] = a[k];
   __syncthreads();
   for (int off = kStatsThreads / 2; off > 0; off >>= 1) {
     if (t < off) {
       for (int k = 0; k < 4; ++k) sm[k][t] += sm[k][t + off];
       sm[4][t] = fmin(sm[4][t], sm[4][t + off]);
       sm[5][t] = fmax(sm[5][t], sm[5][t + off]);
+      sm[6][t] += sm[6][t + off];
+      sm[7][t] += sm[7][t + off];
     }
     __syncthreads();
   }
   if (t == 0) {
-    for (int k = 0; k < 6; ++k) out[k] = sm[k][0];
+    for (int k = 0; k < 8; ++k) out[k] = sm[k][0];
     const bool bad = sm[5][0] != 0.0 || !(sm[4][0] > 0.0) || !isfinite(sm[0][0]);
     if (bad && *diverged_step < 0) *diverged_step = step;
   }
@@ -215,12 +246,12 @@ hipError_t launch_moments(int storage, int Q, const void* lat, long long qs, int
   return hipGetLastError();
 }
 
-long long stats_partial_doubles(int, int) { return (long long)kStatsBlocks * 6; }
+long long stats_partial_doubles(int, int) { return (long long)kStatsBlocks * 8; }
 
 hipError_t launch_stats(int storage, int Q, const void* lat, long long qs, int nx, int ny,
-                        int pitch, double rho0, double* partial, double* out,
+                        int pitch, int periodic, double rho0, double* partial, double* out,
                         long long* diverged_step, long long step, hipStream_t s) {
-  LBM_DISPATCH(storage, Q, hipLaunchKernelGGL((k_stats<S, QQ>), dim3(kStatsBlocks), dim3(kStatsThreads), 0, s, (const S*)lat, qs, nx, ny, pitch, rho0, partial));
+  LBM_DISPATCH(storage, Q, hipLaunchKernelGGL((k_stats<S, QQ>), dim3(kStatsBlocks), dim3(kStatsThreads), 0, s, (const S*)lat, qs, nx, ny, pitch, periodic, rho0, partial));
   hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(kStatsThreads), 0, s, (const double*)partial,
                      kStatsBlocks, out, diverged_step, step);
   return hipGetLastError();

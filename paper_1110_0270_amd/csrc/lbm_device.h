@@ -27,7 +27,7 @@ __device__ __forceinline__ R w9(int i) {
   return w1<R>(kAx9[i]) * w1<R>(kBy9[i]);
 }
 
-enum Bc : int { BC_PERIODIC = 0, BC_BOUNCEBACK = 1, BC_CAVITY = 2, BC_COUETTE = 3 };
+enum Bc : int { BC_PERIODIC = 0, BC_BOUNCEBACK = 1, BC_CAVITY = 2, BC_COUETTE = 3, BC_DIFFUSIVE = 4 };
 enum Coll : int { COLL_LBGK = 0, COLL_MRT = 1, COLL_ELBM = 2 };
 enum EqKind : int { EQ_POLY = 0, EQ_ENTROPIC = 1 };
 enum ElbmBranch : int { EB_ROOT = 0, EB_CUTOFF = 1, EB_NOROOT = 2, EB_NONPOS = 3, EB_F64 = 4 };

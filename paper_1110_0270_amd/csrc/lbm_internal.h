@@ -114,6 +114,7 @@ struct StepArgs {
   R omega;
   const R* omega_field;  // [ny][pitch] or nullptr
   R lid[9];              // moving-wall term 6 w_i rho_wall (v_i . u_wall)
+  R lid_u;               // lid speed of the diffusive wall
   // MRT (moment space): F = f + Minv (rates .* (M (f* - f)))
   R M[81];
   R Minv[81];
@@ -180,10 +181,12 @@ hipError_t launch_moments(int storage, int Q, const void* lat, long long qs, int
                           int pitch, double rho0, void* rho, void* ux, void* uy,
                           int out_f64, hipStream_t s);
 // Whole-lattice FP64 reduction into out[0..7] = mass, mom_x, mom_y, entropy,
-// min_rho, nonfinite, -, -.  partial: workspace of stats_partial_doubles().
+// min_rho, nonfinite, the sum of the squared vorticity and the number of
+// sites it covers (four neighbours in the lattice; every site when
+// periodic).  partial: workspace of stats_partial_doubles().
 long long stats_partial_doubles(int nx, int ny);
 hipError_t launch_stats(int storage, int Q, const void* lat, long long qs, int nx, int ny,
-                        int pitch, double rho0, double* partial, double* out,
+                        int pitch, int periodic, double rho0, double* partial, double* out,
                         long long* diverged_step, long long step, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 // Ensemble limiters: before the step kernel, the pre-pass (Delta S of every

@@ -118,6 +118,52 @@ __device__ __forceinline__ void pull(const S* __restrict__ src, long long qs, in
   }
 }
 
+// A node of the diffusive wall (the outer ring of the lattice).
+template <class R>
+__device__ __forceinline__ bool on_wall(const StepArgs<R>& A, int x, int y) {
+  return A.bc == BC_DIFFUSIVE && (x == 0 || y == 0 || x == A.nx - 1 || y == A.ny - 1);
+}
+
+// Diffusive Maxwell wall (section 8, First Hopf bifurcation) at wall node
+// (x, y) of the streamed state v (storage representation): with n the
+// inward normal, the incoming directions are those with v_i . n > 0 (at a
+// corner only v_i = n, which makes the rule bounce-back), gamma = sum of
+// f_opp(i) over them / sum of f*_i(1, u_wall) over them, and every
+// population whose source lies outside (v_i . n > 0 along either axis)
+// becomes gamma f*_i(1, u_wall).  The lid row moves at (lid_u, 0); the other
+// walls and the corners rest.
+template <class S, int Q>
+__device__ __noinline__ void diffusive_wall(const StepArgs<typename StoreT<S>::R>& A, int x, int y,
+                                            typename StoreT<S>::R v[Q]) {
+  using R = typename StoreT<S>::R;
+  constexpr bool SH = StoreT<S>::shifted;
+  if constexpr (Q == 9) {
+    const int n_x = x == 0 ? 1 : (x == A.nx - 1 ? -1 : 0);
+    const int n_y = y == 0 ? 1 : (y == A.ny - 1 ? -1 : 0);
+    const bool corner = n_x != 0 && n_y != 0;
+    const R uw = (n_y == -1 && n_x == 0) ? A.lid_u : R(0);
+    R fw[Q];
+    equilibrium_v<R, Q, false>(R(1), A.rho0, uw, R(0), A.eq_kind, fw);
+    R num = R(0), den = R(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int a = vx_of<Q>(i), b = vy_of<Q>(i);
+      const bool in = corner ? (a == n_x && b == n_y) : (a * n_x + b * n_y > 0);
+      if (in) {
+        const int o = Q - 1 - i;
+        num += v[o] + (SH ? wt<R, Q>(o) * A.rho0 : R(0));
+        den += fw[i];
+      }
+    }
+    const R gamma = num / den;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int a = vx_of<Q>(i), b = vy_of<Q>(i);
+      if (a * n_x > 0 || b * n_y > 0) v[i] = gamma * fw[i] - (SH ? wt<R, Q>(i) * A.rho0 : R(0));
+    }
+  }
+}
+
 template <class R, int Q, bool SH>
 __device__ __forceinline__ void moments_v(const R v[Q], R rho0, R& m0, R& ux, R& uy) {
   R s = R(0), jx = R(0), jy = R(0);
@@ -240,11 +286,14 @@ __device__ __forceinline__ typename StoreT<S>::R site_prep(
   constexpr bool SH = StoreT<S>::shifted;
   if constexpr (PER) pull_periodic<S, Q>((const S*)A.src, A.qs, A.pitch, A.nx, A.ny, x, y, v);
   else pull<S, Q>((const S*)A.src, A.qs, A.pitch, A.nx, A.ny, A.bc, x, y, A.lid, v);
+  // a diffusive wall node: the wall rule, and Delta S 0 (never a candidate)
+  const bool wall = !PER && on_wall<R>(A, x, y);
+  if (wall) diffusive_wall<S, Q>(A, x, y, v);
   moments_v<R, Q, SH>(v, A.rho0, m0, ux, uy);
   equilibrium_v<R, Q, SH>(m0, A.rho0, ux, uy, A.eq_kind, feq);
 #pragma unroll
   for (int i = 0; i < Q; ++i) d[i] = feq[i] - v[i];
-  return need_dS ? site_dS<R, Q, SH>(v, d, m0, A.rho0, ux, uy, A.eq_kind, screen) : R(0);
+  return (need_dS && !wall) ? site_dS<R, Q, SH>(v, d, m0, A.rho0, ux, uy, A.eq_kind, screen) : R(0);
 }
 
 template <class R> struct KeyInf;
@@ -314,6 +363,7 @@ __device__ typename StoreT<S>::R slot_dS(const StepArgs<typename StoreT<S>::R>& 
   if (wrap_x) gx = gx < 0 ? gx + A.nx : (gx >= A.nx ? gx - A.nx : gx);
   if (wrap_y) gy = gy < 0 ? gy + A.ny : (gy >= A.ny ? gy - A.ny : gy);
   if (gx < 0 || gx >= A.nx || gy < 0 || gy >= A.ny) return __builtin_nan("");  // outside
+  if (on_wall<R>(A, gx, gy)) return __builtin_nan("");   // a diffusive wall node
   R v[Q], feq[Q], d[Q], m0, ux, uy;
   return site_prep<S, Q>(A, gx, gy, v, feq, d, m0, ux, uy, true);
 }

@@ -52,7 +52,7 @@ __device__ __forceinline__ void sort_net9(R a[9]) {
 // k_elbm_f64 instead of being collided, limited and stored here.
 template <class S, int Q, int COLL, bool EHR = true, bool DEFER = false>
 __device__ __forceinline__ void site_finish(const StepArgs<typename StoreT<S>::R>& A, int x, int y,
-                                            bool valid, long long region,
+                                            bool valid, bool wall, long long region,
                                             typename StoreT<S>::R v[Q],
                                             typename StoreT<S>::R feq[Q],
                                             typename StoreT<S>::R d[Q], typename StoreT<S>::R m0,
@@ -65,13 +65,20 @@ __device__ __forceinline__ void site_finish(const StepArgs<typename StoreT<S>::R
   if (EHR && A.ehrenfest) {
     using K = typename KeyOf<R>::T;
     const K key = key_of<R>(dS);
-    const bool is_c = valid && (dS > A.ehr_delta) && (key >= (K)fr.floor);
+    const bool is_c = valid && !wall && (dS > A.ehr_delta) && (key >= (K)fr.floor);
     append_candidates<R>(A, fr, region, is_c, key, (uint32_t)(y * A.nx + x), m0, ux, uy);
   }
 
   R post[Q];
   bool pos_event = false, deferred = false;
-  if (valid) {
+  if (valid && wall) {
+    // a diffusive wall node keeps its streamed state after the wall rule
+    S* dst = (S*)A.dst;
+    const unsigned o = (unsigned)(y * A.pitch + x);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) StoreT<S>::st(at(dst + (long long)i * A.qs, o), v[i]);
+  }
+  if (valid && !wall) {
     const R om = A.omega_field ? A.omega_field[(long long)y * A.pitch + x] : A.omega;
     CollInfo<R> ci;
     collide_site<S, Q, COLL, DEFER>(A, v, feq, d, om, post, ci);
@@ -101,6 +108,7 @@ __device__ __forceinline__ void site_finish(const StepArgs<typename StoreT<S>::R
       for (int i = 0; i < Q; ++i) StoreT<S>::st(at(dst + (long long)i * A.qs, o), post[i]);
     }
   } else if constexpr (COLL == COLL_ELBM) {
+    // an empty lane or a wall node: no collision, no events
     if (A.count_events) {
       count_event(false, cnt + CNT_ELBM_NOROOT);
       count_event(false, cnt + CNT_ELBM_F64);
@@ -261,6 +269,7 @@ void k_step(const StepArgs<typename StoreT<S>::R> A) {
   const int lx = tid % TX, ly = tid / TX;
   const int x = tile_x * TX + lx, y = tile_y * TY + ly;
   const bool valid = x < A.nx && y < A.ny;
+  const bool wall = valid && !PER && on_wall<typename StoreT<S>::R>(A, x, y);
 
   unsigned long long* const cnt = A.counters + (blockIdx.x % kCntSlots) * CNT_N;
   const bool need_dS = MEDIAN || ENS || A.ehrenfest;
@@ -325,7 +334,7 @@ void k_step(const StepArgs<typename StoreT<S>::R> A) {
     __shared__ R sdS[SH_ * SW];
     const int by = sub * TY + ly;                         // row within the workgroup
     const int x0 = tile_x * TX, y0 = (tb / A.tiles_x) * NB * TY;
-    sdS[(by + HY) * SW + lx + 1] = valid ? dS : slot_dS<S, Q>(A, x, y);
+    sdS[(by + HY) * SW + lx + 1] = valid ? (wall ? R(__builtin_nan("")) : dS) : slot_dS<S, Q>(A, x, y);
     constexpr int NHALO = SH_ * SW - TX * TY * NB;
     for (int s = threadIdx.x; s < NHALO; s += 256 * NB) {
       // halo slot s -> LDS coordinates: top row, bottom row, then the left
@@ -342,7 +351,7 @@ void k_step(const StepArgs<typename StoreT<S>::R> A) {
       sdS[hy * SW + hx] = slot_dS<S, Q>(A, x0 + hx - 1, y0 + hy - HY);
     }
     __syncthreads();
-    if (valid) {
+    if (valid && !wall) {
       R nb[9];
       int n = 0;
       constexpr int NN = (Q == 9) ? 9 : 3;
@@ -385,8 +394,8 @@ void k_step(const StepArgs<typename StoreT<S>::R> A) {
   }
 
   constexpr bool DEFER = COLL == COLL_ELBM && sizeof(R) == 4 && !MEDIAN && !ENS;
-  site_finish<S, Q, COLL, true, DEFER>(A, x, y, valid, (long long)t * 4 + tid / 64, v, feq, d, m0, ux,
-                          uy, dS, fr, cnt);
+  site_finish<S, Q, COLL, true, DEFER>(A, x, y, valid, wall, (long long)t * 4 + tid / 64, v, feq, d,
+                                       m0, ux, uy, dS, fr, cnt);
 }
 
 // The step on a periodic lattice without the median filter, in rows of 256
@@ -450,8 +459,9 @@ __global__ __launch_bounds__(256) void k_step_rows(const StepArgs<typename Store
                      ? site_dS<R, Q, SH>(v, d, m0, A.rho0, ux, uy, A.eq_kind, screen)
                      : R(0);
     const long long region = ((long long)y * A.tiles_x + tile_x) * 4 + threadIdx.x / 64;
-    site_finish<S, Q, COLL, EHR, COLL == COLL_ELBM && sizeof(R) == 4>(A, x, y, valid, region, v, feq,
-                                                                       d, m0, ux, uy, dS, fr, cnt);
+    site_finish<S, Q, COLL, EHR, COLL == COLL_ELBM && sizeof(R) == 4>(A, x, y, valid, false, region,
+                                                                       v, feq, d, m0, ux, uy, dS, fr,
+                                                                       cnt);
   }
 }
 

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 LBM_OK, LBM_EINVAL, LBM_EWORKSPACE, LBM_EHIP = 0, -1, -2, -3
 LBM_EDIVERGED, LBM_ESTATE, LBM_EUNSUPPORTED, LBM_ESELECT = -4, -5, -6, -7
 LBM_D1Q3, LBM_D2Q9 = 1, 2
-LBM_BC_PERIODIC, LBM_BC_BOUNCEBACK, LBM_BC_CAVITY, LBM_BC_COUETTE = 0, 1, 2, 3
+LBM_BC_PERIODIC, LBM_BC_BOUNCEBACK, LBM_BC_CAVITY, LBM_BC_COUETTE, LBM_BC_DIFFUSIVE = 0, 1, 2, 3, 4
 LBM_LBGK, LBM_MRT, LBM_ELBM = 0, 1, 2
 LBM_EQ_POLY, LBM_EQ_ENTROPIC = 0, 1
 LBM_MRT_M1, LBM_MRT_M2 = 0, 1
@@ -74,7 +74,7 @@ class lbm_stats(ctypes.Structure):
         ("select_overflow", ctypes.c_longlong), ("select_candidates", ctypes.c_longlong),
         ("nonfinite", ctypes.c_int), ("ens_threshold", ctypes.c_double),
         ("ens_mean", ctypes.c_double), ("lbgk_production", ctypes.c_double),
-        ("limiter_production", ctypes.c_double),
+        ("limiter_production", ctypes.c_double), ("enstrophy", ctypes.c_double),
     ]
 
 
@@ -254,7 +254,7 @@ def lbm_destroy(ctx):
 # that owns the workspace tensor and the context.
 # ---------------------------------------------------------------------------
 _BC = {"periodic": LBM_BC_PERIODIC, "bounceback": LBM_BC_BOUNCEBACK, "cavity": LBM_BC_CAVITY,
-       "couette": LBM_BC_COUETTE}
+       "couette": LBM_BC_COUETTE, "diffusive": LBM_BC_DIFFUSIVE}
 _COLL = {"lbgk": LBM_LBGK, "mrt": LBM_MRT, "elbm": LBM_ELBM}
 _STORE = {"f64": LBM_F64, "f32": LBM_F32, "f16s": LBM_F16S, "bf16s": LBM_BF16S}
 _PRESET = {"given": LBM_RATES_GIVEN, "trt": LBM_RATES_TRT, "mrt_trtq": LBM_RATES_MRT_TRTQ,
