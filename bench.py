@@ -35,6 +35,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -579,6 +580,110 @@ def c5_study(steps: int, K: int, checkpoints: list) -> dict:
     return out
 
 
+def hopf_study(res: list, L: int, steps_factor: float, record_frac: float) -> dict:
+    """The first Hopf bifurcation of the lid-driven cavity (section 8): an
+    L x L lattice with diffusive Maxwell walls, entropic equilibria, LBGK
+    with the median filter (delta 1e-3), lid u0 = 0.1, from rest, FP64; for
+    each Re (nu = u0 L / Re) steps_factor L / u0 steps, u_x at the probe
+    node (L/16, 13L/16) (from the bottom-left corner) recorded over the final
+    record_frac of them, and E_u of eq. energy, sqrt(L / (u0 n)) times the
+    l2 norm of the recorded signal minus its mean.  E_u^2 grows linearly in
+    Re past the bifurcation: a least-squares line through the points above
+    the noise floor places it where the line crosses zero.  Also: the probe
+    signal's dominant frequency, the enstrophy at the end, throughput.  The
+    Reynolds numbers run at once, each lattice on a stream of its own (one
+    small lattice leaves most of the GPU idle)."""
+    import numpy as np
+    import torch
+
+    from lbm_inputs import generators as G
+    from paper_1110_0270_amd import lbm as B
+
+    u0 = 0.1
+    n_steps = int(round(steps_factor * L / u0))
+    n_rec = max(2, int(round(record_frac * n_steps)))
+    n_main = n_steps - n_rec
+    px, py = L // 16, (13 * L) // 16
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")  # noqa: E731
+    rho, ux, uy = (t(a) for a in G.uniform_rest(L, L))
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in res]
+    sims = []
+    for re, st in zip(res, streams):
+        with torch.cuda.stream(st):
+            cfg = B.make_config(lattice="D2Q9", nx=L, ny=L, bc="diffusive", u_lid=u0,
+                                nu=u0 * L / re, equilibrium="entropic", median=True,
+                                med_delta=1e-3, storage="f64")
+            sim = B.Simulation(cfg)
+            sim.set_equilibrium(rho, ux, uy)
+        sims.append(sim)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done, chunk = 0, 250000
+    while done < n_main:
+        m = min(chunk, n_main - done)
+        for sim, st in zip(sims, streams):
+            with torch.cuda.stream(st):
+                sim.step(m)
+        torch.cuda.synchronize()
+        done += m
+        log(f"[hopf] step {done} of {n_steps}, {time.perf_counter() - t0:.1f} s")
+    t1 = time.perf_counter()
+    sigs = [torch.empty((n_rec, 2), dtype=torch.float64, device="cuda") for _ in res]
+    torch.cuda.synchronize()
+    for k in range(n_rec):
+        for sim, st, sig in zip(sims, streams, sigs):
+            with torch.cuda.stream(st):
+                sim.step(1)
+                _, mx, my = sim.moments()
+                sig[k, 0] = mx[py, px]
+                sig[k, 1] = my[py, px]
+        if (k + 1) % 10000 == 0:
+            log(f"[hopf] recorded {k + 1} of {n_rec} steps, {time.perf_counter() - t1:.1f} s")
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    rows = []
+    for re, sim, st, sig in zip(res, sims, streams, sigs):
+        with torch.cuda.stream(st):
+            stt = sim.stats(allow_status=(B.LBM_OK, B.LBM_EDIVERGED))
+            cnt = sim.counters()
+        u = sig[:, 0].cpu().numpy()
+        e_u = float(math.sqrt(L / (u0 * n_rec)) * np.linalg.norm(u - u.mean()))
+        spec = np.abs(np.fft.rfft(u - u.mean()))
+        kmax = int(np.argmax(spec[1:]) + 1) if spec.size > 1 else 0
+        rows.append({
+            "Re": re, "nu": u0 * L / re, "E_u": e_u, "E_u2": e_u * e_u,
+            "u_mean": float(u.mean()), "v_mean": float(sig[:, 1].mean()),
+            "u_std": float(u.std()),
+            # cycles per step, and per L / u0 (the flow's time unit)
+            "dominant_frequency_per_step": kmax / n_rec,
+            "dominant_frequency_per_L_over_u0": kmax / n_rec * L / u0,
+            "enstrophy": stt.enstrophy, "diverged_step": int(stt.diverged_step),
+            # sites the median filter changed, per fluid-site update
+            "median_per_update": cnt[1] / ((L - 2) * (L - 2) * n_steps),
+        })
+        log(f"[hopf] Re {re}: E_u {e_u:.4g}, enstrophy {stt.enstrophy:.4g}, "
+            f"median {rows[-1]['median_per_update']:.3g} per update")
+    del sims
+    torch.cuda.empty_cache()
+    # least-squares line of E_u^2 over Re through the points above the noise
+    # floor (E_u^2 above a tenth of the largest)
+    e2 = np.array([r["E_u2"] for r in rows])
+    rr = np.array([r["Re"] for r in rows], dtype=float)
+    fit = None
+    on = e2 > 0.1 * e2.max()
+    if on.sum() >= 2:
+        slope, icpt = np.polyfit(rr[on], e2[on], 1)
+        fit = {"points": int(on.sum()), "slope": float(slope), "intercept": float(icpt),
+               "re_critical": float(-icpt / slope) if slope != 0 else None}
+    return {"workload": "hopf_cavity", "L": L, "u0": u0, "steps": n_steps,
+            "recorded_steps": n_rec, "probe": [px, py], "median_delta": 1e-3,
+            "equilibrium": "entropic", "storage": "f64", "runs": rows, "fit": fit,
+            "lattices_at_once": len(res),
+            "mlups_all_lattices": len(res) * L * L * n_main / (t1 - t0) / 1e6,
+            "main_s": t1 - t0, "record_s": t2 - t1}
+
+
 def _round(x):
     if isinstance(x, dict):
         return {k: _round(v) for k, v in x.items()}
@@ -598,9 +703,17 @@ def main():
                     "against FP64 over a long shear-layer run; 'cavity': the four 256^2 "
                     "cavity runs in FP64 and FP32; 'c5': the 8192^2 ELBM workload, "
                     "FP16 forward plus adjoint over --study-steps steps, with FP64, "
-                    "FP32 and FP64-control forward runs (one JSON document each)")
+                    "FP32 and FP64-control forward runs; 'hopf': the first Hopf "
+                    "bifurcation of the diffusive-wall cavity (one JSON document each)")
     ap.add_argument("--study-checkpoints", default="100,1000,5000,10000,20000")
     ap.add_argument("--study-steps", type=int, default=50000)
+    ap.add_argument("--study-re", default="7000,7500,8000,8500",
+                    help="Reynolds numbers of --study hopf")
+    ap.add_argument("--study-l", type=int, default=100, help="lattice side of --study hopf")
+    ap.add_argument("--study-steps-factor", type=float, default=5000.0,
+                    help="--study hopf runs this many L / u0 (5000 in the paper)")
+    ap.add_argument("--study-record-frac", type=float, default=0.01,
+                    help="final fraction of the --study hopf run recorded at the probe")
     ap.add_argument("--study-k", type=int, default=71,
                     help="checkpoint interval of --study c5 (about sqrt of its 5000 steps)")
     ap.add_argument("--adjoint-steps", type=int, default=8192)
@@ -617,6 +730,11 @@ def main():
     if args.study == "cavity":
         cps = [1000, 5000, 10000, 20000, 50000]
         print(json.dumps(_round(cavity_study(args.study_steps, cps))), flush=True)
+        return
+    if args.study == "hopf":
+        res = [float(x) for x in args.study_re.split(",")]
+        print(json.dumps(_round(hopf_study(res, args.study_l, args.study_steps_factor,
+                                           args.study_record_frac))), flush=True)
         return
     if args.study == "c5":
         cps = [int(x) for x in args.study_checkpoints.split(",")]
