@@ -113,3 +113,21 @@ def uniform_noise(shape, seed: int, amp: float = 1.0):
     """Uniform noise on [-amp, amp) of the given shape."""
     rng = np.random.default_rng(seed)
     return rng.uniform(-amp, amp, size=shape)
+
+
+def taylor_green_3d(nx: int, ny: int = None, nz: int = None, u0: float = 0.05):
+    """Three-dimensional Taylor-Green vortex on a periodic nx x ny x nz grid
+    (arrays in (z, y, x) order), wavenumbers 2 pi / n along each axis:
+    u_x = u0 sin(kx x) cos(ky y) cos(kz z), u_y = -u0 cos(kx x) sin(ky y)
+    cos(kz z), u_z = 0, and the density of its pressure field,
+    rho = 1 + (3 u0^2 / 16) (cos 2 kx x + cos 2 ky y) (cos 2 kz z + 2).
+    The velocity is divergence-free when nx = ny."""
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    z, y, x = np.meshgrid(2 * np.pi * np.arange(nz) / nz, 2 * np.pi * np.arange(ny) / ny,
+                          2 * np.pi * np.arange(nx) / nx, indexing="ij")
+    ux = u0 * np.sin(x) * np.cos(y) * np.cos(z)
+    uy = -u0 * np.cos(x) * np.sin(y) * np.cos(z)
+    uz = np.zeros_like(ux)
+    rho = 1.0 + (3.0 * u0 * u0 / 16.0) * (np.cos(2 * x) + np.cos(2 * y)) * (np.cos(2 * z) + 2.0)
+    return rho, ux, uy, uz

@@ -13,6 +13,7 @@ order:
   stream (pull, boundaries)            -- section 2, eq. of free flight
   moments, equilibrium                 -- section 2; section 6 (1D equilibria);
                                           section 8 (2D product equilibrium)
+  nonlocal f_neq filter (optional)     -- section 4, "General nonlocal filters"
   nonequilibrium entropy Delta S       -- section 4, Kullback entropy (eq. Kul, DelS)
   median entropy filter (optional)     -- section 4, "Median entropy filter"
   Ehrenfest selection (optional)       -- section 4, Ehrenfests' regularisation
@@ -41,6 +42,7 @@ __all__ = [
     "ens_phi", "ensemble_limiter", "step", "run",
     "stats", "init_equilibrium", "ELBM_ROOT", "ELBM_CUTOFF", "ELBM_NOROOT",
     "ELBM_NONPOS", "wall_nodes", "diffusive_wall", "enstrophy", "hopf_energy",
+    "nonlocal_filter", "stencil_offsets",
 ]
 
 
@@ -118,6 +120,10 @@ class Config:
     elbm_eps: float = 1e-14
     elbm_max_iter: int = 32
     elbm_dS_cut: float = 1e-15
+    # general nonlocal filter of section 4 (None: off): the coefficients
+    # d(y) of the neighbourhood shifts y in tensor order, (dx) for D1Q3 and
+    # 3 (dy + 1) + (dx + 1) for D2Q9
+    nl_coef: Optional[tuple] = None
 
     def with_(self, **kw) -> "Config":
         return replace(self, **kw)
@@ -629,6 +635,33 @@ def median_filter(lat: Lattice, cfg: Config, f, feq, dS, wall=None):
     return feq + coef.unsqueeze(0) * (f - feq), accept
 
 
+def stencil_offsets(lat: Lattice):
+    """The neighbourhood shifts y = (dy, dx) of the nonlocal filter in tensor
+    order: 3 in 1D, the 3 x 3 block in 2D."""
+    if lat.name == "D1Q3":
+        return [(0, dx) for dx in (-1, 0, 1)]
+    return [(dy, dx) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+
+
+def nonlocal_filter(lat: Lattice, f, feq, coef):
+    """General nonlocal filter (section 4, "General nonlocal filters"): with
+    f_neq = f - f*, every site takes f*(x) + sum_y d(y) f_neq(x + y), the sum
+    over the neighbourhood shifts y (stencil_offsets) with the coefficients
+    d(y) = coef.  Each f_neq(x + y) has zero density and momentum, so the
+    filtered state keeps the moments (and f*) of x.
+    Reading: the shifts must map the grid into itself, which on a finite
+    lattice means a periodic one; the filter acts on the pre-collision state
+    (after streaming), like the other filters of section 4."""
+    offs = stencil_offsets(lat)
+    if len(coef) != len(offs):
+        raise ValueError(f"{lat.name} takes {len(offs)} filter coefficients")
+    neq = f - feq
+    acc = torch.zeros_like(neq)
+    for c, (dy, dx) in zip(coef, offs):
+        acc = acc + float(c) * torch.roll(neq, shifts=(-dy, -dx), dims=(1, 2))  # neq[., y+dy, x+dx]
+    return feq + acc
+
+
 def ens_threshold(dS: torch.Tensor, production: float, delta0: float) -> float:
     """Delta S_0 of eq. EntThresh over the lattice's own values (the
     histogram's density taken as the empirical distribution of Delta S):
@@ -742,6 +775,10 @@ def step(lat: Lattice, cfg: Config, g: torch.Tensor,
         wall = wall_nodes(*pre.shape[1:])
     rho, jx, jy = moments(lat, pre)
     feq = equilibrium(lat, rho, jx / rho, jy / rho, kind)
+    if cfg.nl_coef is not None:
+        if cfg.bc != "periodic":
+            raise ValueError("the nonlocal filter needs a periodic lattice")
+        pre = nonlocal_filter(lat, pre, feq, cfg.nl_coef)
     omega = omega_field if omega_field is not None else relaxation_rate(cfg)
     info = {}
     dS = None
