@@ -322,7 +322,7 @@ void k_adjoint(const StepArgs<typename StoreT<S>::R> A, const AdjArgs<typename S
   for (int j = 0; j < nl; ++j) ehr |= lsel[j] == (int32_t)s;
   const int y = (int)(s / A.nx), x = (int)(s % A.nx);
   R v[Q], feq[Q], d[Q], m0, ux, uy;
-  site_prep<S, Q>(A, x, y, v, feq, d, m0, ux, uy, false);
+  site_prep<S, Q, false, false>(A, x, y, v, feq, d, m0, ux, uy, false);
   const long long o = (long long)y * A.pitch + x;
   const R om = A.omega_field ? A.omega_field[o] : A.omega;
   R lam[Q], a[Q], gw;
@@ -366,7 +366,7 @@ __global__ __launch_bounds__(256) void k_adjoint_med(const StepArgs<typename Sto
   __shared__ int32_t lsel[kAdjListLds];
   const int nl = load_short_list<R>(B, lsel);
   R v[Q], feq[Q], d[Q], m0 = R(0), ux = R(0), uy = R(0), dS = R(0);
-  if (valid) dS = site_prep<S, Q>(A, x, y, v, feq, d, m0, ux, uy, true);
+  if (valid) dS = site_prep<S, Q, false, false>(A, x, y, v, feq, d, m0, ux, uy, true);
   constexpr int HY = (Q == 9) ? 1 : 0;
   constexpr int SW = TX + 2, SH_ = TY + 2 * HY;
   __shared__ R sdS[SH_ * SW];
@@ -483,7 +483,7 @@ __global__ __launch_bounds__(256) void k_median_gather(const StepArgs<typename S
   }
   if (G == R(0)) return;
   R v[Q], feq[Q], d[Q], m0, ux, uy;
-  site_prep<S, Q>(A, x, y, v, feq, d, m0, ux, uy, false);
+  site_prep<S, Q, false, false>(A, x, y, v, feq, d, m0, ux, uy, false);
   R r[Q], tf[Q], g[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -513,7 +513,7 @@ __global__ void k_tape_fix(const StepArgs<typename StoreT<S>::R> A, const int32_
     if (j >= n) continue;
     const int y = idx / A.nx, x = idx % A.nx;
     R v[Q], feq[Q], d[Q], m0, ux, uy;
-    site_prep<S, Q>(A, x, y, v, feq, d, m0, ux, uy, false);
+    site_prep<S, Q, false, false>(A, x, y, v, feq, d, m0, ux, uy, false);
     if (A.sel_mrt) selected_state<S, Q>(A, x, y, m0, ux, uy, feq);
     S* dst = (S*)A.dst;
 #pragma unroll

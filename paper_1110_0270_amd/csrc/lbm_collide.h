@@ -149,6 +149,21 @@ __device__ __forceinline__ R mrt_drate(const StepArgs<R>& A, int k, R om) {
   return R(0);
 }
 
+// Wavefront-aggregated event counter: one atomic per wavefront that has
+// events.
+__device__ __forceinline__ void count_event(bool ev, unsigned long long* ctr) {
+  const unsigned long long m = __ballot(ev);
+  if (m && __lane_id() == (unsigned)(__ffsll((long long)m) - 1))
+    atomicAdd(ctr, (unsigned long long)__popcll(m));
+}
+
+// Sum of a per-lane count over the wavefront, added once.
+__device__ __forceinline__ void count_sum(int v, unsigned long long* ctr) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if (v && __lane_id() == 0) atomicAdd(ctr, (unsigned long long)v);
+}
+
 template <class R>
 struct CollInfo {
   R alpha = R(2);   // ELBM alpha (2 elsewhere)
@@ -288,7 +303,7 @@ __device__ __forceinline__ void selected_state(const StepArgs<typename StoreT<S>
   if constexpr (Q == 9) {
     if (A.sel_mrt) {
       R v[Q], feq[Q], d[Q], mm, vx, vy;
-      site_prep<S, Q>(A, x, y, v, feq, d, mm, vx, vy, false);
+      site_prep<S, Q, false, false>(A, x, y, v, feq, d, mm, vx, vy, false);
       const R om = A.omega_field ? A.omega_field[(long long)y * A.pitch + x] : A.omega;
       CollInfo<R> ci;
       collide_site<S, Q, COLL_MRT>(A, v, feq, d, om, out, ci);
@@ -297,6 +312,92 @@ __device__ __forceinline__ void selected_state(const StepArgs<typename StoreT<S>
     }
   }
   equilibrium_v<R, Q, SH>(m0, A.rho0, ux, uy, A.eq_kind, out);
+}
+
+// The step after the pull (and the median filter): Ehrenfest candidacy
+// (eligible, Delta S > delta, and above the floor), collision, positivity
+// rule, store into the second lattice, and the limiter counters.  Every lane
+// of the wavefront calls it.
+// DEFER (FP32 ELBM): sites whose root solve needs FP64 are listed for
+// k_elbm_f64 instead of being collided, limited and stored here.
+template <class S, int Q, int COLL, bool EHR = true, bool DEFER = false>
+__device__ __forceinline__ void site_finish(const StepArgs<typename StoreT<S>::R>& A, int x, int y,
+                                            bool valid, bool wall, long long region,
+                                            typename StoreT<S>::R v[Q],
+                                            typename StoreT<S>::R feq[Q],
+                                            typename StoreT<S>::R d[Q], typename StoreT<S>::R m0,
+                                            typename StoreT<S>::R ux, typename StoreT<S>::R uy,
+                                            typename StoreT<S>::R dS,
+                                            const StepFrame& fr,
+                                            unsigned long long* cnt) {
+  using R = typename StoreT<S>::R;
+  // Ehrenfest candidates: eligible (Delta S > delta) and above the floor.
+  if (EHR && A.ehrenfest) {
+    using K = typename KeyOf<R>::T;
+    const K key = key_of<R>(dS);
+    const bool is_c = valid && !wall && (dS > A.ehr_delta) && (key >= (K)fr.floor);
+    append_candidates<R>(A, fr, region, is_c, key, (uint32_t)(y * A.nx + x), m0, ux, uy);
+  }
+
+  R post[Q];
+  bool pos_event = false, deferred = false;
+  if (valid && wall) {
+    // a diffusive wall node keeps its streamed state after the wall rule
+    S* dst = (S*)A.dst;
+    const unsigned o = (unsigned)(y * A.pitch + x);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) StoreT<S>::st(at(dst + (long long)i * A.qs, o), v[i]);
+  }
+  if (valid && !wall) {
+    const R om = A.omega_field ? A.omega_field[(long long)y * A.pitch + x] : A.omega;
+    CollInfo<R> ci;
+    collide_site<S, Q, COLL, DEFER>(A, v, feq, d, om, post, ci);
+    deferred = ci.deferred;
+    if constexpr (COLL == COLL_ELBM) {
+      // a deferred site counts no event here (its CollInfo is the default)
+      if (A.alpha_out && !deferred) {
+        const long long o = (long long)y * A.pitch + x;
+        A.alpha_out[o] = ci.alpha;
+        A.branch_out[o] = (unsigned char)ci.branch;
+      }
+      if (A.count_events) {
+        count_event(ci.branch == EB_NOROOT, cnt + CNT_ELBM_NOROOT);
+        count_event(ci.f64, cnt + CNT_ELBM_F64);
+        count_event(ci.branch == EB_NONPOS, cnt + CNT_ELBM_NONPOS);
+        count_sum(ci.iters, cnt + CNT_ELBM_ITERS);
+      }
+    }
+    if (!deferred) {
+      if (A.positivity) {
+        positivity_site<S, Q>(A, feq, post, ci);
+        pos_event = ci.pos_arg >= 0;
+      }
+      S* dst = (S*)A.dst;
+      const unsigned o = (unsigned)(y * A.pitch + x);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) StoreT<S>::st(at(dst + (long long)i * A.qs, o), post[i]);
+    }
+  } else if constexpr (COLL == COLL_ELBM) {
+    // an empty lane or a wall node: no collision, no events
+    if (A.count_events) {
+      count_event(false, cnt + CNT_ELBM_NOROOT);
+      count_event(false, cnt + CNT_ELBM_F64);
+      count_event(false, cnt + CNT_ELBM_NONPOS);
+      count_sum(0, cnt + CNT_ELBM_ITERS);
+    }
+  }
+  if (A.positivity && A.count_events) count_event(pos_event, cnt + CNT_POSITIVITY);
+  if constexpr (DEFER) {
+    // wave-aggregated append to the FP64 list
+    const unsigned long long m = __ballot(deferred);
+    if (m) {
+      const int lane = __lane_id(), leader = __ffsll((long long)m) - 1;
+      unsigned int base = 0;
+      if (lane == leader) base = atomicAdd(A.f64_count, (unsigned int)__popcll(m));
+      base = __shfl(base, leader);
+      if (deferred) A.f64_sites[base + __popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)(y * A.nx + x);
+    }
+  }
 }
 
 }  // namespace lbm

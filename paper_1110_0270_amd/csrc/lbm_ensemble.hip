@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void k_ens_pre(const StepArgs<typename StoreT<
        s += (long long)gridDim.x * blockDim.x) {
     const int y = (int)(s / A.nx), x = (int)(s % A.nx);
     R v[Q], feq[Q], d[Q], m0, ux, uy;
-    const R dS = site_prep<S, Q>(A, x, y, v, feq, d, m0, ux, uy, true);
+    const R dS = site_prep<S, Q, false, false>(A, x, y, v, feq, d, m0, ux, uy, true);
     const long long o = (long long)y * A.pitch + x;
     A.ens_dsb[o] = dS;
     if (ens_finite<R>(dS)) {

@@ -102,7 +102,8 @@ struct StepArgs {
   const void* src;
   void* dst;
   long long qs;          // elements between populations = ny * pitch
-  int nx, ny, pitch;
+  int nx, ny, pitch;     // ny: rows (D3Q27: nz * ny3, row z * ny3 + y)
+  int ny3, nz;           // D3Q27: the grid's y and z extents
   int tiles_x, tiles_y;
   int tile_tx;           // sites per tile row (256 or 64); tiles hold 256 sites
   int bc;
@@ -161,6 +162,9 @@ struct StepArgs {
   // [1] last-workgroup ticket.  nullptr: no such sites can occur.
   uint32_t* f64_sites;
   unsigned int* f64_count;
+  // general nonlocal filter of section 4: the coefficients d(y) in tensor
+  // order of the shifts y ([3] D1Q3, [9] D2Q9), or nullptr
+  const R* nl_coef;
 };
 
 // Launchers (one per translation unit); return hipSuccess or the error.
@@ -168,6 +172,12 @@ struct StepArgs {
 // e0/e1 (optional): events recorded at the step kernel's start and end.
 hipError_t launch_step(int storage, int Q, int coll, bool median, const void* args,
                        hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// The step with the general nonlocal filter (periodic D1Q3 / D2Q9).
+hipError_t launch_step_nl(int storage, int Q, int coll, const void* args, hipStream_t s,
+                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// The D3Q27 step (periodic; LBGK, median filter, positivity rule).
+hipError_t launch_step3(int storage, bool median, const void* args, hipStream_t s,
+                        hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_set_eq(int storage, int Q, const void* rho, const void* ux,
                          const void* uy, int in_f64, void* lat, long long qs, int nx,
                          int ny, int pitch, int eq_kind, double rho0, hipStream_t s);

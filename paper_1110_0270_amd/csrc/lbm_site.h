@@ -18,9 +18,17 @@ inline __host__ __device__ TileShape tile_shape(int Q, bool median, int nx) {
   return nx >= 256 ? TileShape{256, 1} : TileShape{64, 4};
 }
 
-template <int Q> __device__ __forceinline__ int vx_of(int i) { return Q == 9 ? kAx9[i] : i - 1; }
-template <int Q> __device__ __forceinline__ int vy_of(int i) { return Q == 9 ? kBy9[i] : 0; }
+// Velocity components of population i in tensor order: D1Q3 i = a + 1;
+// D2Q9 i = 3 (b + 1) + (a + 1); D3Q27 i = 9 (c + 1) + 3 (b + 1) + (a + 1).
+template <int Q> __device__ __forceinline__ int vx_of(int i) {
+  return Q == 27 ? i % 3 - 1 : (Q == 9 ? kAx9[i] : i - 1);
+}
+template <int Q> __device__ __forceinline__ int vy_of(int i) {
+  return Q == 27 ? (i / 3) % 3 - 1 : (Q == 9 ? kBy9[i] : 0);
+}
+template <int Q> __device__ __forceinline__ int vz_of(int i) { return Q == 27 ? i / 9 - 1 : 0; }
 template <class R, int Q> __device__ __forceinline__ R wt(int i) {
+  if constexpr (Q == 27) return w1<R>(vx_of<27>(i)) * w1<R>(vy_of<27>(i)) * w1<R>(vz_of<27>(i));
   return Q == 9 ? w9<R>(i) : w1<R>(i - 1);
 }
 
@@ -133,7 +141,7 @@ __device__ __forceinline__ bool on_wall(const StepArgs<R>& A, int x, int y) {
 // becomes gamma f*_i(1, u_wall).  The lid row moves at (lid_u, 0); the other
 // walls and the corners rest.
 template <class S, int Q>
-__device__ __noinline__ void diffusive_wall(const StepArgs<typename StoreT<S>::R>& A, int x, int y,
+__device__ __forceinline__ void diffusive_wall(const StepArgs<typename StoreT<S>::R>& A, int x, int y,
                                             typename StoreT<S>::R v[Q]) {
   using R = typename StoreT<S>::R;
   constexpr bool SH = StoreT<S>::shifted;
@@ -195,14 +203,17 @@ __device__ __forceinline__ void moments_v(const R v[Q], R rho0, R& m0, R& ux, R&
 // every y_i <= 1/2) the exact sum is skipped and U is returned: the caller
 // only needs to know that Delta S is below `screen`.  screen = 0 always
 // evaluates the exact sum.
+// D3Q27 (uz): the same with three factors, 1/f*_abc = (216/rho) /
+// ((c_a + dt_a)(c_b + dt_b)(c_c + dt_c)).
 template <class R, int Q, bool SH>
-__device__ __forceinline__ R site_dS(const R v[Q], const R d[Q], R m0, R rho0, R ux, R uy,
-                                     int kind, R screen = R(0)) {
-  R dx[3], dy[3], fx[3], fy[3], rx[3], ry[3];
+__device__ __forceinline__ R site_dS_q(const R v[Q], const R d[Q], R m0, R rho0, R ux, R uy, R uz,
+                                       int kind, R screen) {
+  R dx[3], dy[3], dz[3], fx[3], fy[3], fz[3], rx[3], ry[3], rz[3];
   eq_dev6<R>(ux, kind, dx);
-  if constexpr (Q == 9) eq_dev6<R>(uy, kind, dy);
+  if constexpr (Q >= 9) eq_dev6<R>(uy, kind, dy);
+  if constexpr (Q == 27) eq_dev6<R>(uz, kind, dz);
   const R rho = SH ? rho0 + m0 : m0;
-  constexpr R S = Q == 9 ? R(36) : R(6);
+  constexpr R S = Q == 27 ? R(216) : (Q == 9 ? R(36) : R(6));
   const R irs = S * rcp<R>(rho);
   bool bad = rho <= R(0);
 #pragma unroll
@@ -210,20 +221,25 @@ __device__ __forceinline__ R site_dS(const R v[Q], const R d[Q], R m0, R rho0, R
     fx[a] = (R)c1(a - 1) + dx[a];
     rx[a] = irs * rcp<R>(fx[a]);       // S / (rho (c_a + dt_a))
     bad |= fx[a] <= R(0);
-    if constexpr (Q == 9) {
+    if constexpr (Q >= 9) {
       fy[a] = (R)c1(a - 1) + dy[a];
       ry[a] = rcp<R>(fy[a]);
       bad |= fy[a] <= R(0);
+    }
+    if constexpr (Q == 27) {
+      fz[a] = (R)c1(a - 1) + dz[a];
+      rz[a] = rcp<R>(fz[a]);
+      bad |= fz[a] <= R(0);
     }
   }
   R y[Q];
   R sdy = R(0), ymax = R(0);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const int a = vx_of<Q>(i) + 1, b = vy_of<Q>(i) + 1;
+    const int a = vx_of<Q>(i) + 1, b = vy_of<Q>(i) + 1, cz = vz_of<Q>(i) + 1;
     const R sh = SH ? wt<R, Q>(i) * rho0 : R(0);
     bad |= (v[i] + sh) < R(0);
-    const R inv = Q == 9 ? rx[a] * ry[b] : rx[a];   // 1 / f*_i
+    const R inv = Q == 27 ? rx[a] * ry[b] * rz[cz] : (Q == 9 ? rx[a] * ry[b] : rx[a]);   // 1 / f*_i
     y[i] = d[i] * inv;
     ymax = fmax(ymax, y[i]);
     sdy += d[i] * y[i];
@@ -238,21 +254,32 @@ __device__ __forceinline__ R site_dS(const R v[Q], const R d[Q], R m0, R rho0, R
   bool big = false;
 #pragma unroll
   for (int i = 0; i < Q; ++i) big |= !(fabs(y[i]) < R(0.1));
+  // Each component adds fma(a_i, b_i, acc): (d_i y_i, h_poly(-y_i)) where
+  // |y_i| < 0.1 (f*_i h(x_i) = f*_i y_i^2 h_poly(-y_i) = d_i y_i h_poly), else
+  // (f*_i, h(-y_i)); both branches below form the same terms in the same
+  // order, so a site's value does not depend on the other lanes.
   R acc = R(0);
   if (__ballot(big) == 0ull) {
-    // f*_i h(x_i) = f*_i y_i^2 h_poly(-y_i) = (d_i y_i) h_poly(-y_i)
 #pragma unroll
-    for (int i = 0; i < Q; ++i) acc += (d[i] * y[i]) * h_poly<R>(-y[i]);
-    return acc;
+    for (int i = 0; i < Q; ++i) acc = fma(d[i] * y[i], h_poly<R>(-y[i]), acc);
   } else {
+    const R rs = rho * (R(1) / S);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const int a = vx_of<Q>(i) + 1, b = vy_of<Q>(i) + 1;
-      const R fq = Q == 9 ? fx[a] * fy[b] : fx[a];
-      acc += fq * h_fn<R>(-y[i]);
+      const int a = vx_of<Q>(i) + 1, b = vy_of<Q>(i) + 1, cz = vz_of<Q>(i) + 1;
+      const R fq = Q == 27 ? fx[a] * fy[b] * fz[cz] : (Q == 9 ? fx[a] * fy[b] : fx[a]);
+      const bool small = fabs(y[i]) < R(0.1);
+      const R ta = small ? d[i] * y[i] : fq * rs;
+      const R tb = small ? h_poly<R>(-y[i]) : h_fn<R>(-y[i]);
+      acc = fma(ta, tb, acc);
     }
   }
-  return acc * (rho * (R(1) / S));
+  return acc;
+}
+template <class R, int Q, bool SH>
+__device__ __forceinline__ R site_dS(const R v[Q], const R d[Q], R m0, R rho0, R ux, R uy,
+                                     int kind, R screen = R(0)) {
+  return site_dS_q<R, Q, SH>(v, d, m0, rho0, ux, uy, R(0), kind, screen);
 }
 
 // Ranking key of a non-negative Delta S: its bit pattern (monotone in the
@@ -275,8 +302,10 @@ template <> __device__ __forceinline__ double value_of_key<double>(unsigned long
 
 // Everything up to Delta S for one site: used by the step, the median halo
 // and the selection rescans, so that all of them see bit-identical values.
-// PER: the caller knows the lattice is periodic (branch-free pull).
-template <class S, int Q, bool PER = false>
+// PER: the caller knows the lattice is periodic (branch-free pull).  WALL:
+// the configuration may have the diffusive wall (configurations with the
+// adjoint or an ensemble limiter never do, and their kernels leave it out).
+template <class S, int Q, bool PER = false, bool WALL = !PER>
 __device__ __forceinline__ typename StoreT<S>::R site_prep(
     const StepArgs<typename StoreT<S>::R>& A, int x, int y, typename StoreT<S>::R v[Q],
     typename StoreT<S>::R feq[Q], typename StoreT<S>::R d[Q], typename StoreT<S>::R& m0,
@@ -287,7 +316,7 @@ __device__ __forceinline__ typename StoreT<S>::R site_prep(
   if constexpr (PER) pull_periodic<S, Q>((const S*)A.src, A.qs, A.pitch, A.nx, A.ny, x, y, v);
   else pull<S, Q>((const S*)A.src, A.qs, A.pitch, A.nx, A.ny, A.bc, x, y, A.lid, v);
   // a diffusive wall node: the wall rule, and Delta S 0 (never a candidate)
-  const bool wall = !PER && on_wall<R>(A, x, y);
+  const bool wall = WALL && on_wall<R>(A, x, y);
   if (wall) diffusive_wall<S, Q>(A, x, y, v);
   moments_v<R, Q, SH>(v, A.rho0, m0, ux, uy);
   equilibrium_v<R, Q, SH>(m0, A.rho0, ux, uy, A.eq_kind, feq);
