@@ -27,6 +27,14 @@ One JSON line on stdout:
             shifted storage): forward MLUPS and branch statistics, forward +
             adjoint over 32 steps, and the workspace of its full 5000-step
             adjoint;
+  median3d_256  the 256^3 D3Q27 Taylor-Green vortex with the 27-site median
+            filter (FP32), at the workload's delta = 1e-3 and at delta = 0
+            (every site ranks its neighbourhood): MLUPS and the step kernel's
+            algorithmic bytes (27 populations read and written) over its
+            event-timed duration;
+  nonlocal_4096  the 4096^2 shear layer with the general nonlocal filter
+            (binomial 3 x 3 smoothing of f_neq, FP32): MLUPS and the step
+            kernel against HBM;
   cpu_baseline  the FP64 oracle timed on this host: two full steps on all
             threads, and one step of a 1024-row band on one thread.
 Progress goes to stderr.
@@ -185,6 +193,87 @@ def run_adjoint(w: dict, storage: str, steps: int, K: int, init: str, dldomega: 
     del sim
     torch.cuda.empty_cache()
     return out
+
+
+def run_median3d(steps: int, warmup: int, delta=None) -> dict:
+    """The 256^3 D3Q27 Taylor-Green workload with the 27-site median filter
+    (FP32 storage): throughput, the step kernel against HBM (27 populations
+    of 4 B read and written per site) and the fraction of updates the filter
+    changed.  delta overrides the workload's acceptance threshold."""
+    import torch
+
+    from lbm_inputs import generators as G
+    from lbm_inputs.workloads import workload
+    from paper_1110_0270_amd import lbm as B
+
+    w = workload("median3d_256")
+    if delta is not None:
+        w["med_delta"] = delta
+    n = w["nx"] * w["ny"] * w["nz"]
+    rho, ux, uy, uz = G.taylor_green_3d(w["nx"], w["ny"], w["nz"], u0=w["u0"])
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")  # noqa: E731
+    sim = B.Simulation(B.make_config(**{**w, "storage": "f32"}))
+    sim.set_equilibrium3d(t(rho), t(ux), t(uy), t(uz))
+    del rho, ux, uy, uz
+    sim.step(warmup)
+    c0 = sim.counters()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kern_ms, _ = sim.profile_step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    c1 = sim.counters()
+    st = sim.stats()
+    alg = 2 * 27 * 4 * n
+    us = kern_ms / steps * 1e3
+    res = {"workload": "median3d_256", "storage": "f32", "med_delta": w["med_delta"],
+           "steps": steps, "warmup": warmup, "mlups": n * steps / (t1 - t0) / 1e6,
+           "kernel_us": us, "alg_bytes_per_launch": alg, "kernel_gbs": alg / (us * 1e-6) / 1e9,
+           "kernel_frac_of_hbm_peak": alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+           "median_per_update": (c1[1] - c0[1]) / (n * steps),
+           "diverged_step": int(st.diverged_step), "mass_per_site": st.mass / n}
+    del sim
+    torch.cuda.empty_cache()
+    log(f"[bench] median3d 256^3 f32 delta={w['med_delta']:g}: {res['mlups']:.0f} MLUPS, kernel "
+        f"{us:.0f} us = {res['kernel_gbs']:.0f} GB/s, median on {res['median_per_update']:.4f} of updates")
+    return res
+
+
+def run_nonlocal(steps: int, warmup: int) -> dict:
+    """The 4096^2 shear layer with the general nonlocal filter (binomial 3 x 3
+    smoothing of f_neq), FP32 storage: throughput and the step kernel against
+    HBM (9 populations of 4 B read and written per site)."""
+    import torch
+
+    from lbm_inputs import generators as G
+    from lbm_inputs.workloads import workload
+    from paper_1110_0270_amd import lbm as B
+
+    w = workload("nonlocal_4096")
+    n = w["nx"] * w["ny"]
+    r0, ux, uy = G.double_shear_layer(w["nx"])
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")  # noqa: E731
+    sim = B.Simulation(B.make_config(**{**w, "storage": "f32"}))
+    sim.set_equilibrium(t(r0), t(ux), t(uy))
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kern_ms, _ = sim.profile_step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = sim.stats()
+    alg = 2 * 9 * 4 * n
+    us = kern_ms / steps * 1e3
+    res = {"workload": "nonlocal_4096", "storage": "f32", "steps": steps, "warmup": warmup,
+           "mlups": n * steps / (t1 - t0) / 1e6, "kernel_us": us, "alg_bytes_per_launch": alg,
+           "kernel_gbs": alg / (us * 1e-6) / 1e9,
+           "kernel_frac_of_hbm_peak": alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+           "diverged_step": int(st.diverged_step), "mass_per_site": st.mass / n}
+    del sim
+    torch.cuda.empty_cache()
+    log(f"[bench] nonlocal 4096^2 f32: {res['mlups']:.0f} MLUPS, kernel {us:.1f} us = "
+        f"{res['kernel_gbs']:.0f} GB/s")
+    return res
 
 
 def _cpu_model() -> str:
@@ -720,6 +809,10 @@ def main():
     ap.add_argument("--scale-adjoint-steps", type=int, default=128)
     ap.add_argument("--elbm-steps", type=int, default=50)
     ap.add_argument("--elbm-adjoint-steps", type=int, default=32)
+    ap.add_argument("--median3d-steps", type=int, default=50,
+                    help="timed steps of the 256^3 D3Q27 median workload (0: skip)")
+    ap.add_argument("--nonlocal-steps", type=int, default=200,
+                    help="timed steps of the 4096^2 nonlocal-filter workload (0: skip)")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--median", action="store_true",
@@ -831,6 +924,14 @@ def main():
     if args.elbm_steps > 0:
         elbm = run_elbm_8192(args.elbm_steps, 20, args.elbm_adjoint_steps, 8)
 
+    median3d = None
+    if args.median3d_steps > 0:
+        median3d = {"delta_1e-3": run_median3d(args.median3d_steps, 10),
+                    "delta_0": run_median3d(args.median3d_steps, 10, delta=0.0)}
+    nonlocal_ = None
+    if args.nonlocal_steps > 0:
+        nonlocal_ = run_nonlocal(args.nonlocal_steps, 20)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host ...")
@@ -872,6 +973,8 @@ def main():
         "adjoint": _round(adjoint),
         "adjoint_scale": _round(adjoint_scale),
         "elbm_8192": _round(elbm),
+        "median3d_256": _round(median3d),
+        "nonlocal_4096": _round(nonlocal_),
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -61,7 +61,14 @@ typedef enum {
   LBM_ESELECT = -7        /* Ehrenfest selection could not be resolved exactly */
 } lbm_status;
 
-enum { LBM_D1Q3 = 1, LBM_D2Q9 = 2 };
+/* Lattices: D1Q3 and D2Q9 (sections 2, 5, 6), and D3Q27, the tensor product
+ * of D1Q3 in three dimensions (velocities (a, b, c) in {-1, 0, 1}^3, tensor
+ * order i = 9 (c + 1) + 3 (b + 1) + (a + 1), weights w_a w_b w_c, product
+ * equilibria), whose 27-site neighbourhood is the one of the median entropy
+ * filter in 3D (section 4: the 14th of 27 values).  D3Q27 lattices are
+ * periodic nx x ny x nz grids stepped with LBGK, optionally with the median
+ * filter and the positivity rule; populations are (27, nz, ny, nx). */
+enum { LBM_D1Q3 = 1, LBM_D2Q9 = 2, LBM_D3Q27 = 3 };
 /* Boundaries: periodic in x and y; bounce-back walls on all sides; cavity =
  * bounce-back walls with the top wall moving at (u_lid, 0); couette =
  * periodic in x, resting bottom wall, moving top wall; diffusive = the
@@ -124,7 +131,7 @@ enum { LBM_FB_POSITIVITY = 0, LBM_FB_EHRENFEST = 1 };
 enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16S = 2, LBM_BF16S = 3 };
 
 typedef struct lbm_config {
-  int lattice;            /* LBM_D1Q3 | LBM_D2Q9                                */
+  int lattice;            /* LBM_D1Q3 | LBM_D2Q9 | LBM_D3Q27                    */
   int nx, ny;             /* grid; ny = 1 for D1Q3                              */
   int bc;                 /* LBM_BC_*                                           */
   double u_lid;           /* moving-wall speed (cavity, couette)                */
@@ -159,6 +166,17 @@ typedef struct lbm_config {
   double ens_delta;       /* lower bound delta of the threshold                 */
   double ens_alpha;       /* alpha of SMOOTH and POINTWISE                      */
   double ens_k;           /* exponent k of SMOOTH, DOUBLE_MONOTONE, POINTWISE   */
+  int nz;                 /* D3Q27: layers of the grid (1 otherwise)            */
+  /* General nonlocal filter of section 4: after streaming, every site's
+   * nonequilibrium part f - f* becomes sum_y d(y) (f - f*)(x + y) over the
+   * neighbourhood shifts y (the moments, and so f*, are unchanged), before
+   * the collision.  nl_coef holds d(y) in tensor order of y: D1Q3 the 3
+   * shifts dx = -1, 0, 1; D2Q9 the 9 shifts, index 3 (dy + 1) + (dx + 1);
+   * the remaining entries are ignored.  Periodic D1Q3 and D2Q9 lattices
+   * (the shifts must map the grid into itself); not with the median filter,
+   * the Ehrenfest selection, the ensemble limiters or the adjoint. */
+  int nl_filter;          /* 1: the nonlocal filter is on                       */
+  double nl_coef[27];     /* its coefficients d(y)                              */
 } lbm_config;
 
 typedef struct lbm_stats {
@@ -185,8 +203,9 @@ typedef struct lbm_stats {
   /* enstrophy (section 8, cavity study): the sum of the squared vorticity
    * du_y/dx - du_x/dy (central differences of u, FP64) over the sites with
    * four neighbours in the lattice (every site when periodic), divided by
-   * their number; 0 for D1Q3 */
+   * their number; 0 for D1Q3 and D3Q27 */
   double enstrophy;
+  double mom_z;           /* D3Q27: sum over sites of rho u_z (0 otherwise)     */
 } lbm_stats;
 
 typedef struct lbm_ctx lbm_ctx;
@@ -211,15 +230,26 @@ lbm_status lbm_init(const lbm_config* cfg, void* dev_workspace, size_t ws_bytes,
  * (sections 6 and 8: 1D polynomial or entropic equilibria, and their
  * product in 2D).  rho, ux, uy: device arrays of ny*nx values of the given
  * dtype (LBM_F64 or LBM_F32); uy is ignored for D1Q3 and may be NULL.
- * Resets the step counter and the recorded rollout. */
+ * Resets the step counter and the recorded rollout.  D3Q27:
+ * LBM_EUNSUPPORTED (lbm_set_equilibrium3d). */
 lbm_status lbm_set_equilibrium(lbm_ctx* ctx, const void* rho, const void* ux,
                                const void* uy, int dtype);
 
-/* Set the lattice to caller populations f[Q][ny][nx] (device, dtype
- * LBM_F64 or LBM_F32, unshifted).  Resets the step counter and rollout. */
+/* D3Q27: set the lattice to f*_abc = rho phi_a(ux) phi_b(uy) phi_c(uz), the
+ * product of the 1D equilibria of section 6 of the configured kind.  rho,
+ * ux, uy, uz: device arrays of nz*ny*nx values (index (z * ny + y) * nx + x)
+ * of the given dtype.  LBM_EINVAL on other lattices.  Resets the step
+ * counter. */
+lbm_status lbm_set_equilibrium3d(lbm_ctx* ctx, const void* rho, const void* ux,
+                                 const void* uy, const void* uz, int dtype);
+
+/* Set the lattice to caller populations f[Q][ny][nx] (D3Q27:
+ * f[27][nz][ny][nx]; device, dtype LBM_F64 or LBM_F32, unshifted).  Resets
+ * the step counter and rollout. */
 lbm_status lbm_set_populations(lbm_ctx* ctx, const void* f, int dtype);
 
-/* Copy the lattice out as unshifted populations f[Q][ny][nx]. */
+/* Copy the lattice out as unshifted populations f[Q][ny][nx] (D3Q27:
+ * f[27][nz][ny][nx]). */
 lbm_status lbm_get_populations(lbm_ctx* ctx, void* f, int dtype);
 
 /* Per-site relaxation rate omega(x) (device, ny*nx values, dtype LBM_F64 or
@@ -233,7 +263,7 @@ lbm_status lbm_step(lbm_ctx* ctx, long long n);
 
 /* Density and velocity of every site, rho = sum f_i, u = sum v_i f_i / rho
  * (section 2), into device arrays of ny*nx values (uy may be NULL for
- * D1Q3). */
+ * D1Q3).  D3Q27: LBM_EUNSUPPORTED (read the populations instead). */
 lbm_status lbm_moments(lbm_ctx* ctx, void* rho, void* ux, void* uy, int dtype);
 
 /* Adjoint of the rollout recorded since the last lbm_set_* (requires

@@ -1,4 +1,4 @@
-"""The five synthetic workloads, as plain parameter sets.
+"""The synthetic workloads, as plain parameter sets.
 
 Each entry names the lattice, the grid, the boundary, the collision, the
 limiters with their parameters, the step count and the storage forms, plus
@@ -53,6 +53,24 @@ WORKLOADS = {
         elbm_fallback="positivity",
         steps=5000, storages=("f16s",), checkpoint_every=256,
         init="spectral_velocity", seed=5, target_seed=4),
+    # D3Q27 periodic 256^3 Taylor-Green vortex, LBGK + the 27-site median
+    # entropy filter (delta 1e-3, the paper's value in its cavity study).
+    "median3d_256": dict(
+        lattice="D3Q27", nx=256, ny=256, nz=256, bc="periodic", u_lid=0.0,
+        collision="lbgk", equilibrium="poly", nu=1e-5,
+        ehrenfest=False, ehr_k=0, ehr_delta=0.0,
+        median=True, med_delta=1e-3, positivity=False,
+        steps=1000, storages=("f32",), init="taylor_green_3d", u0=0.05, seed=6),
+    # D2Q9 periodic 4096^2 double shear layer, LBGK with the general nonlocal
+    # filter: the binomial 3 x 3 smoothing (1 2 1; 2 4 2; 1 2 1) / 16 of the
+    # nonequilibrium part, whose coefficients sum to 1.
+    "nonlocal_4096": dict(
+        lattice="D2Q9", nx=4096, ny=4096, bc="periodic", u_lid=0.0,
+        collision="lbgk", equilibrium="poly", nu=1e-5,
+        ehrenfest=False, ehr_k=0, ehr_delta=0.0,
+        median=False, med_delta=1e-3, positivity=False,
+        nl_coef=(1 / 16, 2 / 16, 1 / 16, 2 / 16, 4 / 16, 2 / 16, 1 / 16, 2 / 16, 1 / 16),
+        steps=20000, storages=("f32",), init="double_shear_layer", seed=3),
 }
 
 

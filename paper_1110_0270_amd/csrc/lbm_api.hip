@@ -38,6 +38,8 @@ struct Layout {
   int Q = 0, pitch = 0;
   long long qs = 0, n_sites = 0, cap = 0, k = 0, bcap = 0;
   size_t lat_bytes = 0;
+  int rows = 0;            // ny, or nz * ny for D3Q27
+  size_t off_nl = 0;       // nonlocal filter coefficients (27 values of the compute type)
   size_t off_lat[2] = {0, 0}, off_omega = 0, off_sel = 0, off_cnt = 0, off_partial = 0,
          off_stats = 0, off_div = 0, off_ckey = 0, off_cidx = 0, off_cmom = 0, off_hist = 0,
          off_coarse = 0, off_wcount = 0, off_ccount = 0, off_stage = 0, off_blist = 0,
@@ -47,11 +49,46 @@ struct Layout {
   size_t total = 0;
 };
 
+// Rows of the stored lattice: ny, or nz * ny for D3Q27 (row z * ny + y).
+long long rows_of(const lbm_config* c) {
+  return c->lattice == LBM_D3Q27 ? (long long)c->ny * c->nz : c->ny;
+}
+int q_of(const lbm_config* c) { return c->lattice == LBM_D3Q27 ? 27 : (c->lattice == LBM_D2Q9 ? 9 : 3); }
+
 bool validate(const lbm_config* c, std::string& why) {
   if (!c) { why = "config is NULL"; return false; }
-  if (c->lattice != LBM_D1Q3 && c->lattice != LBM_D2Q9) { why = "lattice must be LBM_D1Q3 or LBM_D2Q9"; return false; }
+  if (c->lattice != LBM_D1Q3 && c->lattice != LBM_D2Q9 && c->lattice != LBM_D3Q27) {
+    why = "lattice must be LBM_D1Q3, LBM_D2Q9 or LBM_D3Q27"; return false;
+  }
   if (c->nx < 1 || c->ny < 1) { why = "nx and ny must be positive"; return false; }
-  if ((long long)c->nx * c->ny >= (1ll << 31)) { why = "nx*ny must be below 2^31"; return false; }
+  if (c->lattice != LBM_D3Q27 && c->nz > 1) { why = "nz > 1 needs LBM_D3Q27"; return false; }
+  if (c->lattice == LBM_D3Q27 && c->nz < 1) { why = "nz must be positive"; return false; }
+  if ((long long)c->nx * rows_of(c) >= (1ll << 31)) { why = "nx*ny*nz must be below 2^31"; return false; }
+  if (c->lattice == LBM_D3Q27) {
+    // population planes are addressed with 32-bit byte offsets
+    const long long plane = (long long)(c->nx + 63) / 64 * 64 * rows_of(c) * elem_bytes(c->storage);
+    if (plane >= (1ll << 32)) { why = "a D3Q27 population plane must stay below 4 GiB"; return false; }
+    if (c->bc != LBM_BC_PERIODIC) { why = "D3Q27 lattices are periodic"; return false; }
+    if (c->collision != LBM_LBGK) { why = "D3Q27 lattices collide with LBGK"; return false; }
+    if (c->limiters & LBM_LIM_EHRENFEST) { why = "D3Q27 has no Ehrenfest selection"; return false; }
+    if (c->ens_limiter != LBM_ENS_NONE || c->checkpoint_every > 0 || c->omega_field || c->nl_filter) {
+      why = "D3Q27 excludes the ensemble limiters, the adjoint, the omega field and the nonlocal filter";
+      return false;
+    }
+  }
+  if (c->nl_filter) {
+    if (c->lattice == LBM_D3Q27 || c->bc != LBM_BC_PERIODIC) {
+      why = "the nonlocal filter needs a periodic D1Q3 or D2Q9 lattice"; return false;
+    }
+    if (c->limiters & (LBM_LIM_MEDIAN | LBM_LIM_EHRENFEST) || c->ens_limiter != LBM_ENS_NONE ||
+        c->checkpoint_every > 0) {
+      why = "the nonlocal filter excludes the median filter, the Ehrenfest selection, the "
+            "ensemble limiters and the adjoint";
+      return false;
+    }
+    for (int k = 0; k < 27; ++k)
+      if (!std::isfinite(c->nl_coef[k])) { why = "nl_coef must be finite"; return false; }
+  }
   if (c->lattice == LBM_D1Q3 && c->ny != 1) { why = "D1Q3 needs ny = 1"; return false; }
   if (c->lattice == LBM_D1Q3 && c->bc != LBM_BC_PERIODIC && c->bc != LBM_BC_BOUNCEBACK) {
     why = "D1Q3 supports periodic and bounce-back ends only"; return false;
@@ -105,10 +142,11 @@ bool validate(const lbm_config* c, std::string& why) {
 // workspace), densely packed (row pitch nx), and no adjoint is recorded.
 Layout make_layout(const lbm_config* c, bool lattices = true) {
   Layout L;
-  L.Q = c->lattice == LBM_D2Q9 ? 9 : 3;
+  L.Q = q_of(c);
+  L.rows = (int)rows_of(c);
   L.pitch = lattices ? (c->nx + 63) / 64 * 64 : c->nx;
-  L.qs = (long long)c->ny * L.pitch;
-  L.n_sites = (long long)c->nx * c->ny;
+  L.qs = (long long)L.rows * L.pitch;
+  L.n_sites = (long long)c->nx * L.rows;
   L.lat_bytes = (size_t)L.Q * L.qs * elem_bytes(c->storage);
   const size_t rb = is_f64(c->storage) ? 8 : 4;
   size_t o = 0;
@@ -120,7 +158,8 @@ Layout make_layout(const lbm_config* c, bool lattices = true) {
   L.off_omega = c->omega_field ? take((size_t)L.qs * rb) : 0;
   L.off_sel = take(sizeof(SelState));
   L.off_cnt = take((size_t)kCntSlots * CNT_N * sizeof(unsigned long long));
-  L.off_partial = take(stats_partial_doubles(c->nx, c->ny) * sizeof(double));
+  L.off_partial = take(stats_partial_doubles(c->nx, L.rows) * sizeof(double));
+  L.off_nl = c->nl_filter ? take(27 * rb) : 0;
   L.off_stats = take(8 * sizeof(double));
   L.off_div = take(sizeof(long long));
   if (c->limiters & LBM_LIM_EHRENFEST) {
@@ -200,7 +239,10 @@ void mrt_matrices(int basis, double M[81], double Minv[81]) {
 template <class R>
 void fill_args(StepArgs<R>& A, const lbm_config* c, const Layout& L, char* ws) {
   std::memset((void*)&A, 0, sizeof(A));
-  A.qs = L.qs; A.nx = c->nx; A.ny = c->ny; A.pitch = L.pitch;
+  A.qs = L.qs; A.nx = c->nx; A.ny = L.rows; A.pitch = L.pitch;
+  A.ny3 = c->ny;
+  A.nz = c->lattice == LBM_D3Q27 ? c->nz : 1;
+  A.nl_coef = L.off_nl ? (const R*)(ws + L.off_nl) : nullptr;
   const TileShape ts = tile_shape(L.Q, (c->limiters & LBM_LIM_MEDIAN) != 0, c->nx);
   A.tiles_x = (c->nx + ts.tx - 1) / ts.tx;
   A.tiles_y = (c->ny + ts.ty - 1) / ts.ty;
@@ -349,7 +391,7 @@ void lbm_config_default(lbm_config* c) {
   c->s_e = 1.64; c->s_eps = 1.54; c->s_q = 1.9;
   c->med_delta = 1e-3; c->elbm_norm = LBM_NORM_ENTROPIC; c->elbm_fallback = LBM_FB_POSITIVITY;
   c->elbm_eps = 1e-14; c->elbm_max_iter = 32; c->elbm_dS_cut = 1e-15; c->elbm_f64_below = 3.0;
-  c->storage = LBM_F32; c->rho0 = 1.0;
+  c->storage = LBM_F32; c->rho0 = 1.0; c->nz = 1;
 }
 
 size_t lbm_workspace_bytes(const lbm_config* cfg) {
@@ -380,6 +422,13 @@ lbm_status lbm_init(const lbm_config* cfg, void* ws, size_t ws_bytes, void* stre
   SelState s0;
   init_select_state(&s0, c->f64());
   hipError_t e = hipMemcpyAsync(c->ws + L.off_sel, &s0, sizeof(SelState), hipMemcpyHostToDevice, c->stream);
+  double coef64[27];
+  float coef32[27];
+  if (e == hipSuccess && L.off_nl) {
+    for (int k = 0; k < 27; ++k) { coef64[k] = cfg->nl_coef[k]; coef32[k] = (float)cfg->nl_coef[k]; }
+    e = hipMemcpyAsync(c->ws + L.off_nl, c->f64() ? (const void*)coef64 : (const void*)coef32,
+                       27 * (c->f64() ? 8 : 4), hipMemcpyHostToDevice, c->stream);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(c->ws + L.off_cnt, 0, (size_t)kCntSlots * CNT_N * 8, c->stream);
   if (e == hipSuccess && L.off_ens) e = hipMemsetAsync(c->ws + L.off_ens, 0, sizeof(EnsState), c->stream);
@@ -433,12 +482,26 @@ lbm_status lbm_set_equilibrium(lbm_ctx* c, const void* rho, const void* ux, cons
   g_err.clear();
   if (!c || !rho || !ux) return fail(LBM_EINVAL, "NULL argument");
   if (dtype != LBM_F64 && dtype != LBM_F32) return fail(LBM_EINVAL, "dtype must be LBM_F64 or LBM_F32");
+  if (c->L.Q == 27) return fail(LBM_EUNSUPPORTED, "D3Q27: use lbm_set_equilibrium3d");
   if (c->L.Q == 9 && !uy) return fail(LBM_EINVAL, "uy is required for D2Q9");
   const int kind = c->cfg.collision == LBM_ELBM ? LBM_EQ_ENTROPIC : c->cfg.equilibrium;
-  hipError_t e = launch_set_eq(c->cfg.storage, c->L.Q, rho, ux, uy, dtype == LBM_F64,
-                               c->lat(c->cur), c->L.qs, c->cfg.nx, c->cfg.ny, c->L.pitch, kind,
+  hipError_t e = launch_set_eq(c->cfg.storage, c->L.Q, rho, ux, uy, nullptr, dtype == LBM_F64,
+                               c->lat(c->cur), c->L.qs, c->cfg.nx, c->L.rows, c->L.pitch, kind,
                                c->cfg.rho0, c->stream);
   if (e != hipSuccess) return hip_fail(e, "lbm_set_equilibrium");
+  return reset_rollout(c);
+}
+
+lbm_status lbm_set_equilibrium3d(lbm_ctx* c, const void* rho, const void* ux, const void* uy,
+                                 const void* uz, int dtype) {
+  g_err.clear();
+  if (!c || !rho || !ux || !uy || !uz) return fail(LBM_EINVAL, "NULL argument");
+  if (dtype != LBM_F64 && dtype != LBM_F32) return fail(LBM_EINVAL, "dtype must be LBM_F64 or LBM_F32");
+  if (c->L.Q != 27) return fail(LBM_EINVAL, "lbm_set_equilibrium3d needs a D3Q27 lattice");
+  hipError_t e = launch_set_eq(c->cfg.storage, 27, rho, ux, uy, uz, dtype == LBM_F64,
+                               c->lat(c->cur), c->L.qs, c->cfg.nx, c->L.rows, c->L.pitch,
+                               c->cfg.equilibrium, c->cfg.rho0, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "lbm_set_equilibrium3d");
   return reset_rollout(c);
 }
 
@@ -447,7 +510,7 @@ lbm_status lbm_set_populations(lbm_ctx* c, const void* f, int dtype) {
   if (!c || !f) return fail(LBM_EINVAL, "NULL argument");
   if (dtype != LBM_F64 && dtype != LBM_F32) return fail(LBM_EINVAL, "dtype must be LBM_F64 or LBM_F32");
   hipError_t e = launch_set_pop(c->cfg.storage, c->L.Q, f, dtype == LBM_F64, c->lat(c->cur),
-                                c->L.qs, c->cfg.nx, c->cfg.ny, c->L.pitch, c->cfg.rho0, c->stream);
+                                c->L.qs, c->cfg.nx, c->L.rows, c->L.pitch, c->cfg.rho0, c->stream);
   if (e != hipSuccess) return hip_fail(e, "lbm_set_populations");
   return reset_rollout(c);
 }
@@ -457,7 +520,7 @@ lbm_status lbm_get_populations(lbm_ctx* c, void* f, int dtype) {
   if (!c || !f) return fail(LBM_EINVAL, "NULL argument");
   if (dtype != LBM_F64 && dtype != LBM_F32) return fail(LBM_EINVAL, "dtype must be LBM_F64 or LBM_F32");
   hipError_t e = launch_get_pop(c->cfg.storage, c->L.Q, f, dtype == LBM_F64, c->lat(c->cur),
-                                c->L.qs, c->cfg.nx, c->cfg.ny, c->L.pitch, c->cfg.rho0, c->stream);
+                                c->L.qs, c->cfg.nx, c->L.rows, c->L.pitch, c->cfg.rho0, c->stream);
   if (e != hipSuccess) return hip_fail(e, "lbm_get_populations");
   return LBM_OK;
 }
@@ -492,8 +555,11 @@ static hipError_t one_step(lbm_ctx* c, hipEvent_t ev0 = nullptr, hipEvent_t ev1 
   if (c->cfg.ens_limiter != LBM_ENS_NONE)
     e = launch_ensemble(c->cfg.storage, c->L.Q, args, c->cfg.ens_delta0, c->cfg.ens_delta,
                         c->stream);
-  if (e == hipSuccess)
-    e = launch_step(c->cfg.storage, c->L.Q, c->cfg.collision, med, args, c->stream, ev0, ev1);
+  if (e == hipSuccess) {
+    if (c->L.Q == 27) e = launch_step3(c->cfg.storage, med, args, c->stream, ev0, ev1);
+    else if (c->cfg.nl_filter) e = launch_step_nl(c->cfg.storage, c->L.Q, c->cfg.collision, args, c->stream, ev0, ev1);
+    else e = launch_step(c->cfg.storage, c->L.Q, c->cfg.collision, med, args, c->stream, ev0, ev1);
+  }
   if (e != hipSuccess) return e;
   if (c->cfg.limiters & LBM_LIM_EHRENFEST) {
     SelectArgs sa = select_args(c, args);
@@ -565,7 +631,7 @@ static lbm_status replay_graph(lbm_ctx* c) {
 
 // The periodic divergence check (FP64 reduction) after a step.
 static hipError_t check_now(lbm_ctx* c) {
-  return launch_stats(c->cfg.storage, c->L.Q, c->lat(c->cur), c->L.qs, c->cfg.nx, c->cfg.ny,
+  return launch_stats(c->cfg.storage, c->L.Q, c->lat(c->cur), c->L.qs, c->cfg.nx, c->L.rows,
                       c->L.pitch, c->cfg.bc == LBM_BC_PERIODIC, c->cfg.rho0,
                       (double*)(c->ws + c->L.off_partial),
                       (double*)(c->ws + c->L.off_stats), (long long*)(c->ws + c->L.off_div),
@@ -672,6 +738,7 @@ lbm_status lbm_moments(lbm_ctx* c, void* rho, void* ux, void* uy, int dtype) {
   g_err.clear();
   if (!c || !rho || !ux) return fail(LBM_EINVAL, "NULL argument");
   if (dtype != LBM_F64 && dtype != LBM_F32) return fail(LBM_EINVAL, "dtype must be LBM_F64 or LBM_F32");
+  if (c->L.Q == 27) return fail(LBM_EUNSUPPORTED, "D3Q27: read the populations (lbm_get_populations)");
   hipError_t e = launch_moments(c->cfg.storage, c->L.Q, c->lat(c->cur), c->L.qs, c->cfg.nx,
                                 c->cfg.ny, c->L.pitch, c->cfg.rho0, rho, ux, uy,
                                 dtype == LBM_F64, c->stream);
@@ -683,7 +750,7 @@ lbm_status lbm_stats_get(lbm_ctx* c, lbm_stats* out) {
   g_err.clear();
   if (!c || !out) return fail(LBM_EINVAL, "NULL argument");
   hipError_t e = launch_stats(c->cfg.storage, c->L.Q, c->lat(c->cur), c->L.qs, c->cfg.nx,
-                              c->cfg.ny, c->L.pitch, c->cfg.bc == LBM_BC_PERIODIC, c->cfg.rho0,
+                              c->L.rows, c->L.pitch, c->cfg.bc == LBM_BC_PERIODIC, c->cfg.rho0,
                               (double*)(c->ws + c->L.off_partial),
                               (double*)(c->ws + c->L.off_stats),
                               (long long*)(c->ws + c->L.off_div), c->steps, c->stream);
@@ -700,7 +767,8 @@ lbm_status lbm_stats_get(lbm_ctx* c, lbm_stats* out) {
   std::memset(out, 0, sizeof(*out));
   out->mass = st[0]; out->mom_x = st[1]; out->mom_y = st[2]; out->entropy = st[3];
   out->min_rho = st[4]; out->nonfinite = st[5] != 0.0;
-  out->enstrophy = st[7] > 0.0 ? st[6] / st[7] : 0.0;
+  if (c->L.Q == 27) out->mom_z = st[6];   // the z momentum takes the enstrophy slots in 3D
+  else out->enstrophy = st[7] > 0.0 ? st[6] / st[7] : 0.0;
   out->steps = c->steps;
   out->diverged_step = div;
   out->n_selected = sel.n_sel;
@@ -978,6 +1046,8 @@ extern "C" lbm_status lbm_step_noalloc(const lbm_config* cfg, const void* f_src,
     return fail(LBM_EINVAL, "f_src and f_dst must be distinct device buffers");
   if (cfg->checkpoint_every != 0 || cfg->omega_field != 0)
     return fail(LBM_EINVAL, "lbm_step_noalloc needs checkpoint_every = 0 and omega_field = 0");
+  if (cfg->lattice == LBM_D3Q27 || cfg->nl_filter)
+    return fail(LBM_EUNSUPPORTED, "lbm_step_noalloc covers the D1Q3 and D2Q9 steps without the nonlocal filter");
   const Layout L = make_layout(cfg, false);
   if (L.total > (size_t)LBM_NOALLOC_SCRATCH_BYTES)
     return fail(LBM_EWORKSPACE, "lbm_step_noalloc: this configuration needs " +

@@ -1,6 +1,6 @@
 // Lattice initialisation, population I/O, moments and the whole-lattice
 // FP64 reductions (mass, momentum, entropy, divergence check).
-#include "lbm_site.h"
+#include "lbm_site3.h"
 
 namespace lbm {
 
@@ -15,7 +15,7 @@ __device__ __forceinline__ void wr(void* p, long long i, double v, int f64) {
 
 // f = f*(rho, u) of the configured kind (sections 6 and 8).
 template <class S, int Q>
-__global__ void k_set_eq(const void* rho, const void* ux, const void* uy, int in_f64, S* lat,
+__global__ void k_set_eq(const void* rho, const void* ux, const void* uy, const void* uz, int in_f64, S* lat,
                          long long qs, int nx, int ny, int pitch, int kind, double rho0) {
   using R = typename StoreT<S>::R;
   constexpr bool SH = StoreT<S>::shifted;
@@ -25,9 +25,14 @@ __global__ void k_set_eq(const void* rho, const void* ux, const void* uy, int in
     const int y = (int)(s / nx), x = (int)(s % nx);
     const R r = (R)rd<R>(rho, s, in_f64);
     const R u = (R)rd<R>(ux, s, in_f64);
-    const R w = (Q == 9 && uy) ? (R)rd<R>(uy, s, in_f64) : R(0);
+    const R w = (Q >= 9 && uy) ? (R)rd<R>(uy, s, in_f64) : R(0);
     R feq[Q];
-    equilibrium_v<R, Q, SH>(SH ? r - (R)rho0 : r, (R)rho0, u, w, kind, feq);
+    if constexpr (Q == 27) {
+      const R wz = uz ? (R)rd<R>(uz, s, in_f64) : R(0);
+      equilibrium27<R, SH>(SH ? r - (R)rho0 : r, (R)rho0, u, w, wz, kind, feq);
+    } else {
+      equilibrium_v<R, Q, SH>(SH ? r - (R)rho0 : r, (R)rho0, u, w, kind, feq);
+    }
 #pragma unroll
     for (int i = 0; i < Q; ++i) StoreT<S>::st(lat + (long long)i * qs + (long long)y * pitch + x, feq[i]);
   }
@@ -137,6 +142,11 @@ __global__ __launch_bounds__(kStatsThreads) void k_stats(const S* lat, long long
       if (f[i] > 0.0) ent -= f[i] * log(f[i] / wt<double, Q>(i));
     }
     a_m += r; a_x += jx; a_y += jy; a_s += ent;
+    if constexpr (Q == 27) {
+      // the z momentum (D3Q27) in the slot of the vorticity sum
+#pragma unroll
+      for (int i = 0; i < Q; ++i) a_w += vz_of<Q>(i) * (f[i] - (StoreT<S>::shifted ? wt<double, Q>(i) * rho0 : 0.0));
+    }
     a_min = fmin(a_min, r);
     // vorticity du_y/dx - du_x/dy by central differences (D2Q9)
     if (Q == 9 && (periodic || (x > 0 && y > 0 && x < nx - 1 && y < ny - 1))) {
@@ -208,19 +218,23 @@ static inline int grid_for(long long n) {
   return (int)(g < 4096 ? (g < 1 ? 1 : g) : 4096);
 }
 
-#define LBM_DISPATCH(storage, Q, CALL)                               \
-  do {                                                               \
-    if (storage == 0) { using S = double; if (Q == 9) { constexpr int QQ = 9; CALL; } else { constexpr int QQ = 3; CALL; } } \
-    else if (storage == 1) { using S = float; if (Q == 9) { constexpr int QQ = 9; CALL; } else { constexpr int QQ = 3; CALL; } } \
-    else if (storage == 2) { using S = _Float16; if (Q == 9) { constexpr int QQ = 9; CALL; } else { constexpr int QQ = 3; CALL; } } \
-    else { using S = bf16_t; if (Q == 9) { constexpr int QQ = 9; CALL; } else { constexpr int QQ = 3; CALL; } } \
+#define LBM_QSWITCH(Q, ...)                                                              \
+  if (Q == 27) { constexpr int QQ = 27; __VA_ARGS__; }                                   \
+  else if (Q == 9) { constexpr int QQ = 9; __VA_ARGS__; }                                \
+  else { constexpr int QQ = 3; __VA_ARGS__; }
+#define LBM_DISPATCH(storage, Q, ...)                                                    \
+  do {                                                                                   \
+    if (storage == 0) { using S = double; LBM_QSWITCH(Q, __VA_ARGS__) }                   \
+    else if (storage == 1) { using S = float; LBM_QSWITCH(Q, __VA_ARGS__) }               \
+    else if (storage == 2) { using S = _Float16; LBM_QSWITCH(Q, __VA_ARGS__) }            \
+    else { using S = bf16_t; LBM_QSWITCH(Q, __VA_ARGS__) }                                \
   } while (0)
 
 hipError_t launch_set_eq(int storage, int Q, const void* rho, const void* ux, const void* uy,
-                         int in_f64, void* lat, long long qs, int nx, int ny, int pitch,
+                         const void* uz, int in_f64, void* lat, long long qs, int nx, int ny, int pitch,
                          int eq_kind, double rho0, hipStream_t s) {
   const int g = grid_for((long long)nx * ny);
-  LBM_DISPATCH(storage, Q, hipLaunchKernelGGL((k_set_eq<S, QQ>), dim3(g), dim3(256), 0, s, rho, ux, uy, in_f64, (S*)lat, qs, nx, ny, pitch, eq_kind, rho0));
+  LBM_DISPATCH(storage, Q, hipLaunchKernelGGL((k_set_eq<S, QQ>), dim3(g), dim3(256), 0, s, rho, ux, uy, uz, in_f64, (S*)lat, qs, nx, ny, pitch, eq_kind, rho0));
   return hipGetLastError();
 }
 

@@ -179,7 +179,7 @@ hipError_t launch_step_nl(int storage, int Q, int coll, const void* args, hipStr
 hipError_t launch_step3(int storage, bool median, const void* args, hipStream_t s,
                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_set_eq(int storage, int Q, const void* rho, const void* ux,
-                         const void* uy, int in_f64, void* lat, long long qs, int nx,
+                         const void* uy, const void* uz, int in_f64, void* lat, long long qs, int nx,
                          int ny, int pitch, int eq_kind, double rho0, hipStream_t s);
 hipError_t launch_set_pop(int storage, int Q, const void* f, int in_f64, void* lat,
                           long long qs, int nx, int ny, int pitch, double rho0,

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_EWORKSPACE, LBM_EHIP = 0, -1, -2, -3
 LBM_EDIVERGED, LBM_ESTATE, LBM_EUNSUPPORTED, LBM_ESELECT = -4, -5, -6, -7
-LBM_D1Q3, LBM_D2Q9 = 1, 2
+LBM_D1Q3, LBM_D2Q9, LBM_D3Q27 = 1, 2, 3
 LBM_BC_PERIODIC, LBM_BC_BOUNCEBACK, LBM_BC_CAVITY, LBM_BC_COUETTE, LBM_BC_DIFFUSIVE = 0, 1, 2, 3, 4
 LBM_LBGK, LBM_MRT, LBM_ELBM = 0, 1, 2
 LBM_EQ_POLY, LBM_EQ_ENTROPIC = 0, 1
@@ -34,6 +34,7 @@ LBM_ENS_NONE, LBM_ENS_THRESHOLD, LBM_ENS_SMOOTH, LBM_ENS_DOUBLE_MONOTONE, LBM_EN
 
 EXPORTED = [
     "lbm_config_default", "lbm_workspace_bytes", "lbm_init", "lbm_set_equilibrium",
+    "lbm_set_equilibrium3d",
     "lbm_set_populations", "lbm_get_populations", "lbm_set_omega", "lbm_step",
     "lbm_moments", "lbm_backward", "lbm_stats_get", "lbm_selected", "lbm_counters",
     "lbm_profile_step", "lbm_profile_backward", "lbm_step_noalloc", "lbm_destroy",
@@ -61,7 +62,8 @@ class lbm_config(ctypes.Structure):
         ("mrt_preset", ctypes.c_int), ("sel_action", ctypes.c_int),
         ("ens_limiter", ctypes.c_int), ("ens_delta0", ctypes.c_double),
         ("ens_delta", ctypes.c_double), ("ens_alpha", ctypes.c_double),
-        ("ens_k", ctypes.c_double),
+        ("ens_k", ctypes.c_double), ("nz", ctypes.c_int), ("nl_filter", ctypes.c_int),
+        ("nl_coef", ctypes.c_double * 27),
     ]
 
 
@@ -75,6 +77,7 @@ class lbm_stats(ctypes.Structure):
         ("nonfinite", ctypes.c_int), ("ens_threshold", ctypes.c_double),
         ("ens_mean", ctypes.c_double), ("lbgk_production", ctypes.c_double),
         ("limiter_production", ctypes.c_double), ("enstrophy", ctypes.c_double),
+        ("mom_z", ctypes.c_double),
     ]
 
 
@@ -96,6 +99,7 @@ def library() -> ctypes.CDLL:
         "lbm_workspace_bytes": (SZ, [cfgp]),
         "lbm_init": (I, [cfgp, P, SZ, P, ctypes.POINTER(P)]),
         "lbm_set_equilibrium": (I, [P, P, P, P, I]),
+        "lbm_set_equilibrium3d": (I, [P, P, P, P, P, I]),
         "lbm_set_populations": (I, [P, P, I]),
         "lbm_get_populations": (I, [P, P, I]),
         "lbm_set_omega": (I, [P, P, I]),
@@ -174,6 +178,11 @@ def lbm_init(cfg: lbm_config, workspace: torch.Tensor):
 def lbm_set_equilibrium(ctx, rho, ux, uy=None):
     _check(library().lbm_set_equilibrium(ctx, _ptr(rho), _ptr(ux), _ptr(uy), _dtype_code(rho)),
            "lbm_set_equilibrium")
+
+
+def lbm_set_equilibrium3d(ctx, rho, ux, uy, uz):
+    _check(library().lbm_set_equilibrium3d(ctx, _ptr(rho), _ptr(ux), _ptr(uy), _ptr(uz),
+                                           _dtype_code(rho)), "lbm_set_equilibrium3d")
 
 
 def lbm_set_populations(ctx, f):
@@ -272,11 +281,15 @@ def make_config(*, lattice="D2Q9", nx=64, ny=64, bc="periodic", u_lid=0.0, rho_w
                 elbm_dS_cut=1e-15, elbm_f64_below=3.0, storage="f32", rho0=1.0,
                 omega_field=False, checkpoint_every=0, max_steps=0, check_interval=0,
                 mrt_preset="given", sel_action="equilibrium", ens_limiter="none",
-                ens_delta0=0.1, ens_delta=0.0, ens_alpha=1.0, ens_k=1.0,
+                ens_delta0=0.1, ens_delta=0.0, ens_alpha=1.0, ens_k=1.0, nz=1, nl_coef=None,
                 **_ignored) -> lbm_config:
     c = lbm_config_default()
-    c.lattice = LBM_D2Q9 if lattice == "D2Q9" else LBM_D1Q3
-    c.nx, c.ny = int(nx), int(ny)
+    c.lattice = {"D1Q3": LBM_D1Q3, "D2Q9": LBM_D2Q9, "D3Q27": LBM_D3Q27}[lattice]
+    c.nx, c.ny, c.nz = int(nx), int(ny), int(nz)
+    if nl_coef is not None:
+        c.nl_filter = 1
+        for k, v in enumerate(nl_coef):
+            c.nl_coef[k] = float(v)
     c.bc = _BC[bc]
     c.u_lid, c.rho_wall = float(u_lid), float(rho_wall)
     c.collision = _COLL[collision]
@@ -312,8 +325,9 @@ class Simulation:
 
     def __init__(self, cfg: lbm_config, device="cuda"):
         self.cfg = cfg
-        self.Q = 9 if cfg.lattice == LBM_D2Q9 else 3
-        self.shape = (self.Q, cfg.ny, cfg.nx)
+        self.Q = {LBM_D1Q3: 3, LBM_D2Q9: 9, LBM_D3Q27: 27}[cfg.lattice]
+        self.shape = ((27, cfg.nz, cfg.ny, cfg.nx) if cfg.lattice == LBM_D3Q27
+                      else (self.Q, cfg.ny, cfg.nx))
         nbytes = lbm_workspace_bytes(cfg)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
         off = (-self.workspace.data_ptr()) % 256
@@ -334,6 +348,11 @@ class Simulation:
 
     def set_equilibrium(self, rho, ux, uy=None):
         lbm_set_equilibrium(self.ctx, rho, ux, uy)
+        self.generation += 1
+        self.steps_taken = 0
+
+    def set_equilibrium3d(self, rho, ux, uy, uz):
+        lbm_set_equilibrium3d(self.ctx, rho, ux, uy, uz)
         self.generation += 1
         self.steps_taken = 0
 

@@ -39,7 +39,7 @@ def test_config_struct_matches_header_field_order():
         typ_len = 2 if toks[0] in ("long", "unsigned") and toks[1] in ("long",) else 1
         if toks[0] == "long" and toks[1] == "long":
             typ_len = 2
-        fields += toks[typ_len:]
+        fields += [t.split("[")[0] for t in toks[typ_len:]]
     assert fields == [f for f, _ in B.lbm_config._fields_]
 
 
@@ -61,6 +61,34 @@ def test_workspace_sizing_and_validation():
         cfg = B.make_config(**{"nu": 0.01, **bad})
         assert B.library().lbm_workspace_bytes(ctypes.byref(cfg)) == 0
         assert B.library().lbm_last_error().decode() != ""
+
+
+def test_d3q27_and_nonlocal_filter_validation():
+    """D3Q27 lattices and the nonlocal filter: the workspace holds the 27
+    population planes of nz * ny rows, and unsupported combinations are
+    rejected on the host with a reason."""
+    lib = B.library()
+    c3 = B.make_config(lattice="D3Q27", nx=64, ny=32, nz=16, nu=0.01, median=True,
+                       positivity=True, storage="f32")
+    n3 = B.lbm_workspace_bytes(c3)
+    assert n3 >= 2 * 27 * 32 * 16 * 64 * 4
+    nl = B.make_config(nx=64, ny=64, nu=0.01, nl_coef=[0.1] * 9, collision="elbm")
+    assert B.lbm_workspace_bytes(nl) > 0
+    bad = [dict(lattice="D3Q27", nx=8, ny=8, nz=0),
+           dict(lattice="D3Q27", nx=8, ny=8, nz=8, bc="cavity"),
+           dict(lattice="D3Q27", nx=8, ny=8, nz=8, collision="mrt"),
+           dict(lattice="D3Q27", nx=8, ny=8, nz=8, ehrenfest=True, ehr_k=4),
+           dict(lattice="D3Q27", nx=8, ny=8, nz=8, nl_coef=[0.0] * 27),
+           dict(lattice="D3Q27", nx=8, ny=8, nz=8, checkpoint_every=4, max_steps=8),
+           dict(lattice="D2Q9", nx=8, ny=8, nz=4),
+           dict(nx=16, ny=16, bc="cavity", nl_coef=[0.1] * 9),
+           dict(nx=16, ny=16, median=True, nl_coef=[0.1] * 9),
+           dict(nx=16, ny=16, ehrenfest=True, ehr_k=3, nl_coef=[0.1] * 9),
+           dict(nx=16, ny=16, nl_coef=[float("nan")] + [0.0] * 8)]
+    for b in bad:
+        cfg = B.make_config(**{"nu": 0.01, **b})
+        assert lib.lbm_workspace_bytes(ctypes.byref(cfg)) == 0, b
+        assert lib.lbm_last_error().decode() != ""
 
 
 def test_init_rejects_small_or_missing_workspace_without_touching_the_device():

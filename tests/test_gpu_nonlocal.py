@@ -1,0 +1,119 @@
+"""GPU parity of the general nonlocal f_neq filter (section 4, "General
+nonlocal filters") against the FP64 oracle, through the C ABI: after
+streaming, f(x) -> f*(x) + sum_y d(y) f_neq(x + y) over the 3 (D1Q3) or
+3 x 3 (D2Q9) shifts, then the collision and the positivity rule.
+
+Bars as the other parity tests: FP64 one step 1e-12 relative (floor 1e-3),
+20 steps 1e-10; FP32 and FP16 storage within half an ulp of the stored
+deviation plus 8 FP32 roundings.  Sizes span several 64 x 4 (D2Q9) or
+256 x 1 (D1Q3) tiles with ragged edges."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from tests.parity_util import gpu_run, lattice, oracle_run, random_state, rel_err
+
+pytestmark = pytest.mark.gpu
+
+NARROW = dict(nx=70, ny=37)
+WIDE = dict(nx=300, ny=13)
+
+
+def _coef(n, seed):
+    rng = np.random.default_rng(seed)
+    return tuple(float(v) for v in rng.uniform(-0.2, 0.5, n))
+
+
+CASES = {
+    "lbgk": dict(nu=0.01),
+    "lbgk_entropic_pos": dict(nu=1e-4, equilibrium="entropic", positivity=True, _amp=0.5),
+    "mrt": dict(nu=0.002, collision="mrt"),
+    "elbm": dict(nu=1e-4, collision="elbm"),
+    "elbm_pos": dict(nu=1e-4, collision="elbm", positivity=True, _amp=0.5),
+}
+
+
+def _params(name, size, lattice_name="D2Q9", seed=81):
+    d = dict(CASES[name])
+    amp = d.pop("_amp", 0.1)
+    nk = 3 if lattice_name == "D1Q3" else 9
+    return {"lattice": lattice_name, "bc": "periodic", **size, **d,
+            "nl_coef": _coef(nk, seed)}, amp
+
+
+def _kind(p):
+    return "entropic" if p.get("collision") == "elbm" or p.get("equilibrium") == "entropic" \
+        else "poly"
+
+
+@pytest.mark.parametrize("size", ["narrow", "wide"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_nonlocal_one_step_fp64(name, size):
+    p, amp = _params(name, NARROW if size == "narrow" else WIDE)
+    f0 = random_state(p, 82, amp=amp, kind=_kind(p))
+    _, f_gpu, sim = gpu_run(p, f0, 1, "f64")
+    f_ora, infos = oracle_run(p, f0, 1)
+    err = rel_err(f_gpu, f_ora)
+    assert err <= 1e-12, f"max relative error {err:.3e}"
+    if p.get("positivity"):
+        assert sim.counters()[0] == int(infos[0]["positivity_mask"].sum())
+
+
+@pytest.mark.parametrize("name", ["lbgk", "elbm"])
+def test_nonlocal_d1q3_fp64(name):
+    if name == "elbm":
+        p, amp = _params("elbm", dict(nx=600, ny=1), "D1Q3")
+    else:
+        p, amp = _params("lbgk", dict(nx=600, ny=1), "D1Q3")
+    f0 = random_state(p, 83, amp=amp, kind=_kind(p))
+    _, f_gpu, _ = gpu_run(p, f0, 5, "f64")
+    f_ora, _ = oracle_run(p, f0, 5)
+    assert rel_err(f_gpu, f_ora) <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["lbgk", "mrt", "elbm_pos"])
+def test_nonlocal_twenty_steps_fp64(name):
+    p, amp = _params(name, NARROW)
+    f0 = random_state(p, 84, amp=amp, kind=_kind(p))
+    _, f_gpu, _ = gpu_run(p, f0, 20, "f64")
+    f_ora, _ = oracle_run(p, f0, 20)
+    assert rel_err(f_gpu, f_ora) <= 1e-10
+
+
+def test_nonlocal_identity_stencil_is_the_plain_step():
+    p, amp = _params("lbgk", NARROW)
+    p["nl_coef"] = tuple(1.0 if k == 4 else 0.0 for k in range(9))
+    f0 = random_state(p, 85, amp=amp)
+    _, f_gpu, _ = gpu_run(p, f0, 3, "f64")
+    plain = dict(p)
+    plain.pop("nl_coef")
+    _, f_plain, _ = gpu_run(plain, f0, 3, "f64")
+    assert rel_err(f_gpu, f_plain) <= 1e-13
+
+
+ULP_BITS = {"f32": 23, "f16s": 10, "bf16s": 7}
+FP32_TERM = 8.0 * 2.0 ** -24
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16s", "bf16s"])
+@pytest.mark.parametrize("name", ["lbgk", "mrt", "elbm"])
+def test_nonlocal_low_precision_one_step(storage, name):
+    p, amp = _params(name, NARROW)
+    f0 = random_state(p, 86, amp=amp, kind=_kind(p))
+    f_in, f_gpu, _ = gpu_run(p, f0, 1, storage)
+    f_ora, _ = oracle_run(p, f_in, 1)
+    lat = lattice(p)
+    g = f_ora - lat.col(lat.w) if storage != "f32" else f_ora
+    mag = g.abs().clamp(min=2.0 ** -14)
+    bound = 0.5 * torch.pow(2.0, torch.floor(torch.log2(mag)) - ULP_BITS[storage]) + \
+        FP32_TERM * f_ora.abs().clamp(min=1.0)
+    if p.get("collision") == "elbm":
+        # the FP32 root solve resolves alpha to 5e-7
+        pre = O.stream(lat, f_in, "periodic")
+        r, jx, jy = O.moments(lat, pre)
+        feq = O.equilibrium(lat, r, jx / r, jy / r, "entropic")
+        filt = O.nonlocal_filter(lat, pre, feq, p["nl_coef"])
+        bound = bound + 2 * 5e-7 * (feq - filt).abs()
+    excess = ((f_gpu - f_ora).abs() - bound).max()
+    assert float(excess) <= 0, f"exceeds the storage bound by {float(excess):.3e}"
