@@ -38,7 +38,8 @@ enum ElbmBranch : int { EB_ROOT = 0, EB_CUTOFF = 1, EB_NOROOT = 2, EB_NONPOS = 3
 // precision is spent on the small deviations from rest.  Populations are
 // loaded and stored nontemporally: a step reads and writes each one once,
 // and the two lattices are far larger than the caches (measured 5 % faster
-// steps at 4096^2 than with cached loads).
+// steps at 4096^2 than with cached loads).  ldc is the cached load, for the
+// kernels that read a population again (halos staged in LDS).
 // ---------------------------------------------------------------------------
 struct bf16_t { uint16_t bits; };
 
@@ -49,6 +50,7 @@ template <> struct StoreT<double> {
   static __device__ __forceinline__ double cvt(double v) { return v; }
   static __device__ __forceinline__ double raw(const double* p) { return __builtin_nontemporal_load(p); }
   static __device__ __forceinline__ double ld(const double* p) { return __builtin_nontemporal_load(p); }
+  static __device__ __forceinline__ double ldc(const double* p) { return *p; }
   static __device__ __forceinline__ void st(double* p, double v) { __builtin_nontemporal_store(v, p); }
 };
 template <> struct StoreT<float> {
@@ -57,6 +59,7 @@ template <> struct StoreT<float> {
   static __device__ __forceinline__ float cvt(float v) { return v; }
   static __device__ __forceinline__ float raw(const float* p) { return __builtin_nontemporal_load(p); }
   static __device__ __forceinline__ float ld(const float* p) { return __builtin_nontemporal_load(p); }
+  static __device__ __forceinline__ float ldc(const float* p) { return *p; }
   static __device__ __forceinline__ void st(float* p, float v) { __builtin_nontemporal_store(v, p); }
 };
 template <> struct StoreT<_Float16> {
@@ -65,6 +68,7 @@ template <> struct StoreT<_Float16> {
   static __device__ __forceinline__ float cvt(_Float16 v) { return (float)v; }
   static __device__ __forceinline__ _Float16 raw(const _Float16* p) { return __builtin_nontemporal_load(p); }
   static __device__ __forceinline__ float ld(const _Float16* p) { return (float)__builtin_nontemporal_load(p); }
+  static __device__ __forceinline__ float ldc(const _Float16* p) { return (float)*p; }
   static __device__ __forceinline__ void st(_Float16* p, float v) { __builtin_nontemporal_store((_Float16)v, p); }
 };
 template <> struct StoreT<bf16_t> {
@@ -78,6 +82,9 @@ template <> struct StoreT<bf16_t> {
   }
   static __device__ __forceinline__ float ld(const bf16_t* p) {
     return __uint_as_float(((uint32_t)__builtin_nontemporal_load(&p->bits)) << 16);
+  }
+  static __device__ __forceinline__ float ldc(const bf16_t* p) {
+    return __uint_as_float(((uint32_t)p->bits) << 16);
   }
   static __device__ __forceinline__ void st(bf16_t* p, float v) {
     uint32_t u = __float_as_uint(v);

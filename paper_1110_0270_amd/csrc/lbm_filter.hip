@@ -5,9 +5,9 @@
 //      state, over the neighbourhood shifts y (3 in 1D, 3 x 3 in 2D)
 //   -> collision (LBGK, MRT or ELBM) -> positivity rule -> store.
 // Each f_neq(x + y) carries no density or momentum, so f*(x) is also the
-// equilibrium of the filtered state.  A workgroup stages f_neq of its
-// 256-site tile and a one-site halo in LDS: every thread first evaluates its
-// own site (whose f* it keeps), then the halo ring is shared out.
+// equilibrium of the filtered state.  A workgroup stages f_neq of its tile
+// and a one-site halo in LDS: every thread first evaluates its own site
+// (whose f* it keeps), then the halo ring is shared out.
 #include <hip/hip_ext.h>
 
 #include "lbm_collide.h"
@@ -21,16 +21,21 @@ __device__ __forceinline__ int wrap1(int g, int n) {
 }
 
 template <class S, int Q, int COLL, int TX, int TY>
-__global__ __launch_bounds__(256) void k_step_nl(const StepArgs<typename StoreT<S>::R> A,
-                                                 int tiles_x) {
+__global__ __launch_bounds__(TX * TY) void k_step_nl(const StepArgs<typename StoreT<S>::R> A,
+                                                     int tiles_x) {
   using R = typename StoreT<S>::R;
   constexpr bool SH = StoreT<S>::shifted;
-  static_assert(TX * TY == 256, "tile must hold 256 sites");
+  constexpr int NT = TX * TY;
   constexpr int HY = Q == 9 ? 1 : 0, SW = TX + 2, SHH = TY + 2 * HY, NS = SW * SHH;
-  constexpr int NRING = NS - 256, NK = Q == 9 ? 9 : 3;
+  constexpr int NRING = NS - NT, NK = Q == 9 ? 9 : 3;
   __shared__ R neq[Q][NS];
 
-  const int tile_x = blockIdx.x % tiles_x, tile_y = blockIdx.x / tiles_x;
+  // Consecutive workgroups are dealt round-robin to the 8 XCDs; each XCD
+  // takes a contiguous band of tiles, so that the halo rows a tile shares
+  // with the tiles above and below come from its own L2.
+  const int T = (int)gridDim.x, b = blockIdx.x;
+  const int tb = (T % 8 == 0) ? (b % 8) * (T / 8) + b / 8 : b;
+  const int tile_x = tb % tiles_x, tile_y = tb / tiles_x;
   const int x0 = tile_x * TX, y0 = tile_y * TY;
   const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX;
   const int x = x0 + lx, y = y0 + ly;
@@ -41,7 +46,7 @@ __global__ __launch_bounds__(256) void k_step_nl(const StepArgs<typename StoreT<
   // special case): its f_neq into LDS slot s
   R v[Q], feq[Q], m0, ux, uy;
   auto stage = [&](int gx, int gy, int s) {
-    pull_periodic<S, Q>((const S*)A.src, A.qs, A.pitch, A.nx, A.ny, wrap1(gx, A.nx),
+    pull_periodic<S, Q, true>((const S*)A.src, A.qs, A.pitch, A.nx, A.ny, wrap1(gx, A.nx),
                         wrap1(gy, A.ny), v);
     moments_v<R, Q, SH>(v, A.rho0, m0, ux, uy);
     equilibrium_v<R, Q, SH>(m0, A.rho0, ux, uy, A.eq_kind, feq);
@@ -54,7 +59,7 @@ __global__ __launch_bounds__(256) void k_step_nl(const StepArgs<typename StoreT<
   for (int i = 0; i < Q; ++i) feq_c[i] = feq[i];
   // the halo ring: top row, bottom row, then the left and right columns
   // (2D); the two end slots of the single row (1D)
-  for (int r = tid; r < NRING; r += 256) {
+  for (int r = tid; r < NRING; r += NT) {
     int hx, hy;
     if constexpr (Q == 9) {
       if (r < SW) { hx = r; hy = 0; }
@@ -94,9 +99,13 @@ template <class S, int Q, int COLL>
 static hipError_t launch_nl(const void* args, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   using R = typename StoreT<S>::R;
   const StepArgs<R>& A = *(const StepArgs<R>*)args;
-  constexpr int TX = Q == 9 ? 64 : 256, TY = 256 / TX;
+  // 2D: 64 x 16 tiles (64 x 8 in FP64, for the LDS) put 1.16 (1.29) halo
+  // sites per site against 1.55 for 64 x 4; FP32 ELBM keeps 64 x 4 (the
+  // root solve's registers do not fit 1024-thread workgroups); 1D: rows of 256
+  constexpr int TX = Q == 9 ? 64 : 256;
+  constexpr int TY = Q != 9 ? 1 : (sizeof(R) == 8 ? 8 : (COLL == COLL_ELBM ? 4 : 16));
   const int tx = (A.nx + TX - 1) / TX, ty = (A.ny + TY - 1) / TY;
-  const dim3 grid(tx * ty), block(256);
+  const dim3 grid(tx * ty), block(TX * TY);
   auto kern = k_step_nl<S, Q, COLL, TX, TY>;
   if (e0 && e1) hipExtLaunchKernelGGL(kern, grid, block, 0, s, e0, e1, 0, A, tx);
   else hipLaunchKernelGGL(kern, grid, block, 0, s, A, tx);

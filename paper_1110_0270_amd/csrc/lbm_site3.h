@@ -11,7 +11,8 @@ namespace lbm {
 
 // Pull on the periodic 3D lattice, branch-free: three source columns, rows
 // and layers, each population at a scalar base plus a 32-bit offset.
-template <class S>
+// CACHED: cached loads (the caller reads populations again).
+template <class S, bool CACHED = false>
 __device__ __forceinline__ void pull27(const S* __restrict__ src, long long qs, int pitch, int nx,
                                        int ny, int nz, int x, int y, int z,
                                        typename StoreT<S>::R v[27]) {
@@ -23,7 +24,8 @@ __device__ __forceinline__ void pull27(const S* __restrict__ src, long long qs, 
 #pragma unroll
   for (int i = 0; i < 27; ++i) {
     const unsigned row = (unsigned)((zs[vz_of<27>(i) + 1] * ny + ys[vy_of<27>(i) + 1]) * pitch);
-    v[i] = StoreT<S>::ld(at(src + (long long)i * qs, row + c[vx_of<27>(i) + 1]));
+    const S* p = at(src + (long long)i * qs, row + c[vx_of<27>(i) + 1]);
+    v[i] = CACHED ? StoreT<S>::ldc(p) : StoreT<S>::ld(p);
   }
 }
 

@@ -31,17 +31,16 @@ __device__ __forceinline__ void finish27(const StepArgs<typename StoreT<S>::R>& 
   using R = typename StoreT<S>::R;
   bool pos_event = false;
   if (valid) {
-    R post[27];
 #pragma unroll
-    for (int i = 0; i < 27; ++i) post[i] = v[i] + A.omega * (feq[i] - v[i]);
+    for (int i = 0; i < 27; ++i) v[i] = v[i] + A.omega * (feq[i] - v[i]);   // collided in place
     if (A.positivity) {
       CollInfo<R> ci;
-      positivity_site<S, 27>(A, feq, post, ci);
+      positivity_site<S, 27>(A, feq, v, ci);
       pos_event = ci.pos_arg >= 0;
     }
     S* dst = (S*)A.dst;
 #pragma unroll
-    for (int i = 0; i < 27; ++i) StoreT<S>::st(at(dst + (long long)i * A.qs, off), post[i]);
+    for (int i = 0; i < 27; ++i) StoreT<S>::st(at(dst + (long long)i * A.qs, off), v[i]);
   }
   if (A.positivity && A.count_events) count_event(pos_event, cnt + CNT_POSITIVITY);
 }
@@ -93,7 +92,7 @@ __device__ __forceinline__ R median27(R a[27]) {
 }
 
 template <class S, int TX, int TY, int ZC>
-__global__ __launch_bounds__(TX * TY) void k_step3_median(const StepArgs<typename StoreT<S>::R> A,
+__global__ __launch_bounds__(TX * TY, sizeof(typename StoreT<S>::R) == 4 ? 4 : 1) void k_step3_median(const StepArgs<typename StoreT<S>::R> A,
                                                           int tiles_x, int tiles_y) {
   using R = typename StoreT<S>::R;
   constexpr bool SH = StoreT<S>::shifted;
@@ -120,14 +119,15 @@ __global__ __launch_bounds__(TX * TY) void k_step3_median(const StepArgs<typenam
   // special case.
   auto layer = [&](int z, int slot) {
     const int zz = wrap_mod(z, A.nz);
+#pragma unroll 1
     for (int s = tid; s < NS; s += NT) {
       const int gx = wrap_mod(x0 + s % SW - 1, A.nx), gy = wrap_mod(y0 + s / SW - 1, A.ny3);
-      R v[27], feq[27], d[27], m0, ux, uy, uz;
-      pull27<S>((const S*)A.src, A.qs, A.pitch, A.nx, A.ny3, A.nz, gx, gy, zz, v);
+      R v[27], d[27], m0, ux, uy, uz;
+      pull27<S, true>((const S*)A.src, A.qs, A.pitch, A.nx, A.ny3, A.nz, gx, gy, zz, v);
       moments27<R, SH>(v, A.rho0, m0, ux, uy, uz);
-      equilibrium27<R, SH>(m0, A.rho0, ux, uy, uz, A.eq_kind, feq);
+      equilibrium27<R, SH>(m0, A.rho0, ux, uy, uz, A.eq_kind, d);
 #pragma unroll
-      for (int i = 0; i < 27; ++i) d[i] = feq[i] - v[i];
+      for (int i = 0; i < 27; ++i) d[i] -= v[i];                      // f* - f
       ring[slot][s] = site_dS_q<R, 27, SH>(v, d, m0, A.rho0, ux, uy, uz, A.eq_kind, R(0));
     }
   };
@@ -138,30 +138,38 @@ __global__ __launch_bounds__(TX * TY) void k_step3_median(const StepArgs<typenam
     const int sc = (z - z0) % 3, sm = (z - z0 + 2) % 3, sp = (z - z0 + 1) % 3;
     layer(z + 1, sp);
     __syncthreads();
-    R v[27], feq[27];
+    // The median decision first, from LDS alone (the site's own state is
+    // not yet live): median < Delta S exactly when at least 14 of the 27
+    // values lie below Delta S; wavefronts without a site above delta skip
+    // the count, and only wavefronts with an accepted site select the 14th.
+    const R dS = valid ? ring[sc][(ly + 1) * SW + lx + 1] : R(0);
+    const bool cand = valid && (dS > A.med_delta) && (dS < r_inf<R>());
     bool acc = false;
-    R med = R(0), dS = R(0);
-    if (valid) {
-      R m0, ux, uy, uz;
-      pull27<S>((const S*)A.src, A.qs, A.pitch, A.nx, A.ny3, A.nz, x, y, z, v);
-      moments27<R, SH>(v, A.rho0, m0, ux, uy, uz);
-      equilibrium27<R, SH>(m0, A.rho0, ux, uy, uz, A.eq_kind, feq);
-      dS = ring[sc][(ly + 1) * SW + lx + 1];
-    }
-    // median < Delta S exactly when at least 14 of the 27 values lie below
-    // Delta S; only then is the median itself needed
-    R nb[27];
-#pragma unroll
-    for (int k = 0; k < 27; ++k) {
+    R med = R(0);
+    auto nbr = [&](int k) {
       const int dz = k / 9 - 1, dy = (k / 3) % 3 - 1, dx = k % 3 - 1;
-      const int sl = dz < 0 ? sm : (dz > 0 ? sp : sc);
-      nb[k] = ring[sl][(ly + 1 + dy) * SW + lx + 1 + dx];
-    }
-    int below = 0;
+      return ring[dz < 0 ? sm : (dz > 0 ? sp : sc)][(ly + 1 + dy) * SW + lx + 1 + dx];
+    };
+    if (__ballot(cand)) {
+      int below = 0;
 #pragma unroll
-    for (int k = 0; k < 27; ++k) below += nb[k] < dS ? 1 : 0;
-    acc = valid && (dS > A.med_delta) && (below >= 14) && (dS < r_inf<R>());
-    if (__ballot(acc)) med = median27<R>(nb);
+      for (int k = 0; k < 27; ++k) below += nbr(k) < dS ? 1 : 0;
+      acc = cand && below >= 14;
+      if (__ballot(acc)) {
+        R nb[27];
+#pragma unroll
+        for (int k = 0; k < 27; ++k) nb[k] = nbr(k);
+        med = median27<R>(nb);
+      }
+    }
+    // every lane pulls (a lane past the lattice edge an in-range site that
+    // it does not store), so that nothing stays undefined from one layer to
+    // the next: the compiler would otherwise carry those values through the
+    // next layer's Delta S and run out of registers
+    R v[27], feq[27], m0, ux, uy, uz;
+    pull27<S, true>((const S*)A.src, A.qs, A.pitch, A.nx, A.ny3, A.nz, valid ? x : x0, valid ? y : y0, z, v);
+    moments27<R, SH>(v, A.rho0, m0, ux, uy, uz);
+    equilibrium27<R, SH>(m0, A.rho0, ux, uy, uz, A.eq_kind, feq);
     if (acc) {
       const R c = sqrt(med / dS);
 #pragma unroll
