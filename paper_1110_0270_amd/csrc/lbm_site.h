@@ -235,30 +235,18 @@ __device__ __forceinline__ R site_dS_q(const R v[Q], const R d[Q], R m0, R rho0,
       bad |= fz[a] <= R(0);
     }
   }
-  // D3Q27 recomputes y_i = d_i / f*_i where it is needed again instead of
-  // keeping all 27 (the same product, so the same value).
-  constexpr bool KEEP_Y = Q != 27;
-  auto inv_of = [&](int i) -> R {   // 1 / f*_i
-    const int a = vx_of<Q>(i) + 1, b = vy_of<Q>(i) + 1, cz = vz_of<Q>(i) + 1;
-    return Q == 27 ? rx[a] * ry[b] * rz[cz] : (Q == 9 ? rx[a] * ry[b] : rx[a]);
-  };
-  R y[KEEP_Y ? Q : 1];
+  R y[Q];
   R sdy = R(0), ymax = R(0);
-  bool big = false;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
+    const int a = vx_of<Q>(i) + 1, b = vy_of<Q>(i) + 1, cz = vz_of<Q>(i) + 1;
     const R sh = SH ? wt<R, Q>(i) * rho0 : R(0);
     bad |= (v[i] + sh) < R(0);
-    const R yi = d[i] * inv_of(i);
-    if constexpr (KEEP_Y) y[i] = yi;
-    else big |= !(fabs(yi) < R(0.1));
-    ymax = fmax(ymax, yi);
-    sdy += d[i] * yi;
+    const R inv = Q == 27 ? rx[a] * ry[b] * rz[cz] : (Q == 9 ? rx[a] * ry[b] : rx[a]);   // 1 / f*_i
+    y[i] = d[i] * inv;
+    ymax = fmax(ymax, y[i]);
+    sdy += d[i] * y[i];
   }
-  auto y_of = [&](int i) -> R {
-    if constexpr (KEEP_Y) return y[i];
-    else return d[i] * inv_of(i);
-  };
   if (bad) return r_inf<R>();
   const R ub = sdy * (R(0.5) + ymax * R(1.0 / 3.0));   // ymax >= 0 (it starts at 0)
   // the margin covers the rounding of the bound itself
@@ -266,10 +254,9 @@ __device__ __forceinline__ R site_dS_q(const R v[Q], const R d[Q], R m0, R rho0,
   // h_fn takes the Taylor series wherever |x| < 0.1; when that holds for
   // every component of every active lane of the wavefront, the logarithms
   // are skipped for all of them (same values, the series either way).
-  if constexpr (KEEP_Y) {
+  bool big = false;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) big |= !(fabs(y[i]) < R(0.1));
-  }
+  for (int i = 0; i < Q; ++i) big |= !(fabs(y[i]) < R(0.1));
   // Each component adds fma(a_i, b_i, acc): (d_i y_i, h_poly(-y_i)) where
   // |y_i| < 0.1 (f*_i h(x_i) = f*_i y_i^2 h_poly(-y_i) = d_i y_i h_poly), else
   // (f*_i, h(-y_i)); both branches below form the same terms in the same
@@ -277,20 +264,16 @@ __device__ __forceinline__ R site_dS_q(const R v[Q], const R d[Q], R m0, R rho0,
   R acc = R(0);
   if (__ballot(big) == 0ull) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const R yi = y_of(i);
-      acc = fma(d[i] * yi, h_poly<R>(-yi), acc);
-    }
+    for (int i = 0; i < Q; ++i) acc = fma(d[i] * y[i], h_poly<R>(-y[i]), acc);
   } else {
     const R rs = rho * (R(1) / S);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const int a = vx_of<Q>(i) + 1, b = vy_of<Q>(i) + 1, cz = vz_of<Q>(i) + 1;
       const R fq = Q == 27 ? fx[a] * fy[b] * fz[cz] : (Q == 9 ? fx[a] * fy[b] : fx[a]);
-      const R yi = y_of(i);
-      const bool small = fabs(yi) < R(0.1);
-      const R ta = small ? d[i] * yi : fq * rs;
-      const R tb = small ? h_poly<R>(-yi) : h_fn<R>(-yi);
+      const bool small = fabs(y[i]) < R(0.1);
+      const R ta = small ? d[i] * y[i] : fq * rs;
+      const R tb = small ? h_poly<R>(-y[i]) : h_fn<R>(-y[i]);
       acc = fma(ta, tb, acc);
     }
   }

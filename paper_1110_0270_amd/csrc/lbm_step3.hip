@@ -92,7 +92,7 @@ __device__ __forceinline__ R median27(R a[27]) {
 }
 
 template <class S, int TX, int TY, int ZC>
-__global__ __launch_bounds__(TX * TY, sizeof(typename StoreT<S>::R) == 4 ? 4 : 1) void k_step3_median(const StepArgs<typename StoreT<S>::R> A,
+__global__ __launch_bounds__(TX * TY, (sizeof(typename StoreT<S>::R) == 4 && TX * TY <= 512) ? 4 : 1) void k_step3_median(const StepArgs<typename StoreT<S>::R> A,
                                                           int tiles_x, int tiles_y) {
   using R = typename StoreT<S>::R;
   constexpr bool SH = StoreT<S>::shifted;
@@ -182,17 +182,18 @@ __global__ __launch_bounds__(TX * TY, sizeof(typename StoreT<S>::R) == 4 ? 4 : 1
 }
 
 // ---------------------------------------------------------------------------
-constexpr int kTX3 = 64, kTY3 = 8, kZC3 = 16;
-
 template <class S>
 static hipError_t launch3(bool median, const void* args, hipStream_t s, hipEvent_t e0,
                           hipEvent_t e1) {
   using R = typename StoreT<S>::R;
   const StepArgs<R>& A = *(const StepArgs<R>*)args;
   if (median) {
-    const int tx = (A.nx + kTX3 - 1) / kTX3, ty = (A.ny3 + kTY3 - 1) / kTY3;
-    const dim3 grid(tx * ty * ((A.nz + kZC3 - 1) / kZC3)), block(kTX3 * kTY3);
-    auto kern = k_step3_median<S, kTX3, kTY3, kZC3>;
+    // 64 x 8 columns of 32 layers: 1.29 halo sites per site, 1.06 layers
+    // per layer (FP32 arithmetic: 64 x 16 tiles measured no faster)
+    constexpr int TX = 64, TY = 8, ZC = sizeof(R) == 4 ? 32 : 16;
+    const int tx = (A.nx + TX - 1) / TX, ty = (A.ny3 + TY - 1) / TY;
+    const dim3 grid(tx * ty * ((A.nz + ZC - 1) / ZC)), block(TX * TY);
+    auto kern = k_step3_median<S, TX, TY, ZC>;
     if (e0 && e1) hipExtLaunchKernelGGL(kern, grid, block, 0, s, e0, e1, 0, A, tx, ty);
     else hipLaunchKernelGGL(kern, grid, block, 0, s, A, tx, ty);
   } else {

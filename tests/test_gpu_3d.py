@@ -119,9 +119,12 @@ def _median_ties(p, f_in):
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16s"])
-@pytest.mark.parametrize("name", ["lbgk", "median", "median_positivity"])
+@pytest.mark.parametrize("name", ["lbgk", "median", "median_positivity", "median:tall"])
 def test_d3q27_low_precision_one_step(storage, name):
-    p, amp = _params(name)
+    """tall: 70 x 20 x 40 spans two rows of 64 x 16 tiles and two 32-layer
+    chunks of the FP32-arithmetic median kernel, both ragged."""
+    name, _, size = name.partition(":")
+    p, amp = _params(name, dict(nx=70, ny=20, nz=40) if size == "tall" else SIZE)
     f0 = random_state3(p, 74, amp)
     f_in, f_gpu, _ = gpu_run(p, f0, 1, storage)
     f_ora, _ = oracle3(p, f_in, 1)
