@@ -99,11 +99,12 @@ template <class S, int Q, int COLL>
 static hipError_t launch_nl(const void* args, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   using R = typename StoreT<S>::R;
   const StepArgs<R>& A = *(const StepArgs<R>*)args;
-  // 2D: 64 x 16 tiles (64 x 8 in FP64, for the LDS) put 1.16 (1.29) halo
-  // sites per site against 1.55 for 64 x 4; FP32 ELBM keeps 64 x 4 (the
-  // root solve's registers do not fit 1024-thread workgroups); 1D: rows of 256
+  // 2D: 64 x 8 tiles (1.29 halo sites per site, against 1.55 for 64 x 4;
+  // 64 x 16 with 1.16 measured 4 % slower: fewer workgroups per CU to
+  // overlap one's loads with another's LDS phase); FP32 ELBM keeps 64 x 4
+  // (the root solve's registers); 1D: rows of 256
   constexpr int TX = Q == 9 ? 64 : 256;
-  constexpr int TY = Q != 9 ? 1 : (sizeof(R) == 8 ? 8 : (COLL == COLL_ELBM ? 4 : 16));
+  constexpr int TY = Q != 9 ? 1 : (sizeof(R) == 8 ? 8 : (COLL == COLL_ELBM ? 4 : 8));
   const int tx = (A.nx + TX - 1) / TX, ty = (A.ny + TY - 1) / TY;
   const dim3 grid(tx * ty), block(TX * TY);
   auto kern = k_step_nl<S, Q, COLL, TX, TY>;
