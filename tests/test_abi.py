@@ -120,6 +120,11 @@ def test_noalloc_host_checks_without_a_gpu():
                         ehr_k=16778)
     assert lib.lbm_step_noalloc(ctypes.byref(big), fake_a, fake_b, None) == B.LBM_EWORKSPACE
     assert b"scratch" in lib.lbm_last_error()
+    # the D3Q27 step and the nonlocal filter are not covered
+    c3 = B.make_config(lattice="D3Q27", nx=8, ny=8, nz=8, nu=0.01)
+    assert lib.lbm_step_noalloc(ctypes.byref(c3), fake_a, fake_b, None) == B.LBM_EUNSUPPORTED
+    cn = B.make_config(nx=64, ny=64, nu=0.01, nl_coef=[0.1] * 9)
+    assert lib.lbm_step_noalloc(ctypes.byref(cn), fake_a, fake_b, None) == B.LBM_EUNSUPPORTED
 
 
 def test_ensemble_limiter_validation():
