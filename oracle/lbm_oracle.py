@@ -591,7 +591,8 @@ def median_filter(lat: Lattice, cfg: Config, f, feq, dS, wall=None):
     neighbourhood of each site (itself included; 3 sites in 1D, 3x3 in 2D);
     where dS_med < dS the homothety f* + sqrt(dS_med / dS) (f - f*) is
     applied (eq. entrHom with the median as threshold).
-    Reading: only neighbours inside the domain count (periodic domains wrap);
+    Reading: only neighbours inside the domain count (periodic directions
+    wrap: both on a periodic lattice, x in the Couette channel);
     with n of them the median is the ceil(n/2)-th smallest (2nd of 3, 5th of
     9 as printed; 3rd of 6 and 2nd of 4 at walls).  Reading: the paper's
     delta (1e-3 in the Hopf study) is an acceptance threshold: only sites
@@ -604,15 +605,16 @@ def median_filter(lat: Lattice, cfg: Config, f, feq, dS, wall=None):
     ys = torch.arange(ny).view(ny, 1)
     xs = torch.arange(nx).view(1, nx)
     vals, valid = [], []
+    wrap_x = cfg.bc in ("periodic", "couette")    # Couette is periodic in x
+    wrap_y = cfg.bc == "periodic"
     for dy, dx in offs:
         v = torch.roll(dS, shifts=(-dy, -dx), dims=(0, 1))   # v[y,x] = dS[y+dy, x+dx]
-        if cfg.bc == "periodic":
-            ok = torch.ones((ny, nx), dtype=torch.bool)
-        else:
-            sy, sx = ys + dy, xs + dx
-            ok = (sy >= 0) & (sy < ny) & (sx >= 0) & (sx < nx)
-            if wall is not None:
-                ok = ok & ~torch.roll(wall, shifts=(-dy, -dx), dims=(0, 1))
+        sy, sx = ys + dy, xs + dx
+        ok_y = torch.ones_like(sy, dtype=torch.bool) if wrap_y else (sy >= 0) & (sy < ny)
+        ok_x = torch.ones_like(sx, dtype=torch.bool) if wrap_x else (sx >= 0) & (sx < nx)
+        ok = (ok_y & ok_x).expand(ny, nx)
+        if wall is not None:
+            ok = ok & ~torch.roll(wall, shifts=(-dy, -dx), dims=(0, 1))
         vals.append(torch.where(ok, v, torch.full_like(v, math.inf)))
         valid.append(ok)
     stack = torch.stack(vals)

@@ -773,7 +773,8 @@ def test_threshold_limiter_dissipation_budget():
 
 
 # ---------------------------------------------------------------- median
-def _median_brute(dS, periodic):
+def _median_brute(dS, periodic, wrap_x=None):
+    wrap_x = periodic if wrap_x is None else wrap_x
     ny, nx = dS.shape
     med = np.zeros_like(dS)
     for y in range(ny):
@@ -785,8 +786,10 @@ def _median_brute(dS, periodic):
                         continue
                     yy, xx = y + dy, x + dx
                     if periodic:
-                        yy, xx = yy % ny, xx % nx
-                    elif not (0 <= yy < ny and 0 <= xx < nx):
+                        yy = yy % ny
+                    if wrap_x:
+                        xx = xx % nx
+                    if not (0 <= yy < ny and 0 <= xx < nx):
                         continue
                     vals.append(dS[yy, xx])
             vals.sort()
@@ -795,6 +798,7 @@ def _median_brute(dS, periodic):
 
 
 @pytest.mark.parametrize("lat,ny,nx,bc", [(L2, 5, 6, "cavity"), (L2, 4, 5, "periodic"),
+                                          (L2, 5, 6, "couette"),
                                           (L1, 1, 9, "bounceback"), (L1, 1, 9, "periodic")])
 def test_median_filter_brute_force(lat, ny, nx, bc):
     f = rand_state(lat, ny, nx, 70, amp=0.1)
@@ -803,7 +807,7 @@ def test_median_filter_brute_force(lat, ny, nx, bc):
     dS = O.kullback_dS(f, q)
     cfg = O.Config(lattice=lat.name, nx=nx, ny=ny, bc=bc, med_delta=1e-4)
     out, acc = O.median_filter(lat, cfg, f, q, dS)
-    med = _median_brute(dS.numpy(), bc == "periodic")
+    med = _median_brute(dS.numpy(), bc == "periodic", bc in ("periodic", "couette"))
     exp_acc = (dS.numpy() > 1e-4) & (med < dS.numpy())
     assert np.array_equal(acc.numpy(), exp_acc) and exp_acc.any()
     coef = np.where(exp_acc, np.sqrt(med / dS.numpy()), 1.0)
