@@ -18,9 +18,12 @@
 
 namespace lbm {
 
+// g mod n for the tile and halo coordinates, which lie within one lattice
+// width of [0, n) unless the lattice is narrower than a tile (then the
+// remainder)
 __device__ __forceinline__ int wrap_mod(int g, int n) {
-  const int r = g % n;
-  return r < 0 ? r + n : r;
+  const int r = g < 0 ? g + n : (g >= n ? g - n : g);
+  return (r < 0 || r >= n) ? ((g % n) + n) % n : r;
 }
 
 // After the filter: LBGK, the positivity rule, the store.
