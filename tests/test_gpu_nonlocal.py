@@ -5,14 +5,15 @@ streaming, f(x) -> f*(x) + sum_y d(y) f_neq(x + y) over the 3 (D1Q3) or
 
 Bars as the other parity tests: FP64 one step 1e-12 relative (floor 1e-3),
 20 steps 1e-10; FP32 and FP16 storage within half an ulp of the stored
-deviation plus 8 FP32 roundings.  Sizes span several 64 x 4 (D2Q9) or
-256 x 1 (D1Q3) tiles with ragged edges."""
+deviation plus 8 FP32 roundings.  Sizes span several tiles (64 x 8 in
+D2Q9, 64 x 4 for FP32 ELBM, rows of 256 in D1Q3) with ragged edges; at the
+benchmark's 4096^2, 200 sampled sites against the oracle."""
 import numpy as np
 import pytest
 import torch
 
 import oracle as O
-from tests.parity_util import gpu_run, lattice, oracle_run, random_state, rel_err
+from tests.parity_util import gpu_run, lattice, make_sim, oracle_run, random_state, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -117,3 +118,44 @@ def test_nonlocal_low_precision_one_step(storage, name):
         bound = bound + 2 * 5e-7 * (feq - filt).abs()
     excess = ((f_gpu - f_ora).abs() - bound).max()
     assert float(excess) <= 0, f"exceeds the storage bound by {float(excess):.3e}"
+
+
+def _window_oracle(p, f_in, y, x):
+    """The oracle's result at one site of a large periodic lattice: its 5 x 5
+    neighbourhood (wrapped) stepped as a periodic lattice of its own; the
+    centre's filter reads f_neq within one site, whose pulls reach within
+    two, so it sees exactly the populations of the full lattice."""
+    ny, nx = f_in.shape[1:]
+    iy = [(y + d) % ny for d in range(-2, 3)]
+    ix = [(x + d) % nx for d in range(-2, 3)]
+    blk = f_in[:, iy][:, :, ix].clone()
+    q = dict(p, nx=5, ny=5)
+    out, _ = oracle_run(q, blk, 1)
+    return out[:, 2, 2]
+
+
+@pytest.mark.timeout(600)
+def test_nonlocal_full_size_sampled_fp32():
+    """The 4096^2 shear layer with the binomial smoothing of f_neq in FP32,
+    the launch configuration the benchmark times: after three steps, one
+    step at 200 sampled sites against the oracle; mass conserved."""
+    from lbm_inputs import generators as G
+    from lbm_inputs.workloads import workload
+    w = workload("nonlocal_4096")
+    p = {k: w[k] for k in ("lattice", "nx", "ny", "bc", "nu", "nl_coef")}
+    sim = make_sim(p, "f32")
+    r0, ux, uy = G.double_shear_layer(w["nx"])
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")  # noqa: E731
+    sim.set_equilibrium(t(r0), t(ux), t(uy))
+    sim.step(3)
+    s0 = sim.stats()
+    f_in = sim.populations().cpu()
+    sim.step(1)
+    f_out = sim.populations().cpu()
+    s1 = sim.stats()
+    rng = np.random.default_rng(9)
+    for _ in range(200):
+        y, x = (int(v) for v in rng.integers(0, 4096, 2))
+        want = _window_oracle(p, f_in, y, x)
+        assert float((f_out[:, y, x] - want).abs().max()) <= 2e-7, (y, x)
+    assert abs(s1.mass - s0.mass) <= 1e-9 * s0.mass
