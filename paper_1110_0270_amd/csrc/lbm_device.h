@@ -87,14 +87,8 @@ template <> struct StoreT<bf16_t> {
     return __uint_as_float(((uint32_t)p->bits) << 16);
   }
   static __device__ __forceinline__ void st(bf16_t* p, float v) {
-    uint32_t u = __float_as_uint(v);
-    uint16_t r;
-    if ((u & 0x7fffffffu) > 0x7f800000u) {
-      r = (uint16_t)((u >> 16) | 0x40u);              // quiet NaN
-    } else {
-      u += 0x7fffu + ((u >> 16) & 1u);                // round to nearest even
-      r = (uint16_t)(u >> 16);
-    }
+    // gfx950's conversion instruction: round to nearest even, NaN stays NaN
+    const uint16_t r = __builtin_bit_cast(uint16_t, (__bf16)v);
     __builtin_nontemporal_store(r, &p->bits);
   }
 };

@@ -49,9 +49,11 @@ __device__ __forceinline__ R qdiv(R a, R b, R rb) {
 // deviation f*_i - w_i rho0) from m0 (rho, or rho - rho0 when shifted):
 // the product of the 1D equilibria (section 8), f*_ab = rho phi_a phi_b,
 // evaluated as (rho/36) (c_a + dt_a)(c_b + dt_b) with integer weights.
+// dx, dy: the deviations dt_a of u_x and u_y, for a caller that goes on to
+// Delta S (site_dS_dev takes them instead of evaluating them again).
 template <class R, int Q, bool SH>
-__device__ __forceinline__ void equilibrium_v(R m0, R rho0, R ux, R uy, int kind, R feq[Q]) {
-  R dx[3], dy[3];
+__device__ __forceinline__ void equilibrium_v(R m0, R rho0, R ux, R uy, int kind, R feq[Q], R dx[3],
+                                              R dy[3]) {
   eq_dev6<R>(ux, kind, dx);
   if constexpr (Q == 9) eq_dev6<R>(uy, kind, dy);
   const R rho = SH ? rho0 + m0 : m0;
@@ -72,6 +74,11 @@ __device__ __forceinline__ void equilibrium_v(R m0, R rho0, R ux, R uy, int kind
       feq[i] = SH ? ms * ca + rs * dx[i] : rs * (ca + dx[i]);
     }
   }
+}
+template <class R, int Q, bool SH>
+__device__ __forceinline__ void equilibrium_v(R m0, R rho0, R ux, R uy, int kind, R feq[Q]) {
+  R dx[3], dy[3];
+  equilibrium_v<R, Q, SH>(m0, rho0, ux, uy, kind, feq, dx, dy);
 }
 
 // Element `off` of an array whose base is the same for the whole wavefront:
@@ -208,13 +215,12 @@ __device__ __forceinline__ void moments_v(const R v[Q], R rho0, R& m0, R& ux, R&
 // evaluates the exact sum.
 // D3Q27 (uz): the same with three factors, 1/f*_abc = (216/rho) /
 // ((c_a + dt_a)(c_b + dt_b)(c_c + dt_c)).
+// site_dS_dev takes the equilibrium's deviations dt_a of u_x, u_y, u_z
+// (eq_dev6) from the caller; site_dS_q evaluates them.
 template <class R, int Q, bool SH>
-__device__ __forceinline__ R site_dS_q(const R v[Q], const R d[Q], R m0, R rho0, R ux, R uy, R uz,
-                                       int kind, R screen) {
-  R dx[3], dy[3], dz[3], fx[3], fy[3], fz[3], rx[3], ry[3], rz[3];
-  eq_dev6<R>(ux, kind, dx);
-  if constexpr (Q >= 9) eq_dev6<R>(uy, kind, dy);
-  if constexpr (Q == 27) eq_dev6<R>(uz, kind, dz);
+__device__ __forceinline__ R site_dS_dev(const R v[Q], const R d[Q], R m0, R rho0, const R dx[3],
+                                         const R dy[3], const R dz[3], R screen) {
+  R fx[3], fy[3], fz[3], rx[3], ry[3], rz[3];
   const R rho = SH ? rho0 + m0 : m0;
   constexpr R S = Q == 27 ? R(216) : (Q == 9 ? R(36) : R(6));
   const R irs = S * rcp<R>(rho);
@@ -241,7 +247,11 @@ __device__ __forceinline__ R site_dS_q(const R v[Q], const R d[Q], R m0, R rho0,
   for (int i = 0; i < Q; ++i) {
     const int a = vx_of<Q>(i) + 1, b = vy_of<Q>(i) + 1, cz = vz_of<Q>(i) + 1;
     const R sh = SH ? wt<R, Q>(i) * rho0 : R(0);
-    bad |= (v[i] + sh) < R(0);
+    // f_i = v_i + sh < 0 exactly when v_i < -sh (a nonzero sum does not
+    // round to zero), one instruction fewer; the D3Q27 median kernel keeps
+    // the sum, with which it spills one register less
+    if constexpr (Q == 27) bad |= (v[i] + sh) < R(0);
+    else bad |= v[i] < -sh;
     const R inv = Q == 27 ? rx[a] * ry[b] * rz[cz] : (Q == 9 ? rx[a] * ry[b] : rx[a]);   // 1 / f*_i
     y[i] = d[i] * inv;
     ymax = fmax(ymax, y[i]);
@@ -278,6 +288,15 @@ __device__ __forceinline__ R site_dS_q(const R v[Q], const R d[Q], R m0, R rho0,
     }
   }
   return acc;
+}
+template <class R, int Q, bool SH>
+__device__ __forceinline__ R site_dS_q(const R v[Q], const R d[Q], R m0, R rho0, R ux, R uy, R uz,
+                                       int kind, R screen) {
+  R dx[3], dy[3], dz[3];
+  eq_dev6<R>(ux, kind, dx);
+  if constexpr (Q >= 9) eq_dev6<R>(uy, kind, dy);
+  if constexpr (Q == 27) eq_dev6<R>(uz, kind, dz);
+  return site_dS_dev<R, Q, SH>(v, d, m0, rho0, dx, dy, dz, screen);
 }
 template <class R, int Q, bool SH>
 __device__ __forceinline__ R site_dS(const R v[Q], const R d[Q], R m0, R rho0, R ux, R uy,
@@ -322,10 +341,11 @@ __device__ __forceinline__ typename StoreT<S>::R site_prep(
   const bool wall = WALL && on_wall<R>(A, x, y);
   if (wall) diffusive_wall<S, Q>(A, x, y, v);
   moments_v<R, Q, SH>(v, A.rho0, m0, ux, uy);
-  equilibrium_v<R, Q, SH>(m0, A.rho0, ux, uy, A.eq_kind, feq);
+  R dx[3], dy[3];
+  equilibrium_v<R, Q, SH>(m0, A.rho0, ux, uy, A.eq_kind, feq, dx, dy);
 #pragma unroll
   for (int i = 0; i < Q; ++i) d[i] = feq[i] - v[i];
-  return (need_dS && !wall) ? site_dS<R, Q, SH>(v, d, m0, A.rho0, ux, uy, A.eq_kind, screen) : R(0);
+  return (need_dS && !wall) ? site_dS_dev<R, Q, SH>(v, d, m0, A.rho0, dx, dy, dx, screen) : R(0);
 }
 
 template <class R> struct KeyInf;

@@ -353,11 +353,12 @@ __global__ __launch_bounds__(256) void k_step_rows(const StepArgs<typename Store
 #pragma unroll
     for (int i = 0; i < Q; ++i) v[i] = StoreT<S>::cvt(cur[i]);
     moments_v<R, Q, SH>(v, A.rho0, m0, ux, uy);
-    equilibrium_v<R, Q, SH>(m0, A.rho0, ux, uy, A.eq_kind, feq);
+    R dx[3], dy[3];
+    equilibrium_v<R, Q, SH>(m0, A.rho0, ux, uy, A.eq_kind, feq, dx, dy);
 #pragma unroll
     for (int i = 0; i < Q; ++i) d[i] = feq[i] - v[i];
     const R dS = (EHR && A.ehrenfest && valid)
-                     ? site_dS<R, Q, SH>(v, d, m0, A.rho0, ux, uy, A.eq_kind, screen)
+                     ? site_dS_dev<R, Q, SH>(v, d, m0, A.rho0, dx, dy, dx, screen)
                      : R(0);
     const long long region = ((long long)y * A.tiles_x + tile_x) * 4 + threadIdx.x / 64;
     site_finish<S, Q, COLL, EHR, COLL == COLL_ELBM && sizeof(R) == 4>(A, x, y, valid, false, region,
