@@ -329,12 +329,6 @@ __device__ __forceinline__ void write_feq_at(const StepArgs<typename StoreT<S>::
     StoreT<S>::st(dst + (long long)i * A.qs + (long long)y * A.pitch + x, feq[i]);
 }
 
-template <class S, int Q>
-__device__ __forceinline__ void write_feq(const StepArgs<typename StoreT<S>::R>& A, long long p) {
-  write_feq_at<S, Q>(A, A.cand_idx[p], A.cand_mom[p], A.cand_mom[A.cap + p],
-                     A.cand_mom[2 * A.cap + p]);
-}
-
 // Wave-aggregated reservation of one slot per set lane on an LDS counter.
 __device__ __forceinline__ unsigned int lds_slot(bool on, unsigned int* ctr) {
   const unsigned long long mask = __ballot(on);
@@ -457,18 +451,33 @@ __device__ void fix_tail(const StepArgs<typename StoreT<S>::R>& A, long long k, 
     const unsigned long long edge = base + ((unsigned long long)boundary << shift);
     const int nb = boundary == kBuckets - 1 ? KeyTraits<R>::bits : (int)shift;
     const int kd = (nb + 7) / 8;
-    // MSD radix select, one byte per pass; up to kTailStage entries are
-    // read from the candidate buffer once into LDS and every pass works
-    // there.  Longer lists (large groups of exactly tied keys, frequent
-    // with 16-bit storage) are written once as 16-byte records (offset,
-    // ~index, position) to a global scratch array, the region sweep's
-    // stage (unused once the sweep has finished), so that every pass reads
-    // one record per entry instead of two dependent loads; without room
-    // there the passes read the candidate buffer.
+    // MSD radix select, one byte per pass: the key digits from the top, then
+    // the site index digits.  Up to kTailStage entries are read from the
+    // candidate buffer once into LDS and every pass works there.  Longer
+    // lists (large groups of exactly tied keys, frequent with 16-bit
+    // storage) are written once as 16-byte records (offset, ~index,
+    // position) to a global scratch array, the region sweep's stage (unused
+    // once the sweep has finished), so that every pass reads one record per
+    // entry instead of two dependent loads; without room there the passes
+    // read the candidate buffer.  The staging read also takes the first
+    // digit's histogram (every entry matches the empty prefix), and once the
+    // entries matching the prefix fit in LDS, one more pass over the list
+    // gathers them there for the remaining digits.
     const bool staged = m <= kTailStage;
     const bool recs = !staged && scratch && 4 * m <= scratch_len;
+    // index digits: the bytes that site indices below n_sites use; above
+    // them every ~index holds ones, and so does the prefix from the start
+    const int kdi = n_sites <= 256 ? 1 : (32 - __clz((unsigned int)(n_sites - 1)) + 7) / 8;
+    const uint32_t ip0 = kdi >= 4 ? 0u : ~((1u << (8 * kdi)) - 1u);
+    auto digit_shift = [&](int dgt) { return dgt < kd ? 8 * (kd - 1 - dgt) : 8 * (kdi - 1 - (dgt - kd)); };
+    const int sb0 = digit_shift(0);
+    __shared__ unsigned int s_last_cnt, s_gather;
+    if (threadIdx.x == 0) { s_off_pref = 0; s_idx_pref = ip0; s_last_cnt = (unsigned int)m; s_gather = 0; }
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) dh[i] = 0;
+    __syncthreads();
     if (staged || recs) {
-      for (long long q0 = threadIdx.x; q0 < m; q0 += 4 * (long long)blockDim.x) {
+      for (long long b0 = 0; b0 < m; b0 += 4 * (long long)blockDim.x) {
+        const long long q0 = b0 + threadIdx.x;
         uint32_t pu[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -478,24 +487,30 @@ __device__ void fix_tail(const StepArgs<typename StoreT<S>::R>& A, long long k, 
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const long long q = q0 + u * (long long)blockDim.x;
-          if (q >= m) continue;
-          const unsigned long long key = (unsigned long long)A.cand_key[pu[u]];
-          const unsigned long long off = key >= edge ? key - edge : 0ull;
-          const uint32_t ni = ~A.cand_idx[pu[u]];
-          if (staged) {
-            t_off[q] = off;
-            t_ni[q] = ni;
-            t_p[q] = pu[u];
-          } else {
-            *reinterpret_cast<uint4*>(scratch + 4 * q) =
-                make_uint4((uint32_t)off, (uint32_t)(off >> 32), ni, pu[u]);
+          unsigned long long off = 0;
+          uint32_t ni = 0;
+          if (q < m) {
+            const unsigned long long key = (unsigned long long)A.cand_key[pu[u]];
+            off = key >= edge ? key - edge : 0ull;
+            ni = ~A.cand_idx[pu[u]];
+            if (staged) {
+              t_off[q] = off;
+              t_ni[q] = ni;
+              t_p[q] = pu[u];
+            } else {
+              *reinterpret_cast<uint4*>(scratch + 4 * q) =
+                  make_uint4((uint32_t)off, (uint32_t)(off >> 32), ni, pu[u]);
+            }
           }
+          hist_add(dh, kd > 0 ? (unsigned int)((off >> sb0) & 0xffu) : (ni >> sb0) & 0xffu, q < m);
         }
       }
       __syncthreads();
     }
-    auto entry = [&](long long q, unsigned long long& off, uint32_t& ni, uint32_t& p) {
-      if (staged) {
+    // entry q of the list, from LDS (`lds`) or from the records / the
+    // candidate buffer
+    auto entry = [&](bool lds, long long q, unsigned long long& off, uint32_t& ni, uint32_t& p) {
+      if (lds) {
         off = t_off[q];
         ni = t_ni[q];
         p = t_p[q];
@@ -511,51 +526,50 @@ __device__ void fix_tail(const StepArgs<typename StoreT<S>::R>& A, long long k, 
         ni = ~A.cand_idx[p];
       }
     };
+    // does (off, ni) match the prefix found so far, down to bit `sb` of the
+    // key digits (on_key) or of the index digits
+    auto matches = [](bool on_key, int sb, unsigned long long off, uint32_t ni,
+                      unsigned long long op, uint32_t ip) {
+      if (on_key) {
+        const unsigned long long hm = sb >= 64 ? 0ull : (~0ull << sb);
+        return (off & hm) == (op & hm);
+      }
+      const uint32_t hm = sb >= 32 ? 0u : (~0u << sb);
+      return off == op && (ni & hm) == (ip & hm);
+    };
+    bool local = staged;      // the entries still matching are all in LDS
+    long long ml = m;         // the entries a pass visits
     unsigned long long need_left = (unsigned long long)take;
-    __shared__ unsigned int s_last_cnt;
-    if (threadIdx.x == 0) { s_off_pref = 0; s_idx_pref = 0; s_last_cnt = (unsigned int)m; }
-    __syncthreads();
-    for (int dgt = 0; dgt < kd + 4; ++dgt) {
+    for (int dgt = 0; dgt < kd + kdi; ++dgt) {
       // after the key digits: if every entry sharing the threshold key is
       // taken, the site-index digits cannot change the set
       if (dgt == kd && s_last_cnt == need_left) break;
-      for (int i = threadIdx.x; i < 256; i += blockDim.x) dh[i] = 0;
-      __syncthreads();
       const bool on_key = dgt < kd;
-      const int sb = on_key ? 8 * (kd - 1 - dgt) : 8 * (3 - (dgt - kd));
-      const unsigned long long op = s_off_pref;
-      const uint32_t ip = s_idx_pref;
-      // four entries per thread in flight
-      for (long long q0 = threadIdx.x; q0 < m; q0 += 4 * (long long)blockDim.x) {
-        unsigned long long offs[4];
-        uint32_t nis[4], ps[4];
+      const int sb = digit_shift(dgt);
+      if (!(dgt == 0 && (staged || recs))) {
+        for (int i = threadIdx.x; i < 256; i += blockDim.x) dh[i] = 0;
+        __syncthreads();
+        const unsigned long long op = s_off_pref;
+        const uint32_t ip = s_idx_pref;
+        // four entries per thread in flight
+        for (long long b0 = 0; b0 < ml; b0 += 4 * (long long)blockDim.x) {
+          const long long q0 = b0 + threadIdx.x;
+          unsigned long long offs[4] = {0ull, 0ull, 0ull, 0ull};
+          uint32_t nis[4] = {0u, 0u, 0u, 0u}, ps[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const long long q = q0 + u * (long long)blockDim.x;
-          if (q < m) entry(q, offs[u], nis[u], ps[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const long long q = q0 + u * (long long)blockDim.x;
-          if (q >= m) continue;
-          const unsigned long long off = offs[u];
-          const uint32_t ni = nis[u];
-          bool match;
-          unsigned int digit;
-          const int topb = sb + 8;
-          if (on_key) {
-            const unsigned long long hm = topb >= 64 ? 0ull : (~0ull << topb);
-            match = (off & hm) == (op & hm);
-            digit = (unsigned int)((off >> sb) & 0xffu);
-          } else {
-            const uint32_t hm = topb >= 32 ? 0u : (~0u << topb);
-            match = off == op && (ni & hm) == (ip & hm);
-            digit = (ni >> sb) & 0xffu;
+          for (int u = 0; u < 4; ++u) {
+            const long long q = q0 + u * (long long)blockDim.x;
+            if (q < ml) entry(local, q, offs[u], nis[u], ps[u]);
           }
-          if (match) atomicAdd(&dh[digit], 1u);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const long long q = q0 + u * (long long)blockDim.x;
+            const bool on = q < ml && matches(on_key, sb + 8, offs[u], nis[u], op, ip);
+            hist_add(dh, on_key ? (unsigned int)((offs[u] >> sb) & 0xffu) : (nis[u] >> sb) & 0xffu, on);
+          }
         }
+        __syncthreads();
       }
-      __syncthreads();
       int dsel;
       unsigned long long dabove;
       find_from_top<256>(dh, need_left, &dsel, &dabove);
@@ -567,21 +581,72 @@ __device__ void fix_tail(const StepArgs<typename StoreT<S>::R>& A, long long k, 
         s_last_cnt = dh[dsel];
       }
       __syncthreads();
+      // the entries matching the extended prefix fit in LDS, and a further
+      // pass follows: gather them (p is not needed, the final pass reads
+      // the list itself)
+      const bool more = dgt + 1 < kd + kdi && !(dgt + 1 == kd && s_last_cnt == need_left);
+      if (!local && more && s_last_cnt <= (unsigned int)kTailStage) {
+        const unsigned long long op = s_off_pref;
+        const uint32_t ip = s_idx_pref;
+        // the same trip count in every thread (the slots come from ballots)
+        for (long long b0 = 0; b0 < m; b0 += 4 * (long long)blockDim.x) {
+          const long long q0 = b0 + threadIdx.x;
+          unsigned long long offs[4] = {0ull, 0ull, 0ull, 0ull};
+          uint32_t nis[4] = {0u, 0u, 0u, 0u}, ps[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const long long q = q0 + u * (long long)blockDim.x;
+            if (q < m) entry(false, q, offs[u], nis[u], ps[u]);
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const long long q = q0 + u * (long long)blockDim.x;
+            const bool on = q < m && matches(on_key, sb, offs[u], nis[u], op, ip);
+            const unsigned int slot = lds_slot(on, &s_gather);
+            if (on && slot < (unsigned int)kTailStage) {   // slot < s_last_cnt
+              t_off[slot] = offs[u];
+              t_ni[slot] = nis[u];
+            }
+          }
+        }
+        __syncthreads();
+        local = true;
+        ml = s_gather;
+      }
     }
+    // The selected entries: four per thread, every load issued before the
+    // first store (the records, then the moments of the selected ones), so
+    // that a long list costs a quarter of the round trips.
     const unsigned long long to = s_off_pref;
     const uint32_t ti = s_idx_pref;
-    for (long long q0 = 0; q0 < m; q0 += blockDim.x) {
-      const long long q = q0 + threadIdx.x;
-      bool sel = false;
-      uint32_t p = 0, ni = 0;
-      if (q < m) {
-        unsigned long long off;
-        entry(q, off, ni, p);
-        sel = off > to || (off == to && ni >= ti);
+    for (long long b0 = 0; b0 < m; b0 += 4 * (long long)blockDim.x) {
+      const long long q0 = b0 + threadIdx.x;
+      unsigned long long offs[4] = {0ull, 0ull, 0ull, 0ull};
+      uint32_t nis[4] = {0u, 0u, 0u, 0u}, ps[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const long long q = q0 + u * (long long)blockDim.x;
+        if (q < m) entry(staged, q, offs[u], nis[u], ps[u]);
       }
-      if (sel) write_feq<S, Q>(A, p);
-      const unsigned int slot = lds_slot(sel, &s_tot);
-      if (sel && (long long)slot < k) selected[slot] = (int32_t)~ni;
+      bool sel[4];
+      R m0s[4], uxs[4], uys[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const long long q = q0 + u * (long long)blockDim.x;
+        sel[u] = q < m && (offs[u] > to || (offs[u] == to && nis[u] >= ti));
+        m0s[u] = uxs[u] = uys[u] = R(0);
+        if (sel[u]) {
+          m0s[u] = A.cand_mom[ps[u]];
+          uxs[u] = A.cand_mom[A.cap + ps[u]];
+          uys[u] = A.cand_mom[2 * A.cap + ps[u]];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (sel[u]) write_feq_at<S, Q>(A, ~nis[u], m0s[u], uxs[u], uys[u]);   // ~ni: the site
+        const unsigned int slot = lds_slot(sel[u], &s_tot);
+        if (sel[u] && (long long)slot < k) selected[slot] = (int32_t)~nis[u];
+      }
     }
   }
   __syncthreads();

@@ -378,6 +378,20 @@ __device__ __forceinline__ StepFrame step_frame(const SelState* sel) {
   return StepFrame{odd ? f1 : f0, odd ? b1 : b0, odd ? s1 : s0};
 }
 
+// h[bin] += 1 for every active lane with `on` (h in LDS or global memory).
+// The lanes whose bin equals the first such lane's add with one atomic: a
+// group of exactly tied keys sends whole wavefronts to one bin, where 64
+// atomics on one address would queue behind each other.
+__device__ __forceinline__ void hist_add(unsigned int* h, unsigned int bin, bool on) {
+  const unsigned long long act = __ballot(on);
+  if (!act) return;
+  const int leader = __ffsll((long long)act) - 1;
+  const unsigned int b0 = (unsigned int)__shfl((int)bin, leader);
+  const unsigned long long same = __ballot(on && bin == b0);
+  if (on && bin != b0) atomicAdd(&h[bin], 1u);
+  else if ((int)__lane_id() == leader) atomicAdd(&h[b0], (unsigned int)__popcll(same));
+}
+
 // Append of Ehrenfest candidates by one wavefront (all its lanes call it):
 // the wavefront owns 64 entries of the candidate buffer (its region), so a
 // ballot gives every candidate its slot without a global counter; the
@@ -402,8 +416,8 @@ __device__ __forceinline__ void append_candidates(const StepArgs<R>& A, const St
     A.cand_mom[pos] = m0;
     A.cand_mom[A.cap + pos] = ux;
     A.cand_mom[2 * A.cap + pos] = uy;
-    atomicAdd(&A.hist[hist_pos(bucket_of<R>((unsigned long long)key, fr.base, fr.shift))], 1u);
   }
+  hist_add(A.hist, (unsigned int)hist_pos(bucket_of<R>((unsigned long long)key, fr.base, fr.shift)), is_c);
 }
 
 template <class S, int Q>
