@@ -305,9 +305,13 @@ void k_step(const StepArgs<typename StoreT<S>::R> A) {
 // computes the current one (two rows of loads in flight per wavefront).
 // Per-site arithmetic is the one-site kernel's, so the results are
 // bit-identical.  Used for the 16-bit storage forms and for ELBM in FP32,
-// with a compile-time variant without the Ehrenfest code.
+// with a compile-time variant without the Ehrenfest code.  16-bit LBGK is
+// held to 64 registers (eight wavefronts per SIMD; the Ehrenfest variant
+// would take 65 and run seven): three spilled values cost less than the
+// lost wavefront (FP16 115.2 -> 112.3 us, BF16 133.6 -> 128.2 us at 4096^2
+// with the limiter).
 template <class S, int Q, int COLL, int ROWS, bool EHR>
-__global__ __launch_bounds__(256) void k_step_rows(const StepArgs<typename StoreT<S>::R> A) {
+__global__ __launch_bounds__(256, (COLL == COLL_LBGK && sizeof(S) == 2) ? 8 : 1) void k_step_rows(const StepArgs<typename StoreT<S>::R> A) {
   using R = typename StoreT<S>::R;
   constexpr bool SH = StoreT<S>::shifted;
   const int nyc = (A.ny + ROWS - 1) / ROWS;
