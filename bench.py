@@ -54,11 +54,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the FP32 step kernel on this workload (periodic
 # one-site kernel, LBGK + Ehrenfest): rocprofv3 FETCH_SIZE and WRITE_SIZE
-# medians over 25 launches, scaled by what the counters read for a device
+# medians over 45 launches, scaled by what the counters read for a device
 # copy of 1,207,959,552 bytes (FETCH x 2.0, WRITE x 1.0); summary in
 # profiles/hbm_traffic_k_step_shear_layer_4096_f32.md.  Retake after any
 # change of the kernel.
-HBM_TRAFFIC_F32 = 647_891_456 + 607_371_715
+HBM_TRAFFIC_F32 = 647_844_864 + 607_076_800
 ELEM = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}
 METRIC = "MLUPS and % HBM roofline, D2Q9 fwd+adjoint, FP64 vs FP32/FP16-storage at stated err"
 
