@@ -113,6 +113,42 @@ def test_shear_layer_4096_four_steps(storage):
     assert fallbacks[3] == fallbacks[1]
 
 
+@pytest.mark.timeout(900)
+def test_shear_layer_4096_bf16_later_steps():
+    """BF16 storage after 44 steps, where its rounding has made large groups
+    of exactly tied Delta S (the boundary bucket's exact resolution then
+    works on thousands of entries, with site-index digits): three further
+    steps, each against the oracle's step from the stored state, with the
+    selected sets equal up to near ties."""
+    w = workload("shear_layer_4096")
+    keys = ("lattice", "nx", "ny", "bc", "collision", "equilibrium", "nu", "ehrenfest",
+            "ehr_k", "ehr_delta")
+    p = {k: w[k] for k in keys}
+    lat, cfg = lattice(p), oracle_config(p)
+    rho, ux, uy = G.double_shear_layer(p["nx"])
+    f0 = O.init_equilibrium(lat, rho, ux, uy)
+    sim = make_sim(p, "bf16s")
+    sim.set_populations(f0.to("cuda"))
+    del f0
+    sim.step(44)
+    f_in = sim.populations().cpu()
+    groups = []
+    for t in range(3):
+        sim.step(1)
+        f_gpu = sim.populations().cpu()
+        sel_gpu = sim.selected()
+        with torch.no_grad():
+            f_ora, info = O.step(lat, cfg, f_in)
+        kth = torch.sort(info["dS"].flatten(), descending=True).values[p["ehr_k"] - 1]
+        groups.append(int((info["dS"] == kth).sum()))
+        moved = _compare_step(p, "bf16s", f_gpu, f_ora, sel_gpu, info, 1e-5)
+        print(f"step {45 + t}: tie group at the k-th Delta S {groups[-1]}, near-tie moves {moved}",
+              flush=True)
+        del f_ora, info
+        f_in = f_gpu
+    assert max(groups) > 1      # the ties this test is about
+
+
 def _crop_params(urms):
     w = workload("elbm_8192")
     p = {k: w[k] for k in ("lattice", "bc", "collision", "equilibrium", "nu", "ehrenfest",
