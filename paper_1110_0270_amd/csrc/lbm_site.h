@@ -247,11 +247,10 @@ __device__ __forceinline__ R site_dS_dev(const R v[Q], const R d[Q], R m0, R rho
   for (int i = 0; i < Q; ++i) {
     const int a = vx_of<Q>(i) + 1, b = vy_of<Q>(i) + 1, cz = vz_of<Q>(i) + 1;
     const R sh = SH ? wt<R, Q>(i) * rho0 : R(0);
-    // f_i = v_i + sh < 0 exactly when v_i < -sh (a nonzero sum does not
-    // round to zero), one instruction fewer; the D3Q27 median kernel keeps
-    // the sum, with which it spills one register less
+    // D3Q27 (whose callers take the exact sum everywhere) tests for negative
+    // populations here; deferring the test costs that kernel spilled
+    // registers
     if constexpr (Q == 27) bad |= (v[i] + sh) < R(0);
-    else bad |= v[i] < -sh;
     const R inv = Q == 27 ? rx[a] * ry[b] * rz[cz] : (Q == 9 ? rx[a] * ry[b] : rx[a]);   // 1 / f*_i
     y[i] = d[i] * inv;
     ymax = fmax(ymax, y[i]);
@@ -261,6 +260,16 @@ __device__ __forceinline__ R site_dS_dev(const R v[Q], const R d[Q], R m0, R rho
   const R ub = sdy * (R(0.5) + ymax * R(1.0 / 3.0));   // ymax >= 0 (it starts at 0)
   // the margin covers the rounding of the bound itself
   if (!(ymax > R(0.5)) && ub * R(1.0001) < screen) return ub;
+  // A negative population f_i = v_i + w_i rho0 < 0 has y_i = (f*_i - f_i) /
+  // f*_i > 1 (f*_i > 0 here), so the screen above never returns for it and
+  // the test is needed only from here on.  f_i < 0 exactly when v_i < -sh (a
+  // nonzero sum does not round to zero), one instruction fewer.
+  if constexpr (Q != 27) {
+    bool neg = false;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) neg |= v[i] < -(SH ? wt<R, Q>(i) * rho0 : R(0));
+    if (neg) return r_inf<R>();
+  }
   // h_fn takes the Taylor series wherever |x| < 0.1; when that holds for
   // every component of every active lane of the wavefront, the logarithms
   // are skipped for all of them (same values, the series either way).
