@@ -145,6 +145,46 @@ def test_d3q27_low_precision_one_step(storage, name):
     assert not bool(bad.any()), f"{int(bad.sum())} sites beyond the storage bound"
 
 
+def _spotty_state(p, seed, frac=0.03):
+    """A uniform flow with 1e-4 noise (Delta S near 1e-9 after streaming) and
+    strongly perturbed populations at a fraction of the sites: with delta
+    between the two, half of the sites lie far below delta, while the
+    neighbourhoods of the spots hold candidates whose median is often one
+    of those small values."""
+    rng = np.random.default_rng(seed)
+    shape = (p["nz"], p["ny"], p["nx"])
+    ones = np.ones(shape)
+    f = O.init_equilibrium3(ones, 0.02 * ones, -0.01 * ones, 0.015 * ones, "poly")
+    small = torch.tensor(G.uniform_noise(f.shape, seed + 1000, 1e-4))
+    big = torch.tensor(G.uniform_noise(f.shape, seed + 2000, 0.3))
+    spots = torch.tensor(rng.random(shape) < frac).unsqueeze(0)
+    return f * (1.0 + torch.where(spots, big, small))
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_d3q27_median_small_neighbourhoods(storage):
+    """delta = 1e-6 on the spotty state (about 6.7 k accepted sites of
+    17 k, 1.3 k of them with a median below delta).  Against the oracle:
+    FP64 at 1e-12 with the median counter equal to the oracle's mask; FP32
+    within the storage bound away from near-tie median decisions."""
+    p, _ = _params("median")
+    p["med_delta"] = 1e-6
+    f0 = _spotty_state(p, 76)
+    f_in, f_gpu, sim = gpu_run(p, f0, 1, storage)
+    f_ora, infos = oracle3(p, f_in, 1)
+    n_med = int(infos[0]["median_mask"].sum())
+    assert n_med > 0
+    if storage == "f64":
+        assert rel_err(f_gpu, f_ora) <= 1e-12
+        assert sim.counters()[1] == n_med
+    else:
+        mag = f_ora.abs().clamp(min=2.0 ** -14)
+        bound = 0.5 * torch.pow(2.0, torch.floor(torch.log2(mag)) - ULP_BITS["f32"]) + \
+            FP32_TERM * f_ora.abs().clamp(min=1.0)
+        bad = (((f_gpu - f_ora).abs() - bound) > 0).any(0) & ~_median_ties(p, f_in)
+        assert not bool(bad.any()), f"{int(bad.sum())} sites beyond the storage bound"
+
+
 def test_d3q27_set_equilibrium3d_and_stats():
     p = {"lattice": "D3Q27", "bc": "periodic", **SIZE, "nu": 0.01, "equilibrium": "entropic"}
     rho, ux, uy, uz = G.taylor_green_3d(p["nx"], p["ny"], p["nz"], u0=0.05)
