@@ -301,11 +301,12 @@ __device__ __forceinline__ int load_short_list(const AdjArgs<R>& B, int32_t* lse
   return nl;
 }
 
-// LBGK in FP32 arithmetic keeps six wavefronts per SIMD (at most 80
-// registers, no spills): with five the 4096^2 FP32 adjoint step took 553
-// against 363 us.
+// LBGK in FP32 arithmetic keeps seven wavefronts per SIMD (at most 72
+// registers, 8 bytes of spills): the 4096^2 FP32 adjoint step took 359
+// against 368 us with six (75 registers, no spills) and 553 us with five;
+// eight (64 registers) spill 112 bytes.
 template <class S, int Q, int COLL, bool SELMRT = false>
-__global__ __launch_bounds__(256, (COLL == COLL_LBGK && !SELMRT && sizeof(S) <= 4) ? 6 : 1)
+__global__ __launch_bounds__(256, (COLL == COLL_LBGK && !SELMRT && sizeof(S) <= 4) ? 7 : 1)
 void k_adjoint(const StepArgs<typename StoreT<S>::R> A, const AdjArgs<typename StoreT<S>::R> B) {
   using R = typename StoreT<S>::R;
   // Workgroups go round-robin to the 8 XCDs; each XCD takes pairs of
