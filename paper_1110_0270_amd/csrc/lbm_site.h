@@ -273,17 +273,30 @@ __device__ __forceinline__ R site_dS_dev(const R v[Q], const R d[Q], R m0, R rho
   // h_fn takes the Taylor series wherever |x| < 0.1; when that holds for
   // every component of every active lane of the wavefront, the logarithms
   // are skipped for all of them (same values, the series either way).
-  bool big = false;
+  R ya = R(0);                           // max |y_i|
 #pragma unroll
-  for (int i = 0; i < Q; ++i) big |= !(fabs(y[i]) < R(0.1));
+  for (int i = 0; i < Q; ++i) ya = fmax(ya, fabs(y[i]));
+  const bool big = !(ya < R(0.1));
+  // FP32: a site with every |y_i| < 0.01 takes the short series in every
+  // component (h_poly_short), chosen by the site's own values only.
+  const bool tiny = sizeof(R) == 4 && ya < R(0.01);
+  auto hp = [&](R x) {
+    if constexpr (sizeof(R) == 4) return tiny ? (R)h_poly_short((float)x) : h_poly<R>(x);
+    else return h_poly<R>(x);
+  };
   // Each component adds fma(a_i, b_i, acc): (d_i y_i, h_poly(-y_i)) where
   // |y_i| < 0.1 (f*_i h(x_i) = f*_i y_i^2 h_poly(-y_i) = d_i y_i h_poly), else
   // (f*_i, h(-y_i)); both branches below form the same terms in the same
   // order, so a site's value does not depend on the other lanes.
   R acc = R(0);
   if (__ballot(big) == 0ull) {
+    if (sizeof(R) == 4 && tiny) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) acc = fma(d[i] * y[i], h_poly<R>(-y[i]), acc);
+      for (int i = 0; i < Q; ++i) acc = fma(d[i] * y[i], hp(-y[i]), acc);
+    } else {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) acc = fma(d[i] * y[i], h_poly<R>(-y[i]), acc);
+    }
   } else {
     const R rs = rho * (R(1) / S);
 #pragma unroll
@@ -292,7 +305,7 @@ __device__ __forceinline__ R site_dS_dev(const R v[Q], const R d[Q], R m0, R rho
       const R fq = Q == 27 ? fx[a] * fy[b] * fz[cz] : (Q == 9 ? fx[a] * fy[b] : fx[a]);
       const bool small = fabs(y[i]) < R(0.1);
       const R ta = small ? d[i] * y[i] : fq * rs;
-      const R tb = small ? h_poly<R>(-y[i]) : h_fn<R>(-y[i]);
+      const R tb = small ? hp(-y[i]) : h_fn<R>(-y[i]);
       acc = fma(ta, tb, acc);
     }
   }
