@@ -257,9 +257,14 @@ __device__ __forceinline__ R site_dS_dev(const R v[Q], const R d[Q], R m0, R rho
     sdy += d[i] * y[i];
   }
   if (bad) return r_inf<R>();
-  const R ub = sdy * (R(0.5) + ymax * R(1.0 / 3.0));   // ymax >= 0 (it starts at 0)
-  // the margin covers the rounding of the bound itself
-  if (!(ymax > R(0.5)) && ub * R(1.0001) < screen) return ub;
+  // the bound is non-negative, so a screen of 0 (a literal in the callers
+  // that need every value exact) never returns it: the test, and with it
+  // the bound, drop out of their code
+  if (screen > R(0)) {
+    const R ub = sdy * (R(0.5) + ymax * R(1.0 / 3.0));   // ymax >= 0 (it starts at 0)
+    // the margin covers the rounding of the bound itself
+    if (!(ymax > R(0.5)) && ub * R(1.0001) < screen) return ub;
+  }
   // A negative population f_i = v_i + w_i rho0 < 0 has y_i = (f*_i - f_i) /
   // f*_i > 1 (f*_i > 0 here), so the screen above never returns for it and
   // the test is needed only from here on.  f_i < 0 exactly when v_i < -sh (a
