@@ -115,8 +115,8 @@ __device__ __forceinline__ void pull_periodic(const S* __restrict__ src, long lo
 // the source lies above the top row.  Branch-free: the plane and offset are
 // selected and every population is one unconditional load (both candidate
 // addresses lie inside the lattice), so that the nine loads issue together
-// instead of each waiting at the join of an if/else.
-template <class S, int Q>
+// instead of each waiting at the join of an if/else.  CACHED: cached loads.
+template <class S, int Q, bool CACHED = false>
 __device__ __forceinline__ void pull(const S* __restrict__ src, long long qs, int pitch, int nx,
                                      int ny, int bc, int x, int y,
                                      const typename StoreT<S>::R* lid,
@@ -131,7 +131,8 @@ __device__ __forceinline__ void pull(const S* __restrict__ src, long long qs, in
     const bool out = (sx < 0) | (sx >= nx) | (sy < 0) | (sy >= ny);
     const int plane = out ? Q - 1 - i : i;
     const unsigned off = out ? (unsigned)(y * pitch + x) : (unsigned)(sy * pitch + sx);
-    const R val = StoreT<S>::ld(at(src + (long long)plane * qs, off));
+    const S* p = at(src + (long long)plane * qs, off);
+    const R val = CACHED ? StoreT<S>::ldc(p) : StoreT<S>::ld(p);
     v[i] = sy >= ny ? val + lid[i] : val;
   }
 }
@@ -354,7 +355,9 @@ template <> __device__ __forceinline__ double value_of_key<double>(unsigned long
 // PER: the caller knows the lattice is periodic (branch-free pull).  WALL:
 // the configuration may have the diffusive wall (configurations with the
 // adjoint or an ensemble limiter never do, and their kernels leave it out).
-template <class S, int Q, bool PER = false, bool WALL = !PER>
+// CACHED: cached loads (the median kernel pulls halo sites that neighbouring
+// tiles pull too).
+template <class S, int Q, bool PER = false, bool WALL = !PER, bool CACHED = false>
 __device__ __forceinline__ typename StoreT<S>::R site_prep(
     const StepArgs<typename StoreT<S>::R>& A, int x, int y, typename StoreT<S>::R v[Q],
     typename StoreT<S>::R feq[Q], typename StoreT<S>::R d[Q], typename StoreT<S>::R& m0,
@@ -362,8 +365,8 @@ __device__ __forceinline__ typename StoreT<S>::R site_prep(
     typename StoreT<S>::R screen = typename StoreT<S>::R(0)) {
   using R = typename StoreT<S>::R;
   constexpr bool SH = StoreT<S>::shifted;
-  if constexpr (PER) pull_periodic<S, Q>((const S*)A.src, A.qs, A.pitch, A.nx, A.ny, x, y, v);
-  else pull<S, Q>((const S*)A.src, A.qs, A.pitch, A.nx, A.ny, A.bc, x, y, A.lid, v);
+  if constexpr (PER) pull_periodic<S, Q, CACHED>((const S*)A.src, A.qs, A.pitch, A.nx, A.ny, x, y, v);
+  else pull<S, Q, CACHED>((const S*)A.src, A.qs, A.pitch, A.nx, A.ny, A.bc, x, y, A.lid, v);
   // a diffusive wall node: the wall rule, and Delta S 0 (never a candidate)
   const bool wall = WALL && on_wall<R>(A, x, y);
   if (wall) diffusive_wall<S, Q>(A, x, y, v);
@@ -447,7 +450,7 @@ __device__ __forceinline__ void append_candidates(const StepArgs<R>& A, const St
   hist_add(A.hist, (unsigned int)hist_pos(bucket_of<R>((unsigned long long)key, fr.base, fr.shift)), is_c);
 }
 
-template <class S, int Q>
+template <class S, int Q, bool CACHED = false>
 __device__ typename StoreT<S>::R slot_dS(const StepArgs<typename StoreT<S>::R>& A, int gx,
                                          int gy) {
   using R = typename StoreT<S>::R;
@@ -458,7 +461,7 @@ __device__ typename StoreT<S>::R slot_dS(const StepArgs<typename StoreT<S>::R>& 
   if (gx < 0 || gx >= A.nx || gy < 0 || gy >= A.ny) return __builtin_nan("");  // outside
   if (on_wall<R>(A, gx, gy)) return __builtin_nan("");   // a diffusive wall node
   R v[Q], feq[Q], d[Q], m0, ux, uy;
-  return site_prep<S, Q>(A, gx, gy, v, feq, d, m0, ux, uy, true);
+  return site_prep<S, Q, false, true, CACHED>(A, gx, gy, v, feq, d, m0, ux, uy, true);
 }
 
 }  // namespace lbm

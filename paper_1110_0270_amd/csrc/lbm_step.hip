@@ -179,7 +179,9 @@ void k_step(const StepArgs<typename StoreT<S>::R> A) {
   const StepFrame fr = step_frame(A.sel);
   const R screen = (!MEDIAN && !ENS && A.ehrenfest) ? value_of_key<R>(fr.floor) : R(0);
   R v[Q], feq[Q], d[Q], m0 = R(0), ux = R(0), uy = R(0), dS = R(0);
-  if (valid) dS = site_prep<S, Q, PER>(A, x, y, v, feq, d, m0, ux, uy, need_dS, screen);
+  // the median kernel's pulls are cached: its halo sites are pulled again,
+  // here or by the neighbouring tiles
+  if (valid) dS = site_prep<S, Q, PER, !PER, MEDIAN>(A, x, y, v, feq, d, m0, ux, uy, need_dS, screen);
 
   if constexpr (ENS) {
     double prod = 0.0, lim = 0.0, sdS = 0.0, nfin = 0.0;
@@ -235,7 +237,7 @@ void k_step(const StepArgs<typename StoreT<S>::R> A) {
     __shared__ R sdS[SH_ * SW];
     const int by = sub * TY + ly;                         // row within the workgroup
     const int x0 = tile_x * TX, y0 = (tb / A.tiles_x) * NB * TY;
-    sdS[(by + HY) * SW + lx + 1] = valid ? (wall ? R(__builtin_nan("")) : dS) : slot_dS<S, Q>(A, x, y);
+    sdS[(by + HY) * SW + lx + 1] = valid ? (wall ? R(__builtin_nan("")) : dS) : slot_dS<S, Q, true>(A, x, y);
     constexpr int NHALO = SH_ * SW - TX * TY * NB;
     for (int s = threadIdx.x; s < NHALO; s += 256 * NB) {
       // halo slot s -> LDS coordinates: top row, bottom row, then the left
@@ -249,7 +251,7 @@ void k_step(const StepArgs<typename StoreT<S>::R> A) {
         hy = 0;
         hx = (s == 0) ? 0 : SW - 1;
       }
-      sdS[hy * SW + hx] = slot_dS<S, Q>(A, x0 + hx - 1, y0 + hy - HY);
+      sdS[hy * SW + hx] = slot_dS<S, Q, true>(A, x0 + hx - 1, y0 + hy - HY);
     }
     __syncthreads();
     if (valid && !wall) {
