@@ -255,33 +255,38 @@ void k_step(const StepArgs<typename StoreT<S>::R> A) {
     }
     __syncthreads();
     if (valid && !wall) {
-      R nb[9];
-      int n = 0;
-      constexpr int NN = (Q == 9) ? 9 : 3;
+      // only a site above delta can be filtered: wavefronts without one
+      // skip the neighbourhood's sort
+      const bool cand = (dS > A.med_delta) & (dS < r_inf<R>());
+      R med = R(0);
+      if (__ballot(cand)) {
+        R nb[9];
+        int n = 0;
+        constexpr int NN = (Q == 9) ? 9 : 3;
 #pragma unroll
-      for (int k = 0; k < NN; ++k) {
-        const int dy = (Q == 9) ? k / 3 - 1 : 0, dx = (Q == 9) ? k % 3 - 1 : k - 1;
-        const R val = sdS[(by + HY + dy) * SW + lx + 1 + dx];
-        const bool in = !(val != val);
-        n += in ? 1 : 0;
-        nb[k] = in ? val : r_inf<R>();
-      }
-      R med;
-      if constexpr (Q == 9) {
-        sort_net9<R>(nb);
-        const int rank = (n + 1) / 2 - 1;
-        med = nb[0];
+        for (int k = 0; k < NN; ++k) {
+          const int dy = (Q == 9) ? k / 3 - 1 : 0, dx = (Q == 9) ? k % 3 - 1 : k - 1;
+          const R val = sdS[(by + HY + dy) * SW + lx + 1 + dx];
+          const bool in = !(val != val);
+          n += in ? 1 : 0;
+          nb[k] = in ? val : r_inf<R>();
+        }
+        if constexpr (Q == 9) {
+          sort_net9<R>(nb);
+          const int rank = (n + 1) / 2 - 1;
+          med = nb[0];
 #pragma unroll
-        for (int k = 1; k < 9; ++k) med = rank == k ? nb[k] : med;
-      } else {
-        R a0 = fmin(nb[0], nb[1]), a1 = fmax(nb[0], nb[1]);
-        const R a2 = fmax(a1, nb[2]);
-        a1 = fmin(a1, nb[2]);
-        const R b0 = fmin(a0, a1), b1 = fmax(a0, a1);
-        (void)a2;
-        med = ((n + 1) / 2 - 1) == 0 ? b0 : b1;
+          for (int k = 1; k < 9; ++k) med = rank == k ? nb[k] : med;
+        } else {
+          R a0 = fmin(nb[0], nb[1]), a1 = fmax(nb[0], nb[1]);
+          const R a2 = fmax(a1, nb[2]);
+          a1 = fmin(a1, nb[2]);
+          const R b0 = fmin(a0, a1), b1 = fmax(a0, a1);
+          (void)a2;
+          med = ((n + 1) / 2 - 1) == 0 ? b0 : b1;
+        }
       }
-      const bool acc = (dS > A.med_delta) & (med < dS) & (dS < r_inf<R>());
+      const bool acc = cand & (med < dS);
       if (acc) {
         const R c = sqrt(med / dS);
 #pragma unroll
