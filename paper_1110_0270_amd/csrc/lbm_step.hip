@@ -237,67 +237,70 @@ void k_step(const StepArgs<typename StoreT<S>::R> A) {
     __shared__ R sdS[SH_ * SW];
     const int by = sub * TY + ly;                         // row within the workgroup
     const int x0 = tile_x * TX, y0 = (tb / A.tiles_x) * NB * TY;
-    sdS[(by + HY) * SW + lx + 1] = valid ? (wall ? R(__builtin_nan("")) : dS) : slot_dS<S, Q, true>(A, x, y);
-    constexpr int NHALO = SH_ * SW - TX * TY * NB;
-    for (int s = threadIdx.x; s < NHALO; s += 256 * NB) {
-      // halo slot s -> LDS coordinates: top row, bottom row, then the left
-      // and right columns (2D); the two end slots of the single row (1D)
-      int hx, hy;
-      if constexpr (HY == 1) {
-        if (s < SW) { hx = s; hy = 0; }
-        else if (s < 2 * SW) { hx = s - SW; hy = SH_ - 1; }
-        else { const int r = s - 2 * SW; hy = 1 + r / 2; hx = (r & 1) ? SW - 1 : 0; }
-      } else {
-        hy = 0;
-        hx = (s == 0) ? 0 : SW - 1;
-      }
-      sdS[hy * SW + hx] = slot_dS<S, Q, true>(A, x0 + hx - 1, y0 + hy - HY);
-    }
-    __syncthreads();
-    if (valid && !wall) {
-      // only a site above delta can be filtered: wavefronts without one
-      // skip the neighbourhood's sort
-      const bool cand = (dS > A.med_delta) & (dS < r_inf<R>());
-      R med = R(0);
-      if (__ballot(cand)) {
-        R nb[9];
-        int n = 0;
-        constexpr int NN = (Q == 9) ? 9 : 3;
-#pragma unroll
-        for (int k = 0; k < NN; ++k) {
-          const int dy = (Q == 9) ? k / 3 - 1 : 0, dx = (Q == 9) ? k % 3 - 1 : k - 1;
-          const R val = sdS[(by + HY + dy) * SW + lx + 1 + dx];
-          const bool in = !(val != val);
-          n += in ? 1 : 0;
-          nb[k] = in ? val : r_inf<R>();
-        }
-        if constexpr (Q == 9) {
-          sort_net9<R>(nb);
-          const int rank = (n + 1) / 2 - 1;
-          med = nb[0];
-#pragma unroll
-          for (int k = 1; k < 9; ++k) med = rank == k ? nb[k] : med;
+    // only a site above delta can be filtered: a workgroup without one needs
+    // neither the halo's Delta S nor the neighbourhoods
+    const bool cand = valid && !wall && (dS > A.med_delta) && (dS < r_inf<R>());
+    if (__syncthreads_or(cand)) {
+      sdS[(by + HY) * SW + lx + 1] = valid ? (wall ? R(__builtin_nan("")) : dS) : slot_dS<S, Q, true>(A, x, y);
+      constexpr int NHALO = SH_ * SW - TX * TY * NB;
+      for (int s = threadIdx.x; s < NHALO; s += 256 * NB) {
+        // halo slot s -> LDS coordinates: top row, bottom row, then the left
+        // and right columns (2D); the two end slots of the single row (1D)
+        int hx, hy;
+        if constexpr (HY == 1) {
+          if (s < SW) { hx = s; hy = 0; }
+          else if (s < 2 * SW) { hx = s - SW; hy = SH_ - 1; }
+          else { const int r = s - 2 * SW; hy = 1 + r / 2; hx = (r & 1) ? SW - 1 : 0; }
         } else {
-          R a0 = fmin(nb[0], nb[1]), a1 = fmax(nb[0], nb[1]);
-          const R a2 = fmax(a1, nb[2]);
-          a1 = fmin(a1, nb[2]);
-          const R b0 = fmin(a0, a1), b1 = fmax(a0, a1);
-          (void)a2;
-          med = ((n + 1) / 2 - 1) == 0 ? b0 : b1;
+          hy = 0;
+          hx = (s == 0) ? 0 : SW - 1;
         }
+        sdS[hy * SW + hx] = slot_dS<S, Q, true>(A, x0 + hx - 1, y0 + hy - HY);
       }
-      const bool acc = cand & (med < dS);
-      if (acc) {
-        const R c = sqrt(med / dS);
+      __syncthreads();
+      if (valid && !wall) {
+        // wavefronts without a site above delta skip the neighbourhood's sort
+        R med = R(0);
+        if (__ballot(cand)) {
+          R nb[9];
+          int n = 0;
+          constexpr int NN = (Q == 9) ? 9 : 3;
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-          v[i] = feq[i] + c * (v[i] - feq[i]);
-          d[i] = feq[i] - v[i];
+          for (int k = 0; k < NN; ++k) {
+            const int dy = (Q == 9) ? k / 3 - 1 : 0, dx = (Q == 9) ? k % 3 - 1 : k - 1;
+            const R val = sdS[(by + HY + dy) * SW + lx + 1 + dx];
+            const bool in = !(val != val);
+            n += in ? 1 : 0;
+            nb[k] = in ? val : r_inf<R>();
+          }
+          if constexpr (Q == 9) {
+            sort_net9<R>(nb);
+            const int rank = (n + 1) / 2 - 1;
+            med = nb[0];
+#pragma unroll
+            for (int k = 1; k < 9; ++k) med = rank == k ? nb[k] : med;
+          } else {
+            R a0 = fmin(nb[0], nb[1]), a1 = fmax(nb[0], nb[1]);
+            const R a2 = fmax(a1, nb[2]);
+            a1 = fmin(a1, nb[2]);
+            const R b0 = fmin(a0, a1), b1 = fmax(a0, a1);
+            (void)a2;
+            med = ((n + 1) / 2 - 1) == 0 ? b0 : b1;
+          }
         }
+        const bool acc = cand & (med < dS);
+        if (acc) {
+          const R c = sqrt(med / dS);
+#pragma unroll
+          for (int i = 0; i < Q; ++i) {
+            v[i] = feq[i] + c * (v[i] - feq[i]);
+            d[i] = feq[i] - v[i];
+          }
+        }
+        if (A.count_events) count_event(acc, cnt + CNT_MEDIAN);
+      } else if (A.count_events) {
+        count_event(false, cnt + CNT_MEDIAN);
       }
-      if (A.count_events) count_event(acc, cnt + CNT_MEDIAN);
-    } else if (A.count_events) {
-      count_event(false, cnt + CNT_MEDIAN);
     }
   }
 
