@@ -217,10 +217,13 @@ __device__ __forceinline__ void moments_v(const R v[Q], R rho0, R& m0, R& ux, R&
 // D3Q27 (uz): the same with three factors, 1/f*_abc = (216/rho) /
 // ((c_a + dt_a)(c_b + dt_b)(c_c + dt_c)).
 // site_dS_dev takes the equilibrium's deviations dt_a of u_x, u_y, u_z
-// (eq_dev6) from the caller; site_dS_q evaluates them.
+// (eq_dev6) from the caller; site_dS_q evaluates them.  `screened`, when
+// given, is set when the value returned is the bound U (below `screen`)
+// rather than Delta S itself.
 template <class R, int Q, bool SH>
 __device__ __forceinline__ R site_dS_dev(const R v[Q], const R d[Q], R m0, R rho0, const R dx[3],
-                                         const R dy[3], const R dz[3], R screen) {
+                                         const R dy[3], const R dz[3], R screen,
+                                         bool* screened = nullptr) {
   R fx[3], fy[3], fz[3], rx[3], ry[3], rz[3];
   const R rho = SH ? rho0 + m0 : m0;
   constexpr R S = Q == 27 ? R(216) : (Q == 9 ? R(36) : R(6));
@@ -264,7 +267,10 @@ __device__ __forceinline__ R site_dS_dev(const R v[Q], const R d[Q], R m0, R rho
   if (screen > R(0)) {
     const R ub = sdy * (R(0.5) + ymax * R(1.0 / 3.0));   // ymax >= 0 (it starts at 0)
     // the margin covers the rounding of the bound itself
-    if (!(ymax > R(0.5)) && ub * R(1.0001) < screen) return ub;
+    if (!(ymax > R(0.5)) && ub * R(1.0001) < screen) {
+      if (screened) *screened = true;
+      return ub;
+    }
   }
   // A negative population f_i = v_i + w_i rho0 < 0 has y_i = (f*_i - f_i) /
   // f*_i > 1 (f*_i > 0 here), so the screen above never returns for it and
@@ -362,7 +368,7 @@ __device__ __forceinline__ typename StoreT<S>::R site_prep(
     const StepArgs<typename StoreT<S>::R>& A, int x, int y, typename StoreT<S>::R v[Q],
     typename StoreT<S>::R feq[Q], typename StoreT<S>::R d[Q], typename StoreT<S>::R& m0,
     typename StoreT<S>::R& ux, typename StoreT<S>::R& uy, bool need_dS,
-    typename StoreT<S>::R screen = typename StoreT<S>::R(0)) {
+    typename StoreT<S>::R screen = typename StoreT<S>::R(0), bool* screened = nullptr) {
   using R = typename StoreT<S>::R;
   constexpr bool SH = StoreT<S>::shifted;
   if constexpr (PER) pull_periodic<S, Q, CACHED>((const S*)A.src, A.qs, A.pitch, A.nx, A.ny, x, y, v);
@@ -375,7 +381,8 @@ __device__ __forceinline__ typename StoreT<S>::R site_prep(
   equilibrium_v<R, Q, SH>(m0, A.rho0, ux, uy, A.eq_kind, feq, dx, dy);
 #pragma unroll
   for (int i = 0; i < Q; ++i) d[i] = feq[i] - v[i];
-  return (need_dS && !wall) ? site_dS_dev<R, Q, SH>(v, d, m0, A.rho0, dx, dy, dx, screen) : R(0);
+  return (need_dS && !wall) ? site_dS_dev<R, Q, SH>(v, d, m0, A.rho0, dx, dy, dx, screen, screened)
+                            : R(0);
 }
 
 template <class R> struct KeyInf;

@@ -174,14 +174,21 @@ void k_step(const StepArgs<typename StoreT<S>::R> A) {
 
   unsigned long long* const cnt = A.counters + (blockIdx.x % kCntSlots) * CNT_N;
   const bool need_dS = MEDIAN || ENS || A.ehrenfest;
-  // Without the median filter, Delta S only decides Ehrenfest candidacy:
-  // sites provably below the floor skip its exact evaluation.
+  // Sites provably below the Ehrenfest floor skip the exact Delta S; with
+  // the median filter, sites provably below delta as well (below both,
+  // a site is no candidate of either), and a workgroup that holds a
+  // median candidate evaluates them exactly further down.
   const StepFrame fr = step_frame(A.sel);
-  const R screen = (!MEDIAN && !ENS && A.ehrenfest) ? value_of_key<R>(fr.floor) : R(0);
+  const R ehr_screen = A.ehrenfest ? value_of_key<R>(fr.floor) : r_inf<R>();
+  const R screen = ENS ? R(0)
+                       : (MEDIAN ? fmin(A.med_delta, ehr_screen) : (A.ehrenfest ? ehr_screen : R(0)));
   R v[Q], feq[Q], d[Q], m0 = R(0), ux = R(0), uy = R(0), dS = R(0);
+  bool screened = false;
   // the median kernel's pulls are cached: its halo sites are pulled again,
   // here or by the neighbouring tiles
-  if (valid) dS = site_prep<S, Q, PER, !PER, MEDIAN>(A, x, y, v, feq, d, m0, ux, uy, need_dS, screen);
+  if (valid)
+    dS = site_prep<S, Q, PER, !PER, MEDIAN>(A, x, y, v, feq, d, m0, ux, uy, need_dS, screen,
+                                            &screened);
 
   if constexpr (ENS) {
     double prod = 0.0, lim = 0.0, sdS = 0.0, nfin = 0.0;
@@ -241,6 +248,8 @@ void k_step(const StepArgs<typename StoreT<S>::R> A) {
     // neither the halo's Delta S nor the neighbourhoods
     const bool cand = valid && !wall && (dS > A.med_delta) && (dS < r_inf<R>());
     if (__syncthreads_or(cand)) {
+      // the neighbourhoods need every Delta S exact
+      if (screened) dS = site_dS<R, Q, SH>(v, d, m0, A.rho0, ux, uy, A.eq_kind, R(0));
       sdS[(by + HY) * SW + lx + 1] = valid ? (wall ? R(__builtin_nan("")) : dS) : slot_dS<S, Q, true>(A, x, y);
       constexpr int NHALO = SH_ * SW - TX * TY * NB;
       for (int s = threadIdx.x; s < NHALO; s += 256 * NB) {
