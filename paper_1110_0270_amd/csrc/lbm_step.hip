@@ -427,7 +427,9 @@ static hipError_t launch_t(const void* args, hipStream_t s, hipEvent_t e0, hipEv
     // tile 412 us, two 379, three 353; four 457 on another (one workgroup
     // per CU).  FP64 and ELBM (over 128 registers) keep one tile.
     constexpr int NB = (COLL != COLL_ELBM && sizeof(typename StoreT<S>::R) == 4) ? 3 : 1;
-    launch_k<S, Q, COLL, MEDIAN, 64, 4, false, false, NB>(A, s, e0, e1);
+    // periodic lattices: the branch-free pull of the tile's own sites
+    if (A.bc == BC_PERIODIC) launch_k<S, Q, COLL, MEDIAN, 64, 4, true, false, NB>(A, s, e0, e1);
+    else launch_k<S, Q, COLL, MEDIAN, 64, 4, false, false, NB>(A, s, e0, e1);
   } else {
     if (tile_shape(Q, MEDIAN, A.nx).tx == 256) {
       // 16-bit storage and ELBM.  With cached loads the one-site-per-lane
