@@ -652,15 +652,16 @@ __device__ void fix_tail(const StepArgs<typename StoreT<S>::R>& A, long long k, 
   __syncthreads();
 
   // --- floor and frame for the next step of this parity --------------------
-  // Keep between 2k and 4k candidates (aim at 3k); the floor is never raised
-  // when k is at least a tenth of the lattice.  (A window up to 6k let the
-  // count drift to 4.5-4.7k, each extra candidate an exact Delta S in the
-  // step kernel and an entry for the selection kernels to sort.)  The frame spans twice the
+  // Keep between 2k and 3.5k candidates (aim at 3k); the floor is never
+  // raised when k is at least a tenth of the lattice.  (A window up to 6k
+  // let the count drift to 4.5-4.7k, each extra candidate an exact Delta S
+  // in the step kernel and an entry for the selection kernels to sort; one
+  // up to 3k re-aims almost every step, which cost more than it saved.)  The frame spans twice the
   // current candidates' range above the floor.
   const unsigned long long dk = delta_key<R>(A.ehr_delta);
   unsigned long long fnext = dk;
   if (10 * k < n_sites && k > 0) {
-    const bool keep = raised && !fell_back && nc >= 2 * k && nc <= 4 * k;
+    const bool keep = raised && !fell_back && nc >= 2 * k && nc <= 7 * k / 2;
     if (keep) {
       fnext = floor_prev;
     } else {
